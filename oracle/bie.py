@@ -1,0 +1,56 @@
+"""Oracle Dirichlet BVP solve through the boundary integral equation
+(TEST INFRASTRUCTURE ONLY).
+
+For lap u - kappa u = f in Omega, u = g on Gamma (eq. 3.13), the density
+phi of the double-layer potential solves the second-kind equation (3.17),
+1/2 phi + W phi + Y f = g, and u = W phi + Y f (eq. 3.18).  Each of W phi
+and Y f is the solution of an interface problem (3.24)/(3.27), so with
+IS(f, phi) the interface solve of oracle.interface (reading R2):
+
+    K v  = IS(0, v).U^+           (the discrete 1/2 I + W at Gamma)
+    b    = g - IS(f, 0).U^+
+    phi  = GMRES(K, b)            (reading R1)
+    U    = IS(f, phi).U            on the grid; u = U at inside nodes.
+"""
+
+import numpy as np
+
+from . import gmres as _gmres
+from .interface import interface_solve
+
+
+def matvec(dom, kappa, v):
+    return interface_solve(dom, kappa, None, None, v)[1]
+
+
+def rhs(dom, kappa, f_grid, f_gamma, g):
+    if f_grid is None:
+        return np.asarray(g).copy()
+    return g - interface_solve(dom, kappa, f_grid, f_gamma,
+                               np.zeros(dom.Nb, dtype=np.result_type(g, f_gamma, kappa)))[1]
+
+
+def dense_operator(dom, kappa):
+    """K assembled column by column (small Nb only)."""
+    dtype = np.complex128 if np.iscomplexobj(kappa) else np.float64
+    K = np.zeros((dom.Nb, dom.Nb), dtype=dtype)
+    for k in range(dom.Nb):
+        e = np.zeros(dom.Nb, dtype=dtype)
+        e[k] = 1.0
+        K[:, k] = matvec(dom, kappa, e)
+    return K
+
+
+def helmholtz_solve(dom, kappa, f_grid, f_gamma, g, phi0=None, tol=1e-10,
+                    restart=50, max_iter=500, fixed_iters=None):
+    """Solve the Dirichlet problem.  Returns (U, phi, stats)."""
+    cplx = any(np.iscomplexobj(v) for v in (kappa, f_grid, f_gamma, g, phi0)
+               if v is not None)
+    dtype = np.complex128 if cplx else np.float64
+    g = np.asarray(g, dtype=dtype)
+    b = rhs(dom, kappa, f_grid, f_gamma, g)
+    phi, iters, rel, conv = _gmres.gmres(
+        lambda v: matvec(dom, kappa, v), b, phi0, tol=tol, restart=restart,
+        max_iter=max_iter, fixed_iters=fixed_iters)
+    U, _ = interface_solve(dom, kappa, f_grid, f_gamma, phi)
+    return U, phi, {"iters": iters, "rel_resid": rel, "converged": conv}
