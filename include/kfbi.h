@@ -1,0 +1,224 @@
+/*
+ * kfbi.h -- C ABI of the MI355X (gfx950) kernel-free boundary integral
+ * (KFBI) time-stepping library.
+ *
+ * The library solves, on an irregular 2-D domain Omega inside the box
+ * B = [-L, L]^2 (paper section 3.2),
+ *
+ *     lap u - kappa u = f  in Omega,   u = g  on Gamma = dOmega     (eq. 3.13)
+ *
+ * through the second-kind boundary integral equation
+ * 1/2 phi + W phi + Y f = g (eq. 3.17) for the double-layer density phi,
+ * u = W phi + Y f (eq. 3.18), where every application of W and Y is the
+ * solution of an interface problem on the Cartesian grid (eqs. 3.24, 3.27,
+ * 3.30): jump corrections at irregular nodes (section 3.2.4), a five-point
+ * (Delta_h - kappa) solve on B with u = 0 on dB (eq. 3.31), and extraction
+ * of the interior limit at the boundary collocation points (section 3.2.6).
+ * GMRES solves the integral equation.  On top of it the implicit time steps
+ * of section 3.1 -- Crank-Nicolson for the heat equation (eqs. 3.1-3.4),
+ * the implicit theta-scheme for the wave equation (eqs. 3.5-3.7) and Strang
+ * splitting for the Schroedinger equation (eqs. 3.8-3.12) -- each reduce to
+ * one such solve.
+ *
+ * Conventions for every call
+ *   - Grid arrays are (M+1) x (M+1), row-major with x fastest:
+ *     element (i, j) at index j*(M+1) + i, node (x_i, y_j) = (-L + i h,
+ *     -L + j h), h = 2L/M.  Boundary arrays have Nb entries ordered by the
+ *     collocation parameter theta_k = 2 pi k / Nb.
+ *   - Arrays passed to the solve and step calls are DEVICE pointers owned by
+ *     the caller; real domains use float64, complex domains interleaved
+ *     complex128 (re, im), as torch stores them.  The library never frees or
+ *     retains caller memory.  Arrays of the copy_* calls are HOST pointers.
+ *   - All device work of a domain is enqueued on the stream given at
+ *     creation (NULL = the default stream).  A call returns after its work
+ *     is enqueued and the scalars it reports have been read back.
+ *   - Every call returns a kfbi_status; on failure kfbi_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this interface.
+ */
+#ifndef KFBI_H
+#define KFBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KFBI_OK = 0,
+    KFBI_EINVAL = 1,   /* bad argument (null pointer, size, mode)            */
+    KFBI_EDOMAIN = 2,  /* interface within 3h of the box, or too few points  */
+    KFBI_ENOMEM = 3,   /* device allocation failed                           */
+    KFBI_ENOCONV = 4,  /* GMRES hit max_iter; outputs and stats still valid  */
+    KFBI_EDEVICE = 5,  /* a HIP runtime call failed                          */
+    KFBI_ENOTSUP = 6   /* combination not supported                          */
+} kfbi_status;
+
+typedef enum { KFBI_CURVE_DISK = 0, KFBI_CURVE_ELLIPSE = 1, KFBI_CURVE_STAR = 2 } kfbi_curve_kind;
+typedef enum { KFBI_REAL = 0, KFBI_COMPLEX = 1 } kfbi_scalar;
+typedef enum { KFBI_PREC_FP64 = 0, KFBI_PREC_MIXED = 1 } kfbi_precision;
+typedef enum { KFBI_HEAT = 0, KFBI_WAVE = 1, KFBI_SCHRODINGER = 2 } kfbi_equation;
+
+/* Domain description (section 3.2.4 grid, Procedure 1 of section 3.3).
+ * Curves, counter-clockwise in theta in [0, 2 pi):
+ *   DISK     (cx + R cos t, cy + R sin t)
+ *   ELLIPSE  (cx + a cos t, cy + b sin t)
+ *   STAR     (cx, cy) + (r0 + amp sin(lobes t)) (cos t, sin t), amp < r0
+ * M: grid intervals per axis, a power of two with 16 <= M <= 4096.
+ * Nb: number of collocation points, 8 <= Nb <= 16384. */
+typedef struct {
+    double L;
+    int32_t M;
+    int32_t Nb;
+    int32_t kind;        /* kfbi_curve_kind */
+    int32_t lobes;
+    double cx, cy;
+    double R;
+    double a, b;
+    double r0, amp;
+    int32_t scalar;      /* kfbi_scalar: element type of every array */
+    int32_t precision;   /* kfbi_precision: default grid-solve precision */
+    void *stream;        /* hipStream_t; NULL = default stream */
+} kfbi_domain_desc;
+
+typedef struct {
+    int32_t M, Nb;
+    double L, h;
+    int32_t n_inside;     /* grid nodes inside Omega                        */
+    int32_t n_irregular;  /* interior nodes with a 4-neighbour on the other
+                             side of Gamma (section 3.2.4)                  */
+    int32_t n_edges;      /* grid edges crossed by Gamma                    */
+    int32_t pad;
+    uint64_t device_bytes;/* device memory held by the domain               */
+} kfbi_domain_info;
+
+typedef struct {
+    double tol;           /* stop when ||b - K phi|| / ||b|| <= tol; default 1e-10 */
+    int32_t max_iter;     /* maximum GMRES iterations (Arnoldi steps); default 500 */
+    int32_t restart;      /* GMRES restart length m, 1..64; default 50             */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations (parity mode)   */
+    int32_t precision;    /* -1: the domain's default; else kfbi_precision         */
+} kfbi_solve_opts;
+
+typedef struct {
+    int32_t iters;        /* GMRES iterations (matrix-vector products in Arnoldi) */
+    int32_t converged;
+    double rel_resid;     /* final ||b - K phi|| / ||b|| estimate                  */
+    int32_t refinements;  /* outer FP64 refinement sweeps (mixed precision)        */
+    int32_t pad;
+    double device_ms;     /* device time of the call (HIP events)                  */
+} kfbi_solve_stats;
+
+typedef struct kfbi_domain kfbi_domain;
+typedef struct kfbi_stepper kfbi_stepper;
+
+/* Thread-local description of the last failure. */
+const char *kfbi_last_error(void);
+
+/* Procedure 1 (section 3.3; parallel form in section 3.4.2): build the grid,
+ * classify every node as inside/outside (strict polynomial test, a node on
+ * Gamma is outside), list irregular nodes in increasing linear index, find
+ * every grid edge crossed by Gamma and its intersection, place Nb
+ * collocation points and factor their six-point extraction stencils
+ * (section 3.2.6).  All of it runs in device kernels.
+ * Errors: EINVAL (bad sizes), EDOMAIN (Gamma within 3h of dB, or the
+ * interface too close to the box), ENOMEM, EDEVICE. */
+int kfbi_domain_create(const kfbi_domain_desc *desc, kfbi_domain **out);
+
+/* Frees the domain's device memory.  Caller buffers are never touched. */
+int kfbi_domain_destroy(kfbi_domain *dom);
+
+int kfbi_domain_get_info(const kfbi_domain *dom, kfbi_domain_info *out);
+
+/* Node classes, (M+1)^2 host bytes: bit 0 = inside, bit 1 = irregular. */
+int kfbi_domain_copy_classification(const kfbi_domain *dom, uint8_t *host_out);
+
+/* Collocation points z_k, host array of 2*Nb doubles (x0, y0, x1, y1, ...). */
+int kfbi_domain_copy_boundary(const kfbi_domain *dom, double *host_out);
+
+/* Crossed edges: host arrays of n_edges entries each.  pq[2e], pq[2e+1] are
+ * the linear indices of the edge's inside and outside node; xyt[3e..3e+2]
+ * are the intersection (x, y) and its curve parameter theta. */
+int kfbi_domain_copy_edges(const kfbi_domain *dom, int32_t *pq, double *xyt);
+
+/* The five-point solve of eq. (3.31) alone: (Delta_h - kappa) U = rhs at
+ * the interior nodes, U = 0 on dB.  rhs and u_out are device grid arrays
+ * (boundary entries of rhs are ignored; those of u_out are written 0).
+ * kappa = kappa_re + i kappa_im; kappa_im must be 0 for a real domain. */
+int kfbi_grid_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
+                    const void *rhs, void *u_out);
+
+/* One interface-problem evaluation (Procedure 2; eqs. 3.30 and the table
+ * after it with Phi = phi, Psi = 0, F = f~): jumps (section 3.2.5),
+ * corrections (section 3.2.4), grid solve, extraction (section 3.2.6).
+ * f_grid (nullable: f = 0) is f on the grid, used at inside nodes only
+ * (eq. 3.25); f_gamma is f's trace on Gamma at the collocation points
+ * (required when f_grid is given); phi (nullable: 0) the density.
+ * u_grid_out (nullable) receives the grid solution, uplus_out (nullable)
+ * the interior limit U+ at the collocation points. */
+int kfbi_interface_apply(kfbi_domain *dom, double kappa_re, double kappa_im,
+                         const void *f_grid, const void *f_gamma,
+                         const void *phi, void *u_grid_out, void *uplus_out);
+
+/* Solve lap u - kappa u = f in Omega, u = g on Gamma (eq. 3.13) through the
+ * integral equation (3.17) by GMRES and the representation (3.18).
+ * f_grid (nullable) / f_gamma as for kfbi_interface_apply; g_gamma the
+ * Dirichlet data at the collocation points; u_grid_out the grid solution
+ * (meaningful at inside nodes); phi_inout (nullable) the warm start on
+ * entry and the density on exit.  opts nullable (defaults), stats nullable.
+ * Returns ENOCONV when max_iter is reached first (outputs still written). */
+int kfbi_helmholtz_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
+                         const void *f_grid, const void *f_gamma,
+                         const void *g_gamma, void *u_grid_out, void *phi_inout,
+                         const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+/* Time-step parameters (section 3.1).
+ *   HEAT: c u_t = lap u + s; Crank-Nicolson, kappa = 2c/tau (c = diffusivity,
+ *         0 means 1).
+ *   WAVE: u_tt = lap u; implicit theta-scheme (eq. 3.5), kappa = 1/(theta
+ *         tau^2); theta in (0, 1/2].
+ *   SCHRODINGER: i u_t = lap u + v u + w |u|^2 u (eq. 2.2); Strang splitting,
+ *         kappa = 2i/tau; v_grid / v_gamma are device arrays (float64) of the
+ *         potential on the grid and at the collocation points (nullable: 0).
+ * The domain must be REAL for HEAT and WAVE, COMPLEX for SCHRODINGER. */
+typedef struct {
+    double tau;
+    double theta;
+    double diffusivity;
+    double w;
+    const void *v_grid;
+    const void *v_gamma;
+} kfbi_step_params;
+
+int kfbi_stepper_create(kfbi_domain *dom, int32_t equation,
+                        const kfbi_step_params *params, kfbi_stepper **out);
+int kfbi_stepper_destroy(kfbi_stepper *st);
+
+/* Initial state "by initial boundary condition" (Procedure 3a):
+ * u0 and lap u0 on the grid and on Gamma (all required); for WAVE also
+ * u^{-1} and lap u^{-1} (the state one step before t = 0), else NULL. */
+int kfbi_stepper_init(kfbi_stepper *st, const void *u0_grid, const void *lap_u0_grid,
+                      const void *u0_gamma, const void *lap_u0_gamma,
+                      const void *uprev_grid, const void *lap_uprev_grid,
+                      const void *uprev_gamma, const void *lap_uprev_gamma);
+
+/* One Crank-Nicolson step t^n -> t^{n+1} (eqs. 3.2-3.4): g_next is u on
+ * Gamma at t^{n+1}; src_grid / src_gamma (nullable) hold s^n + s^{n+1}.
+ * u_grid_out receives u^{n+1}. */
+int kfbi_step_heat(kfbi_stepper *st, const void *g_next_gamma, const void *src_grid,
+                   const void *src_gamma, void *u_grid_out,
+                   const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+/* One theta-scheme step (eqs. 3.5-3.7 and the F recurrence after them). */
+int kfbi_step_wave(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
+                   const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+/* One Strang-splitting step (the three-step algorithm after eq. 3.12). */
+int kfbi_step_schrodinger(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
+                          const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFBI_H */

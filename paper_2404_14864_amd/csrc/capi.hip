@@ -1,0 +1,398 @@
+// C ABI of the library (declared in include/kfbi.h): domain lifecycle, the
+// solve entry points and the time steppers of section 3.1.
+//
+// The steppers carry the paper's right-hand-side recurrences so that no
+// discrete Laplacian of the numerical solution is ever formed; the same
+// recurrence runs on the boundary trace with u = g there, which supplies
+// f on Gamma for the jump conditions.
+//   heat (eqs. 3.2-3.4, c u_t = lap u + s):  kappa = 2c/tau,
+//        f = -(G + s^n + s^{n+1}),  G <- 2 kappa u^{n+1} + f
+//        (G^n = kappa u^n + lap u^n; the paper's F^{n+1} = -f).
+//   wave (eqs. 3.5-3.7, theta-scheme):  kappa = 1/(theta tau^2),
+//        f = -F^{n+1},  F^{n+2} = (kappa/theta) u^{n+1}
+//                                  - (1-2 theta)/theta F^{n+1} - F^n.
+//   Schroedinger (Strang splitting after eq. 3.12):  kappa = 2i/tau,
+//        u** = u* (1 - i beta)/(1 + i beta), beta = tau/2 (v + w|u*|^2),
+//        f = -kappa u**,  u* <- 2 u^{n+1} - u**.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <utility>
+
+#include "kfbi_internal.h"
+
+namespace kfbi {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+int dalloc(kfbi_domain *d, void **p, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        *p = nullptr;
+        return KFBI_ENOMEM;
+    }
+    d->allocs.push_back(*p);
+    d->bytes += bytes;
+    return KFBI_OK;
+}
+
+size_t gmres_bytes(kfbi_domain *d);
+
+namespace {
+
+// out = sum_q c_q x_q over up to four operands (null operands are skipped)
+template <class T>
+__global__ void k_lin4(int n, T *out, T c0, const T *x0, T c1, const T *x1, T c2, const T *x2, T c3,
+                       const T *x3) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T acc = zero<T>();
+    if (x0) acc += c0 * x0[i];
+    if (x1) acc += c1 * x1[i];
+    if (x2) acc += c2 * x2[i];
+    if (x3) acc += c3 * x3[i];
+    out[i] = acc;
+}
+
+// Schroedinger B-step in closed form, in place on u (u* -> u**), and
+// f = -kappa u** with kappa = 2i/tau
+__global__ void k_schr_b(int n, cd *u, const double *v, double w, double tau, cd *f) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cd us = u[i];
+    double beta = 0.5 * tau * ((v ? v[i] : 0.0) + w * abs2(us));
+    cd uss = us * make_cd(1.0, -beta) / make_cd(1.0, beta);
+    u[i] = uss;
+    // -(2i/tau) uss
+    f[i] = make_cd(2.0 / tau * uss.y, -2.0 / tau * uss.x);
+}
+
+template <class T>
+int lin4(kfbi_domain *d, int n, void *out, T c0, const void *x0, T c1 = zero<T>(), const void *x1 = nullptr,
+         T c2 = zero<T>(), const void *x2 = nullptr, T c3 = zero<T>(), const void *x3 = nullptr) {
+    k_lin4<T><<<(n + 255) / 256, 256, 0, d->stream>>>(n, (T *)out, c0, (const T *)x0, c1, (const T *)x1, c2,
+                                                       (const T *)x2, c3, (const T *)x3);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+}  // namespace kfbi
+
+using namespace kfbi;
+
+struct kfbi_stepper {
+    kfbi_domain *dom = nullptr;
+    int eq = 0;
+    kfbi_step_params p{};
+    double kre = 0, kim = 0;
+    bool initialized = false;
+    std::vector<void *> allocs;
+    // state (grid, Gamma)
+    void *A = nullptr, *Ag = nullptr;   // heat: G;  wave: F^{n+1};  schr: u*
+    void *B = nullptr, *Bg = nullptr;   // wave: F^n
+    void *f = nullptr, *fg = nullptr;   // right-hand side of the current solve
+    void *phi = nullptr;                // warm start / density
+};
+
+extern "C" {
+
+const char *kfbi_last_error(void) { return g_err.c_str(); }
+
+int kfbi_domain_create(const kfbi_domain_desc *desc, kfbi_domain **out) {
+    if (!desc || !out) { set_error("null argument"); return KFBI_EINVAL; }
+    *out = nullptr;
+    const kfbi_domain_desc &D = *desc;
+    if (!is_pow2(D.M) || D.M < 16 || D.M > 2048) {
+        set_error("M must be a power of two in [16, 2048]");
+        return KFBI_EINVAL;
+    }
+    if (D.Nb < 8 || D.Nb > 16384) { set_error("Nb must be in [8, 16384]"); return KFBI_EDOMAIN; }
+    if (!(D.L > 0)) { set_error("L must be positive"); return KFBI_EINVAL; }
+    if (D.kind < 0 || D.kind > 2) { set_error("unknown curve kind"); return KFBI_EINVAL; }
+    if (D.kind == KFBI_CURVE_DISK && !(D.R > 0)) { set_error("disk radius must be positive"); return KFBI_EINVAL; }
+    if (D.kind == KFBI_CURVE_ELLIPSE && !(D.a > 0 && D.b > 0)) { set_error("ellipse axes must be positive"); return KFBI_EINVAL; }
+    if (D.kind == KFBI_CURVE_STAR && !(D.r0 > 0 && D.amp >= 0 && D.amp < D.r0 && D.lobes >= 1 && D.lobes <= 64)) {
+        set_error("star needs r0 > amp >= 0 and 1 <= lobes <= 64");
+        return KFBI_EINVAL;
+    }
+    if (D.scalar != KFBI_REAL && D.scalar != KFBI_COMPLEX) { set_error("bad scalar type"); return KFBI_EINVAL; }
+    kfbi_domain *d = new kfbi_domain();
+    d->desc = D;
+    d->M = D.M;
+    d->Nb = D.Nb;
+    d->n = D.M - 1;
+    d->L = D.L;
+    d->h = (2.0 * D.L) / D.M;
+    d->cplx = D.scalar == KFBI_COMPLEX;
+    d->stream = (hipStream_t)D.stream;
+    int st = build_domain(d);
+    if (st == KFBI_OK) {
+        const size_t es = elem_size(d), n = d->n, Nb = d->Nb;
+        const size_t nodes = (size_t)(d->M + 1) * (d->M + 1);
+        (void)nodes;
+        int s2 = KFBI_OK;
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->rhat, n * n * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->uhat, n * n * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->corr, (size_t)d->n_irr * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->ust, 6 * Nb * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->etab, n * n * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->elim, n * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, (void **)&d->tconv, n * sizeof(int32_t));
+        if (s2 == KFBI_OK) { d->gm_bytes = gmres_bytes(d); s2 = dalloc(d, &d->gm, d->gm_bytes); }
+        st = s2;
+    }
+    if (st != KFBI_OK) {
+        std::string keep = g_err;
+        kfbi_domain_destroy(d);
+        g_err = keep;
+        return st;
+    }
+    *out = d;
+    return KFBI_OK;
+}
+
+int kfbi_domain_destroy(kfbi_domain *d) {
+    if (!d) return KFBI_OK;
+    if (d->stream) hipStreamSynchronize(d->stream);
+    else hipDeviceSynchronize();
+    for (void *p : d->allocs) hipFree(p);
+    delete d;
+    return KFBI_OK;
+}
+
+int kfbi_domain_get_info(const kfbi_domain *d, kfbi_domain_info *out) {
+    if (!d || !out) { set_error("null argument"); return KFBI_EINVAL; }
+    memset(out, 0, sizeof(*out));
+    out->M = d->M;
+    out->Nb = d->Nb;
+    out->L = d->L;
+    out->h = d->h;
+    out->n_inside = d->n_inside;
+    out->n_irregular = d->n_irr;
+    out->n_edges = d->n_edges;
+    out->device_bytes = d->bytes;
+    return KFBI_OK;
+}
+
+int kfbi_domain_copy_classification(const kfbi_domain *d, uint8_t *host_out) {
+    if (!d || !host_out) { set_error("null argument"); return KFBI_EINVAL; }
+    size_t nodes = (size_t)(d->M + 1) * (d->M + 1);
+    KFBI_HIP(hipMemcpyAsync(host_out, d->flags, nodes, hipMemcpyDeviceToHost, d->stream));
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    return KFBI_OK;
+}
+
+int kfbi_domain_copy_boundary(const kfbi_domain *d, double *host_out) {
+    if (!d || !host_out) { set_error("null argument"); return KFBI_EINVAL; }
+    std::vector<Colloc> c(d->Nb);
+    KFBI_HIP(hipMemcpyAsync(c.data(), d->col, d->Nb * sizeof(Colloc), hipMemcpyDeviceToHost, d->stream));
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    for (int k = 0; k < d->Nb; ++k) {
+        host_out[2 * k] = c[k].x;
+        host_out[2 * k + 1] = c[k].y;
+    }
+    return KFBI_OK;
+}
+
+int kfbi_domain_copy_edges(const kfbi_domain *d, int32_t *pq, double *xyt) {
+    if (!d || !pq || !xyt) { set_error("null argument"); return KFBI_EINVAL; }
+    std::vector<Edge> e(d->n_edges);
+    KFBI_HIP(hipMemcpyAsync(e.data(), d->edges, d->n_edges * sizeof(Edge), hipMemcpyDeviceToHost, d->stream));
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    for (int q = 0; q < d->n_edges; ++q) {
+        pq[2 * q] = e[q].p_in;
+        pq[2 * q + 1] = e[q].q_out;
+        xyt[3 * q] = e[q].X;
+        xyt[3 * q + 1] = e[q].Y;
+        xyt[3 * q + 2] = e[q].theta;
+    }
+    return KFBI_OK;
+}
+
+static int check_kappa(const kfbi_domain *d, double kim) {
+    if (!d->cplx && kim != 0.0) {
+        set_error("complex kappa needs a complex domain");
+        return KFBI_EINVAL;
+    }
+    return KFBI_OK;
+}
+
+int kfbi_grid_solve(kfbi_domain *d, double kre, double kim, const void *rhs, void *u_out) {
+    if (!d || !rhs || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
+    KFBI_TRY(check_kappa(d, kim));
+    KFBI_TRY(dst_rows_dense(d, rhs, false, d->rhat));
+    KFBI_TRY(ensure_coefficients(d, kre, kim));
+    KFBI_TRY(tridiag_solve(d, d->rhat, nullptr, d->uhat));
+    KFBI_TRY(idst_rows_dense(d, d->uhat, u_out));
+    return KFBI_OK;
+}
+
+int kfbi_interface_apply(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
+                         const void *phi, void *u_grid_out, void *uplus_out) {
+    if (!d) { set_error("null domain"); return KFBI_EINVAL; }
+    KFBI_TRY(check_kappa(d, kim));
+    if (f_grid && !f_gamma) { set_error("f_gamma is required when f_grid is given"); return KFBI_EINVAL; }
+    KFBI_TRY(interface_solve(d, kre, kim, f_grid, f_gamma, phi, u_grid_out, uplus_out, false));
+    return KFBI_OK;
+}
+
+int kfbi_helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
+                         const void *g_gamma, void *u_grid_out, void *phi_inout, const kfbi_solve_opts *opts,
+                         kfbi_solve_stats *stats) {
+    if (!d || !g_gamma) { set_error("null argument"); return KFBI_EINVAL; }
+    KFBI_TRY(check_kappa(d, kim));
+    return helmholtz_solve(d, kre, kim, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
+}
+
+// ---------------------------------------------------------------------------
+// steppers
+// ---------------------------------------------------------------------------
+static int st_alloc(kfbi_stepper *s, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) { set_error("hipMalloc failed for stepper state"); return KFBI_ENOMEM; }
+    s->allocs.push_back(*p);
+    return KFBI_OK;
+}
+
+int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, kfbi_stepper **out) {
+    if (!d || !p || !out) { set_error("null argument"); return KFBI_EINVAL; }
+    *out = nullptr;
+    if (eq < 0 || eq > 2) { set_error("unknown equation"); return KFBI_EINVAL; }
+    if (!(p->tau > 0)) { set_error("tau must be positive"); return KFBI_EINVAL; }
+    if ((eq == KFBI_SCHRODINGER) != d->cplx) {
+        set_error("Schroedinger needs a complex domain; heat and wave a real one");
+        return KFBI_EINVAL;
+    }
+    kfbi_stepper *s = new kfbi_stepper();
+    s->dom = d;
+    s->eq = eq;
+    s->p = *p;
+    if (eq == KFBI_HEAT) {
+        double c = p->diffusivity > 0 ? p->diffusivity : 1.0;
+        s->kre = 2.0 * c / p->tau;
+    } else if (eq == KFBI_WAVE) {
+        if (!(p->theta > 0 && p->theta <= 0.5)) { delete s; set_error("theta must be in (0, 1/2]"); return KFBI_EINVAL; }
+        s->kre = 1.0 / (p->theta * p->tau * p->tau);
+    } else {
+        s->kre = 0.0;
+        s->kim = 2.0 / p->tau;
+    }
+    const size_t es = elem_size(d), nodes = (size_t)(d->M + 1) * (d->M + 1), Nb = d->Nb;
+    int st = KFBI_OK;
+    if (st == KFBI_OK) st = st_alloc(s, &s->A, nodes * es);
+    if (st == KFBI_OK) st = st_alloc(s, &s->Ag, Nb * es);
+    if (st == KFBI_OK) st = st_alloc(s, &s->B, nodes * es);
+    if (st == KFBI_OK) st = st_alloc(s, &s->Bg, Nb * es);
+    if (st == KFBI_OK) st = st_alloc(s, &s->f, nodes * es);
+    if (st == KFBI_OK) st = st_alloc(s, &s->fg, Nb * es);
+    if (st == KFBI_OK) st = st_alloc(s, &s->phi, Nb * es);
+    if (st == KFBI_OK && hipMemsetAsync(s->phi, 0, Nb * es, d->stream) != hipSuccess) st = KFBI_EDEVICE;
+    if (st != KFBI_OK) { kfbi_stepper_destroy(s); return st; }
+    *out = s;
+    return KFBI_OK;
+}
+
+int kfbi_stepper_destroy(kfbi_stepper *s) {
+    if (!s) return KFBI_OK;
+    if (s->dom && s->dom->stream) hipStreamSynchronize(s->dom->stream);
+    else hipDeviceSynchronize();
+    for (void *p : s->allocs) hipFree(p);
+    delete s;
+    return KFBI_OK;
+}
+
+int kfbi_stepper_init(kfbi_stepper *s, const void *u0, const void *lap0, const void *u0g, const void *lap0g,
+                      const void *um1, const void *lapm1, const void *um1g, const void *lapm1g) {
+    if (!s || !u0 || !lap0 || !u0g || !lap0g) { set_error("u0 and lap u0 on grid and Gamma are required"); return KFBI_EINVAL; }
+    kfbi_domain *d = s->dom;
+    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+    if (s->eq == KFBI_HEAT) {
+        // G^0 = kappa u^0 + lap u^0
+        KFBI_TRY(lin4<double>(d, ng, s->A, s->kre, u0, 1.0, lap0));
+        KFBI_TRY(lin4<double>(d, Nb, s->Ag, s->kre, u0g, 1.0, lap0g));
+    } else if (s->eq == KFBI_WAVE) {
+        if (!um1 || !lapm1 || !um1g || !lapm1g) { set_error("wave needs u^{-1} and lap u^{-1}"); return KFBI_EINVAL; }
+        const double k = s->kre, th = s->p.theta, c1 = (1.0 - 2.0 * th) / th;
+        // F^1 = kappa (2 u^0 - u^{-1}) + c1 lap u^0 + lap u^{-1};  F^0 = kappa u^0 - lap u^0
+        KFBI_TRY(lin4<double>(d, ng, s->A, 2.0 * k, u0, -k, um1, c1, lap0, 1.0, lapm1));
+        KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * k, u0g, -k, um1g, c1, lap0g, 1.0, lapm1g));
+        KFBI_TRY(lin4<double>(d, ng, s->B, k, u0, -1.0, lap0));
+        KFBI_TRY(lin4<double>(d, Nb, s->Bg, k, u0g, -1.0, lap0g));
+    } else {
+        // u*^0 = u^0 - i tau/2 lap u^0
+        const cd c = make_cd(0.0, -0.5 * s->p.tau);
+        KFBI_TRY(lin4<cd>(d, ng, s->A, make_cd(1.0, 0.0), u0, c, lap0));
+        KFBI_TRY(lin4<cd>(d, Nb, s->Ag, make_cd(1.0, 0.0), u0g, c, lap0g));
+    }
+    KFBI_HIP(hipMemsetAsync(s->phi, 0, Nb * elem_size(d), d->stream));
+    s->initialized = true;
+    return KFBI_OK;
+}
+
+static int step_solve(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_solve_opts *opts,
+                      kfbi_solve_stats *stats) {
+    return helmholtz_solve(s->dom, s->kre, s->kim, s->f, s->fg, g_next, u_out, s->phi, opts, stats);
+}
+
+int kfbi_step_heat(kfbi_stepper *s, const void *g_next, const void *src, const void *srcg, void *u_out,
+                   const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+    if (!s || !g_next || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
+    if (s->eq != KFBI_HEAT || !s->initialized) { set_error("not an initialised heat stepper"); return KFBI_EINVAL; }
+    kfbi_domain *d = s->dom;
+    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+    KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A, -1.0, src));
+    KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag, -1.0, srcg));
+    int st = step_solve(s, g_next, u_out, opts, stats);
+    if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
+    KFBI_TRY(lin4<double>(d, ng, s->A, 2.0 * s->kre, u_out, 1.0, s->f));
+    KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * s->kre, g_next, 1.0, s->fg));
+    return st;
+}
+
+int kfbi_step_wave(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_solve_opts *opts,
+                   kfbi_solve_stats *stats) {
+    if (!s || !g_next || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
+    if (s->eq != KFBI_WAVE || !s->initialized) { set_error("not an initialised wave stepper"); return KFBI_EINVAL; }
+    kfbi_domain *d = s->dom;
+    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+    KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A));
+    KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag));
+    int st = step_solve(s, g_next, u_out, opts, stats);
+    if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
+    const double th = s->p.theta, c1 = (1.0 - 2.0 * th) / th, a = s->kre / th;
+    // F^{n+2} into the F^n buffer, then swap
+    KFBI_TRY(lin4<double>(d, ng, s->B, a, u_out, -c1, s->A, -1.0, s->B));
+    KFBI_TRY(lin4<double>(d, Nb, s->Bg, a, g_next, -c1, s->Ag, -1.0, s->Bg));
+    std::swap(s->A, s->B);
+    std::swap(s->Ag, s->Bg);
+    return st;
+}
+
+int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_solve_opts *opts,
+                          kfbi_solve_stats *stats) {
+    if (!s || !g_next || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
+    if (s->eq != KFBI_SCHRODINGER || !s->initialized) { set_error("not an initialised Schroedinger stepper"); return KFBI_EINVAL; }
+    kfbi_domain *d = s->dom;
+    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+    k_schr_b<<<(ng + 255) / 256, 256, 0, d->stream>>>(ng, (cd *)s->A, (const double *)s->p.v_grid, s->p.w,
+                                                     s->p.tau, (cd *)s->f);
+    KFBI_CHECK_LAUNCH();
+    k_schr_b<<<(Nb + 255) / 256, 256, 0, d->stream>>>(Nb, (cd *)s->Ag, (const double *)s->p.v_gamma, s->p.w,
+                                                     s->p.tau, (cd *)s->fg);
+    KFBI_CHECK_LAUNCH();
+    int st = step_solve(s, g_next, u_out, opts, stats);
+    if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
+    const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
+    KFBI_TRY(lin4<cd>(d, ng, s->A, two, u_out, m1, s->A));
+    KFBI_TRY(lin4<cd>(d, Nb, s->Ag, two, g_next, m1, s->Ag));
+    return st;
+}
+
+}  // extern "C"

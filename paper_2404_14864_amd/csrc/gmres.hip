@@ -1,0 +1,441 @@
+// GMRES for the discrete second-kind integral equation (3.17) on the device.
+//
+// The paper iterates (3.17) with Richardson's method (3.21) and names GMRES
+// as the better Krylov choice in its conclusion; this library uses
+// restarted GMRES(m).  All Krylov state lives on the device: a control block
+// (current column j, iteration count, residual, done flag), the basis V,
+// the Hessenberg matrix H and the Givens rotations.  Every kernel of an
+// iteration reads j and the done flag from the control block, so a chunk of
+// iterations is enqueued without host round trips and the host reads the
+// control block once per chunk; after convergence the remaining kernels of
+// the chunk return at once.
+//
+// Arnoldi orthogonalisation is classical Gram-Schmidt applied twice (CGS2:
+// two passes of all inner products at once, so a step costs a fixed handful
+// of workgroup reductions instead of one per basis vector); it gives the same
+// basis as modified Gram-Schmidt up to rounding.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kfbi_internal.h"
+
+namespace kfbi {
+
+struct GmCtl {
+    int j, done, iters, converged;
+    int max_iter, m, fixed, breakdown;
+    double tol, bnorm, beta, resid;
+};
+
+namespace {
+
+constexpr int kGmThreads = 1024;
+
+
+template <class T> struct WS;
+template <> struct WS<double> {
+    __device__ static double xr(double v, int o) { return __shfl_xor(v, o, 64); }
+};
+template <> struct WS<cd> {
+    __device__ static cd xr(cd v, int o) { return make_cd(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64)); }
+};
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += WS<T>::xr(v, o);
+    return v;
+}
+
+// block-wide sum; every thread gets the result
+template <class T>
+__device__ T block_sum(T v, T *red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    T s = zero<T>();
+    const int nw = blockDim.x >> 6;
+    for (int q = 0; q < nw; ++q) s += red[q];
+    __syncthreads();
+    return s;
+}
+
+__device__ inline double absv(double a) { return fabs(a); }
+__device__ inline double absv(cd a) { return hypot(a.x, a.y); }
+
+template <class T> __device__ inline T scale_of(double s);
+template <> __device__ inline double scale_of<double>(double s) { return s; }
+template <> __device__ inline cd scale_of<cd>(double s) { return make_cd(s, 0.0); }
+
+// ||b|| into the control block
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_bnorm(GmCtl *ctl, const T *b, int Nb) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < Nb; i += blockDim.x) s += abs2(b[i]);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) ctl->bnorm = sqrt(s);
+}
+
+// start of a cycle: v_0 = r/||r||, g = ||r|| e_1
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_start(GmCtl *ctl, const T *r, T *V, T *g, int Nb) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < Nb; i += blockDim.x) s += abs2(r[i]);
+    s = block_sum(s, red);
+    const double beta = sqrt(s);
+    const int limit = ctl->fixed > 0 ? ctl->fixed : ctl->max_iter;
+    const bool conv = beta <= ctl->tol * ctl->bnorm;
+    const bool stop = (ctl->fixed == 0 && conv) || beta == 0.0 || ctl->iters >= limit;
+    if (!stop) {
+        const double inv = 1.0 / beta;
+        for (int i = threadIdx.x; i < Nb; i += blockDim.x) V[i] = r[i] * inv;
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q <= ctl->m; ++q) g[q] = zero<T>();
+        g[0] = scale_of<T>(beta);
+        ctl->beta = beta;
+        ctl->resid = beta;
+        ctl->j = 0;
+        ctl->breakdown = 0;
+        ctl->converged = conv ? 1 : 0;
+        ctl->done = stop ? 1 : 0;
+    }
+}
+
+// one Arnoldi step on column j: w = V[j+1] holds K v_j on entry
+template <class T, int EPT>
+__global__ __launch_bounds__(kGmThreads) void k_gm_arnoldi(GmCtl *ctl, T *V, T *H, T *g, double *cs, T *sn,
+                                                           int Nb) {
+    if (ctl->done) return;
+    __shared__ T red[16][8];
+    __shared__ T hs[72];
+    __shared__ double redd[16];
+    const int j = ctl->j, m = ctl->m;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    T *w = V + (size_t)(j + 1) * Nb;
+    T wl[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        int idx = tid + e * kGmThreads;
+        wl[e] = idx < Nb ? w[idx] : zero<T>();
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = 0; i0 <= j; i0 += 8) {
+            T part[8];
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii) part[ii] = zero<T>();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                int idx = tid + e * kGmThreads;
+                if (idx < Nb) {
+#pragma unroll
+                    for (int ii = 0; ii < 8; ++ii)
+                        if (i0 + ii <= j) part[ii] += conjv(V[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii) {
+                T s = wave_sum(part[ii]);
+                if (lane == 0) red[wid][ii] = s;
+            }
+            __syncthreads();
+            if (tid < 8 && i0 + tid <= j) {
+                T s = zero<T>();
+                for (int q = 0; q < (kGmThreads >> 6); ++q) s += red[q][tid];
+                hs[i0 + tid] = s;
+                size_t hidx = (size_t)(i0 + tid) * m + j;
+                H[hidx] = pass == 0 ? s : H[hidx] + s;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            int idx = tid + e * kGmThreads;
+            if (idx < Nb)
+                for (int i = 0; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+        }
+        __syncthreads();
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) s2 += abs2(wl[e]);
+    const double hn = sqrt(block_sum(s2, redd));
+    if (hn > 0.0) {
+        const double inv = 1.0 / hn;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            int idx = tid + e * kGmThreads;
+            if (idx < Nb) w[idx] = wl[e] * inv;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        H[(size_t)(j + 1) * m + j] = scale_of<T>(hn);
+        for (int i = 0; i < j; ++i) {
+            T a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+            H[(size_t)i * m + j] = a * cs[i] + sn[i] * b;
+            H[(size_t)(i + 1) * m + j] = b * cs[i] - conjv(sn[i]) * a;
+        }
+        T a = H[(size_t)j * m + j];
+        const double bb = hn;
+        const double aa = absv(a);
+        const double rho = hypot(aa, bb);
+        double c;
+        T s;
+        if (aa == 0.0) {
+            c = 0.0;
+            s = scale_of<T>(1.0);
+        } else {
+            c = aa / rho;
+            s = a * (bb / (aa * rho));   // (a/|a|) conj(b)/rho with b real
+        }
+        cs[j] = c;
+        sn[j] = s;
+        H[(size_t)j * m + j] = a * c + s * bb;
+        H[(size_t)(j + 1) * m + j] = zero<T>();
+        T gj = g[j];
+        g[j + 1] = -(conjv(s) * gj);
+        g[j] = gj * c;
+        const double resid = absv(g[j + 1]);
+        ctl->resid = resid;
+        const int it = ctl->iters + 1;
+        ctl->iters = it;
+        ctl->j = j + 1;
+        const bool conv = resid <= ctl->tol * ctl->bnorm;
+        ctl->converged = conv ? 1 : 0;
+        const int limit = ctl->fixed > 0 ? ctl->fixed : ctl->max_iter;
+        if (hn == 0.0) ctl->breakdown = 1;
+        if ((ctl->fixed == 0 && conv) || it >= limit || j + 1 >= m || hn == 0.0) ctl->done = 1;
+    }
+}
+
+// end of a cycle: y = H^{-1} g on the leading j x j block, x += V y
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_update(GmCtl *ctl, const T *V, const T *H, const T *g, T *y,
+                                                          T *x, int Nb) {
+    __shared__ T ys[72];
+    const int jj = ctl->j, m = ctl->m;
+    if (threadIdx.x == 0) {
+        for (int i = jj - 1; i >= 0; --i) {
+            T s = g[i];
+            for (int l = i + 1; l < jj; ++l) s -= H[(size_t)i * m + l] * ys[l];
+            ys[i] = s / H[(size_t)i * m + i];
+            y[i] = ys[i];
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < Nb; idx += blockDim.x) {
+        T acc = x[idx];
+        for (int i = 0; i < jj; ++i) acc += V[(size_t)i * Nb + idx] * ys[i];
+        x[idx] = acc;
+    }
+}
+
+struct GmPtrs {
+    GmCtl *ctl;
+    void *V, *H, *g, *sn, *y, *x, *b, *r;
+    double *cs;
+};
+
+GmPtrs gm_layout(kfbi_domain *d, int mmax) {
+    GmPtrs P;
+    const size_t es = elem_size(d), Nb = d->Nb;
+    char *base = (char *)d->gm;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return (void *)p;
+    };
+    P.ctl = (GmCtl *)take(sizeof(GmCtl));
+    P.V = take((mmax + 1) * Nb * es);
+    P.H = take((size_t)(mmax + 1) * mmax * es);
+    P.g = take((mmax + 1) * es);
+    P.cs = (double *)take(mmax * sizeof(double));
+    P.sn = take(mmax * es);
+    P.y = take(mmax * es);
+    P.x = take(Nb * es);
+    P.b = take(Nb * es);
+    P.r = take(Nb * es);
+    return P;
+}
+
+}  // namespace
+
+size_t gmres_bytes(kfbi_domain *d) {
+    const size_t es = elem_size(d), Nb = d->Nb, mmax = 64;
+    size_t tot = 0;
+    auto add = [&](size_t b) { tot += (b + 255) & ~(size_t)255; };
+    add(sizeof(GmCtl));
+    add((mmax + 1) * Nb * es);
+    add((mmax + 1) * mmax * es);
+    add((mmax + 1) * es);
+    add(mmax * sizeof(double));
+    add(mmax * es);
+    add(mmax * es);
+    add(Nb * es);
+    add(Nb * es);
+    add(Nb * es);
+    return tot;
+}
+
+// elements of a basis vector per thread: the smallest power of two that covers Nb
+template <class T>
+static int launch_arnoldi(GmPtrs &P, int Nb, hipStream_t s) {
+    const int ept = (Nb + kGmThreads - 1) / kGmThreads;
+#define KFBI_ARN(E) k_gm_arnoldi<T, E><<<1, kGmThreads, 0, s>>>(P.ctl, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn, Nb)
+    if (ept <= 1) KFBI_ARN(1);
+    else if (ept <= 2) KFBI_ARN(2);
+    else if (ept <= 4) KFBI_ARN(4);
+    else if (ept <= 8) KFBI_ARN(8);
+    else KFBI_ARN(16);
+#undef KFBI_ARN
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+// K x (or b - K x when g/scale say so) for an explicit density pointer
+static int matvec_explicit(kfbi_domain *d, double kre, double kim, const void *phi, const void *g,
+                           double scale, void *out) {
+    KFBI_TRY(compute_corrections(d, kre, kim, phi, nullptr, d->corr));
+    KFBI_TRY(tridiag_solve(d, nullptr, d->corr, d->uhat));
+    KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
+    KFBI_TRY(extract_boundary(d, kre, kim, d->ust, phi, nullptr, g, scale, out));
+    return KFBI_OK;
+}
+
+template <class T>
+static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kfbi_solve_opts &o,
+                     int *iters_out, double *rel_out, int *conv_out) {
+    hipStream_t s = d->stream;
+    const int Nb = d->Nb;
+    GmCtl h;
+    memset(&h, 0, sizeof(h));
+    h.max_iter = o.max_iter;
+    h.m = o.restart;
+    h.fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
+    h.tol = o.tol;
+    KFBI_HIP(hipMemcpyAsync(P.ctl, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    k_gm_bnorm<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.b, Nb);
+    KFBI_CHECK_LAUNCH();
+    int *jptr = &P.ctl->j;
+    int *done = &P.ctl->done;
+    const int chunk = 4;
+    for (int cycle = 0; cycle < 100000; ++cycle) {
+        // r = b - K x, then v_0 = r / ||r||
+        KFBI_TRY(matvec_explicit(d, kre, kim, P.x, P.b, -1.0, P.r));
+        k_gm_start<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.r, (T *)P.V, (T *)P.g, Nb);
+        KFBI_CHECK_LAUNCH();
+        for (;;) {
+            for (int c = 0; c < chunk; ++c) {
+                KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.V, jptr, nullptr, d->corr, done));
+                KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, done));
+                KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, done));
+                KFBI_TRY(extract_boundary_ctl(d, kre, kim, d->ust, P.V, jptr, nullptr, nullptr, 1.0, P.V, 1, done));
+                KFBI_TRY(launch_arnoldi<T>(P, Nb, s));
+            }
+            KFBI_HIP(hipMemcpyAsync(&h, P.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
+            KFBI_HIP(hipStreamSynchronize(s));
+            if (h.done) break;
+        }
+        if (h.j > 0) {
+            k_gm_update<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.V, (const T *)P.H, (const T *)P.g,
+                                                    (T *)P.y, (T *)P.x, Nb);
+            KFBI_CHECK_LAUNCH();
+        }
+        const int limit = h.fixed > 0 ? h.fixed : h.max_iter;
+        if ((h.fixed == 0 && h.converged) || h.iters >= limit || h.beta == 0.0 || h.j == 0) break;
+    }
+    *iters_out = h.iters;
+    *rel_out = h.bnorm > 0 ? h.resid / h.bnorm : h.resid;
+    *conv_out = h.converged;
+    return KFBI_OK;
+}
+
+int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
+                    const void *g_gamma, void *u_grid_out, void *phi_inout, const kfbi_solve_opts *opts,
+                    kfbi_solve_stats *stats) {
+    kfbi_solve_opts o;
+    o.tol = 1e-10;
+    o.max_iter = 500;
+    o.restart = 50;
+    o.fixed_iters = 0;
+    o.precision = -1;
+    if (opts) {
+        if (opts->tol > 0) o.tol = opts->tol;
+        if (opts->max_iter > 0) o.max_iter = opts->max_iter;
+        if (opts->restart > 0) o.restart = opts->restart;
+        o.fixed_iters = opts->fixed_iters;
+        o.precision = opts->precision;
+    }
+    if (o.restart > 64) {
+        set_error("restart length must be at most 64");
+        return KFBI_EINVAL;
+    }
+    if (f_grid && !f_gamma) {
+        set_error("f_gamma is required when f_grid is given");
+        return KFBI_EINVAL;
+    }
+    if (d->Nb > kGmThreads * 16) {
+        set_error("too many collocation points for the Arnoldi kernel");
+        return KFBI_ENOTSUP;
+    }
+    hipStream_t s = d->stream;
+    hipEvent_t e0, e1;
+    KFBI_HIP(hipEventCreate(&e0));
+    KFBI_HIP(hipEventCreate(&e1));
+    KFBI_HIP(hipEventRecord(e0, s));
+    GmPtrs P = gm_layout(d, 64);
+    const size_t vb = (size_t)d->Nb * elem_size(d);
+    KFBI_TRY(ensure_coefficients(d, kre, kim));
+    // b = g - IS(f, 0).U+
+    if (f_grid) {
+        KFBI_TRY(dst_rows_dense(d, f_grid, true, d->rhat));
+        KFBI_TRY(compute_corrections(d, kre, kim, nullptr, f_gamma, d->corr));
+        KFBI_TRY(tridiag_solve(d, d->rhat, d->corr, d->uhat));
+        KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
+        KFBI_TRY(extract_boundary(d, kre, kim, d->ust, nullptr, f_gamma, g_gamma, -1.0, P.b));
+    } else {
+        KFBI_HIP(hipMemcpyAsync(P.b, g_gamma, vb, hipMemcpyDeviceToDevice, s));
+    }
+    if (phi_inout) KFBI_HIP(hipMemcpyAsync(P.x, phi_inout, vb, hipMemcpyDeviceToDevice, s));
+    else KFBI_HIP(hipMemsetAsync(P.x, 0, vb, s));
+    int iters = 0, conv = 0;
+    double rel = 0.0;
+    int st;
+    if (d->cplx) st = gmres_run<cd>(d, kre, kim, P, o, &iters, &rel, &conv);
+    else st = gmres_run<double>(d, kre, kim, P, o, &iters, &rel, &conv);
+    if (st != KFBI_OK) return st;
+    // U = IS(f, phi).U on the grid
+    KFBI_TRY(compute_corrections(d, kre, kim, P.x, f_gamma, d->corr));
+    KFBI_TRY(tridiag_solve(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat));
+    if (u_grid_out) KFBI_TRY(idst_rows_dense(d, d->uhat, u_grid_out));
+    if (phi_inout) KFBI_HIP(hipMemcpyAsync(phi_inout, P.x, vb, hipMemcpyDeviceToDevice, s));
+    KFBI_HIP(hipEventRecord(e1, s));
+    KFBI_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    KFBI_HIP(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (stats) {
+        stats->iters = iters;
+        stats->converged = conv;
+        stats->rel_resid = rel;
+        stats->refinements = 0;
+        stats->device_ms = ms;
+    }
+    const bool fixed = o.fixed_iters > 0;
+    if (!conv && !fixed) {
+        set_error("GMRES reached max_iter before the tolerance");
+        return KFBI_ENOCONV;
+    }
+    return KFBI_OK;
+}
+
+}  // namespace kfbi

@@ -1,0 +1,411 @@
+// Five-point (Delta_h - kappa) solve on the box with u = 0 on dB (eq. 3.31),
+// by a sine transform in x and one tridiagonal solve per x-mode in y.
+//
+// With R^[t][k] = sum_i R[t][i] sin(pi i k / M) (DST-I along x, modes
+// k = 1..M-1) the system decouples into, for every mode k,
+//
+//     U^_{t-1} - d_k U^_t + U^_{t+1} = h^2 R^_t,   U^_0 = U^_M = 0,
+//     d_k = 2 + 4 sin^2(pi k / 2M) + kappa h^2,
+//
+// which is strictly diagonally dominant (|d_k| > 2, also for complex kappa),
+// and U = (2/M) DST-I(U^) row by row.
+//
+// Layout: mode-space arrays are n x n (n = M - 1), row t (grid row j = t+1)
+// major, mode fastest: element (t, k-1) at t*n + (k-1).
+//
+// Kernels
+//   k_dst_rows      dense DST-I of whole rows through a radix-2 FFT of the
+//                   odd extension (length 2M) held in LDS; two real rows are
+//                   packed into one complex transform.
+//   k_coef          Thomas coefficients e_t of every mode (per kappa).
+//   k_tridiag       one wavefront per mode: the Thomas forward and backward
+//                   recurrences are first-order affine recurrences, solved as
+//                   a chunked scan -- each lane composes the affine maps of
+//                   its rows, a wavefront-shuffle scan combines the lanes,
+//                   and each lane replays its rows.  The right-hand side of a
+//                   correction-only solve is sparse (irregular nodes only), so
+//                   its x-transform is synthesised in place from a sine table
+//                   instead of being read from memory.
+//   k_eval_nodes    U at single grid nodes: one wavefront per node reduces
+//                   the inverse transform of its row.
+#include <hip/hip_runtime.h>
+
+#include "kfbi_internal.h"
+
+namespace kfbi {
+
+namespace {
+
+template <class T> struct Shfl;
+template <> struct Shfl<double> {
+    __device__ static double up(double v, int o) { return __shfl_up(v, o, 64); }
+    __device__ static double down(double v, int o) { return __shfl_down(v, o, 64); }
+    __device__ static double xr(double v, int o) { return __shfl_xor(v, o, 64); }
+};
+template <> struct Shfl<cd> {
+    __device__ static cd up(cd v, int o) { return make_cd(__shfl_up(v.x, o, 64), __shfl_up(v.y, o, 64)); }
+    __device__ static cd down(cd v, int o) { return make_cd(__shfl_down(v.x, o, 64), __shfl_down(v.y, o, 64)); }
+    __device__ static cd xr(cd v, int o) { return make_cd(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64)); }
+};
+
+template <class T> __device__ inline T one();
+template <> __device__ inline double one<double>() { return 1.0; }
+template <> __device__ inline cd one<cd>() { return make_cd(1.0, 0.0); }
+
+__device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (32 - bits); }
+
+// ---------------------------------------------------------------------------
+// dense DST-I of rows.
+//   in(t, i)  for i = 1..M-1 at in[in_off(t) + i - 1]
+//   out(t, k) for k = 1..M-1 at out[out_off(t) + k - 1], scaled by `scale`
+// grid layout: row t at (t+1)*(M+1) + 1;  mode layout: row t at t*n.
+// Real rows are paired (t = 2b, 2b+1) into one complex transform
+// z = y1 + i y2 of the odd extensions, whose transform is Z_k = 2 S2_k -
+// 2i S1_k; a complex row's transform is Y_k = -2i S_k.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_dst_rows(int M, int logN2, const T *in, bool in_grid,
+                                                  const uint8_t *mask, T *out, bool out_grid,
+                                                  double scale, const double *twiddle) {
+    extern __shared__ double lds[];
+    double2 *a = reinterpret_cast<double2 *>(lds);
+    const int n = M - 1, N2 = 2 * M;
+    constexpr bool CPLX = sizeof(T) == sizeof(cd);
+    const int rows_per = CPLX ? 1 : 2;
+    const int t_first = blockIdx.x * rows_per;
+    // load the odd extension, bit-reversed
+    for (int m = threadIdx.x; m < N2; m += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        int i = (m <= M) ? m : N2 - m;      // position in the row
+        double sgn = (m <= M) ? 1.0 : -1.0;
+        if (i >= 1 && i <= n) {
+            for (int r = 0; r < rows_per; ++r) {
+                int t = t_first + r;
+                if (t >= n) continue;
+                size_t idx = in_grid ? (size_t)(t + 1) * (M + 1) + i : (size_t)t * n + (i - 1);
+                bool keep = (mask == nullptr) || (mask[(size_t)(t + 1) * (M + 1) + i] & 1);
+                if (!keep) continue;
+                if constexpr (CPLX) {
+                    const cd v = reinterpret_cast<const cd *>(in)[idx];
+                    re = sgn * v.x;
+                    im = sgn * v.y;
+                } else {
+                    double v = reinterpret_cast<const double *>(in)[idx];
+                    if (r == 0) re = sgn * v; else im = sgn * v;
+                }
+            }
+        }
+        a[bitrev(m, logN2)] = make_double2(re, im);
+    }
+    __syncthreads();
+    // in-place radix-2 decimation-in-time, twiddle exp(-2 pi i m / N2)
+    for (int len = 2, tstep = M; len <= N2; len <<= 1, tstep >>= 1) {
+        int half = len >> 1;
+        for (int b = threadIdx.x; b < M; b += blockDim.x) {
+            int grp = b / half, pos = b - grp * half;
+            int i0 = grp * len + pos, i1 = i0 + half;
+            double wr = twiddle[2 * pos * tstep], wi = twiddle[2 * pos * tstep + 1];
+            double2 u = a[i0], v = a[i1];
+            double vr = v.x * wr - v.y * wi, vi = v.x * wi + v.y * wr;
+            a[i0] = make_double2(u.x + vr, u.y + vi);
+            a[i1] = make_double2(u.x - vr, u.y - vi);
+        }
+        __syncthreads();
+    }
+    // unpack
+    for (int k = 1 + threadIdx.x; k <= n; k += blockDim.x) {
+        double2 Z = a[k];
+        for (int r = 0; r < rows_per; ++r) {
+            int t = t_first + r;
+            if (t >= n) continue;
+            size_t idx = out_grid ? (size_t)(t + 1) * (M + 1) + k : (size_t)t * n + (k - 1);
+            if constexpr (CPLX) {
+                // S_k = i Y_k / 2
+                reinterpret_cast<cd *>(out)[idx] = make_cd(-0.5 * scale * Z.y, 0.5 * scale * Z.x);
+            } else {
+                double v = (r == 0) ? -0.5 * Z.y : 0.5 * Z.x;
+                reinterpret_cast<double *>(out)[idx] = scale * v;
+            }
+        }
+    }
+    if (out_grid) {  // boundary columns of the interior rows
+        for (int r = threadIdx.x; r < rows_per; r += blockDim.x) {
+            int t = t_first + r;
+            if (t >= n) continue;
+            size_t base = (size_t)(t + 1) * (M + 1);
+            reinterpret_cast<T *>(out)[base] = zero<T>();
+            reinterpret_cast<T *>(out)[base + M] = zero<T>();
+        }
+    }
+}
+
+// first and last grid rows of a grid array: zero
+template <class T>
+__global__ void k_zero_edge_rows(int M, T *grid) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > M) return;
+    grid[i] = zero<T>();
+    grid[(size_t)M * (M + 1) + i] = zero<T>();
+}
+
+// ---------------------------------------------------------------------------
+// Thomas coefficients.  With e_1 = 1/d, e_t = 1/(d - e_{t-1}) the forward
+// sweep is x_t = e_t (x_{t-1} - rho_t) and the backward sweep
+// U_t = e_t U_{t+1} + x_t.  e_t converges geometrically to the root of
+// e = 1/(d - e) inside the unit disk; it is tabulated until it stops
+// changing (relative 1e-17) and the limit is used afterwards.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_coef(int M, double kh2_re, double kh2_im, T *etab, T *elim, int32_t *tconv) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = M - 1;
+    if (k >= n) return;
+    double s = sinpi((double)(k + 1) / (2.0 * M));
+    T dk = from_re_im<T>(2.0 + 4.0 * s * s + kh2_re, kh2_im);
+    T e = one<T>() / dk;
+    int t = 0;
+    for (; t < n; ++t) {
+        etab[(size_t)t * n + k] = e;
+        T nx = one<T>() / (dk - e);
+        T df = nx - e;
+        if (abs2(df) <= 1e-34 * abs2(e)) { e = nx; ++t; break; }
+        e = nx;
+    }
+    tconv[k] = t;
+    elim[k] = e;
+}
+
+// ---------------------------------------------------------------------------
+// tridiagonal solves: one 64-lane wavefront per mode, C rows per lane
+// (64*C >= n).  rho_t = h^2 (rhat[t][k] + sum over irregular nodes q of row
+// t of corr[q] sin(pi i_q k / M)).
+// ---------------------------------------------------------------------------
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_tridiag(int M, double h2, const T *__restrict__ rhat,
+                                                 const T *__restrict__ corr,
+                                                 const int32_t *__restrict__ irr_col,
+                                                 const int32_t *__restrict__ row_ptr,
+                                                 const double *__restrict__ sine,
+                                                 const T *__restrict__ etab, const T *__restrict__ elim,
+                                                 const int32_t *__restrict__ tconv, T *__restrict__ uhat,
+                                                 const int *__restrict__ done) {
+    extern __shared__ double S[];  // 2M sine values
+    const int n = M - 1;
+    const int mask2M = 2 * M - 1;
+    if (done && *done) return;
+    for (int m = threadIdx.x; m < 2 * M; m += blockDim.x) S[m] = sine[m];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);  // 0-based mode (mode number k+1)
+    if (k >= n) return;
+    const int mode = k + 1;
+    const int t0 = lane * C;
+    const int tc = tconv[k];
+    const T lim = elim[k];
+
+    T v[C];
+    // pass 1: right-hand side, chunk composite of x -> e (x - rho)
+    T A = one<T>(), B = zero<T>();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        int t = t0 + c;
+        T r = zero<T>();
+        if (t < n) {
+            if (rhat) r = rhat[(size_t)t * n + k];
+            if (corr) {
+                int q1 = row_ptr[t + 1];
+                for (int q = row_ptr[t]; q < q1; ++q) r += corr[q] * S[(irr_col[q] * mode) & mask2M];
+            }
+            r = h2 * r;
+            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
+            B = e * (B - r);
+            A = e * A;
+        }
+        v[c] = r;
+    }
+    // inclusive scan of affine maps over lanes (earlier lanes applied first)
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T Ap = Shfl<T>::up(A, off), Bp = Shfl<T>::up(B, off);
+        if (lane >= off) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    T x = Shfl<T>::up(B, 1);
+    if (lane == 0) x = zero<T>();
+    // replay: forward values x_t
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        int t = t0 + c;
+        if (t < n) {
+            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
+            x = e * (x - v[c]);
+            v[c] = x;
+        }
+    }
+    // backward: U_t = e_t U_{t+1} + x_t, composite over the chunk from its end
+    A = one<T>();
+    B = zero<T>();
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        int t = t0 + c;
+        if (t < n) {
+            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
+            B = e * B + v[c];
+            A = e * A;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T Ap = Shfl<T>::down(A, off), Bp = Shfl<T>::down(B, off);
+        if (lane + off < 64) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    T y = Shfl<T>::down(B, 1);
+    if (lane == 63) y = zero<T>();
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        int t = t0 + c;
+        if (t < n) {
+            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
+            y = e * y + v[c];
+            uhat[(size_t)t * n + k] = y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// U at listed nodes: one wavefront per node, U = (2/M) sum_k U^[t][k]
+// sin(pi i k / M).  nodes: linear grid indices (interior nodes only).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int32_t *__restrict__ nodes,
+                                                    int node_stride, const T *__restrict__ uhat,
+                                                    const double *__restrict__ sine, T *__restrict__ out,
+                                                    const int *__restrict__ done) {
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nnodes) return;
+    const int n = M - 1, mask2M = 2 * M - 1;
+    // nodes of a stencil record are 6 consecutive int32 followed by the rest of
+    // the record; node_stride is the record size in int32 units
+    int node = nodes[(size_t)(p / 6) * node_stride + (p % 6)];
+    int i = node % (M + 1), j = node / (M + 1);
+    const T *row = uhat + (size_t)(j - 1) * n;
+    T acc = zero<T>();
+    for (int k = lane; k < n; k += 64) acc += row[k] * sine[(i * (k + 1)) & mask2M];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+    if (lane == 0) out[p] = (2.0 / M) * acc;
+}
+
+template <class T>
+int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out,
+               bool out_grid, double scale) {
+    const int M = d->M, n = M - 1;
+    int logN2 = 0;
+    while ((1 << logN2) < 2 * M) ++logN2;
+    const bool cplx = sizeof(T) == sizeof(cd);
+    int blocks = cplx ? n : (n + 1) / 2;
+    size_t lds = (size_t)2 * M * sizeof(double2);
+    k_dst_rows<T><<<blocks, 256, lds, d->stream>>>(M, logN2, (const T *)in, in_grid, mask, (T *)out,
+                                                   out_grid, scale, d->twiddle);
+    KFBI_CHECK_LAUNCH();
+    if (out_grid) {
+        k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(M, (T *)out);
+        KFBI_CHECK_LAUNCH();
+    }
+    return KFBI_OK;
+}
+
+template <class T>
+int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
+    const int M = d->M, n = M - 1;
+    const double h2 = d->h * d->h;
+    int blocks = (n + 3) / 4;
+    size_t lds = (size_t)2 * M * sizeof(double);
+#define KFBI_TRI(CC)                                                                              \
+    k_tridiag<T, CC><<<blocks, 256, lds, d->stream>>>(M, h2, (const T *)rhat, (const T *)corr,    \
+                                                      d->irr_col, d->irr_row_ptr, d->sine,        \
+                                                      (const T *)d->etab, (const T *)d->elim,     \
+                                                      d->tconv, (T *)uhat, done)
+    int c = (n + 63) / 64;
+    if (c <= 1) KFBI_TRI(1);
+    else if (c <= 2) KFBI_TRI(2);
+    else if (c <= 4) KFBI_TRI(4);
+    else if (c <= 8) KFBI_TRI(8);
+    else if (c <= 16) KFBI_TRI(16);
+    else if (c <= 32) KFBI_TRI(32);
+    else {
+        set_error("grid too large for the tridiagonal kernel");
+        return KFBI_ENOTSUP;
+    }
+#undef KFBI_TRI
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+}  // namespace
+
+int ensure_coefficients(kfbi_domain *d, double kre, double kim) {
+    if (d->coef_valid && d->coef_kre == kre && d->coef_kim == kim) return KFBI_OK;
+    const int M = d->M, n = M - 1;
+    const double h2 = d->h * d->h;
+    if (d->cplx)
+        k_coef<cd><<<(n + 127) / 128, 128, 0, d->stream>>>(M, kre * h2, kim * h2, (cd *)d->etab,
+                                                          (cd *)d->elim, d->tconv);
+    else
+        k_coef<double><<<(n + 127) / 128, 128, 0, d->stream>>>(M, kre * h2, 0.0, (double *)d->etab,
+                                                              (double *)d->elim, d->tconv);
+    KFBI_CHECK_LAUNCH();
+    d->coef_valid = true;
+    d->coef_kre = kre;
+    d->coef_kim = kim;
+    return KFBI_OK;
+}
+
+int dst_rows_dense(kfbi_domain *d, const void *grid, bool mask_inside, void *rhat_out) {
+    const uint8_t *mask = mask_inside ? d->flags : nullptr;
+    if (d->cplx) return launch_dst<cd>(d, grid, true, mask, rhat_out, false, 1.0);
+    return launch_dst<double>(d, grid, true, mask, rhat_out, false, 1.0);
+}
+
+int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out) {
+    double scale = 2.0 / d->M;
+    if (d->cplx) return launch_dst<cd>(d, uhat, false, nullptr, grid_out, true, scale);
+    return launch_dst<double>(d, uhat, false, nullptr, grid_out, true, scale);
+}
+
+int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out) {
+    return tridiag_solve_ctl(d, rhat, corr, uhat_out, nullptr);
+}
+
+int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out, const int *done) {
+    if (d->cplx) return launch_tridiag<cd>(d, rhat, corr, uhat_out, done);
+    return launch_tridiag<double>(d, rhat, corr, uhat_out, done);
+}
+
+int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out) {
+    return eval_stencil_nodes_ctl(d, uhat, ust_out, nullptr);
+}
+
+int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done) {
+    const int nn = 6 * d->Nb;
+    const int stride = (int)(sizeof(Stencil) / sizeof(int32_t));
+    const int32_t *nodes = reinterpret_cast<const int32_t *>(d->st);
+    if (d->cplx)
+        k_eval_nodes<cd><<<(nn + 3) / 4, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cd *)uhat,
+                                                             d->sine, (cd *)ust_out, done);
+    else
+        k_eval_nodes<double><<<(nn + 3) / 4, 256, 0, d->stream>>>(d->M, nn, nodes, stride,
+                                                                 (const double *)uhat, d->sine,
+                                                                 (double *)ust_out, done);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+}  // namespace kfbi

@@ -1,0 +1,206 @@
+// One interface-problem evaluation on the device (Procedure 2 of section
+// 3.3; the unified interface problem (3.30) with [u] = phi, [u_n] = 0 and
+// F = f~ of eq. 3.25):
+//   * jumps of u and its derivatives across Gamma (section 3.2.5),
+//   * corrections of the five-point equations at irregular nodes (section
+//     3.2.4) -- one thread per irregular node gathers over its own crossed
+//     edges, the "decoupled" strategy of section 3.4.2, so no atomics,
+//   * the grid solve (gridsolve.hip),
+//   * extraction of the interior limit U+ at the collocation points
+//     (section 3.2.6) -- one thread per collocation point.
+//
+// The density phi and its theta-derivatives reach a crossing parameter by
+// fourth-order periodic differences at the collocation points and cubic
+// Lagrange interpolation in theta; the 3x3 second-derivative system is
+// solved in closed form in the (tangent, normal) frame:
+//   u_tt = phi_ss - t'.[grad u],  u_tn = t'_x [u_y] - t'_y [u_x],
+//   u_nn = f + kappa phi - u_tt,  [Hessian] = Q [[u_tt,u_tn],[u_tn,u_nn]] Q^T,
+// Q = (t | n), n = (t_y, -t_x).
+#include <hip/hip_runtime.h>
+
+#include "kfbi_internal.h"
+
+namespace kfbi {
+
+namespace {
+
+template <class T> struct Jumps {
+    T u, ux, uy, uxx, uxy, uyy;
+};
+
+template <class T>
+__device__ inline Jumps<T> jumps_dirichlet(const Frame &f, T phi, T pt, T ptt, T fval, T kappa) {
+    Jumps<T> J;
+    const double inv = 1.0 / f.sigma;
+    const T ps = pt * inv;
+    const T pss = (ptt - ps * f.dsigma) * (inv * inv);
+    J.u = phi;
+    J.ux = ps * f.tx;
+    J.uy = ps * f.ty;
+    const T rtt = pss - (J.ux * f.dtx + J.uy * f.dty);
+    const T rtn = J.uy * f.dtx - J.ux * f.dty;
+    const T rnn = fval + kappa * phi - rtt;
+    const double c = f.tx, s = f.ty;
+    J.uxx = rtt * (c * c) + rtn * (2.0 * c * s) + rnn * (s * s);
+    J.uxy = rtt * (c * s) + rtn * (s * s - c * c) - rnn * (s * c);
+    J.uyy = rtt * (s * s) - rtn * (2.0 * s * c) + rnn * (c * c);
+    return J;
+}
+
+__device__ inline int wrapk(int k, int Nb) {
+    k %= Nb;
+    return k < 0 ? k + Nb : k;
+}
+
+// phi, phi_theta, phi_thetatheta at collocation point k (periodic 4th-order
+// central differences)
+template <class T>
+__device__ inline void bdata(const T *phi, int Nb, int k, double i12d, double i12d2, T &p, T &pt, T &ptt) {
+    T m2 = phi[wrapk(k - 2, Nb)], m1 = phi[wrapk(k - 1, Nb)], c0 = phi[k];
+    T p1 = phi[wrapk(k + 1, Nb)], p2 = phi[wrapk(k + 2, Nb)];
+    p = c0;
+    pt = ((m2 - p2) + (p1 - m1) * 8.0) * i12d;
+    ptt = ((p1 + m1) * 16.0 - (p2 + m2) - c0 * 30.0) * i12d2;
+}
+
+template <class T>
+__device__ inline const T *at_slot(const T *base, const int *jptr, int add, size_t stride) {
+    if (!base) return nullptr;
+    return base + (jptr ? (size_t)(*jptr + add) * stride : 0);
+}
+
+template <class T>
+__global__ void k_corrections(int n_irr, const IrrNode *__restrict__ irr, const Edge *__restrict__ edges,
+                              int Nb, double dth, double h, T kappa, const T *phi_base, const int *jptr,
+                              const T *__restrict__ fg, T *__restrict__ corr, const int *done) {
+    if (done && *done) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_irr) return;
+    const T *phi = at_slot(phi_base, jptr, 0, (size_t)Nb);
+    const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
+    const IrrNode R = irr[q];
+    T acc = zero<T>();
+    for (int s = 0; s < R.nedge; ++s) {
+        const Edge &E = edges[R.edge[s]];
+        T p = zero<T>(), pt = zero<T>(), ptt = zero<T>(), fv = zero<T>();
+        for (int o = 0; o < 4; ++o) {
+            int kk = wrapk(E.k0 - 1 + o, Nb);
+            double w = E.w[o];
+            if (phi) {
+                T a, b, c;
+                bdata(phi, Nb, kk, i12d, i12d2, a, b, c);
+                p += a * w;
+                pt += b * w;
+                ptt += c * w;
+            }
+            if (fg) fv += fg[kk] * w;
+        }
+        Jumps<T> J = jumps_dirichlet(E.fr, p, pt, ptt, fv, kappa);
+        const T ua = E.axis == 0 ? J.ux : J.uy;
+        const T uaa = E.axis == 0 ? J.uxx : J.uyy;
+        const double dd = R.d[s];
+        acc += J.u + ua * dd + uaa * (0.5 * dd * dd);
+    }
+    corr[q] = acc * (-R.sgn / (h * h));
+}
+
+// U+(z_k) = sum_p w_p (U(p) + [p outside] J_k(p)); out = g + scale U+
+template <class T>
+__global__ void k_extract(int Nb, double dth, const Colloc *__restrict__ col, const Stencil *__restrict__ st,
+                          T kappa, const T *__restrict__ ust, const T *phi_base, const int *jptr,
+                          const T *__restrict__ fg, const T *__restrict__ g, double scale, T *out_base,
+                          int out_add, const int *done) {
+    if (done && *done) return;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Nb) return;
+    const T *phi = at_slot(phi_base, jptr, 0, (size_t)Nb);
+    T *out = out_base + (jptr ? (size_t)(*jptr + out_add) * Nb : 0);
+    const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
+    T p = zero<T>(), pt = zero<T>(), ptt = zero<T>();
+    if (phi) bdata(phi, Nb, k, i12d, i12d2, p, pt, ptt);
+    T fv = fg ? fg[k] : zero<T>();
+    Jumps<T> J = jumps_dirichlet(col[k].fr, p, pt, ptt, fv, kappa);
+    const Stencil &S = st[k];
+    T up = zero<T>();
+    for (int q = 0; q < 6; ++q) {
+        T val = ust[6 * k + q];
+        if ((S.out_mask >> q) & 1) {
+            const double xi = S.xi[q], eta = S.eta[q];
+            val += J.u + J.ux * xi + J.uy * eta + J.uxx * (0.5 * xi * xi) + J.uxy * (xi * eta) +
+                   J.uyy * (0.5 * eta * eta);
+        }
+        up += val * S.w[q];
+    }
+    T res = up * scale;
+    if (g) res += g[k];
+    out[k] = res;
+}
+
+template <class T> T kappa_of(double kre, double kim);
+template <> double kappa_of<double>(double kre, double) { return kre; }
+template <> cd kappa_of<cd>(double kre, double kim) { return make_cd(kre, kim); }
+
+template <class T>
+int launch_corr(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
+                const void *fg, void *corr, const int *done) {
+    const double dth = 6.283185307179586476925286766559 / d->Nb;
+    k_corrections<T><<<(d->n_irr + 127) / 128, 128, 0, d->stream>>>(
+        d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kappa_of<T>(kre, kim), (const T *)phi_base, jptr,
+        (const T *)fg, (T *)corr, done);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+template <class T>
+int launch_extract(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi_base,
+                   const int *jptr, const void *fg, const void *g, double scale, void *out_base,
+                   int out_add, const int *done) {
+    const double dth = 6.283185307179586476925286766559 / d->Nb;
+    k_extract<T><<<(d->Nb + 127) / 128, 128, 0, d->stream>>>(
+        d->Nb, dth, d->col, d->st, kappa_of<T>(kre, kim), (const T *)ust, (const T *)phi_base, jptr,
+        (const T *)fg, (const T *)g, scale, (T *)out_base, out_add, done);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+}  // namespace
+
+int compute_corrections_ctl(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
+                            const void *f_gamma, void *corr_out, const int *done) {
+    if (d->cplx) return launch_corr<cd>(d, kre, kim, phi_base, jptr, f_gamma, corr_out, done);
+    return launch_corr<double>(d, kre, kim, phi_base, jptr, f_gamma, corr_out, done);
+}
+
+int compute_corrections(kfbi_domain *d, double kre, double kim, const void *phi, const void *f_gamma,
+                        void *corr_out) {
+    return compute_corrections_ctl(d, kre, kim, phi, nullptr, f_gamma, corr_out, nullptr);
+}
+
+int extract_boundary_ctl(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi_base,
+                         const int *jptr, const void *f_gamma, const void *g, double scale, void *out_base,
+                         int out_add, const int *done) {
+    if (d->cplx)
+        return launch_extract<cd>(d, kre, kim, ust, phi_base, jptr, f_gamma, g, scale, out_base, out_add, done);
+    return launch_extract<double>(d, kre, kim, ust, phi_base, jptr, f_gamma, g, scale, out_base, out_add, done);
+}
+
+int extract_boundary(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi,
+                     const void *f_gamma, const void *g_minus, double scale, void *out) {
+    return extract_boundary_ctl(d, kre, kim, ust, phi, nullptr, f_gamma, g_minus, scale, out, 0, nullptr);
+}
+
+int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
+                    const void *phi, void *u_grid_out, void *uplus_out, bool reuse_rhat) {
+    if (f_grid && !reuse_rhat) KFBI_TRY(dst_rows_dense(d, f_grid, true, d->rhat));
+    KFBI_TRY(compute_corrections(d, kre, kim, phi, f_gamma, d->corr));
+    KFBI_TRY(ensure_coefficients(d, kre, kim));
+    KFBI_TRY(tridiag_solve(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat));
+    if (uplus_out) {
+        KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
+        KFBI_TRY(extract_boundary(d, kre, kim, d->ust, phi, f_gamma, nullptr, 1.0, uplus_out));
+    }
+    if (u_grid_out) KFBI_TRY(idst_rows_dense(d, d->uhat, u_grid_out));
+    return KFBI_OK;
+}
+
+}  // namespace kfbi

@@ -1,0 +1,227 @@
+// Internal declarations of the KFBI HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kfbi.h"
+
+namespace kfbi {
+
+// ---------------------------------------------------------------------------
+// scalar types: real double, and an interleaved complex double that matches
+// torch's complex128 layout.
+// ---------------------------------------------------------------------------
+struct cd {
+    double x, y;
+};
+
+__host__ __device__ inline cd make_cd(double a, double b) { cd r; r.x = a; r.y = b; return r; }
+__host__ __device__ inline cd operator+(cd a, cd b) { return make_cd(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cd operator-(cd a, cd b) { return make_cd(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cd operator-(cd a) { return make_cd(-a.x, -a.y); }
+__host__ __device__ inline cd operator*(cd a, cd b) { return make_cd(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline cd operator*(double s, cd a) { return make_cd(s * a.x, s * a.y); }
+__host__ __device__ inline cd operator*(cd a, double s) { return make_cd(s * a.x, s * a.y); }
+__host__ __device__ inline cd operator/(cd a, cd b) {
+    // Smith's algorithm
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, den = b.x + b.y * r;
+        return make_cd((a.x + a.y * r) / den, (a.y - a.x * r) / den);
+    }
+    double r = b.x / b.y, den = b.x * r + b.y;
+    return make_cd((a.x * r + a.y) / den, (a.y * r - a.x) / den);
+}
+__host__ __device__ inline cd &operator+=(cd &a, cd b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline cd &operator-=(cd &a, cd b) { a.x -= b.x; a.y -= b.y; return a; }
+
+// generic helpers over double / cd
+__host__ __device__ inline double conjv(double a) { return a; }
+__host__ __device__ inline cd conjv(cd a) { return make_cd(a.x, -a.y); }
+__host__ __device__ inline double abs2(double a) { return a * a; }
+__host__ __device__ inline double abs2(cd a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double realv(double a) { return a; }
+__host__ __device__ inline double realv(cd a) { return a.x; }
+template <class T> __host__ __device__ inline T zero();
+template <> __host__ __device__ inline double zero<double>() { return 0.0; }
+template <> __host__ __device__ inline cd zero<cd>() { return make_cd(0.0, 0.0); }
+template <class T> __host__ __device__ inline T from_re_im(double re, double im);
+template <> __host__ __device__ inline double from_re_im<double>(double re, double) { return re; }
+template <> __host__ __device__ inline cd from_re_im<cd>(double re, double im) { return make_cd(re, im); }
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+
+#define KFBI_HIP(call)                                                                 \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            ::kfbi::set_error(std::string(#call) + ": " + hipGetErrorString(_e));       \
+            return KFBI_EDEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+
+#define KFBI_CHECK_LAUNCH()                                                            \
+    do {                                                                               \
+        hipError_t _e = hipGetLastError();                                             \
+        if (_e != hipSuccess) {                                                        \
+            ::kfbi::set_error(std::string("kernel launch: ") + hipGetErrorString(_e)); \
+            return KFBI_EDEVICE;                                                       \
+        }                                                                              \
+    } while (0)
+
+#define KFBI_TRY(expr)                     \
+    do {                                   \
+        int _s = (expr);                   \
+        if (_s != KFBI_OK) return _s;      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry of one point on Gamma (curve frame, section 3.2.5)
+// ---------------------------------------------------------------------------
+struct Frame {
+    double sigma, dsigma;   // |gamma'|, d|gamma'|/dtheta
+    double tx, ty;          // unit tangent
+    double dtx, dty;        // dt/ds
+};
+
+// per crossed edge: the data the jump computation and the corrections need
+struct Edge {
+    double X, Y, theta;     // intersection and its curve parameter
+    Frame fr;
+    int32_t p_in, q_out;    // linear indices of the inside / outside node
+    int32_t axis;           // 0: x-edge, 1: y-edge
+    int32_t k0;             // Lagrange base: nodes k0-1 .. k0+2 (mod Nb)
+    double w[4];            // cubic Lagrange weights
+};
+
+// per irregular node: its crossed edges (up to 4) and the signed offsets of
+// the neighbour across each edge from the intersection
+struct IrrNode {
+    int32_t node;           // linear index
+    int32_t nedge;
+    int32_t edge[4];
+    double d[4];            // (other node)_a - X_a along the edge axis
+    double sgn;             // +1 inside, -1 outside
+    int32_t row_i;          // x index i of the node
+    int32_t pad;
+};
+
+struct Colloc {
+    double x, y;
+    Frame fr;
+};
+
+struct Stencil {
+    int32_t node[6];        // linear indices
+    int32_t out_mask;       // bit p set: node p is outside Omega
+    int32_t pad;
+    double w[6];            // extraction weights (row 0 of A^{-1})
+    double xi[6], eta[6];   // node - z
+};
+
+// ---------------------------------------------------------------------------
+// the domain: everything Procedure 1 builds, resident on the device
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace kfbi
+
+struct kfbi_domain {
+    kfbi_domain_desc desc;
+    int M = 0, Nb = 0, n = 0;           // n = M - 1 interior nodes per axis
+    double L = 0, h = 0;
+    bool cplx = false;
+    hipStream_t stream = nullptr;
+    int n_inside = 0, n_irr = 0, n_edges = 0;
+    size_t bytes = 0;
+    std::vector<void *> allocs;         // every device allocation of the domain
+
+    // device data
+    uint8_t *flags = nullptr;           // (M+1)^2
+    kfbi::Edge *edges = nullptr;        // n_edges
+    kfbi::IrrNode *irr = nullptr;       // n_irr, sorted by linear index
+    int32_t *irr_row_ptr = nullptr;     // n+1: irregular nodes of interior row t (j = t+1)
+    int32_t *irr_col = nullptr;         // n_irr: x index i of each irregular node
+    kfbi::Colloc *col = nullptr;        // Nb
+    kfbi::Stencil *st = nullptr;        // Nb
+    double *sine = nullptr;             // 2M: sin(pi m / M)
+    double *twiddle = nullptr;          // 2M complex: exp(-2 pi i m / 2M), m < M
+
+    // scratch for solves (element type T = double or cd; sized for cd)
+    void *rhat = nullptr;               // n*n: DST of the dense right-hand side
+    void *uhat = nullptr;               // n*n: mode-space solution
+    void *corr = nullptr;               // n_irr: corrections
+    void *ust = nullptr;                // 6*Nb: grid solution at stencil nodes
+    void *tmp_grid = nullptr;           // (M+1)^2
+    void *vec = nullptr;                // scratch boundary vectors (8*Nb)
+
+    // tridiagonal coefficient table (per kappa)
+    bool coef_valid = false;
+    double coef_kre = 0, coef_kim = 0;
+    void *etab = nullptr;               // n*n worst case, [t][k]
+    void *elim = nullptr;               // n: converged e_inf per mode
+    int32_t *tconv = nullptr;           // n: first t that uses the limit
+
+    // GMRES workspace
+    void *gm = nullptr;                 // device GmresState (+ basis)
+    size_t gm_bytes = 0;
+};
+
+namespace kfbi {
+
+// allocation helper: records the pointer in the domain
+int dalloc(kfbi_domain *d, void **p, size_t bytes);
+
+// setup (domain.hip)
+int build_domain(kfbi_domain *d);
+
+// grid solve pieces (gridsolve.hip)
+int ensure_coefficients(kfbi_domain *d, double kre, double kim);
+// R = dense rhs (grid array, nullable) masked to inside nodes when mask_inside
+int dst_rows_dense(kfbi_domain *d, const void *grid, bool mask_inside, void *rhat_out);
+// Uhat = T^{-1} h^2 (rhat (nullable) + synth(corr))
+int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out);
+int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out, const int *done);
+// U on the full grid from Uhat
+int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out);
+// U at the 6 Nb stencil nodes
+int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out);
+int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done);
+
+// interface pieces (interface.hip)
+int compute_corrections(kfbi_domain *d, double kre, double kim, const void *phi,
+                        const void *f_gamma, void *corr_out);
+int extract_boundary(kfbi_domain *d, double kre, double kim, const void *ust,
+                     const void *phi, const void *f_gamma, const void *g_minus,
+                     double scale, void *out);
+// variants whose density / output slot is base + (*jptr + add) * Nb and that
+// return at once when *done is set (device-resident GMRES control)
+int compute_corrections_ctl(kfbi_domain *d, double kre, double kim, const void *phi_base,
+                            const int *jptr, const void *f_gamma, void *corr_out, const int *done);
+int extract_boundary_ctl(kfbi_domain *d, double kre, double kim, const void *ust,
+                         const void *phi_base, const int *jptr, const void *f_gamma,
+                         const void *g, double scale, void *out_base, int out_add,
+                         const int *done);
+
+// one full interface solve IS(f, f_gamma, phi) -> (u grid, U+)
+int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
+                    const void *f_gamma, const void *phi, void *u_grid_out,
+                    void *uplus_out, bool reuse_rhat);
+
+// GMRES (gmres.hip)
+int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
+                    const void *f_gamma, const void *g_gamma, void *u_grid_out,
+                    void *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : sizeof(double); }
+
+}  // namespace kfbi

@@ -1,0 +1,262 @@
+"""Thin Python binding of the KFBI HIP library (include/kfbi.h).
+
+Argument marshalling only: every function below forwards to the C entry
+point of the same name in libkfbi.so, passing torch tensors as raw device
+pointers and the current torch stream as the domain stream.  Nothing here
+computes any part of the method; if the library is missing the import of
+the functions fails loudly.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkfbi.so")
+
+KFBI_OK, KFBI_EINVAL, KFBI_EDOMAIN, KFBI_ENOMEM, KFBI_ENOCONV, KFBI_EDEVICE, KFBI_ENOTSUP = range(7)
+CURVES = {"disk": 0, "ellipse": 1, "star": 2}
+KFBI_REAL, KFBI_COMPLEX = 0, 1
+KFBI_PREC_FP64, KFBI_PREC_MIXED = 0, 1
+KFBI_HEAT, KFBI_WAVE, KFBI_SCHRODINGER = 0, 1, 2
+
+
+class KfbiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("kfbi error %d: %s" % (code, msg))
+        self.code = code
+
+
+class DomainDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("M", ctypes.c_int32), ("Nb", ctypes.c_int32),
+                ("kind", ctypes.c_int32), ("lobes", ctypes.c_int32),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("R", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("r0", ctypes.c_double), ("amp", ctypes.c_double),
+                ("scalar", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class DomainInfo(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("Nb", ctypes.c_int32), ("L", ctypes.c_double),
+                ("h", ctypes.c_double), ("n_inside", ctypes.c_int32),
+                ("n_irregular", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("refinements", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "converged": bool(self.converged),
+                "rel_resid": self.rel_resid, "refinements": self.refinements,
+                "device_ms": self.device_ms}
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("theta", ctypes.c_double),
+                ("diffusivity", ctypes.c_double), ("w", ctypes.c_double),
+                ("v_grid", ctypes.c_void_p), ("v_gamma", ctypes.c_void_p)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib():
+    """Load libkfbi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libkfbi.so not built; run python -m paper_2404_14864_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "kfbi_last_error": ([], ctypes.c_char_p),
+        "kfbi_domain_create": ([ctypes.POINTER(DomainDesc), ctypes.POINTER(_P)], ctypes.c_int),
+        "kfbi_domain_destroy": ([_P], ctypes.c_int),
+        "kfbi_domain_get_info": ([_P, ctypes.POINTER(DomainInfo)], ctypes.c_int),
+        "kfbi_domain_copy_classification": ([_P, _P], ctypes.c_int),
+        "kfbi_domain_copy_boundary": ([_P, _P], ctypes.c_int),
+        "kfbi_domain_copy_edges": ([_P, _P, _P], ctypes.c_int),
+        "kfbi_grid_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
+        "kfbi_interface_apply": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P], ctypes.c_int),
+        "kfbi_helmholtz_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
+                                  ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_stepper_create": ([_P, ctypes.c_int32, ctypes.POINTER(StepParams), ctypes.POINTER(_P)], ctypes.c_int),
+        "kfbi_stepper_destroy": ([_P], ctypes.c_int),
+        "kfbi_stepper_init": ([_P] + [_P] * 8, ctypes.c_int),
+        "kfbi_step_heat": ([_P, _P, _P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_step_wave": ([_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_step_schrodinger": ([_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfbi_domain_get_info",
+            "kfbi_domain_copy_classification", "kfbi_domain_copy_boundary", "kfbi_domain_copy_edges",
+            "kfbi_grid_solve", "kfbi_interface_apply", "kfbi_helmholtz_solve", "kfbi_stepper_create",
+            "kfbi_stepper_destroy", "kfbi_stepper_init", "kfbi_step_heat", "kfbi_step_wave",
+            "kfbi_step_schrodinger")
+
+
+def _check(code, allow=()):
+    if code != KFBI_OK and code not in allow:
+        raise KfbiError(code, lib().kfbi_last_error().decode())
+    return code
+
+
+def _ptr(t, dtype=None, numel=None, name="array"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    o = SolveOpts(tol=opts.get("tol", 0.0), max_iter=opts.get("max_iter", 0),
+                  restart=opts.get("restart", 0), fixed_iters=opts.get("fixed_iters", 0),
+                  precision=opts.get("precision", -1))
+    return ctypes.byref(o)
+
+
+# ---- domain ----------------------------------------------------------------
+def kfbi_domain_create(desc, scalar=KFBI_REAL, precision=KFBI_PREC_FP64, stream=None):
+    """desc: a workload descriptor dict (kind, cx, cy, R, a, b, r0, amp, lobes,
+    L, M, Nb).  Returns an opaque domain handle."""
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    d = DomainDesc(L=desc["L"], M=desc["M"], Nb=desc["Nb"], kind=CURVES[desc["kind"]],
+                   lobes=int(desc.get("lobes", 0)), cx=desc.get("cx", 0.0), cy=desc.get("cy", 0.0),
+                   R=desc.get("R", 0.0), a=desc.get("a", 0.0), b=desc.get("b", 0.0),
+                   r0=desc.get("r0", 0.0), amp=desc.get("amp", 0.0), scalar=scalar,
+                   precision=precision, stream=ctypes.c_void_p(stream))
+    h = _P()
+    _check(lib().kfbi_domain_create(ctypes.byref(d), ctypes.byref(h)))
+    return h
+
+
+def kfbi_domain_destroy(h):
+    _check(lib().kfbi_domain_destroy(h))
+
+
+def kfbi_domain_get_info(h):
+    info = DomainInfo()
+    _check(lib().kfbi_domain_get_info(h, ctypes.byref(info)))
+    return {"M": info.M, "Nb": info.Nb, "L": info.L, "h": info.h, "n_inside": info.n_inside,
+            "n_irregular": info.n_irregular, "n_edges": info.n_edges,
+            "device_bytes": int(info.device_bytes)}
+
+
+def kfbi_domain_copy_classification(h):
+    import numpy as np
+    info = kfbi_domain_get_info(h)
+    out = np.zeros((info["M"] + 1) * (info["M"] + 1), dtype=np.uint8)
+    _check(lib().kfbi_domain_copy_classification(h, out.ctypes.data_as(ctypes.c_void_p)))
+    return out.reshape(info["M"] + 1, info["M"] + 1)
+
+
+def kfbi_domain_copy_boundary(h):
+    import numpy as np
+    info = kfbi_domain_get_info(h)
+    out = np.zeros(2 * info["Nb"], dtype=np.float64)
+    _check(lib().kfbi_domain_copy_boundary(h, out.ctypes.data_as(ctypes.c_void_p)))
+    return out[0::2].copy(), out[1::2].copy()
+
+
+def kfbi_domain_copy_edges(h):
+    import numpy as np
+    info = kfbi_domain_get_info(h)
+    n = info["n_edges"]
+    pq = np.zeros(2 * n, dtype=np.int32)
+    xyt = np.zeros(3 * n, dtype=np.float64)
+    _check(lib().kfbi_domain_copy_edges(h, pq.ctypes.data_as(ctypes.c_void_p),
+                                        xyt.ctypes.data_as(ctypes.c_void_p)))
+    return pq.reshape(n, 2), xyt.reshape(n, 3)
+
+
+# ---- solves ----------------------------------------------------------------
+def kfbi_grid_solve(h, kappa, rhs, u_out):
+    k = complex(kappa)
+    _check(lib().kfbi_grid_solve(h, k.real, k.imag, _ptr(rhs, name="rhs"), _ptr(u_out, name="u_out")))
+
+
+def kfbi_interface_apply(h, kappa, f_grid, f_gamma, phi, u_grid_out, uplus_out):
+    k = complex(kappa)
+    _check(lib().kfbi_interface_apply(h, k.real, k.imag, _ptr(f_grid), _ptr(f_gamma), _ptr(phi),
+                                      _ptr(u_grid_out), _ptr(uplus_out)))
+
+
+def kfbi_helmholtz_solve(h, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout=None, opts=None):
+    k = complex(kappa)
+    st = SolveStats()
+    code = lib().kfbi_helmholtz_solve(h, k.real, k.imag, _ptr(f_grid), _ptr(f_gamma), _ptr(g_gamma),
+                                      _ptr(u_grid_out), _ptr(phi_inout), _opts(opts), ctypes.byref(st))
+    _check(code, allow=(KFBI_ENOCONV,))
+    return st.as_dict()
+
+
+# ---- steppers --------------------------------------------------------------
+def kfbi_stepper_create(h, equation, tau, theta=0.25, diffusivity=1.0, w=0.0, v_grid=None, v_gamma=None):
+    p = StepParams(tau=tau, theta=theta, diffusivity=diffusivity, w=w,
+                   v_grid=_ptr(v_grid, torch.float64, name="v_grid"),
+                   v_gamma=_ptr(v_gamma, torch.float64, name="v_gamma"))
+    s = _P()
+    _check(lib().kfbi_stepper_create(h, equation, ctypes.byref(p), ctypes.byref(s)))
+    return s
+
+
+def kfbi_stepper_destroy(s):
+    _check(lib().kfbi_stepper_destroy(s))
+
+
+def kfbi_stepper_init(s, u0, lap_u0, u0_gamma, lap_u0_gamma, uprev=None, lap_uprev=None,
+                      uprev_gamma=None, lap_uprev_gamma=None):
+    _check(lib().kfbi_stepper_init(s, _ptr(u0), _ptr(lap_u0), _ptr(u0_gamma), _ptr(lap_u0_gamma),
+                                   _ptr(uprev), _ptr(lap_uprev), _ptr(uprev_gamma),
+                                   _ptr(lap_uprev_gamma)))
+
+
+def kfbi_step_heat(s, g_next, src_grid, src_gamma, u_out, opts=None):
+    st = SolveStats()
+    _check(lib().kfbi_step_heat(s, _ptr(g_next), _ptr(src_grid), _ptr(src_gamma), _ptr(u_out),
+                                _opts(opts), ctypes.byref(st)), allow=(KFBI_ENOCONV,))
+    return st.as_dict()
+
+
+def kfbi_step_wave(s, g_next, u_out, opts=None):
+    st = SolveStats()
+    _check(lib().kfbi_step_wave(s, _ptr(g_next), _ptr(u_out), _opts(opts), ctypes.byref(st)),
+           allow=(KFBI_ENOCONV,))
+    return st.as_dict()
+
+
+def kfbi_step_schrodinger(s, g_next, u_out, opts=None):
+    st = SolveStats()
+    _check(lib().kfbi_step_schrodinger(s, _ptr(g_next), _ptr(u_out), _opts(opts), ctypes.byref(st)),
+           allow=(KFBI_ENOCONV,))
+    return st.as_dict()

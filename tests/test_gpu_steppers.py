@@ -1,0 +1,151 @@
+"""GPU parity of the three time steppers against the oracle steppers, step by
+step on the same seeded synthetic inputs (FP64 path, tolerance 1e-10
+relative over inside nodes), plus a sampled check at the wave workload's
+full size (512 grid) in the configuration the benchmark times.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import manufactured as mf
+from oracle.geometry import Domain
+from oracle.steppers import HeatStepper, SchrodingerStepper, WaveStepper
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2404_14864_amd import kfbi  # noqa: E402
+from tests.gpu_util import GpuDomain, dev, empty_grid, host, rel_err  # noqa: E402
+
+TOL = 1e-10
+
+
+def test_heat_crank_nicolson_c1():
+    """Disk R = 0.5, 64 grid, 128 points, tau = h, 10 steps (the heat
+    workload), manufactured u = exp(-t) sin(pi x) cos(pi y) with source."""
+    desc = W.domain_c1_heat(64)
+    od = Domain(desc)
+    tau = od.h
+    X, Y = od.X, od.Y
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    ref = HeatStepper(od, tau, mf.heat_u(X, Y, 0), mf.heat_lap(X, Y, 0), mf.heat_u(zx, zy, 0),
+                      mf.heat_lap(zx, zy, 0), tol=1e-12)
+    with GpuDomain(desc) as g:
+        gx, gy = g.zx, g.zy
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_HEAT, tau)
+        kfbi.kfbi_stepper_init(s, dev(mf.heat_u(X, Y, 0).ravel()), dev(mf.heat_lap(X, Y, 0).ravel()),
+                               dev(mf.heat_u(gx, gy, 0)), dev(mf.heat_lap(gx, gy, 0)))
+        u = empty_grid(g.M)
+        for n in range(10):
+            t0, t1 = n * tau, (n + 1) * tau
+            Ur = ref.step(mf.heat_u(zx, zy, t1), mf.heat_src(X, Y, t0) + mf.heat_src(X, Y, t1),
+                          mf.heat_src(zx, zy, t0) + mf.heat_src(zx, zy, t1))
+            st = kfbi.kfbi_step_heat(s, dev(mf.heat_u(gx, gy, t1)),
+                                     dev((mf.heat_src(X, Y, t0) + mf.heat_src(X, Y, t1)).ravel()),
+                                     dev(mf.heat_src(gx, gy, t0) + mf.heat_src(gx, gy, t1)), u,
+                                     opts={"tol": 1e-12})
+            U = host(u).reshape(g.M + 1, g.M + 1)
+            assert st["converged"]
+            assert rel_err(U, Ur, od.inside) < TOL, n
+        err = np.max(np.abs(U - mf.heat_u(X, Y, 10 * tau))[od.inside])
+        assert err < 1e-3
+        kfbi.kfbi_stepper_destroy(s)
+
+
+def _wave_run(desc, steps, c=1.0, theta=0.25, tol=1e-12):
+    od = Domain(desc)
+    tau = c * od.h
+    X, Y = od.X, od.Y
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    ref = WaveStepper(od, tau, mf.wave_u(X, Y, 0), mf.wave_lap(X, Y, 0), mf.wave_u(zx, zy, 0),
+                      mf.wave_lap(zx, zy, 0), mf.wave_u(X, Y, -tau), mf.wave_lap(X, Y, -tau),
+                      mf.wave_u(zx, zy, -tau), mf.wave_lap(zx, zy, -tau), theta=theta, tol=tol)
+    errs = []
+    with GpuDomain(desc) as g:
+        gx, gy = g.zx, g.zy
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_WAVE, tau, theta=theta)
+        kfbi.kfbi_stepper_init(s, dev(mf.wave_u(X, Y, 0).ravel()), dev(mf.wave_lap(X, Y, 0).ravel()),
+                               dev(mf.wave_u(gx, gy, 0)), dev(mf.wave_lap(gx, gy, 0)),
+                               dev(mf.wave_u(X, Y, -tau).ravel()), dev(mf.wave_lap(X, Y, -tau).ravel()),
+                               dev(mf.wave_u(gx, gy, -tau)), dev(mf.wave_lap(gx, gy, -tau)))
+        u = empty_grid(g.M)
+        for n in range(steps):
+            t1 = (n + 1) * tau
+            Ur = ref.step(mf.wave_u(zx, zy, t1))
+            st = kfbi.kfbi_step_wave(s, dev(mf.wave_u(gx, gy, t1)), u, opts={"tol": tol})
+            U = host(u).reshape(g.M + 1, g.M + 1)
+            errs.append(rel_err(U, Ur, od.inside))
+            assert st["converged"]
+            assert abs(st["iters"] - ref.last_stats["iters"]) <= 1
+        kfbi.kfbi_stepper_destroy(s)
+    return errs, U, od
+
+
+def test_wave_theta_scheme_star():
+    errs, U, od = _wave_run(W.domain_c2_wave(128, Nb=128), 20)
+    assert max(errs) < TOL, errs
+
+
+def test_wave_full_size_sampled():
+    """The wave workload at its full size (star, 512 grid, Nb = M, tau = h),
+    first 3 steps, in the configuration the benchmark times."""
+    errs, U, od = _wave_run(W.domain_c2_wave(512, Nb=512), 3)
+    assert max(errs) < TOL, errs
+
+
+def test_schrodinger_packet_ellipse():
+    """Ellipse 0.6/0.4, harmonic potential 50|x|^2, Gaussian packet
+    (width 0.1, k = (20, 0)), tau = h/2, g = 0 (the Schroedinger workload at
+    a reduced grid)."""
+    M = 128
+    desc = W.domain_c3_schrodinger(M)
+    od = Domain(desc)
+    tau = od.h / 2
+    X, Y = od.X, od.Y
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    V, Vg = mf.harmonic_potential(X, Y), mf.harmonic_potential(zx, zy)
+    ref = SchrodingerStepper(od, tau, mf.packet_u0(X, Y), mf.packet_lap(X, Y), mf.packet_u0(zx, zy),
+                             mf.packet_lap(zx, zy), V, Vg, tol=1e-12)
+    with GpuDomain(desc, cplx=True) as g:
+        gx, gy = g.zx, g.zy
+        vg = dev(mf.harmonic_potential(X, Y).ravel())
+        vgam = dev(mf.harmonic_potential(gx, gy))
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, v_grid=vg, v_gamma=vgam)
+        kfbi.kfbi_stepper_init(s, dev(mf.packet_u0(X, Y).ravel()), dev(mf.packet_lap(X, Y).ravel()),
+                               dev(mf.packet_u0(gx, gy)), dev(mf.packet_lap(gx, gy)))
+        u = empty_grid(g.M, cplx=True)
+        zero = dev(np.zeros(g.Nb, dtype=np.complex128))
+        for n in range(8):
+            Ur = ref.step(np.zeros(od.Nb, dtype=np.complex128))
+            st = kfbi.kfbi_step_schrodinger(s, zero, u, opts={"tol": 1e-12})
+            U = host(u).reshape(g.M + 1, g.M + 1)
+            assert st["converged"]
+            assert rel_err(U, Ur, od.inside) < TOL, n
+        kfbi.kfbi_stepper_destroy(s)
+
+
+def test_schrodinger_free_closed_form():
+    """V = 0: u = exp(i 2 pi^2 t) sin(pi x) sin(pi y); GPU error close to the
+    oracle's and small."""
+    M = 128
+    desc = W.domain_c3_schrodinger(M)
+    od = Domain(desc)
+    tau = od.h / 2
+    X, Y = od.X, od.Y
+    with GpuDomain(desc, cplx=True) as g:
+        gx, gy = g.zx, g.zy
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau)
+        kfbi.kfbi_stepper_init(s, dev(mf.schr_free_u(X, Y, 0).ravel()), dev(mf.schr_free_lap(X, Y, 0).ravel()),
+                               dev(mf.schr_free_u(gx, gy, 0)), dev(mf.schr_free_lap(gx, gy, 0)))
+        u = empty_grid(g.M, cplx=True)
+        n = 16
+        for k in range(n):
+            kfbi.kfbi_step_schrodinger(s, dev(mf.schr_free_u(gx, gy, (k + 1) * tau)), u)
+        U = host(u).reshape(g.M + 1, g.M + 1)
+        kfbi.kfbi_stepper_destroy(s)
+    err = np.max(np.abs(U - mf.schr_free_u(X, Y, n * tau))[od.inside])
+    assert err < 1e-3

@@ -12,9 +12,14 @@ A descriptor is a plain dict:
     Nb      number of boundary collocation points
 
 The shapes and sizes follow the workloads the method is measured on: a disk
-of radius 0.5 with a 64-interval grid (heat), a five-lobed star 0.5+0.1 sin 5t
-on a 512 grid (wave), an ellipse 0.6/0.4 on a 1024 grid (Schroedinger) and
-seeded random stars for the batched Helmholtz instances.
+of radius 0.5 with a 64-interval grid and 128 points (heat), a five-lobed
+star 0.5+0.1 sin 5t on a 512 grid (wave), an ellipse 0.6/0.4 on a 1024 grid
+(Schroedinger) and seeded random stars for the batched Helmholtz instances.
+Apart from the heat disk, the collocation count is the paper's Nb = M
+(section 4): with Nb = 2M the boundary is sampled finer than the grid
+resolves, the discrete integral operator gains near-null high-frequency
+modes, GMRES needs 3-40x more iterations and the theta = 1/4 wave
+recurrence diverges.
 """
 
 import numpy as np
@@ -56,13 +61,15 @@ def domain_c1_heat(M=64, Nb=None):
 
 
 def domain_c2_wave(M=512, Nb=None):
-    """Star r = 0.5 + 0.1 sin(5 theta) in [-1,1]^2; 2M collocation points."""
-    return star(0.5, 0.1, 5, 1.0, M, 2 * M if Nb is None else Nb)
+    """Star r = 0.5 + 0.1 sin(5 theta) in [-1,1]^2; M collocation points
+    (the paper's count, section 4) unless Nb is given."""
+    return star(0.5, 0.1, 5, 1.0, M, M if Nb is None else Nb)
 
 
 def domain_c3_schrodinger(M=1024, Nb=None):
-    """Ellipse with semi-axes 0.6 / 0.4 in [-1,1]^2; 2M collocation points."""
-    return ellipse(0.6, 0.4, 1.0, M, 2 * M if Nb is None else Nb)
+    """Ellipse with semi-axes 0.6 / 0.4 in [-1,1]^2; M collocation points
+    unless Nb is given."""
+    return ellipse(0.6, 0.4, 1.0, M, M if Nb is None else Nb)
 
 
 def domain_c4_instance(index, grids=(128, 256, 512, 1024)):
@@ -71,11 +78,11 @@ def domain_c4_instance(index, grids=(128, 256, 512, 1024)):
     Returns (descriptor, kappa, rng) where rng continues the instance's
     PCG64 stream (used for its random right-hand side and boundary data).
     Star radius r0 ~ U[0.3, 0.6], lobes ~ U{3..8}, amp = 0.2 r0,
-    kappa ~ U[1, 1e4], M uniform over `grids`, Nb = 2M.
+    kappa ~ U[1, 1e4], M uniform over `grids`, Nb = M.
     """
     rng = np.random.default_rng(BASE_SEED + int(index))
     M = int(grids[rng.integers(0, len(grids))])
     r0 = float(rng.uniform(0.3, 0.6))
     lobes = int(rng.integers(3, 9))
     kappa = float(rng.uniform(1.0, 1.0e4))
-    return star(r0, 0.2 * r0, lobes, 1.0, M, 2 * M), kappa, rng
+    return star(r0, 0.2 * r0, lobes, 1.0, M, M), kappa, rng
