@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the KFBI wave time-stepping path on one MI355X.
+
+Workload (the configuration the throughput metric is quoted on): wave
+equation, implicit theta-scheme with theta = 1/4, star domain
+r = 0.5 + 0.1 sin(5 theta) in [-1,1]^2, 512 x 512 grid, tau = h, 512
+collocation points (the paper's Nb = M), manufactured solution
+u = cos(sqrt2 pi t) sin(pi x) sin(pi y) for the initial and boundary data.
+One step = one implicit time step: the right-hand-side recurrence, the
+b-solve, GMRES on the boundary integral equation (each iteration: jumps and
+corrections, DST-x / tridiagonal-y grid solve, extraction, Arnoldi) and the
+final grid solve.
+
+Metric: grid-pts * GMRES-iters / s = sum over steps of (M-1)^2 * iterations,
+divided by the wall time of the timed steps (inputs resident in HBM).
+
+Also reported: p50/p99 step latency, the dominant kernel's achieved
+algorithmic bandwidth against the 8 TB/s HBM peak (HIP events around its
+launches), and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 200] [--warmup 3]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--M", type=int, default=512)
+    ap.add_argument("--profile-steps", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(M, seconds):
+    """The oracle (numpy/scipy, unchanged) on the same workload, timed on the
+    host: as many time steps as fit in about `seconds`."""
+    import numpy as np
+    import workloads as W
+    from workloads import manufactured as mf
+    from oracle.geometry import Domain
+    from oracle.steppers import WaveStepper
+    od = Domain(W.domain_c2_wave(M))
+    tau = od.h
+    X, Y = od.X, od.Y
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    st = WaveStepper(od, tau, mf.wave_u(X, Y, 0), mf.wave_lap(X, Y, 0), mf.wave_u(zx, zy, 0),
+                     mf.wave_lap(zx, zy, 0), mf.wave_u(X, Y, -tau), mf.wave_lap(X, Y, -tau),
+                     mf.wave_u(zx, zy, -tau), mf.wave_lap(zx, zy, -tau))
+    iters, n = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        st.step(mf.wave_u(zx, zy, (n + 1) * tau))
+        iters += st.last_stats["iters"]
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    del np
+    return {"value": (M - 1) ** 2 * iters / el, "unit": "grid-pts*GMRES-iters/s",
+            "cores": 1, "kind": "oracle",
+            "sample": "first %d time steps of the same wave workload (%d GMRES iterations) in %.1f s; "
+                      "numpy/scipy oracle, single-threaded FFTs" % (n, iters, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the whole method on a single "
+              "MI355X (no collectives or sharding); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    from workloads import manufactured as mf
+    from paper_2404_14864_amd import kfbi
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    M = args.M
+    desc = W.domain_c2_wave(M)
+    Nb = desc["Nb"]
+    theta = 0.25
+    h = 2.0 / M
+    tau = h
+    dom = kfbi.kfbi_domain_create(desc)
+    info = kfbi.kfbi_domain_get_info(dom)
+    zx, zy = kfbi.kfbi_domain_copy_boundary(dom)
+    x = W.grid_coords(1.0, M)
+    X, Y = np.meshgrid(x, x)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    total = args.warmup + args.steps
+    # every input resident in HBM before the timed region
+    g_all = d(np.stack([mf.wave_u(zx, zy, (n + 1) * tau) for n in range(total)]))
+    init = [d(mf.wave_u(X, Y, 0).ravel()), d(mf.wave_lap(X, Y, 0).ravel()), d(mf.wave_u(zx, zy, 0)),
+            d(mf.wave_lap(zx, zy, 0)), d(mf.wave_u(X, Y, -tau).ravel()), d(mf.wave_lap(X, Y, -tau).ravel()),
+            d(mf.wave_u(zx, zy, -tau)), d(mf.wave_lap(zx, zy, -tau))]
+    u = torch.zeros((M + 1) * (M + 1), dtype=torch.float64, device=dev)
+    st = kfbi.kfbi_stepper_create(dom, kfbi.KFBI_WAVE, tau, theta=theta)
+    kfbi.kfbi_stepper_init(st, *init)
+    log("domain M=%d Nb=%d inside=%d irregular=%d edges=%d" % (M, Nb, info["n_inside"], info["n_irregular"],
+                                                             info["n_edges"]))
+    for n in range(args.warmup):
+        kfbi.kfbi_step_wave(st, g_all[n], u)
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+
+    lat, iters = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        s = kfbi.kfbi_step_wave(st, g_all[args.warmup + k], u)
+        lat.append(time.perf_counter() - ts)
+        iters.append(s["iters"])
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    log("timed %d steps in %.3f s, %d GMRES iterations" % (args.steps, T, sum(iters)))
+    U = u.cpu().numpy().reshape(M + 1, M + 1)
+    finite = bool(np.all(np.isfinite(U)))
+
+    pts = (M - 1) ** 2
+    value = pts * sum(iters) / T
+
+    # profiled pass: HIP events around every kernel launch of the same steps
+    kfbi.kfbi_stepper_init(st, *init)
+    kfbi.kfbi_profile_enable(dom, True)
+    np_steps = min(args.profile_steps, total)
+    for n in range(np_steps):
+        kfbi.kfbi_step_wave(st, g_all[n], u)
+    torch.cuda.synchronize()
+    prof = kfbi.kfbi_profile_read(dom)
+    kfbi.kfbi_profile_enable(dom, False)
+    kdom = max(prof, key=lambda k: prof[k]["total_ms"])
+    p = prof[kdom]
+    avg_ms = p["total_ms"] / max(p["launches"], 1)
+    achieved = p["bytes"] / max(p["launches"], 1) / (avg_ms * 1e-3) / 1e9
+    breakdown = {k: {"launches": v["launches"], "avg_us": 1e3 * v["total_ms"] / max(v["launches"], 1),
+                     "share": v["total_ms"] / max(sum(q["total_ms"] for q in prof.values()), 1e-30)}
+                 for k, v in prof.items() if v["launches"]}
+    log("dominant kernel %s: %d launches, avg %.2f us" % (kdom, p["launches"], 1e3 * avg_ms))
+
+    kfbi.kfbi_stepper_destroy(st)
+    kfbi.kfbi_domain_destroy(dom)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(M, args.cpu_seconds)
+
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "grid-pts*GMRES-iters/s per KFBI step",
+        "value": value,
+        "unit": "grid-pts*GMRES-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "wave theta-scheme (theta=0.25), star r=0.5+0.1sin5t in [-1,1]^2, "
+                               "%dx%d grid, Nb=%d, dt=h" % (M, M, Nb),
+                   "equation": "wave", "M": M, "Nb": Nb, "tau": tau, "theta": theta,
+                   "precision": "fp64", "parallelism": "single GPU"},
+        "p50_step_ms": float(np.percentile(lat_ms, 50)),
+        "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "gmres_iters_per_step": float(np.mean(iters)),
+        "solution_finite": finite,
+        "roofline": {"bound": "hbm", "kernel": kdom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * avg_ms,
+                     "bytes_per_launch": p["bytes"] / max(p["launches"], 1),
+                     "profiled_steps": np_steps},
+        "kernels": breakdown,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -218,6 +218,34 @@ int kfbi_step_wave(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
 int kfbi_step_schrodinger(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
                           const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
+/* Per-kernel device timing (instrumentation for benchmarks).  When enabled,
+ * every launch of the listed kernels of this domain is bracketed by two HIP
+ * events on the domain stream; launches inside a GMRES chunk that found the
+ * solve already finished are not counted.  kfbi_profile_enable(dom, 1)
+ * resets the counters; kfbi_profile_read waits for the outstanding events
+ * and fills KFBI_K_COUNT entries: launches, summed event time and summed
+ * algorithmic bytes (the bytes the kernel must move by design: its dense
+ * inputs and outputs, not cache re-reads). */
+enum {
+    KFBI_K_TRIDIAG_SPARSE = 0,  /* y-solve, right-hand side synthesised from corrections */
+    KFBI_K_TRIDIAG_DENSE = 1,   /* y-solve reading a dense x-transformed right-hand side */
+    KFBI_K_DST = 2,             /* dense DST-I along x                                   */
+    KFBI_K_IDST = 3,            /* dense inverse DST-I along x to the grid               */
+    KFBI_K_EVAL_NODES = 4,      /* grid solution at extraction-stencil nodes             */
+    KFBI_K_CORRECTIONS = 5,
+    KFBI_K_EXTRACT = 6,
+    KFBI_K_ARNOLDI = 7,
+    KFBI_K_COUNT = 8
+};
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} kfbi_kernel_prof;
+
+int kfbi_profile_enable(kfbi_domain *dom, int32_t on);
+int kfbi_profile_read(kfbi_domain *dom, kfbi_kernel_prof *out);
+
 #ifdef __cplusplus
 }
 #endif

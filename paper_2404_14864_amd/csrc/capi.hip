@@ -42,6 +42,53 @@ int dalloc(kfbi_domain *d, void **p, size_t bytes) {
 
 size_t gmres_bytes(kfbi_domain *d);
 
+int prof_begin(kfbi_domain *d) {
+    if (!d->prof_on) return -1;
+    kfbi_domain::ProfSlot s;
+    hipEvent_t ev[2];
+    for (int q = 0; q < 2; ++q) {
+        if (!d->prof_pool.empty()) {
+            ev[q] = d->prof_pool.back();
+            d->prof_pool.pop_back();
+        } else if (hipEventCreate(&ev[q]) != hipSuccess) {
+            return -1;
+        }
+    }
+    s.a = ev[0];
+    s.b = ev[1];
+    s.kind = -1;
+    s.tag = d->prof_tag;
+    s.bytes = 0.0;
+    if (hipEventRecord(s.a, d->stream) != hipSuccess) return -1;
+    d->prof_live.push_back(s);
+    return (int)d->prof_live.size() - 1;
+}
+
+void prof_end(kfbi_domain *d, int slot, int kind, double bytes) {
+    if (slot < 0 || slot >= (int)d->prof_live.size()) return;
+    kfbi_domain::ProfSlot &s = d->prof_live[slot];
+    s.kind = kind;
+    s.bytes = bytes;
+    (void)hipEventRecord(s.b, d->stream);
+}
+
+int prof_flush(kfbi_domain *d, int keep_tags_below) {
+    for (auto &s : d->prof_live) {
+        KFBI_HIP(hipEventSynchronize(s.b));
+        if (s.kind >= 0 && (s.tag < 0 || s.tag < keep_tags_below)) {
+            float ms = 0.f;
+            KFBI_HIP(hipEventElapsedTime(&ms, s.a, s.b));
+            d->prof_count[s.kind] += 1;
+            d->prof_ms[s.kind] += ms;
+            d->prof_bytes[s.kind] += s.bytes;
+        }
+        d->prof_pool.push_back(s.a);
+        d->prof_pool.push_back(s.b);
+    }
+    d->prof_live.clear();
+    return KFBI_OK;
+}
+
 namespace {
 
 // out = sum_q c_q x_q over up to four operands (null operands are skipped)
@@ -158,10 +205,35 @@ int kfbi_domain_create(const kfbi_domain_desc *desc, kfbi_domain **out) {
     return KFBI_OK;
 }
 
+int kfbi_profile_enable(kfbi_domain *d, int32_t on) {
+    if (!d) { set_error("null domain"); return KFBI_EINVAL; }
+    KFBI_TRY(prof_flush(d, 0));
+    for (int k = 0; k < KFBI_K_COUNT; ++k) {
+        d->prof_count[k] = 0;
+        d->prof_ms[k] = 0.0;
+        d->prof_bytes[k] = 0.0;
+    }
+    d->prof_on = on != 0;
+    return KFBI_OK;
+}
+
+int kfbi_profile_read(kfbi_domain *d, kfbi_kernel_prof *out) {
+    if (!d || !out) { set_error("null argument"); return KFBI_EINVAL; }
+    KFBI_TRY(prof_flush(d, 1 << 30));
+    for (int k = 0; k < KFBI_K_COUNT; ++k) {
+        out[k].launches = d->prof_count[k];
+        out[k].total_ms = d->prof_ms[k];
+        out[k].bytes = d->prof_bytes[k];
+    }
+    return KFBI_OK;
+}
+
 int kfbi_domain_destroy(kfbi_domain *d) {
     if (!d) return KFBI_OK;
     if (d->stream) hipStreamSynchronize(d->stream);
     else hipDeviceSynchronize();
+    for (auto &s : d->prof_live) { hipEventDestroy(s.a); hipEventDestroy(s.b); }
+    for (hipEvent_t e : d->prof_pool) hipEventDestroy(e);
     for (void *p : d->allocs) hipFree(p);
     delete d;
     return KFBI_OK;

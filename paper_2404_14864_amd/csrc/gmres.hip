@@ -287,8 +287,9 @@ size_t gmres_bytes(kfbi_domain *d) {
 
 // elements of a basis vector per thread: the smallest power of two that covers Nb
 template <class T>
-static int launch_arnoldi(GmPtrs &P, int Nb, hipStream_t s) {
+static int launch_arnoldi(kfbi_domain *d, GmPtrs &P, int Nb, hipStream_t s) {
     const int ept = (Nb + kGmThreads - 1) / kGmThreads;
+    const int ps = prof_begin(d);
 #define KFBI_ARN(E) k_gm_arnoldi<T, E><<<1, kGmThreads, 0, s>>>(P.ctl, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn, Nb)
     if (ept <= 1) KFBI_ARN(1);
     else if (ept <= 2) KFBI_ARN(2);
@@ -297,6 +298,7 @@ static int launch_arnoldi(GmPtrs &P, int Nb, hipStream_t s) {
     else KFBI_ARN(16);
 #undef KFBI_ARN
     KFBI_CHECK_LAUNCH();
+    prof_end(d, ps, KFBI_K_ARNOLDI, 0.0);
     return KFBI_OK;
 }
 
@@ -333,15 +335,19 @@ static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kf
         k_gm_start<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.r, (T *)P.V, (T *)P.g, Nb);
         KFBI_CHECK_LAUNCH();
         for (;;) {
+            const int iters_before = h.iters;
             for (int c = 0; c < chunk; ++c) {
+                d->prof_tag = c;
                 KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.V, jptr, nullptr, d->corr, done));
                 KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, done));
                 KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, done));
                 KFBI_TRY(extract_boundary_ctl(d, kre, kim, d->ust, P.V, jptr, nullptr, nullptr, 1.0, P.V, 1, done));
-                KFBI_TRY(launch_arnoldi<T>(P, Nb, s));
+                KFBI_TRY(launch_arnoldi<T>(d, P, Nb, s));
             }
+            d->prof_tag = -1;
             KFBI_HIP(hipMemcpyAsync(&h, P.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
             KFBI_HIP(hipStreamSynchronize(s));
+            if (d->prof_on) KFBI_TRY(prof_flush(d, h.iters - iters_before));
             if (h.done) break;
         }
         if (h.j > 0) {

@@ -312,9 +312,15 @@ int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask
     const bool cplx = sizeof(T) == sizeof(cd);
     int blocks = cplx ? n : (n + 1) / 2;
     size_t lds = (size_t)2 * M * sizeof(double2);
+    const int ps = prof_begin(d);
     k_dst_rows<T><<<blocks, 256, lds, d->stream>>>(M, logN2, (const T *)in, in_grid, mask, (T *)out,
                                                    out_grid, scale, d->twiddle);
     KFBI_CHECK_LAUNCH();
+    {
+        const double es = sizeof(T), nn = (double)n * n, grid = (double)(M + 1) * (M + 1);
+        const double bytes = in_grid ? es * (nn + nn) + (mask ? nn : 0.0) : es * (nn + grid);
+        prof_end(d, ps, in_grid ? KFBI_K_DST : KFBI_K_IDST, bytes);
+    }
     if (out_grid) {
         k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(M, (T *)out);
         KFBI_CHECK_LAUNCH();
@@ -334,6 +340,7 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
                                                       (const T *)d->etab, (const T *)d->elim,     \
                                                       d->tconv, (T *)uhat, done)
     int c = (n + 63) / 64;
+    const int ps = prof_begin(d);
     if (c <= 1) KFBI_TRI(1);
     else if (c <= 2) KFBI_TRI(2);
     else if (c <= 4) KFBI_TRI(4);
@@ -346,6 +353,13 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
     }
 #undef KFBI_TRI
     KFBI_CHECK_LAUNCH();
+    {
+        // algorithmic bytes: write U^ (and read R^ when dense) plus the sparse input
+        const double es = sizeof(T), nn = (double)n * n;
+        const double sparse = corr ? (double)d->n_irr * (es + 4.0) + 4.0 * (n + 1) : 0.0;
+        prof_end(d, ps, rhat ? KFBI_K_TRIDIAG_DENSE : KFBI_K_TRIDIAG_SPARSE,
+                 es * nn * (rhat ? 2.0 : 1.0) + sparse);
+    }
     return KFBI_OK;
 }
 
@@ -397,6 +411,7 @@ int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, cons
     const int nn = 6 * d->Nb;
     const int stride = (int)(sizeof(Stencil) / sizeof(int32_t));
     const int32_t *nodes = reinterpret_cast<const int32_t *>(d->st);
+    const int ps = prof_begin(d);
     if (d->cplx)
         k_eval_nodes<cd><<<(nn + 3) / 4, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cd *)uhat,
                                                              d->sine, (cd *)ust_out, done);
@@ -405,6 +420,7 @@ int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, cons
                                                                  (const double *)uhat, d->sine,
                                                                  (double *)ust_out, done);
     KFBI_CHECK_LAUNCH();
+    prof_end(d, ps, KFBI_K_EVAL_NODES, (double)nn * ((d->M - 1) * (double)elem_size(d) + 4.0 + elem_size(d)));
     return KFBI_OK;
 }
 

@@ -144,10 +144,12 @@ template <class T>
 int launch_corr(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
                 const void *fg, void *corr, const int *done) {
     const double dth = 6.283185307179586476925286766559 / d->Nb;
+    const int ps = prof_begin(d);
     k_corrections<T><<<(d->n_irr + 127) / 128, 128, 0, d->stream>>>(
         d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kappa_of<T>(kre, kim), (const T *)phi_base, jptr,
         (const T *)fg, (T *)corr, done);
     KFBI_CHECK_LAUNCH();
+    prof_end(d, ps, KFBI_K_CORRECTIONS, (double)d->n_irr * (sizeof(IrrNode) + sizeof(T)));
     return KFBI_OK;
 }
 
@@ -156,10 +158,12 @@ int launch_extract(kfbi_domain *d, double kre, double kim, const void *ust, cons
                    const int *jptr, const void *fg, const void *g, double scale, void *out_base,
                    int out_add, const int *done) {
     const double dth = 6.283185307179586476925286766559 / d->Nb;
+    const int ps = prof_begin(d);
     k_extract<T><<<(d->Nb + 127) / 128, 128, 0, d->stream>>>(
         d->Nb, dth, d->col, d->st, kappa_of<T>(kre, kim), (const T *)ust, (const T *)phi_base, jptr,
         (const T *)fg, (const T *)g, scale, (T *)out_base, out_add, done);
     KFBI_CHECK_LAUNCH();
+    prof_end(d, ps, KFBI_K_EXTRACT, (double)d->Nb * (sizeof(Colloc) + sizeof(Stencil) + 8.0 * sizeof(T)));
     return KFBI_OK;
 }
 

@@ -174,6 +174,21 @@ struct kfbi_domain {
     // GMRES workspace
     void *gm = nullptr;                 // device GmresState (+ basis)
     size_t gm_bytes = 0;
+
+    // optional per-kernel timing with HIP events (kfbi_profile_*)
+    struct ProfSlot {
+        hipEvent_t a, b;
+        int kind;
+        int tag;                        // -1: always counted; else GMRES chunk position
+        double bytes;
+    };
+    bool prof_on = false;
+    int prof_tag = -1;
+    std::vector<ProfSlot> prof_live;
+    std::vector<hipEvent_t> prof_pool;
+    long long prof_count[KFBI_K_COUNT] = {};
+    double prof_ms[KFBI_K_COUNT] = {};
+    double prof_bytes[KFBI_K_COUNT] = {};
 };
 
 namespace kfbi {
@@ -223,5 +238,14 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
                     void *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
 inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : sizeof(double); }
+
+// kernel timing: prof_begin returns a slot (or -1 when profiling is off);
+// prof_end closes it with the launch's algorithmic bytes; prof_flush waits
+// for the recorded events and accumulates every slot whose tag is -1 or
+// below keep_tags_below (GMRES launches that found the solve finished are
+// dropped).
+int prof_begin(kfbi_domain *d);
+void prof_end(kfbi_domain *d, int slot, int kind, double bytes);
+int prof_flush(kfbi_domain *d, int keep_tags_below);
 
 }  // namespace kfbi

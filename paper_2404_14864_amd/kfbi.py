@@ -68,6 +68,13 @@ class StepParams(ctypes.Structure):
                 ("v_grid", ctypes.c_void_p), ("v_gamma", ctypes.c_void_p)]
 
 
+class KernelProf(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KERNELS = ("tridiag_sparse", "tridiag_dense", "dst", "idst", "eval_nodes", "corrections",
+           "extract", "arnoldi")
+
 _lib = None
 _P = ctypes.c_void_p
 
@@ -98,6 +105,8 @@ def lib():
         "kfbi_step_heat": ([_P, _P, _P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
         "kfbi_step_wave": ([_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
         "kfbi_step_schrodinger": ([_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_profile_enable": ([_P, ctypes.c_int32], ctypes.c_int),
+        "kfbi_profile_read": ([_P, ctypes.POINTER(KernelProf)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -111,7 +120,18 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_domain_copy_classification", "kfbi_domain_copy_boundary", "kfbi_domain_copy_edges",
             "kfbi_grid_solve", "kfbi_interface_apply", "kfbi_helmholtz_solve", "kfbi_stepper_create",
             "kfbi_stepper_destroy", "kfbi_stepper_init", "kfbi_step_heat", "kfbi_step_wave",
-            "kfbi_step_schrodinger")
+            "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read")
+
+
+def kfbi_profile_enable(h, on=True):
+    _check(lib().kfbi_profile_enable(h, 1 if on else 0))
+
+
+def kfbi_profile_read(h):
+    arr = (KernelProf * len(KERNELS))()
+    _check(lib().kfbi_profile_read(h, arr))
+    return {name: {"launches": int(arr[i].launches), "total_ms": arr[i].total_ms,
+                   "bytes": arr[i].bytes} for i, name in enumerate(KERNELS)}
 
 
 def _check(code, allow=()):
