@@ -140,6 +140,34 @@ def main():
     pts = (M - 1) ** 2
     value = pts * sum(iters) / T
 
+    # the same steps with FP32 grid solves inside FP64 refinement
+    kfbi.kfbi_stepper_init(st, *init)
+    mopts = {"precision": kfbi.KFBI_PREC_MIXED}
+    for n in range(args.warmup):
+        kfbi.kfbi_step_wave(st, g_all[n], u, opts=mopts)
+    kfbi.kfbi_stepper_init(st, *init)
+    mlat, miters, mref = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        s = kfbi.kfbi_step_wave(st, g_all[k], u, opts=mopts)
+        mlat.append(time.perf_counter() - ts)
+        miters.append(s["iters"])
+        mref.append(s["refinements"])
+    torch.cuda.synchronize()
+    Tm = time.perf_counter() - t0
+    # FP64 reference of the same steps for the agreement figure
+    Um = u.cpu().numpy().reshape(M + 1, M + 1)
+    kfbi.kfbi_stepper_init(st, *init)
+    for k in range(args.steps):
+        kfbi.kfbi_step_wave(st, g_all[k], u)
+    U64 = u.cpu().numpy().reshape(M + 1, M + 1)
+    inside = (kfbi.kfbi_domain_copy_classification(dom) & 1).astype(bool)
+    mixed_err = float(np.max(np.abs(Um - U64)[inside]) / max(np.max(np.abs(U64[inside])), 1e-300))
+    log("mixed: %d steps in %.3f s, %d iterations, rel diff vs FP64 %.2e" % (args.steps, Tm, sum(miters),
+                                                                          mixed_err))
+
     # profiled pass: HIP events around every kernel launch of the same steps
     kfbi.kfbi_stepper_init(st, *init)
     kfbi.kfbi_profile_enable(dom, True)
@@ -194,6 +222,13 @@ def main():
                      "bytes_per_launch": p["bytes"] / max(p["launches"], 1),
                      "profiled_steps": np_steps},
         "kernels": breakdown,
+        "mixed_precision": {"value": pts * sum(miters) / Tm, "ms_per_step": 1e3 * Tm / args.steps,
+                            "p50_step_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
+                            "p99_step_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
+                            "gmres_iters_per_step": float(np.mean(miters)),
+                            "refinements_per_step": float(np.mean(mref)),
+                            "grid_solve": "fp32", "refinement": "fp64",
+                            "rel_diff_vs_fp64_after_steps": mixed_err},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

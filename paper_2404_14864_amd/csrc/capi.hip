@@ -234,6 +234,8 @@ int kfbi_domain_destroy(kfbi_domain *d) {
     else hipDeviceSynchronize();
     for (auto &s : d->prof_live) { hipEventDestroy(s.a); hipEventDestroy(s.b); }
     for (hipEvent_t e : d->prof_pool) hipEventDestroy(e);
+    if (d->ev0) hipEventDestroy(d->ev0);
+    if (d->ev1) hipEventDestroy(d->ev1);
     for (void *p : d->allocs) hipFree(p);
     delete d;
     return KFBI_OK;

@@ -24,10 +24,14 @@
 
 namespace kfbi {
 
+// eta > 0 (mixed precision): a cycle runs until its residual estimate falls
+// below thresh = max(tol ||b||, eta beta); convergence is then decided only
+// by the FP64 residual computed at the start of the next cycle
 struct GmCtl {
     int j, done, iters, converged;
     int max_iter, m, fixed, breakdown;
     double tol, bnorm, beta, resid;
+    double eta, thresh;
 };
 
 namespace {
@@ -215,25 +219,289 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_arnoldi(GmCtl *ctl, T *V, T *
     }
 }
 
-// end of a cycle: y = H^{-1} g on the leading j x j block, x += V y
+// ---------------------------------------------------------------------------
+// Fast path with the merged corrections operator: one 16-point window of phi
+// per irregular node, phi read from LDS.
+// ---------------------------------------------------------------------------
+constexpr int kWin = 16;
+
 template <class T>
-__global__ __launch_bounds__(kGmThreads) void k_gm_update(GmCtl *ctl, const T *V, const T *H, const T *g, T *y,
-                                                          T *x, int Nb) {
-    __shared__ T ys[72];
-    const int jj = ctl->j, m = ctl->m;
-    if (threadIdx.x == 0) {
-        for (int i = jj - 1; i >= 0; --i) {
-            T s = g[i];
-            for (int l = i + 1; l < jj; ++l) s -= H[(size_t)i * m + l] * ys[l];
-            ys[i] = s / H[(size_t)i * m + i];
-            y[i] = ys[i];
+__device__ void corr_merged_block(const T *phi_lds, int Nb, int n_irr, const T *__restrict__ mcoef,
+                                  const int32_t *__restrict__ mbase, T *__restrict__ corr) {
+    for (int q = threadIdx.x; q < n_irr; q += blockDim.x) {
+        const int b = mbase[q];
+        T c[kWin];
+#pragma unroll
+        for (int o = 0; o < kWin; ++o) c[o] = mcoef[(size_t)o * n_irr + q];
+        T acc = zero<T>();
+#pragma unroll
+        for (int o = 0; o < kWin; ++o) {
+            int idx = b + o;
+            if (idx >= Nb) idx -= Nb;
+            acc += c[o] * phi_lds[idx];
         }
+        corr[q] = acc;
+    }
+}
+
+// corrections of an explicit density (the current iterate), many workgroups
+template <class T>
+__global__ void k_corr_merged(const T *__restrict__ phi, int Nb, int n_irr, const T *__restrict__ mcoef,
+                              const int32_t *__restrict__ mbase, T *__restrict__ corr) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_irr) return;
+    const int b = mbase[q];
+    T acc = zero<T>();
+#pragma unroll
+    for (int o = 0; o < kWin; ++o) {
+        int idx = b + o;
+        if (idx >= Nb) idx -= Nb;
+        acc += mcoef[(size_t)o * n_irr + q] * phi[idx];
+    }
+    corr[q] = acc;
+}
+
+// extraction K phi at collocation point k from the grid values at its stencil
+template <class T>
+__device__ inline T extract_k(int k, int Nb, const T *__restrict__ ust, const double *__restrict__ w6,
+                              const T *__restrict__ bop, const T *__restrict__ phi) {
+    T acc = zero<T>();
+#pragma unroll
+    for (int p = 0; p < 6; ++p) acc += ust[6 * k + p] * w6[6 * k + p];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        int idx = k - 2 + o;
+        idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
+        acc += bop[5 * k + o] * phi[idx];
+    }
+    return acc;
+}
+
+// Start of a cycle: r = b - K x (extraction of the product whose grid solve
+// has just run), beta = ||r||, v_0 = r / beta, g = beta e_1, and the
+// corrections of v_0 for the first product of the cycle.  Dynamic LDS:
+// Nb elements.
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_start_res(GmCtl *ctl, const T *__restrict__ x,
+                                                             const T *__restrict__ b, T *V, T *g, int Nb,
+                                                             const T *__restrict__ ust, const double *__restrict__ w6,
+                                                             const T *__restrict__ bop, int n_irr,
+                                                             const T *__restrict__ mcoef,
+                                                             const int32_t *__restrict__ mbase, T *corr) {
+    extern __shared__ double dyn[];
+    T *sv = reinterpret_cast<T *>(dyn);
+    __shared__ double red[16];
+    __shared__ int sstop;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
+        const T r = b[k] - extract_k(k, Nb, ust, w6, bop, x);
+        sv[k] = r;
+        s += abs2(r);
+    }
+    s = block_sum(s, red);
+    const double beta = sqrt(s);
+    const int limit = ctl->fixed > 0 ? ctl->fixed : ctl->max_iter;
+    const bool conv = beta <= ctl->tol * ctl->bnorm;
+    const bool stop = (ctl->fixed == 0 && conv) || beta == 0.0 || ctl->iters >= limit;
+    const double inv = stop ? 0.0 : 1.0 / beta;
+    for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
+        const T v = sv[k] * inv;
+        sv[k] = v;
+        V[k] = v;
+    }
+    if ((int)threadIdx.x <= ctl->m) g[threadIdx.x] = threadIdx.x == 0 ? scale_of<T>(beta) : zero<T>();
+    if (threadIdx.x == 0) {
+        ctl->beta = beta;
+        ctl->resid = beta;
+        ctl->j = 0;
+        ctl->breakdown = 0;
+        ctl->converged = conv ? 1 : 0;
+        ctl->done = stop ? 1 : 0;
+        const double t0 = ctl->tol * ctl->bnorm, t1 = ctl->eta * beta;
+        ctl->thresh = t1 > t0 ? t1 : t0;
+        sstop = stop ? 1 : 0;
     }
     __syncthreads();
+    if (!sstop) corr_merged_block(sv, Nb, n_irr, mcoef, mbase, corr);
+}
+
+// One GMRES iteration after the grid solve of v_j (j is the launch's position
+// in the cycle, passed by the host; launches after the cycle has finished
+// find the done flag set and return):
+//   extraction of w = K v_j, CGS2 against v_0..v_j, normalisation, Givens
+//   update of column j and of the residual estimate, and the corrections of
+//   v_{j+1} for the next product.
+// All loads that do not depend on the done flag are issued before it is
+// tested; the extracted vector is parked in LDS so they cannot be deferred.
+template <class T, int EPT>
+__global__ __launch_bounds__(kGmThreads) void k_gm_iter(GmCtl *ctl, T *V, T *H, T *g, double *cs, T *sn, int Nb,
+                                                        int j_arg, int m, const T *__restrict__ ust,
+                                                        const double *__restrict__ w6, const T *__restrict__ bop,
+                                                        int n_irr, const T *__restrict__ mcoef,
+                                                        const int32_t *__restrict__ mbase, T *corr) {
+    extern __shared__ double dyn[];
+    T *sw = reinterpret_cast<T *>(dyn);  // Nb: the new basis vector
+    __shared__ T red[16][8];
+    __shared__ T hcol[72];
+    __shared__ T hs[72];
+    __shared__ T ssn[72];
+    __shared__ double scs[72];
+    __shared__ double redd[16];
+    __shared__ T sg;
+    __shared__ int sdone;
+    const int j = j_arg < m - 1 ? j_arg : m - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int done_flag = ctl->done;
+    const T *vj = V + (size_t)j * Nb;
+    T *w = V + (size_t)(j + 1) * Nb;
+    if (tid < j) {
+        scs[tid] = cs[tid];
+        ssn[tid] = sn[tid];
+    }
+    if (tid == 0) sg = g[j];
+    for (int k = tid; k < Nb; k += kGmThreads) sw[k] = extract_k(k, Nb, ust, w6, bop, vj);
+    if (done_flag) return;
+    __syncthreads();
+    T wl[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int k = tid + e * kGmThreads;
+        wl[e] = k < Nb ? sw[k] : zero<T>();
+    }
+    // CGS2
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = 0; i0 <= j; i0 += 8) {
+            T part[8];
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii) part[ii] = zero<T>();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int idx = tid + e * kGmThreads;
+                if (idx < Nb) {
+#pragma unroll
+                    for (int ii = 0; ii < 8; ++ii)
+                        if (i0 + ii <= j) part[ii] += conjv(V[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < 8; ++ii) {
+                T s = wave_sum(part[ii]);
+                if (lane == 0) red[wid][ii] = s;
+            }
+            __syncthreads();
+            if (tid < 8 && i0 + tid <= j) {
+                T s = zero<T>();
+                for (int q = 0; q < (kGmThreads >> 6); ++q) s += red[q][tid];
+                hs[i0 + tid] = s;
+                hcol[i0 + tid] = pass == 0 ? s : hcol[i0 + tid] + s;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int idx = tid + e * kGmThreads;
+            if (idx < Nb)
+                for (int i = 0; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+        }
+        __syncthreads();
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) s2 += abs2(wl[e]);
+    const double hn = sqrt(block_sum(s2, redd));
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + e * kGmThreads;
+        if (idx < Nb) {
+            const T v = wl[e] * inv;
+            w[idx] = v;
+            sw[idx] = v;
+        }
+    }
+    if (tid == 0) {
+        for (int i = 0; i < j; ++i) {
+            const T a = hcol[i], b = hcol[i + 1];
+            hcol[i] = a * scs[i] + ssn[i] * b;
+            hcol[i + 1] = b * scs[i] - conjv(ssn[i]) * a;
+        }
+        const T a = hcol[j];
+        const double bb = hn;
+        const double aa = absv(a);
+        const double rho = hypot(aa, bb);
+        double c;
+        T s;
+        if (aa == 0.0) {
+            c = 0.0;
+            s = scale_of<T>(1.0);
+        } else {
+            c = aa / rho;
+            s = a * (bb / (aa * rho));
+        }
+        cs[j] = c;
+        sn[j] = s;
+        hcol[j] = a * c + s * bb;
+        hcol[j + 1] = zero<T>();
+        const T gj = sg;
+        const T gj1 = -(conjv(s) * gj);
+        g[j + 1] = gj1;
+        g[j] = gj * c;
+        const double resid = absv(gj1);
+        ctl->resid = resid;
+        const int it = ctl->iters + 1;
+        ctl->iters = it;
+        ctl->j = j + 1;
+        const bool conv = resid <= ctl->thresh;
+        ctl->converged = (conv && ctl->eta == 0.0) ? 1 : 0;
+        const int limit = ctl->fixed > 0 ? ctl->fixed : ctl->max_iter;
+        if (hn == 0.0) ctl->breakdown = 1;
+        const bool dn = (ctl->fixed == 0 && conv) || it >= limit || j + 1 >= m || hn == 0.0;
+        ctl->done = dn ? 1 : 0;
+        sdone = dn ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid <= j + 1) H[(size_t)tid * m + j] = hcol[tid];
+    if (!sdone) corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr);
+}
+
+// end of a cycle: y = H^{-1} g on the leading j x j block, x += V y (and,
+// on the fast path, the corrections of the updated x for the next residual)
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_update(GmCtl *ctl, const T *V, const T *H, const T *g, T *y,
+                                                          T *x, int Nb, int n_irr, const T *mcoef, const int32_t *mbase,
+                                                          T *corr) {
+    __shared__ T ys[72];
+    __shared__ T hrow[72];
+    const int jj = ctl->j, m = ctl->m;
+    for (int i = jj - 1; i >= 0; --i) {
+        if ((int)threadIdx.x < jj) hrow[threadIdx.x] = H[(size_t)i * m + threadIdx.x];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T s = g[i];
+            for (int l = i + 1; l < jj; ++l) s -= hrow[l] * ys[l];
+            ys[i] = s / hrow[i];
+            y[i] = ys[i];
+        }
+        __syncthreads();
+    }
     for (int idx = threadIdx.x; idx < Nb; idx += blockDim.x) {
         T acc = x[idx];
         for (int i = 0; i < jj; ++i) acc += V[(size_t)i * Nb + idx] * ys[i];
         x[idx] = acc;
+    }
+    if (mcoef) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < n_irr; q += blockDim.x) {
+            const int b = mbase[q];
+            T acc = zero<T>();
+#pragma unroll
+            for (int o = 0; o < kWin; ++o) {
+                int idx = b + o;
+                if (idx >= Nb) idx -= Nb;
+                acc += mcoef[(size_t)o * n_irr + q] * x[idx];
+            }
+            corr[q] = acc;
+        }
     }
 }
 
@@ -302,6 +570,25 @@ static int launch_arnoldi(kfbi_domain *d, GmPtrs &P, int Nb, hipStream_t s) {
     return KFBI_OK;
 }
 
+template <class T>
+static int launch_iter(kfbi_domain *d, GmPtrs &P, int Nb, int j, int m, hipStream_t s) {
+    const int ept = (Nb + kGmThreads - 1) / kGmThreads;
+    const size_t lds = (size_t)Nb * sizeof(T);
+    const int ps = prof_begin(d);
+#define KFBI_ITER(E)                                                                                            \
+    k_gm_iter<T, E><<<1, kGmThreads, lds, s>>>(P.ctl, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn, Nb, j, m,     \
+                                               (const T *)d->ust, d->w6, (const T *)d->bop, d->n_irr,            \
+                                               (const T *)d->mcoef, d->mbase, (T *)d->corr)
+    if (ept <= 1) KFBI_ITER(1);
+    else if (ept <= 2) KFBI_ITER(2);
+    else if (ept <= 4) KFBI_ITER(4);
+    else KFBI_ITER(8);
+#undef KFBI_ITER
+    KFBI_CHECK_LAUNCH();
+    prof_end(d, ps, KFBI_K_ARNOLDI, 0.0);
+    return KFBI_OK;
+}
+
 // K x (or b - K x when g/scale say so) for an explicit density pointer
 static int matvec_explicit(kfbi_domain *d, double kre, double kim, const void *phi, const void *g,
                            double scale, void *out) {
@@ -313,8 +600,8 @@ static int matvec_explicit(kfbi_domain *d, double kre, double kim, const void *p
 }
 
 template <class T>
-static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kfbi_solve_opts &o,
-                     int *iters_out, double *rel_out, int *conv_out) {
+static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kfbi_solve_opts &o, bool mixed,
+                     int *iters_out, double *rel_out, int *conv_out, int *cycles_out) {
     hipStream_t s = d->stream;
     const int Nb = d->Nb;
     GmCtl h;
@@ -323,36 +610,85 @@ static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kf
     h.m = o.restart;
     h.fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
     h.tol = o.tol;
+    // mixed precision: each cycle reduces its FP64 residual by ~1e-5 with
+    // FP32 grid solves (about the accuracy of the FP32 operator)
+    h.eta = mixed ? 1e-5 : 0.0;
     KFBI_HIP(hipMemcpyAsync(P.ctl, &h, sizeof(h), hipMemcpyHostToDevice, s));
     k_gm_bnorm<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.b, Nb);
     KFBI_CHECK_LAUNCH();
     int *jptr = &P.ctl->j;
     int *done = &P.ctl->done;
-    const int chunk = 4;
+    const size_t es = sizeof(T);
+    const bool fast = d->op_merged && (size_t)Nb * es <= 65536;
+    if (mixed && !fast) {
+        set_error("mixed precision needs the merged correction operator (Nb too large or windows too wide)");
+        return KFBI_ENOTSUP;
+    }
+    int cycles = 0;
+    const int limit_all = h.fixed > 0 ? h.fixed : h.max_iter;
+    if (fast) {
+        k_corr_merged<T><<<(d->n_irr + 255) / 256, 256, 0, s>>>((const T *)P.x, Nb, d->n_irr,
+                                                                (const T *)d->mcoef, d->mbase, (T *)d->corr);
+        KFBI_CHECK_LAUNCH();
+    }
     for (int cycle = 0; cycle < 100000; ++cycle) {
         // r = b - K x, then v_0 = r / ||r||
-        KFBI_TRY(matvec_explicit(d, kre, kim, P.x, P.b, -1.0, P.r));
-        k_gm_start<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.r, (T *)P.V, (T *)P.g, Nb);
+        if (fast) {
+            KFBI_TRY(tridiag_solve(d, nullptr, d->corr, d->uhat));
+            KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
+            k_gm_start_res<T><<<1, kGmThreads, Nb * es, s>>>(P.ctl, (const T *)P.x, (const T *)P.b, (T *)P.V,
+                                                              (T *)P.g, Nb, (const T *)d->ust, d->w6,
+                                                              (const T *)d->bop, d->n_irr, (const T *)d->mcoef,
+                                                              d->mbase, (T *)d->corr);
+        } else {
+            KFBI_TRY(matvec_explicit(d, kre, kim, P.x, P.b, -1.0, P.r));
+            k_gm_start<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.r, (T *)P.V, (T *)P.g, Nb);
+        }
         KFBI_CHECK_LAUNCH();
+        // enqueue the expected number of iterations (the previous solve's
+        // count on this domain, or the fixed count) before the first read
+        // of the control block, then smaller chunks
+        int jnext = 0;
+        const int cycle_start_iters = h.iters;
+        int chunk = h.fixed > 0 ? h.fixed : (d->last_iters > 0 ? d->last_iters : 4);
+        if (chunk > o.restart) chunk = o.restart;
+        if (chunk > limit_all - h.iters) chunk = limit_all - h.iters;
+        if (chunk < 1) chunk = 1;
+        ++cycles;
         for (;;) {
             const int iters_before = h.iters;
             for (int c = 0; c < chunk; ++c) {
                 d->prof_tag = c;
-                KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.V, jptr, nullptr, d->corr, done));
-                KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, done));
-                KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, done));
-                KFBI_TRY(extract_boundary_ctl(d, kre, kim, d->ust, P.V, jptr, nullptr, nullptr, 1.0, P.V, 1, done));
-                KFBI_TRY(launch_arnoldi<T>(d, P, Nb, s));
+                if (fast && mixed) {
+                    KFBI_TRY(tridiag_solve_low(d, d->corr, d->uhat32, done));
+                    KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat32, d->ust, done, true));
+                    KFBI_TRY(launch_iter<T>(d, P, Nb, jnext++, o.restart, s));
+                } else if (fast) {
+                    KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, done));
+                    KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, done));
+                    KFBI_TRY(launch_iter<T>(d, P, Nb, jnext++, o.restart, s));
+                } else {
+                    KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.V, jptr, nullptr, d->corr, done));
+                    KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, done));
+                    KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, done));
+                    KFBI_TRY(extract_boundary_ctl(d, kre, kim, d->ust, P.V, jptr, nullptr, nullptr, 1.0, P.V, 1,
+                                                  done));
+                    KFBI_TRY(launch_arnoldi<T>(d, P, Nb, s));
+                }
             }
             d->prof_tag = -1;
             KFBI_HIP(hipMemcpyAsync(&h, P.ctl, sizeof(h), hipMemcpyDeviceToHost, s));
             KFBI_HIP(hipStreamSynchronize(s));
             if (d->prof_on) KFBI_TRY(prof_flush(d, h.iters - iters_before));
             if (h.done) break;
+            chunk = 2;
         }
+        // the first cycle's length sizes the first chunk of the next solve
+        if (cycles == 1 && h.fixed == 0 && h.iters > cycle_start_iters) d->last_iters = h.iters - cycle_start_iters;
         if (h.j > 0) {
             k_gm_update<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.V, (const T *)P.H, (const T *)P.g,
-                                                    (T *)P.y, (T *)P.x, Nb);
+                                                    (T *)P.y, (T *)P.x, Nb, d->n_irr,
+                                                    fast ? (const T *)d->mcoef : nullptr, d->mbase, (T *)d->corr);
             KFBI_CHECK_LAUNCH();
         }
         const int limit = h.fixed > 0 ? h.fixed : h.max_iter;
@@ -361,6 +697,7 @@ static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kf
     *iters_out = h.iters;
     *rel_out = h.bnorm > 0 ? h.resid / h.bnorm : h.resid;
     *conv_out = h.converged;
+    *cycles_out = cycles;
     return KFBI_OK;
 }
 
@@ -392,14 +729,24 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
         set_error("too many collocation points for the Arnoldi kernel");
         return KFBI_ENOTSUP;
     }
+    const int prec = o.precision >= 0 ? o.precision : d->desc.precision;
+    if (prec != KFBI_PREC_FP64 && prec != KFBI_PREC_MIXED) {
+        set_error("unknown precision mode");
+        return KFBI_EINVAL;
+    }
+    const bool mixed = prec == KFBI_PREC_MIXED;
     hipStream_t s = d->stream;
-    hipEvent_t e0, e1;
-    KFBI_HIP(hipEventCreate(&e0));
-    KFBI_HIP(hipEventCreate(&e1));
+    if (!d->ev0) {
+        KFBI_HIP(hipEventCreate(&d->ev0));
+        KFBI_HIP(hipEventCreate(&d->ev1));
+    }
+    hipEvent_t e0 = d->ev0, e1 = d->ev1;
     KFBI_HIP(hipEventRecord(e0, s));
     GmPtrs P = gm_layout(d, 64);
     const size_t vb = (size_t)d->Nb * elem_size(d);
     KFBI_TRY(ensure_coefficients(d, kre, kim));
+    KFBI_TRY(ensure_operators(d, kre, kim));
+    if (mixed) KFBI_TRY(ensure_coefficients_low(d, kre, kim));
     // b = g - IS(f, 0).U+
     if (f_grid) {
         KFBI_TRY(dst_rows_dense(d, f_grid, true, d->rhat));
@@ -412,11 +759,11 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     }
     if (phi_inout) KFBI_HIP(hipMemcpyAsync(P.x, phi_inout, vb, hipMemcpyDeviceToDevice, s));
     else KFBI_HIP(hipMemsetAsync(P.x, 0, vb, s));
-    int iters = 0, conv = 0;
+    int iters = 0, conv = 0, cycles = 0;
     double rel = 0.0;
     int st;
-    if (d->cplx) st = gmres_run<cd>(d, kre, kim, P, o, &iters, &rel, &conv);
-    else st = gmres_run<double>(d, kre, kim, P, o, &iters, &rel, &conv);
+    if (d->cplx) st = gmres_run<cd>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
+    else st = gmres_run<double>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
     if (st != KFBI_OK) return st;
     // U = IS(f, phi).U on the grid
     KFBI_TRY(compute_corrections(d, kre, kim, P.x, f_gamma, d->corr));
@@ -427,13 +774,11 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     KFBI_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     KFBI_HIP(hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     if (stats) {
         stats->iters = iters;
         stats->converged = conv;
         stats->rel_resid = rel;
-        stats->refinements = 0;
+        stats->refinements = mixed ? cycles : 0;
         stats->device_ms = ms;
     }
     const bool fixed = o.fixed_iters > 0;

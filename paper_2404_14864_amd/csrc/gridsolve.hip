@@ -38,19 +38,41 @@ namespace {
 
 template <class T> struct Shfl;
 template <> struct Shfl<double> {
-    __device__ static double up(double v, int o) { return __shfl_up(v, o, 64); }
-    __device__ static double down(double v, int o) { return __shfl_down(v, o, 64); }
+    __device__ static double up(double v, int o, int w = 64) { return __shfl_up(v, o, w); }
+    __device__ static double down(double v, int o, int w = 64) { return __shfl_down(v, o, w); }
     __device__ static double xr(double v, int o) { return __shfl_xor(v, o, 64); }
 };
 template <> struct Shfl<cd> {
-    __device__ static cd up(cd v, int o) { return make_cd(__shfl_up(v.x, o, 64), __shfl_up(v.y, o, 64)); }
-    __device__ static cd down(cd v, int o) { return make_cd(__shfl_down(v.x, o, 64), __shfl_down(v.y, o, 64)); }
+    __device__ static cd up(cd v, int o, int w = 64) { return make_cd(__shfl_up(v.x, o, w), __shfl_up(v.y, o, w)); }
+    __device__ static cd down(cd v, int o, int w = 64) {
+        return make_cd(__shfl_down(v.x, o, w), __shfl_down(v.y, o, w));
+    }
     __device__ static cd xr(cd v, int o) { return make_cd(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64)); }
+};
+
+template <> struct Shfl<float> {
+    __device__ static float up(float v, int o, int w = 64) { return __shfl_up(v, o, w); }
+    __device__ static float down(float v, int o, int w = 64) { return __shfl_down(v, o, w); }
+    __device__ static float xr(float v, int o) { return __shfl_xor(v, o, 64); }
+};
+template <> struct Shfl<cf> {
+    __device__ static cf up(cf v, int o, int w = 64) { return make_cf(__shfl_up(v.x, o, w), __shfl_up(v.y, o, w)); }
+    __device__ static cf down(cf v, int o, int w = 64) {
+        return make_cf(__shfl_down(v.x, o, w), __shfl_down(v.y, o, w));
+    }
+    __device__ static cf xr(cf v, int o) { return make_cf(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64)); }
 };
 
 template <class T> __device__ inline T one();
 template <> __device__ inline double one<double>() { return 1.0; }
 template <> __device__ inline cd one<cd>() { return make_cd(1.0, 0.0); }
+template <> __device__ inline float one<float>() { return 1.0f; }
+template <> __device__ inline cf one<cf>() { return make_cf(1.0f, 0.0f); }
+
+// real scalar type of an element type (sine tables, scale factors)
+template <class T> struct Real { typedef double type; };
+template <> struct Real<float> { typedef float type; };
+template <> struct Real<cf> { typedef float type; };
 
 __device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (32 - bits); }
 
@@ -155,125 +177,186 @@ __global__ void k_zero_edge_rows(int M, T *grid) {
 // e = 1/(d - e) inside the unit disk; it is tabulated until it stops
 // changing (relative 1e-17) and the limit is used afterwards.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void k_coef(int M, double kh2_re, double kh2_im, T *etab, T *elim, int32_t *tconv) {
+// computed in FP64 (complex128) and stored in the solve precision S
+template <class S>
+__global__ void k_coef(int M, double kh2_re, double kh2_im, S *etab, S *elim, int32_t *tconv) {
+    typedef typename High<S>::type H;
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = M - 1;
     if (k >= n) return;
     double s = sinpi((double)(k + 1) / (2.0 * M));
-    T dk = from_re_im<T>(2.0 + 4.0 * s * s + kh2_re, kh2_im);
-    T e = one<T>() / dk;
+    H dk = from_re_im<H>(2.0 + 4.0 * s * s + kh2_re, kh2_im);
+    H e = one<H>() / dk;
     int t = 0;
     for (; t < n; ++t) {
-        etab[(size_t)t * n + k] = e;
-        T nx = one<T>() / (dk - e);
-        T df = nx - e;
+        etab[(size_t)t * n + k] = Conv<S>::from(e);
+        H nx = one<H>() / (dk - e);
+        H df = nx - e;
         if (abs2(df) <= 1e-34 * abs2(e)) { e = nx; ++t; break; }
         e = nx;
     }
     tconv[k] = t;
-    elim[k] = e;
+    elim[k] = Conv<S>::from(e);
 }
 
 // ---------------------------------------------------------------------------
-// tridiagonal solves: one 64-lane wavefront per mode, C rows per lane
-// (64*C >= n).  rho_t = h^2 (rhat[t][k] + sum over irregular nodes q of row
-// t of corr[q] sin(pi i_q k / M)).
+// tridiagonal solves for MB consecutive modes per workgroup of MB*LANES
+// threads; LANES lanes (one wavefront or half of one) share a mode, each
+// owning C consecutive rows (LANES*C >= n).
+//   phase A  the right-hand side rho_t = h^2 (rhat[t][k] + sum over the
+//            irregular nodes q of row t of corr[q] sin(pi i_q k / M)) is
+//            built in an LDS tile, threads over (row, mode) so that the MB
+//            threads of a row read the same correction entries and the
+//            dense rhat rows are read as MB-mode contiguous segments;
+//   phase B  forward / backward recurrences as chunked affine scans with
+//            wavefront shuffles, in place in the tile;
+//   phase C  the tile is written out as contiguous MB-mode row segments.
+// The tile index is t*MB + m + t/C: one element of padding per chunk keeps
+// the lanes of phase B (stride C rows) off a single LDS bank.
 // ---------------------------------------------------------------------------
-template <class T, int C>
-__global__ __launch_bounds__(256) void k_tridiag(int M, double h2, const T *__restrict__ rhat,
-                                                 const T *__restrict__ corr,
-                                                 const int32_t *__restrict__ irr_col,
-                                                 const int32_t *__restrict__ row_ptr,
-                                                 const double *__restrict__ sine,
-                                                 const T *__restrict__ etab, const T *__restrict__ elim,
-                                                 const int32_t *__restrict__ tconv, T *__restrict__ uhat,
-                                                 const int *__restrict__ done) {
-    extern __shared__ double S[];  // 2M sine values
+template <int MB, int C>
+__device__ inline int tidx(int t, int m) {
+    return t * MB + m + t / C;
+}
+
+// T: the solve precision (double / cd, or float / cf for the mixed mode);
+// the corrections arrive in FP64 (TC) and are rounded once when staged.
+template <class T, class TC, int MB, int LANES, int C>
+__global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T *__restrict__ rhat,
+                                                       const TC *__restrict__ corr,
+                                                       const int32_t *__restrict__ irr_col,
+                                                       const int32_t *__restrict__ row_ptr,
+                                                       const T *__restrict__ etab, const T *__restrict__ elim,
+                                                       const int32_t *__restrict__ tconv, T *__restrict__ uhat,
+                                                       const int *__restrict__ done, int nnz, int stage) {
+    typedef typename Real<T>::type R;
+    extern __shared__ double lds[];
+    constexpr int NT = MB * LANES;
     const int n = M - 1;
     const int mask2M = 2 * M - 1;
     if (done && *done) return;
-    for (int m = threadIdx.x; m < 2 * M; m += blockDim.x) S[m] = sine[m];
+    R *S = reinterpret_cast<R *>(lds);                   // 2M sine values
+    T *tile = reinterpret_cast<T *>(lds + 2 * M);       // n*MB + n/C + 1
+    const int tile_len = n * MB + n / C + 1;
+    // staged sparse right-hand side: row pointers, values, columns
+    int32_t *srp = reinterpret_cast<int32_t *>(tile + tile_len);
+    T *sval = reinterpret_cast<T *>(srp + ((n + 1 + 3) & ~3));
+    int32_t *scol = reinterpret_cast<int32_t *>(sval + (stage ? nnz : 0));
+    const int k0 = blockIdx.x * MB;
+    // the sine table is computed in place (same expression as the domain's
+    // table) instead of being fetched: no global round trip before phase A
+    for (int q = threadIdx.x; q < 2 * M; q += NT) S[q] = (R)sinpi((double)q / (double)M);
+    if (corr && stage) {
+        for (int q = threadIdx.x; q <= n; q += NT) srp[q] = row_ptr[q];
+        for (int q = threadIdx.x; q < nnz; q += NT) {
+            sval[q] = Conv<T>::from(corr[q]);
+            scol[q] = irr_col[q];
+        }
+    }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);  // 0-based mode (mode number k+1)
-    if (k >= n) return;
-    const int mode = k + 1;
-    const int t0 = lane * C;
-    const int tc = tconv[k];
-    const T lim = elim[k];
-
-    T v[C];
-    // pass 1: right-hand side, chunk composite of x -> e (x - rho)
-    T A = one<T>(), B = zero<T>();
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        int t = t0 + c;
+    // phase A
+    for (int p = threadIdx.x; p < n * MB; p += NT) {
+        const int t = p / MB, m = p - t * MB;
+        const int k = k0 + m;
         T r = zero<T>();
-        if (t < n) {
+        if (k < n) {
             if (rhat) r = rhat[(size_t)t * n + k];
             if (corr) {
-                int q1 = row_ptr[t + 1];
-                for (int q = row_ptr[t]; q < q1; ++q) r += corr[q] * S[(irr_col[q] * mode) & mask2M];
+                const int mode = k + 1;
+                if (stage) {
+                    const int q1 = srp[t + 1];
+                    T r2 = zero<T>();
+                    int q = srp[t];
+                    for (; q + 1 < q1; q += 2) {  // two independent chains
+                        r += sval[q] * S[(scol[q] * mode) & mask2M];
+                        r2 += sval[q + 1] * S[(scol[q + 1] * mode) & mask2M];
+                    }
+                    if (q < q1) r += sval[q] * S[(scol[q] * mode) & mask2M];
+                    r += r2;
+                } else {
+                    const int q1 = row_ptr[t + 1];
+                    for (int q = row_ptr[t]; q < q1; ++q)
+                        r += Conv<T>::from(corr[q]) * S[(irr_col[q] * mode) & mask2M];
+                }
             }
-            r = h2 * r;
-            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
-            B = e * (B - r);
-            A = e * A;
         }
-        v[c] = r;
+        tile[tidx<MB, C>(t, m)] = r * (R)h2;
     }
-    // inclusive scan of affine maps over lanes (earlier lanes applied first)
+    __syncthreads();
+    // phase B
+    const int lane = threadIdx.x % LANES;
+    const int m = threadIdx.x / LANES;
+    const int k = k0 + m;
+    const int t0 = lane * C;
+    if (k < n) {
+        const int tc = tconv[k];
+        const T lim = elim[k];
+        T e[C];
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        T Ap = Shfl<T>::up(A, off), Bp = Shfl<T>::up(B, off);
-        if (lane >= off) {
-            B = A * Bp + B;
-            A = A * Ap;
+        for (int c = 0; c < C; ++c) {
+            const int t = t0 + c;
+            e[c] = (t < tc && t < n) ? etab[(size_t)t * n + k] : lim;
         }
-    }
-    T x = Shfl<T>::up(B, 1);
-    if (lane == 0) x = zero<T>();
-    // replay: forward values x_t
+        // the lane's rows in registers for all four passes (rows past n: 0 with
+        // e = 0, which leaves every composite unchanged)
+        T v[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        int t = t0 + c;
-        if (t < n) {
-            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
-            x = e * (x - v[c]);
+        for (int c = 0; c < C; ++c) {
+            const bool ok = t0 + c < n;
+            v[c] = ok ? tile[tidx<MB, C>(t0 + c, m)] : zero<T>();
+            if (!ok) e[c] = zero<T>();
+        }
+        T A = one<T>(), B = zero<T>();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if (t0 + c < n) {
+                B = e[c] * (B - v[c]);
+                A = e[c] * A;
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < LANES; off <<= 1) {
+            T Ap = Shfl<T>::up(A, off, LANES), Bp = Shfl<T>::up(B, off, LANES);
+            if (lane >= off) {
+                B = A * Bp + B;
+                A = A * Ap;
+            }
+        }
+        T x = Shfl<T>::up(B, 1, LANES);
+        if (lane == 0) x = zero<T>();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            x = e[c] * (x - v[c]);
             v[c] = x;
         }
-    }
-    // backward: U_t = e_t U_{t+1} + x_t, composite over the chunk from its end
-    A = one<T>();
-    B = zero<T>();
+        A = one<T>();
+        B = zero<T>();
 #pragma unroll
-    for (int c = C - 1; c >= 0; --c) {
-        int t = t0 + c;
-        if (t < n) {
-            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
-            B = e * B + v[c];
-            A = e * A;
+        for (int c = C - 1; c >= 0; --c) {
+            B = e[c] * B + v[c];
+            A = e[c] * A;
+        }
+#pragma unroll
+        for (int off = 1; off < LANES; off <<= 1) {
+            T Ap = Shfl<T>::down(A, off, LANES), Bp = Shfl<T>::down(B, off, LANES);
+            if (lane + off < LANES) {
+                B = A * Bp + B;
+                A = A * Ap;
+            }
+        }
+        T y = Shfl<T>::down(B, 1, LANES);
+        if (lane == LANES - 1) y = zero<T>();
+#pragma unroll
+        for (int c = C - 1; c >= 0; --c) {
+            y = e[c] * y + v[c];
+            if (t0 + c < n) tile[tidx<MB, C>(t0 + c, m)] = y;
         }
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        T Ap = Shfl<T>::down(A, off), Bp = Shfl<T>::down(B, off);
-        if (lane + off < 64) {
-            B = A * Bp + B;
-            A = A * Ap;
-        }
-    }
-    T y = Shfl<T>::down(B, 1);
-    if (lane == 63) y = zero<T>();
-#pragma unroll
-    for (int c = C - 1; c >= 0; --c) {
-        int t = t0 + c;
-        if (t < n) {
-            T e = (t < tc) ? etab[(size_t)t * n + k] : lim;
-            y = e * y + v[c];
-            uhat[(size_t)t * n + k] = y;
-        }
+    __syncthreads();
+    // phase C
+    for (int p = threadIdx.x; p < n * MB; p += NT) {
+        const int t = p / MB, mm = p - t * MB;
+        if (k0 + mm < n) uhat[(size_t)t * n + k0 + mm] = tile[tidx<MB, C>(t, mm)];
     }
 }
 
@@ -281,11 +364,13 @@ __global__ __launch_bounds__(256) void k_tridiag(int M, double h2, const T *__re
 // U at listed nodes: one wavefront per node, U = (2/M) sum_k U^[t][k]
 // sin(pi i k / M).  nodes: linear grid indices (interior nodes only).
 // ---------------------------------------------------------------------------
-template <class T>
+// T: precision of U^ and of the sum; the result is stored in FP64 (TO)
+template <class T, class TO>
 __global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int32_t *__restrict__ nodes,
                                                     int node_stride, const T *__restrict__ uhat,
-                                                    const double *__restrict__ sine, T *__restrict__ out,
-                                                    const int *__restrict__ done) {
+                                                    const typename Real<T>::type *__restrict__ sine,
+                                                    TO *__restrict__ out, const int *__restrict__ done) {
+    typedef typename Real<T>::type R;
     if (done && *done) return;
     const int lane = threadIdx.x & 63;
     const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -300,7 +385,7 @@ __global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int
     for (int k = lane; k < n; k += 64) acc += row[k] * sine[(i * (k + 1)) & mask2M];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
-    if (lane == 0) out[p] = (2.0 / M) * acc;
+    if (lane == 0) out[p] = to_high(acc * (R)(2.0 / M));
 }
 
 template <class T>
@@ -332,25 +417,56 @@ template <class T>
 int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
     const int M = d->M, n = M - 1;
     const double h2 = d->h * d->h;
-    int blocks = (n + 3) / 4;
-    size_t lds = (size_t)2 * M * sizeof(double);
-#define KFBI_TRI(CC)                                                                              \
-    k_tridiag<T, CC><<<blocks, 256, lds, d->stream>>>(M, h2, (const T *)rhat, (const T *)corr,    \
-                                                      d->irr_col, d->irr_row_ptr, d->sine,        \
-                                                      (const T *)d->etab, (const T *)d->elim,     \
-                                                      d->tconv, (T *)uhat, done)
-    int c = (n + 63) / 64;
-    const int ps = prof_begin(d);
-    if (c <= 1) KFBI_TRI(1);
-    else if (c <= 2) KFBI_TRI(2);
-    else if (c <= 4) KFBI_TRI(4);
-    else if (c <= 8) KFBI_TRI(8);
-    else if (c <= 16) KFBI_TRI(16);
-    else if (c <= 32) KFBI_TRI(32);
-    else {
+    // modes per workgroup: the largest power of two (<= 8) whose LDS tile
+    // stays within 32 KB; eight modes use 32-lane groups, fewer use 64
+    int mb = d->tri_mb;
+    if (mb <= 0) {
+        mb = 8;
+        while (mb > 1 && (size_t)n * mb * sizeof(T) > 32768) mb >>= 1;
+    }
+    const int lanes = mb == 8 ? 32 : 64;
+    int c = 1;
+    while (lanes * c < n) c <<= 1;
+    const int blocks = (n + mb - 1) / mb;
+    size_t lds = (size_t)2 * M * sizeof(double) + ((size_t)n * mb + n / c + 1) * sizeof(T) +
+                 (size_t)((n + 1 + 3) & ~3) * sizeof(int32_t);
+    if (c > 32 || lds > 65536) {
         set_error("grid too large for the tridiagonal kernel");
         return KFBI_ENOTSUP;
     }
+    // stage the sparse right-hand side in LDS when it fits the 64 KB budget
+    const int nnz = d->n_irr;
+    int stage = 0;
+    if (corr && lds + (size_t)nnz * (sizeof(T) + sizeof(int32_t)) <= 65536) {
+        stage = 1;
+        lds += (size_t)nnz * (sizeof(T) + sizeof(int32_t));
+    }
+    typedef typename High<T>::type TC;
+    const bool low = sizeof(T) < sizeof(TC);
+    const T *etab = (const T *)(low ? d->etab32 : d->etab);
+    const T *elim = (const T *)(low ? d->elim32 : d->elim);
+    const int32_t *tconv = low ? d->tconv32 : d->tconv;
+#define KFBI_TRI(MBv, Lv, CC)                                                                        \
+    k_tridiag<T, TC, MBv, Lv, CC><<<blocks, MBv * Lv, lds, d->stream>>>(                             \
+        M, h2, (const T *)rhat, (const TC *)corr, d->irr_col, d->irr_row_ptr, etab, elim, tconv, (T *)uhat, \
+        done, nnz, stage)
+#define KFBI_TRI_C(MBv, Lv)                 \
+    switch (c) {                            \
+        case 1: KFBI_TRI(MBv, Lv, 1); break;   \
+        case 2: KFBI_TRI(MBv, Lv, 2); break;   \
+        case 4: KFBI_TRI(MBv, Lv, 4); break;   \
+        case 8: KFBI_TRI(MBv, Lv, 8); break;   \
+        case 16: KFBI_TRI(MBv, Lv, 16); break; \
+        default: KFBI_TRI(MBv, Lv, 32); break; \
+    }
+    const int ps = prof_begin(d);
+    switch (mb) {
+        case 8: KFBI_TRI_C(8, 32); break;
+        case 4: KFBI_TRI_C(4, 64); break;
+        case 2: KFBI_TRI_C(2, 64); break;
+        default: KFBI_TRI_C(1, 64); break;
+    }
+#undef KFBI_TRI_C
 #undef KFBI_TRI
     KFBI_CHECK_LAUNCH();
     {
@@ -382,6 +498,47 @@ int ensure_coefficients(kfbi_domain *d, double kre, double kim) {
     return KFBI_OK;
 }
 
+namespace {
+__global__ void k_sine32(int M, float *s) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < 2 * M) s[m] = (float)sinpi((double)m / (double)M);
+}
+}  // namespace
+
+// FP32 / complex64 coefficient table and scratch for the mixed-precision
+// grid solve (allocated on first use)
+int ensure_coefficients_low(kfbi_domain *d, double kre, double kim) {
+    if (d->coef32_valid && d->coef32_kre == kre && d->coef32_kim == kim) return KFBI_OK;
+    const int M = d->M, n = M - 1;
+    const size_t ls = d->cplx ? sizeof(cf) : sizeof(float);
+    if (!d->uhat32) {
+        KFBI_TRY(dalloc(d, &d->uhat32, (size_t)n * n * ls));
+        KFBI_TRY(dalloc(d, &d->etab32, (size_t)n * n * ls));
+        KFBI_TRY(dalloc(d, &d->elim32, (size_t)n * ls));
+        KFBI_TRY(dalloc(d, (void **)&d->tconv32, (size_t)n * sizeof(int32_t)));
+        KFBI_TRY(dalloc(d, (void **)&d->sine32, (size_t)2 * M * sizeof(float)));
+        k_sine32<<<(2 * M + 255) / 256, 256, 0, d->stream>>>(M, d->sine32);
+        KFBI_CHECK_LAUNCH();
+    }
+    const double h2 = d->h * d->h;
+    if (d->cplx)
+        k_coef<cf><<<(n + 127) / 128, 128, 0, d->stream>>>(M, kre * h2, kim * h2, (cf *)d->etab32,
+                                                          (cf *)d->elim32, d->tconv32);
+    else
+        k_coef<float><<<(n + 127) / 128, 128, 0, d->stream>>>(M, kre * h2, 0.0, (float *)d->etab32,
+                                                             (float *)d->elim32, d->tconv32);
+    KFBI_CHECK_LAUNCH();
+    d->coef32_valid = true;
+    d->coef32_kre = kre;
+    d->coef32_kim = kim;
+    return KFBI_OK;
+}
+
+int tridiag_solve_low(kfbi_domain *d, const void *corr, void *uhat32_out, const int *done) {
+    if (d->cplx) return launch_tridiag<cf>(d, nullptr, corr, uhat32_out, done);
+    return launch_tridiag<float>(d, nullptr, corr, uhat32_out, done);
+}
+
 int dst_rows_dense(kfbi_domain *d, const void *grid, bool mask_inside, void *rhat_out) {
     const uint8_t *mask = mask_inside ? d->flags : nullptr;
     if (d->cplx) return launch_dst<cd>(d, grid, true, mask, rhat_out, false, 1.0);
@@ -404,23 +561,35 @@ int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *
 }
 
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out) {
-    return eval_stencil_nodes_ctl(d, uhat, ust_out, nullptr);
+    return eval_stencil_nodes_ctl(d, uhat, ust_out, nullptr, false);
 }
 
-int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done) {
+int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low) {
     const int nn = 6 * d->Nb;
     const int stride = (int)(sizeof(Stencil) / sizeof(int32_t));
     const int32_t *nodes = reinterpret_cast<const int32_t *>(d->st);
+    const int grid = (nn + 3) / 4;
     const int ps = prof_begin(d);
-    if (d->cplx)
-        k_eval_nodes<cd><<<(nn + 3) / 4, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cd *)uhat,
-                                                             d->sine, (cd *)ust_out, done);
-    else
-        k_eval_nodes<double><<<(nn + 3) / 4, 256, 0, d->stream>>>(d->M, nn, nodes, stride,
-                                                                 (const double *)uhat, d->sine,
-                                                                 (double *)ust_out, done);
+    if (d->cplx) {
+        if (low)
+            k_eval_nodes<cf, cd><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cf *)uhat,
+                                                              d->sine32, (cd *)ust_out, done);
+        else
+            k_eval_nodes<cd, cd><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cd *)uhat, d->sine,
+                                                              (cd *)ust_out, done);
+    } else {
+        if (low)
+            k_eval_nodes<float, double><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride,
+                                                                     (const float *)uhat, d->sine32,
+                                                                     (double *)ust_out, done);
+        else
+            k_eval_nodes<double, double><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride,
+                                                                      (const double *)uhat, d->sine,
+                                                                      (double *)ust_out, done);
+    }
     KFBI_CHECK_LAUNCH();
-    prof_end(d, ps, KFBI_K_EVAL_NODES, (double)nn * ((d->M - 1) * (double)elem_size(d) + 4.0 + elem_size(d)));
+    const double es = low ? elem_size(d) / 2.0 : elem_size(d);
+    prof_end(d, ps, KFBI_K_EVAL_NODES, (double)nn * ((d->M - 1) * es + 4.0 + elem_size(d)));
     return KFBI_OK;
 }
 

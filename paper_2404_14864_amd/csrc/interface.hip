@@ -136,6 +136,127 @@ __global__ void k_extract(int Nb, double dth, const Colloc *__restrict__ col, co
     out[k] = res;
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-vector operators (f = 0).  The corrections and the jump part of the
+// extraction are linear in phi and, by the finite-difference and
+// interpolation stencils above, each touches a short window of phi: a
+// crossed edge reads phi at k0-3 .. k0+4, a collocation point at k-2 .. k+2.
+// Their coefficients are obtained once per kappa by evaluating the same
+// device code on unit windows, so the iteration applies them as small dense
+// stencils.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ inline void window_derivs(const T *win, int L, double i12d, double i12d2, T &p, T &pt, T &ptt) {
+    const T m2 = win[L - 2], m1 = win[L - 1], c0 = win[L], p1 = win[L + 1], p2 = win[L + 2];
+    p = c0;
+    pt = ((m2 - p2) + (p1 - m1) * 8.0) * i12d;
+    ptt = ((p1 + m1) * 16.0 - (p2 + m2) - c0 * 30.0) * i12d2;
+}
+
+template <class T>
+__global__ void k_build_corr_op(int n_irr, const IrrNode *__restrict__ irr, const Edge *__restrict__ edges, int Nb,
+                                double dth, double h, T kappa, T *__restrict__ coef, int32_t *__restrict__ base) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_irr) return;
+    const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
+    const IrrNode R = irr[q];
+    const double scale = -R.sgn / (h * h);
+    // layout: base[s * n_irr + q], coef[(s * 8 + o) * n_irr + q] (consecutive
+    // nodes adjacent); an unused slot has base 0 and zero coefficients
+    for (int s = 0; s < 4; ++s) {
+        if (s >= R.nedge) {
+            base[s * n_irr + q] = 0;
+            for (int o = 0; o < 8; ++o) coef[(size_t)(s * 8 + o) * n_irr + q] = zero<T>();
+            continue;
+        }
+        const Edge &E = edges[R.edge[s]];
+        base[s * n_irr + q] = wrapk(E.k0 - 3, Nb);
+        const double dd = R.d[s];
+        for (int o = 0; o < 8; ++o) {
+            T win[8];
+            for (int u = 0; u < 8; ++u) win[u] = zero<T>();
+            win[o] = from_re_im<T>(1.0, 0.0);
+            T p = zero<T>(), pt = zero<T>(), ptt = zero<T>();
+            for (int l = 0; l < 4; ++l) {  // Lagrange nodes k0-1 .. k0+2 = window 2 .. 5
+                T a, b, c;
+                window_derivs(win, 2 + l, i12d, i12d2, a, b, c);
+                p += a * E.w[l];
+                pt += b * E.w[l];
+                ptt += c * E.w[l];
+            }
+            Jumps<T> J = jumps_dirichlet(E.fr, p, pt, ptt, zero<T>(), kappa);
+            const T ua = E.axis == 0 ? J.ux : J.uy;
+            const T uaa = E.axis == 0 ? J.uxx : J.uyy;
+            coef[(size_t)(s * 8 + o) * n_irr + q] = (J.u + ua * dd + uaa * (0.5 * dd * dd)) * scale;
+        }
+    }
+}
+
+// Merged form of the corrections operator: the windows of a node's crossed
+// edges lie within a few collocation spacings of each other, so they are
+// summed into one window of kCorrWin coefficients starting at mbase[q]
+// (layout mcoef[o * n_irr + q]).  A node whose windows span more than
+// kCorrWin points raises *overflow (the caller then keeps the per-edge form).
+constexpr int kCorrWin = 16;
+
+template <class T>
+__global__ void k_merge_corr_op(int n_irr, int Nb, const T *__restrict__ coef, const int32_t *__restrict__ base,
+                                const IrrNode *__restrict__ irr, T *__restrict__ mcoef, int32_t *__restrict__ mbase,
+                                int *overflow) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_irr) return;
+    const int ne = irr[q].nedge;
+    const int ref = base[q];
+    int rel[4], lo = 0, hi = 0;
+    for (int s = 0; s < ne; ++s) {
+        int r = base[s * n_irr + q] - ref;     // signed periodic offset in (-Nb/2, Nb/2]
+        if (r > Nb / 2) r -= Nb;
+        if (r <= -Nb / 2) r += Nb;
+        rel[s] = r;
+        lo = r < lo ? r : lo;
+        hi = r > hi ? r : hi;
+    }
+    for (int o = 0; o < kCorrWin; ++o) mcoef[(size_t)o * n_irr + q] = zero<T>();
+    mbase[q] = wrapk(ref + lo, Nb);
+    if (hi - lo + 8 > kCorrWin) {
+        atomicOr(overflow, 1);
+        return;
+    }
+    for (int s = 0; s < ne; ++s)
+        for (int o = 0; o < 8; ++o) {
+            const size_t dst = (size_t)(rel[s] - lo + o) * n_irr + q;
+            mcoef[dst] = mcoef[dst] + coef[(size_t)(s * 8 + o) * n_irr + q];
+        }
+}
+
+template <class T>
+__global__ void k_build_ext_op(int Nb, double dth, const Colloc *__restrict__ col, const Stencil *__restrict__ st,
+                               T kappa, T *__restrict__ bop, double *__restrict__ w6) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Nb) return;
+    const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
+    const Stencil &S = st[k];
+    for (int p = 0; p < 6; ++p) w6[k * 6 + p] = S.w[p];
+    for (int o = 0; o < 5; ++o) {
+        T win[5];
+        for (int u = 0; u < 5; ++u) win[u] = zero<T>();
+        win[o] = from_re_im<T>(1.0, 0.0);
+        T p, pt, ptt;
+        window_derivs(win, 2, i12d, i12d2, p, pt, ptt);
+        Jumps<T> J = jumps_dirichlet(col[k].fr, p, pt, ptt, zero<T>(), kappa);
+        T acc = zero<T>();
+        for (int q = 0; q < 6; ++q) {
+            if ((S.out_mask >> q) & 1) {
+                const double xi = S.xi[q], eta = S.eta[q];
+                T jq = J.u + J.ux * xi + J.uy * eta + J.uxx * (0.5 * xi * xi) + J.uxy * (xi * eta) +
+                       J.uyy * (0.5 * eta * eta);
+                acc += jq * S.w[q];
+            }
+        }
+        bop[k * 5 + o] = acc;
+    }
+}
+
 template <class T> T kappa_of(double kre, double kim);
 template <> double kappa_of<double>(double kre, double) { return kre; }
 template <> cd kappa_of<cd>(double kre, double kim) { return make_cd(kre, kim); }
@@ -191,6 +312,54 @@ int extract_boundary_ctl(kfbi_domain *d, double kre, double kim, const void *ust
 int extract_boundary(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi,
                      const void *f_gamma, const void *g_minus, double scale, void *out) {
     return extract_boundary_ctl(d, kre, kim, ust, phi, nullptr, f_gamma, g_minus, scale, out, 0, nullptr);
+}
+
+int ensure_operators(kfbi_domain *d, double kre, double kim) {
+    if (d->op_valid && d->op_kre == kre && d->op_kim == kim) return KFBI_OK;
+    const size_t es = elem_size(d);
+    if (!d->cop_coef) {
+        KFBI_TRY(dalloc(d, &d->cop_coef, (size_t)d->n_irr * 32 * es));
+        KFBI_TRY(dalloc(d, (void **)&d->cop_base, (size_t)d->n_irr * 4 * sizeof(int32_t)));
+        KFBI_TRY(dalloc(d, &d->mcoef, (size_t)d->n_irr * kCorrWin * es));
+        KFBI_TRY(dalloc(d, (void **)&d->mbase, (size_t)d->n_irr * sizeof(int32_t) + 256));
+        KFBI_TRY(dalloc(d, &d->bop, (size_t)d->Nb * 5 * es));
+        KFBI_TRY(dalloc(d, (void **)&d->w6, (size_t)d->Nb * 6 * sizeof(double)));
+    }
+    // overflow flag lives after the merged bases
+    int *overflow = reinterpret_cast<int *>(reinterpret_cast<char *>(d->mbase) +
+                                            (((size_t)d->n_irr * sizeof(int32_t) + 127) & ~(size_t)127));
+    KFBI_HIP(hipMemsetAsync(overflow, 0, sizeof(int), d->stream));
+    const double dth = 6.283185307179586476925286766559 / d->Nb;
+    const int gi = (d->n_irr + 127) / 128, gk = (d->Nb + 127) / 128;
+    if (d->cplx) {
+        k_build_corr_op<cd><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h,
+                                                       make_cd(kre, kim), (cd *)d->cop_coef, d->cop_base);
+        KFBI_CHECK_LAUNCH();
+        k_build_ext_op<cd><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->col, d->st, make_cd(kre, kim), (cd *)d->bop,
+                                                      d->w6);
+    } else {
+        k_build_corr_op<double><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kre,
+                                                           (double *)d->cop_coef, d->cop_base);
+        KFBI_CHECK_LAUNCH();
+        k_build_ext_op<double><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->col, d->st, kre, (double *)d->bop, d->w6);
+    }
+    KFBI_CHECK_LAUNCH();
+    if (d->cplx)
+        k_merge_corr_op<cd><<<gi, 128, 0, d->stream>>>(d->n_irr, d->Nb, (const cd *)d->cop_coef, d->cop_base, d->irr,
+                                                       (cd *)d->mcoef, d->mbase, overflow);
+    else
+        k_merge_corr_op<double><<<gi, 128, 0, d->stream>>>(d->n_irr, d->Nb, (const double *)d->cop_coef,
+                                                           d->cop_base, d->irr, (double *)d->mcoef, d->mbase,
+                                                           overflow);
+    KFBI_CHECK_LAUNCH();
+    int hov = 0;
+    KFBI_HIP(hipMemcpyAsync(&hov, overflow, sizeof(int), hipMemcpyDeviceToHost, d->stream));
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    d->op_merged = hov == 0;
+    d->op_valid = true;
+    d->op_kre = kre;
+    d->op_kim = kim;
+    return KFBI_OK;
 }
 
 int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,

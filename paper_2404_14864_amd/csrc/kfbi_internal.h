@@ -38,6 +38,33 @@ __host__ __device__ inline cd operator/(cd a, cd b) {
 __host__ __device__ inline cd &operator+=(cd &a, cd b) { a.x += b.x; a.y += b.y; return a; }
 __host__ __device__ inline cd &operator-=(cd &a, cd b) { a.x -= b.x; a.y -= b.y; return a; }
 
+// single-precision counterparts for the mixed-precision grid solve
+struct cf {
+    float x, y;
+};
+__host__ __device__ inline cf make_cf(float a, float b) { cf r; r.x = a; r.y = b; return r; }
+__host__ __device__ inline cf operator+(cf a, cf b) { return make_cf(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cf operator-(cf a, cf b) { return make_cf(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cf operator*(cf a, cf b) { return make_cf(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline cf operator*(float s, cf a) { return make_cf(s * a.x, s * a.y); }
+__host__ __device__ inline cf operator*(cf a, float s) { return make_cf(s * a.x, s * a.y); }
+__host__ __device__ inline cf operator*(cf a, double s) { return make_cf((float)s * a.x, (float)s * a.y); }
+__host__ __device__ inline cf &operator+=(cf &a, cf b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline cf &operator-=(cf &a, cf b) { a.x -= b.x; a.y -= b.y; return a; }
+
+// element type conversions between the FP64 path and the FP32 grid solve
+__host__ __device__ inline float to_low(double a) { return (float)a; }
+__host__ __device__ inline cf to_low(cd a) { return make_cf((float)a.x, (float)a.y); }
+__host__ __device__ inline double to_high(float a) { return (double)a; }
+__host__ __device__ inline cd to_high(cf a) { return make_cd((double)a.x, (double)a.y); }
+__host__ __device__ inline double to_high(double a) { return a; }
+__host__ __device__ inline cd to_high(cd a) { return a; }
+template <class S> struct Conv;
+template <> struct Conv<double> { __host__ __device__ static double from(double a) { return a; } };
+template <> struct Conv<cd> { __host__ __device__ static cd from(cd a) { return a; } };
+template <> struct Conv<float> { __host__ __device__ static float from(double a) { return (float)a; } };
+template <> struct Conv<cf> { __host__ __device__ static cf from(cd a) { return to_low(a); } };
+
 // generic helpers over double / cd
 __host__ __device__ inline double conjv(double a) { return a; }
 __host__ __device__ inline cd conjv(cd a) { return make_cd(a.x, -a.y); }
@@ -48,9 +75,17 @@ __host__ __device__ inline double realv(cd a) { return a.x; }
 template <class T> __host__ __device__ inline T zero();
 template <> __host__ __device__ inline double zero<double>() { return 0.0; }
 template <> __host__ __device__ inline cd zero<cd>() { return make_cd(0.0, 0.0); }
+template <> __host__ __device__ inline float zero<float>() { return 0.0f; }
+template <> __host__ __device__ inline cf zero<cf>() { return make_cf(0.0f, 0.0f); }
 template <class T> __host__ __device__ inline T from_re_im(double re, double im);
 template <> __host__ __device__ inline double from_re_im<double>(double re, double) { return re; }
 template <> __host__ __device__ inline cd from_re_im<cd>(double re, double im) { return make_cd(re, im); }
+template <> __host__ __device__ inline float from_re_im<float>(double re, double) { return (float)re; }
+template <> __host__ __device__ inline cf from_re_im<cf>(double re, double im) { return make_cf((float)re, (float)im); }
+// the FP64 type an element of either precision is assembled in
+template <class S> struct High { typedef S type; };
+template <> struct High<float> { typedef double type; };
+template <> struct High<cf> { typedef cd type; };
 
 // ---------------------------------------------------------------------------
 // error handling
@@ -164,6 +199,35 @@ struct kfbi_domain {
     void *tmp_grid = nullptr;           // (M+1)^2
     void *vec = nullptr;                // scratch boundary vectors (8*Nb)
 
+    // launch shape of the tridiagonal kernel: modes per workgroup (0: default)
+    int tri_mb = 0;
+
+    // mixed precision (FP32 / complex64 grid solve), allocated on first use
+    void *uhat32 = nullptr;
+    void *etab32 = nullptr;
+    void *elim32 = nullptr;
+    int32_t *tconv32 = nullptr;
+    float *sine32 = nullptr;
+    bool coef32_valid = false;
+    double coef32_kre = 0, coef32_kim = 0;
+
+    // matrix-vector operators (per kappa): corrections = sum over the <= 4
+    // crossed edges of each irregular node of an 8-point window of phi
+    // starting at cop_base; extraction = sum_p w6[k][p] U(stencil p) + a
+    // 5-point window of phi around k with coefficients bop
+    bool op_valid = false;
+    double op_kre = 0, op_kim = 0;
+    void *cop_coef = nullptr;           // n_irr * 4 * 8
+    int32_t *cop_base = nullptr;        // n_irr * 4 (-1: unused slot)
+    void *bop = nullptr;                // Nb * 5
+    double *w6 = nullptr;               // Nb * 6
+    // merged corrections: one 16-point window per node at mbase (layout
+    // mcoef[o * n_irr + q]); op_merged false when some node's windows are
+    // too far apart, and the per-edge form is used instead
+    void *mcoef = nullptr;
+    int32_t *mbase = nullptr;
+    bool op_merged = false;
+
     // tridiagonal coefficient table (per kappa)
     bool coef_valid = false;
     double coef_kre = 0, coef_kim = 0;
@@ -174,6 +238,8 @@ struct kfbi_domain {
     // GMRES workspace
     void *gm = nullptr;                 // device GmresState (+ basis)
     size_t gm_bytes = 0;
+    int last_iters = 0;                 // iterations of the previous solve (chunk sizing)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // solve timing
 
     // optional per-kernel timing with HIP events (kfbi_profile_*)
     struct ProfSlot {
@@ -210,7 +276,10 @@ int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *
 int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out);
 // U at the 6 Nb stencil nodes
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out);
-int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done);
+int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low = false);
+// mixed precision: FP32 / complex64 coefficient tables and grid solve
+int ensure_coefficients_low(kfbi_domain *d, double kre, double kim);
+int tridiag_solve_low(kfbi_domain *d, const void *corr, void *uhat32_out, const int *done);
 
 // interface pieces (interface.hip)
 int compute_corrections(kfbi_domain *d, double kre, double kim, const void *phi,
@@ -226,6 +295,9 @@ int extract_boundary_ctl(kfbi_domain *d, double kre, double kim, const void *ust
                          const void *phi_base, const int *jptr, const void *f_gamma,
                          const void *g, double scale, void *out_base, int out_add,
                          const int *done);
+
+// build the matrix-vector operators for this kappa (no-op when current)
+int ensure_operators(kfbi_domain *d, double kre, double kim);
 
 // one full interface solve IS(f, f_gamma, phi) -> (u grid, U+)
 int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
