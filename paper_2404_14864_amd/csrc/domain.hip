@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <vector>
 
 #include "kfbi_internal.h"
@@ -436,12 +437,43 @@ int build_domain(kfbi_domain *d) {
     // irregular nodes of interior row t (grid row j = t + 1)
     std::vector<int32_t> rowptr(d->n + 1);
     for (int t = 0; t <= d->n; ++t) rowptr[t] = off[t + 1];
+    // rows with irregular nodes, heaviest first: the sparse right-hand side
+    // of the grid solve is built one row per thread, so neighbouring threads
+    // get rows of similar length
+    std::vector<int32_t> order;
+    for (int t = 0; t < d->n; ++t)
+        if (rowptr[t + 1] > rowptr[t]) order.push_back(t);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return rowptr[a + 1] - rowptr[a] > rowptr[b + 1] - rowptr[b];
+    });
+    d->n_act_rows = (int)order.size();
+    // segments in row_order; the segments of one row are consecutive and
+    // a segment's last node is the one before the next segment's first,
+    // except at the row's end (given by the row pointers)
+    std::vector<int32_t> seg_q0, seg_row, row_seg;
+    for (int32_t t : order) {
+        row_seg.push_back((int32_t)seg_q0.size());
+        for (int q = rowptr[t]; q < rowptr[t + 1]; q += kSegLen) {
+            seg_q0.push_back(q);
+            seg_row.push_back(t);
+        }
+    }
+    row_seg.push_back((int32_t)seg_q0.size());
+    d->n_seg = (int)seg_q0.size();
     KFBI_HIP(hipMemcpyAsync(cnt + 2 * (M + 1), off.data(), 2 * (M + 1) * sizeof(int), hipMemcpyHostToDevice, s));
 
     KFBI_TRY(dalloc(d, (void **)&d->edges, (size_t)te * sizeof(Edge)));
     KFBI_TRY(dalloc(d, (void **)&d->irr, (size_t)ti * sizeof(IrrNode)));
     KFBI_TRY(dalloc(d, (void **)&d->irr_row_ptr, (size_t)(d->n + 1) * sizeof(int32_t)));
     KFBI_TRY(dalloc(d, (void **)&d->irr_col, (size_t)ti * sizeof(int32_t)));
+    KFBI_TRY(dalloc(d, (void **)&d->row_order, order.size() * sizeof(int32_t)));
+    KFBI_HIP(hipMemcpyAsync(d->row_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KFBI_TRY(dalloc(d, (void **)&d->seg_q0, seg_q0.size() * sizeof(int32_t)));
+    KFBI_HIP(hipMemcpyAsync(d->seg_q0, seg_q0.data(), seg_q0.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KFBI_TRY(dalloc(d, (void **)&d->seg_row, seg_row.size() * sizeof(int32_t)));
+    KFBI_HIP(hipMemcpyAsync(d->seg_row, seg_row.data(), seg_row.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KFBI_TRY(dalloc(d, (void **)&d->row_seg, row_seg.size() * sizeof(int32_t)));
+    KFBI_HIP(hipMemcpyAsync(d->row_seg, row_seg.data(), row_seg.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KFBI_HIP(hipMalloc(&ex_map, nodes * sizeof(int32_t)));
     KFBI_HIP(hipMalloc(&ey_map, nodes * sizeof(int32_t)));
     KFBI_HIP(hipMalloc(&irr_list, (size_t)ti * sizeof(int32_t)));

@@ -36,7 +36,9 @@ struct GmCtl {
 
 namespace {
 
-constexpr int kGmThreads = 1024;
+constexpr int kGmThreads = 512;
+// dynamic LDS of the iteration kernel: the new vector and staged basis vectors
+constexpr size_t kGmIterLds = 131072;
 
 
 template <class T> struct WS;
@@ -52,6 +54,43 @@ __device__ inline T wave_sum(T v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += WS<T>::xr(v, o);
     return v;
+}
+
+// sixteen wavefront sums at once by a butterfly that halves the values per
+// lane at each exchange (8 + 4 + 2 + 1 + 2 exchanges instead of 16 x 6):
+// lane l returns the total of v[(l >> 2) & 15]
+template <class T>
+__device__ inline T wave_sum16(T (&v)[16], int lane) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const bool hi = lane & 32;
+        const T send = hi ? v[i] : v[i + 8];
+        const T keep = hi ? v[i + 8] : v[i];
+        v[i] = keep + WS<T>::xr(send, 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool hi = lane & 16;
+        const T send = hi ? v[i] : v[i + 4];
+        const T keep = hi ? v[i + 4] : v[i];
+        v[i] = keep + WS<T>::xr(send, 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const bool hi = lane & 8;
+        const T send = hi ? v[i] : v[i + 2];
+        const T keep = hi ? v[i + 2] : v[i];
+        v[i] = keep + WS<T>::xr(send, 8);
+    }
+    {
+        const bool hi = lane & 4;
+        const T send = hi ? v[0] : v[1];
+        const T keep = hi ? v[1] : v[0];
+        v[0] = keep + WS<T>::xr(send, 4);
+    }
+    v[0] += WS<T>::xr(v[0], 2);
+    v[0] += WS<T>::xr(v[0], 1);
+    return v[0];
 }
 
 // block-wide sum; every thread gets the result
@@ -227,8 +266,8 @@ constexpr int kWin = 16;
 
 template <class T>
 __device__ void corr_merged_block(const T *phi_lds, int Nb, int n_irr, const T *__restrict__ mcoef,
-                                  const int32_t *__restrict__ mbase, T *__restrict__ corr) {
-    for (int q = threadIdx.x; q < n_irr; q += blockDim.x) {
+                                  const int32_t *__restrict__ mbase, T *__restrict__ corr, int q_first = 0) {
+    for (int q = q_first + threadIdx.x; q < n_irr; q += blockDim.x) {
         const int b = mbase[q];
         T c[kWin];
 #pragma unroll
@@ -332,16 +371,19 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_start_res(GmCtl *ctl, const T
 //   update of column j and of the residual estimate, and the corrections of
 //   v_{j+1} for the next product.
 // All loads that do not depend on the done flag are issued before it is
-// tested; the extracted vector is parked in LDS so they cannot be deferred.
+// tested: the extracted vector and the first nvl basis vectors go to LDS
+// (dynamic LDS: (1 + nvl) * Nb elements), so each Gram-Schmidt sweep is one
+// pass of dot products, one block reduction for all of them and one update.
 template <class T, int EPT>
 __global__ __launch_bounds__(kGmThreads) void k_gm_iter(GmCtl *ctl, T *V, T *H, T *g, double *cs, T *sn, int Nb,
-                                                        int j_arg, int m, const T *__restrict__ ust,
+                                                        int j_arg, int m, int nvl, const T *__restrict__ ust,
                                                         const double *__restrict__ w6, const T *__restrict__ bop,
                                                         int n_irr, const T *__restrict__ mcoef,
                                                         const int32_t *__restrict__ mbase, T *corr) {
     extern __shared__ double dyn[];
     T *sw = reinterpret_cast<T *>(dyn);  // Nb: the new basis vector
-    __shared__ T red[16][8];
+    T *sV = sw + Nb;                     // nvl * Nb: v_0 .. v_{nvl-1}
+    __shared__ T red[kGmThreads / 64][65];
     __shared__ T hcol[72];
     __shared__ T hs[72];
     __shared__ T ssn[72];
@@ -359,6 +401,16 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_iter(GmCtl *ctl, T *V, T *H, 
         ssn[tid] = sn[tid];
     }
     if (tid == 0) sg = g[j];
+    const int nst = j + 1 < nvl ? j + 1 : nvl;
+    for (int q = tid; q < nst * Nb; q += kGmThreads) sV[q] = V[q];
+    // the first irregular node's correction window of this thread
+    T cpre[kWin];
+    int bpre = 0;
+    if (tid < n_irr) {
+        bpre = mbase[tid];
+#pragma unroll
+        for (int o = 0; o < kWin; ++o) cpre[o] = mcoef[(size_t)o * n_irr + tid];
+    }
     for (int k = tid; k < Nb; k += kGmThreads) sw[k] = extract_k(k, Nb, ust, w6, bop, vj);
     if (done_flag) return;
     __syncthreads();
@@ -368,42 +420,45 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_iter(GmCtl *ctl, T *V, T *H, 
         const int k = tid + e * kGmThreads;
         wl[e] = k < Nb ? sw[k] : zero<T>();
     }
-    // CGS2
+    // CGS2: h = V^H w, w -= V h, twice
     for (int pass = 0; pass < 2; ++pass) {
-        for (int i0 = 0; i0 <= j; i0 += 8) {
-            T part[8];
+        for (int i0 = 0; i0 <= j; i0 += 16) {
+            T part[16];
 #pragma unroll
-            for (int ii = 0; ii < 8; ++ii) part[ii] = zero<T>();
+            for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int idx = tid + e * kGmThreads;
                 if (idx < Nb) {
 #pragma unroll
-                    for (int ii = 0; ii < 8; ++ii)
-                        if (i0 + ii <= j) part[ii] += conjv(V[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+                    for (int ii = 0; ii < 16; ++ii)
+                        if (i0 + ii < nst) part[ii] += conjv(sV[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+#pragma unroll
+                    for (int ii = 0; ii < 16; ++ii)
+                        if (i0 + ii >= nst && i0 + ii <= j)
+                            part[ii] += conjv(V[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
                 }
             }
-#pragma unroll
-            for (int ii = 0; ii < 8; ++ii) {
-                T s = wave_sum(part[ii]);
-                if (lane == 0) red[wid][ii] = s;
-            }
-            __syncthreads();
-            if (tid < 8 && i0 + tid <= j) {
-                T s = zero<T>();
-                for (int q = 0; q < (kGmThreads >> 6); ++q) s += red[q][tid];
-                hs[i0 + tid] = s;
-                hcol[i0 + tid] = pass == 0 ? s : hcol[i0 + tid] + s;
-            }
-            __syncthreads();
+            const T sum = wave_sum16(part, lane);
+            const int ii = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && i0 + ii <= j) red[wid][i0 + ii] = sum;
         }
+        __syncthreads();
+        if (tid <= j) {
+            T sum = zero<T>();
+            for (int q = 0; q < (kGmThreads >> 6); ++q) sum += red[q][tid];
+            hs[tid] = sum;
+            hcol[tid] = pass == 0 ? sum : hcol[tid] + sum;
+        }
+        __syncthreads();
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int idx = tid + e * kGmThreads;
-            if (idx < Nb)
-                for (int i = 0; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+            if (idx < Nb) {
+                for (int i = 0; i < nst; ++i) wl[e] -= hs[i] * sV[(size_t)i * Nb + idx];
+                for (int i = nst; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+            }
         }
-        __syncthreads();
     }
     double s2 = 0.0;
 #pragma unroll
@@ -461,7 +516,19 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_iter(GmCtl *ctl, T *V, T *H, 
     }
     __syncthreads();
     if (tid <= j + 1) H[(size_t)tid * m + j] = hcol[tid];
-    if (!sdone) corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr);
+    if (!sdone) {
+        if (tid < n_irr) {
+            T acc = zero<T>();
+#pragma unroll
+            for (int o = 0; o < kWin; ++o) {
+                int idx = bpre + o;
+                if (idx >= Nb) idx -= Nb;
+                acc += cpre[o] * sw[idx];
+            }
+            corr[tid] = acc;
+        }
+        corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr, kGmThreads);
+    }
 }
 
 // end of a cycle: y = H^{-1} g on the leading j x j block, x += V y (and,
@@ -563,7 +630,8 @@ static int launch_arnoldi(kfbi_domain *d, GmPtrs &P, int Nb, hipStream_t s) {
     else if (ept <= 2) KFBI_ARN(2);
     else if (ept <= 4) KFBI_ARN(4);
     else if (ept <= 8) KFBI_ARN(8);
-    else KFBI_ARN(16);
+    else if (ept <= 16) KFBI_ARN(16);
+    else KFBI_ARN(32);
 #undef KFBI_ARN
     KFBI_CHECK_LAUNCH();
     prof_end(d, ps, KFBI_K_ARNOLDI, 0.0);
@@ -573,19 +641,34 @@ static int launch_arnoldi(kfbi_domain *d, GmPtrs &P, int Nb, hipStream_t s) {
 template <class T>
 static int launch_iter(kfbi_domain *d, GmPtrs &P, int Nb, int j, int m, hipStream_t s) {
     const int ept = (Nb + kGmThreads - 1) / kGmThreads;
-    const size_t lds = (size_t)Nb * sizeof(T);
+    // basis vectors staged in LDS: as many as fit beside the new vector in
+    // kGmIterLds bytes
+    const int jj0 = j < m - 1 ? j : m - 1;
+    int nvl = (int)(kGmIterLds / ((size_t)Nb * sizeof(T))) - 1;
+    if (nvl > jj0 + 1) nvl = jj0 + 1;
+    if (nvl < 0) nvl = 0;
+    const size_t lds = (size_t)(1 + nvl) * Nb * sizeof(T);
     const int ps = prof_begin(d);
 #define KFBI_ITER(E)                                                                                            \
-    k_gm_iter<T, E><<<1, kGmThreads, lds, s>>>(P.ctl, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn, Nb, j, m,     \
+    k_gm_iter<T, E><<<1, kGmThreads, lds, s>>>(P.ctl, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn, Nb, j, m, nvl, \
                                                (const T *)d->ust, d->w6, (const T *)d->bop, d->n_irr,            \
                                                (const T *)d->mcoef, d->mbase, (T *)d->corr)
     if (ept <= 1) KFBI_ITER(1);
     else if (ept <= 2) KFBI_ITER(2);
     else if (ept <= 4) KFBI_ITER(4);
-    else KFBI_ITER(8);
+    else if (ept <= 8) KFBI_ITER(8);
+    else KFBI_ITER(16);
 #undef KFBI_ITER
     KFBI_CHECK_LAUNCH();
-    prof_end(d, ps, KFBI_K_ARNOLDI, 0.0);
+    // algorithmic bytes: extraction inputs (six stencil values, weights and
+    // the five jump coefficients per point, v_j), both Gram-Schmidt sweeps
+    // over v_0..v_j, the new basis vector, the merged correction operator and
+    // the corrections written
+    const int jj = j < m - 1 ? j : m - 1;
+    const double es = (double)sizeof(T);
+    const double bytes = (double)Nb * (6.0 * es + 6.0 * 8.0 + 5.0 * es + es) + 2.0 * (jj + 1) * Nb * es +
+                         (double)Nb * es + (double)d->n_irr * (kWin * es + 4.0 + es);
+    prof_end(d, ps, KFBI_K_ARNOLDI, bytes);
     return KFBI_OK;
 }
 

@@ -205,15 +205,19 @@ __global__ void k_coef(int M, double kh2_re, double kh2_im, S *etab, S *elim, in
 // owning C consecutive rows (LANES*C >= n).
 //   phase A  the right-hand side rho_t = h^2 (rhat[t][k] + sum over the
 //            irregular nodes q of row t of corr[q] sin(pi i_q k / M)) is
-//            built in an LDS tile, threads over (row, mode) so that the MB
-//            threads of a row read the same correction entries and the
-//            dense rhat rows are read as MB-mode contiguous segments;
+//            built in an LDS tile: the dense part (or zero) as MB-mode
+//            contiguous row segments, then the sparse sums over segments of
+//            at most kSegLen nodes of one row (all MB modes at once, so each
+//            staged entry is read once), merged per row in a fixed order;
 //   phase B  forward / backward recurrences as chunked affine scans with
 //            wavefront shuffles, in place in the tile;
 //   phase C  the tile is written out as contiguous MB-mode row segments.
 // The tile index is t*MB + m + t/C: one element of padding per chunk keeps
 // the lanes of phase B (stride C rows) off a single LDS bank.
 // ---------------------------------------------------------------------------
+// LDS per workgroup on gfx950: 160 KB
+constexpr size_t kTriLdsMax = 163840;
+
 template <int MB, int C>
 __device__ inline int tidx(int t, int m) {
     return t * MB + m + t / C;
@@ -221,89 +225,176 @@ __device__ inline int tidx(int t, int m) {
 
 // T: the solve precision (double / cd, or float / cf for the mixed mode);
 // the corrections arrive in FP64 (TC) and are rounded once when staged.
-template <class T, class TC, int MB, int LANES, int C>
+// STAGE: the sparse right-hand side and its segment tables are copied to
+// LDS first; otherwise they are read from global memory.
+struct TriSparse {
+    const int32_t *irr_col, *row_ptr, *row_order, *seg_q0, *seg_row, *row_seg;
+    int nnz, n_act, n_seg;
+};
+
+template <class T, class TC, int MB, int LANES, int C, bool STAGE>
 __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T *__restrict__ rhat,
-                                                       const TC *__restrict__ corr,
-                                                       const int32_t *__restrict__ irr_col,
-                                                       const int32_t *__restrict__ row_ptr,
+                                                       const TC *__restrict__ corr, TriSparse sp,
+                                                       const typename Real<T>::type *__restrict__ sine,
                                                        const T *__restrict__ etab, const T *__restrict__ elim,
                                                        const int32_t *__restrict__ tconv, T *__restrict__ uhat,
-                                                       const int *__restrict__ done, int nnz, int stage) {
+                                                       const int *__restrict__ done) {
     typedef typename Real<T>::type R;
     extern __shared__ double lds[];
     constexpr int NT = MB * LANES;
     const int n = M - 1;
     const int mask2M = 2 * M - 1;
     if (done && *done) return;
+    const int nnz = sp.nnz, n_act = sp.n_act, n_seg = sp.n_seg;
     R *S = reinterpret_cast<R *>(lds);                   // 2M sine values
     T *tile = reinterpret_cast<T *>(lds + 2 * M);       // n*MB + n/C + 1
     const int tile_len = n * MB + n / C + 1;
-    // staged sparse right-hand side: row pointers, values, columns
-    int32_t *srp = reinterpret_cast<int32_t *>(tile + tile_len);
-    T *sval = reinterpret_cast<T *>(srp + ((n + 1 + 3) & ~3));
-    int32_t *scol = reinterpret_cast<int32_t *>(sval + (stage ? nnz : 0));
+    T *spart = tile + tile_len;                          // n_seg*MB partial sums
+    // staged sparse right-hand side: values, columns, row pointers, row
+    // order, segment tables
+    T *sval = spart + (corr ? n_seg * MB : 0);
+    int32_t *scol = reinterpret_cast<int32_t *>(sval + (STAGE ? nnz : 0));
+    int32_t *srp = scol + (STAGE ? nnz : 0);
+    int32_t *srow = srp + (STAGE ? n + 1 : 0);
+    int32_t *ssq0 = srow + (STAGE ? n_act : 0);
+    int32_t *ssrow = ssq0 + (STAGE ? n_seg : 0);
+    int32_t *srseg = ssrow + (STAGE ? n_seg : 0);
     const int k0 = blockIdx.x * MB;
-    // the sine table is computed in place (same expression as the domain's
-    // table) instead of being fetched: no global round trip before phase A
-    for (int q = threadIdx.x; q < 2 * M; q += NT) S[q] = (R)sinpi((double)q / (double)M);
-    if (corr && stage) {
-        for (int q = threadIdx.x; q <= n; q += NT) srp[q] = row_ptr[q];
-        for (int q = threadIdx.x; q < nnz; q += NT) {
-            sval[q] = Conv<T>::from(corr[q]);
-            scol[q] = irr_col[q];
-        }
-    }
-    __syncthreads();
-    // phase A
-    for (int p = threadIdx.x; p < n * MB; p += NT) {
-        const int t = p / MB, m = p - t * MB;
-        const int k = k0 + m;
-        T r = zero<T>();
-        if (k < n) {
-            if (rhat) r = rhat[(size_t)t * n + k];
-            if (corr) {
-                const int mode = k + 1;
-                if (stage) {
-                    const int q1 = srp[t + 1];
-                    T r2 = zero<T>();
-                    int q = srp[t];
-                    for (; q + 1 < q1; q += 2) {  // two independent chains
-                        r += sval[q] * S[(scol[q] * mode) & mask2M];
-                        r2 += sval[q + 1] * S[(scol[q + 1] * mode) & mask2M];
-                    }
-                    if (q < q1) r += sval[q] * S[(scol[q] * mode) & mask2M];
-                    r += r2;
-                } else {
-                    const int q1 = row_ptr[t + 1];
-                    for (int q = row_ptr[t]; q < q1; ++q)
-                        r += Conv<T>::from(corr[q]) * S[(irr_col[q] * mode) & mask2M];
-                }
-            }
-        }
-        tile[tidx<MB, C>(t, m)] = r * (R)h2;
-    }
-    __syncthreads();
-    // phase B
     const int lane = threadIdx.x % LANES;
     const int m = threadIdx.x / LANES;
     const int k = k0 + m;
     const int t0 = lane * C;
+    int tc = 0;
+    T lim = zero<T>();
     if (k < n) {
-        const int tc = tconv[k];
-        const T lim = elim[k];
-        T e[C];
+        tc = tconv[k];
+        lim = elim[k];
+    }
+    // sine table and staging: loads batched so that several are in flight
+    for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * NT) {
+        R v[4];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int t = t0 + c;
-            e[c] = (t < tc && t < n) ? etab[(size_t)t * n + k] : lim;
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u * NT < 2 * M) v[u] = sine[q0 + u * NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u * NT < 2 * M) S[q0 + u * NT] = v[u];
+    }
+    if (STAGE && corr) {
+        for (int q0 = threadIdx.x; q0 < nnz; q0 += 4 * NT) {
+            TC v[4];
+            int32_t c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * NT;
+                if (q < nnz) {
+                    v[u] = corr[q];
+                    c[u] = sp.irr_col[q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * NT;
+                if (q < nnz) {
+                    sval[q] = Conv<T>::from(v[u]);
+                    scol[q] = c[u];
+                }
+            }
         }
+        for (int q = threadIdx.x; q <= n; q += NT) srp[q] = sp.row_ptr[q];
+        for (int q = threadIdx.x; q < n_seg; q += NT) {
+            ssq0[q] = sp.seg_q0[q];
+            ssrow[q] = sp.seg_row[q];
+        }
+        for (int q = threadIdx.x; q < n_act; q += NT) {
+            srow[q] = sp.row_order[q];
+            srseg[q] = sp.row_seg[q];
+        }
+        if (threadIdx.x == 0) srseg[n_act] = sp.row_seg[n_act];
+    }
+    // dense part (or zero) of the right-hand side
+    for (int p = threadIdx.x; p < n * MB; p += NT) {
+        const int t = p / MB, mm = p - t * MB;
+        tile[tidx<MB, C>(t, mm)] = (rhat && k0 + mm < n) ? rhat[(size_t)t * n + k0 + mm] : zero<T>();
+    }
+    __syncthreads();
+    // Thomas coefficients of phase B: loads in flight during phase A
+    T e[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int t = t0 + c;
+        e[c] = (t < tc && t < n) ? etab[(size_t)t * n + k] : lim;
+    }
+    // phase A: sparse sums.  Each thread sums one segment (at most kSegLen
+    // irregular nodes of one row) for all MB modes; four nodes per step keep
+    // several LDS round trips in flight.  Then one thread per row adds its
+    // segments' partial sums in order, so the result does not depend on
+    // the schedule.
+    if (corr) {
+        for (int sg = threadIdx.x; sg < n_seg; sg += NT) {
+            const int t = STAGE ? ssrow[sg] : sp.seg_row[sg];
+            int q = STAGE ? ssq0[sg] : sp.seg_q0[sg];
+            const int rend = STAGE ? srp[t + 1] : sp.row_ptr[t + 1];
+            const int q1 = q + kSegLen < rend ? q + kSegLen : rend;
+            T acc[MB];
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) acc[mm] = zero<T>();
+            for (; q + 4 <= q1; q += 4) {
+                T cv[4];
+                int col[4], idx[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    cv[u] = STAGE ? sval[q + u] : Conv<T>::from(corr[q + u]);
+                    col[u] = STAGE ? scol[q + u] : sp.irr_col[q + u];
+                    idx[u] = (col[u] * (k0 + 1)) & mask2M;
+                }
+#pragma unroll
+                for (int mm = 0; mm < MB; ++mm) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        acc[mm] += cv[u] * S[idx[u]];
+                        idx[u] = (idx[u] + col[u]) & mask2M;
+                    }
+                }
+            }
+            for (; q < q1; ++q) {
+                const T cv = STAGE ? sval[q] : Conv<T>::from(corr[q]);
+                const int col = STAGE ? scol[q] : sp.irr_col[q];
+                int idx = (col * (k0 + 1)) & mask2M;
+#pragma unroll
+                for (int mm = 0; mm < MB; ++mm) {
+                    acc[mm] += cv * S[idx];
+                    idx = (idx + col) & mask2M;
+                }
+            }
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) spart[sg * MB + mm] = acc[mm];
+        }
+        __syncthreads();
+        for (int a = threadIdx.x; a < n_act; a += NT) {
+            const int t = STAGE ? srow[a] : sp.row_order[a];
+            const int s0 = STAGE ? srseg[a] : sp.row_seg[a];
+            const int s1 = STAGE ? srseg[a + 1] : sp.row_seg[a + 1];
+            T acc[MB];
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) acc[mm] = spart[s0 * MB + mm];
+            for (int sg = s0 + 1; sg < s1; ++sg)
+#pragma unroll
+                for (int mm = 0; mm < MB; ++mm) acc[mm] += spart[sg * MB + mm];
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) tile[tidx<MB, C>(t, mm)] += acc[mm];
+        }
+    }
+    __syncthreads();
+    // phase B
+    if (k < n) {
         // the lane's rows in registers for all four passes (rows past n: 0 with
         // e = 0, which leaves every composite unchanged)
         T v[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const bool ok = t0 + c < n;
-            v[c] = ok ? tile[tidx<MB, C>(t0 + c, m)] : zero<T>();
+            v[c] = ok ? tile[tidx<MB, C>(t0 + c, m)] * (R)h2 : zero<T>();
             if (!ok) e[c] = zero<T>();
         }
         T A = one<T>(), B = zero<T>();
@@ -417,39 +508,55 @@ template <class T>
 int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
     const int M = d->M, n = M - 1;
     const double h2 = d->h * d->h;
-    // modes per workgroup: the largest power of two (<= 8) whose LDS tile
-    // stays within 32 KB; eight modes use 32-lane groups, fewer use 64
+    // modes per workgroup: the largest power of two (<= 4) whose LDS tile
+    // stays within 32 KB (a domain may fix it); eight modes use 32-lane
+    // groups, fewer use 64
     int mb = d->tri_mb;
     if (mb <= 0) {
-        mb = 8;
+        mb = 4;
         while (mb > 1 && (size_t)n * mb * sizeof(T) > 32768) mb >>= 1;
     }
     const int lanes = mb == 8 ? 32 : 64;
     int c = 1;
     while (lanes * c < n) c <<= 1;
     const int blocks = (n + mb - 1) / mb;
-    size_t lds = (size_t)2 * M * sizeof(double) + ((size_t)n * mb + n / c + 1) * sizeof(T) +
-                 (size_t)((n + 1 + 3) & ~3) * sizeof(int32_t);
-    if (c > 32 || lds > 65536) {
+    size_t lds = (size_t)2 * M * sizeof(double) + ((size_t)n * mb + n / c + 1) * sizeof(T);
+    if (corr) lds += (size_t)d->n_seg * mb * sizeof(T);
+    if (c > 32 || lds > kTriLdsMax) {
         set_error("grid too large for the tridiagonal kernel");
         return KFBI_ENOTSUP;
     }
-    // stage the sparse right-hand side in LDS when it fits the 64 KB budget
-    const int nnz = d->n_irr;
-    int stage = 0;
-    if (corr && lds + (size_t)nnz * (sizeof(T) + sizeof(int32_t)) <= 65536) {
-        stage = 1;
-        lds += (size_t)nnz * (sizeof(T) + sizeof(int32_t));
-    }
+    // stage the sparse right-hand side in LDS when it fits
+    TriSparse sp;
+    sp.irr_col = d->irr_col;
+    sp.row_ptr = d->irr_row_ptr;
+    sp.row_order = d->row_order;
+    sp.seg_q0 = d->seg_q0;
+    sp.seg_row = d->seg_row;
+    sp.row_seg = d->row_seg;
+    sp.nnz = d->n_irr;
+    sp.n_act = d->n_act_rows;
+    sp.n_seg = d->n_seg;
+    const size_t stage_bytes = (size_t)sp.nnz * (sizeof(T) + sizeof(int32_t)) +
+                               (size_t)(n + 1 + 2 * sp.n_act + 1 + 2 * sp.n_seg) * sizeof(int32_t);
+    const bool stage = corr && lds + stage_bytes <= kTriLdsMax;
+    if (stage) lds += stage_bytes;
     typedef typename High<T>::type TC;
+    typedef typename Real<T>::type R;
     const bool low = sizeof(T) < sizeof(TC);
     const T *etab = (const T *)(low ? d->etab32 : d->etab);
     const T *elim = (const T *)(low ? d->elim32 : d->elim);
     const int32_t *tconv = low ? d->tconv32 : d->tconv;
-#define KFBI_TRI(MBv, Lv, CC)                                                                        \
-    k_tridiag<T, TC, MBv, Lv, CC><<<blocks, MBv * Lv, lds, d->stream>>>(                             \
-        M, h2, (const T *)rhat, (const TC *)corr, d->irr_col, d->irr_row_ptr, etab, elim, tconv, (T *)uhat, \
-        done, nnz, stage)
+    const R *sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+#define KFBI_TRI(MBv, Lv, CC)                                                                                 \
+    do {                                                                                                      \
+        if (stage)                                                                                            \
+            k_tridiag<T, TC, MBv, Lv, CC, true><<<blocks, MBv * Lv, lds, d->stream>>>(                        \
+                M, h2, (const T *)rhat, (const TC *)corr, sp, sine, etab, elim, tconv, (T *)uhat, done);      \
+        else                                                                                                  \
+            k_tridiag<T, TC, MBv, Lv, CC, false><<<blocks, MBv * Lv, lds, d->stream>>>(                       \
+                M, h2, (const T *)rhat, (const TC *)corr, sp, sine, etab, elim, tconv, (T *)uhat, done);      \
+    } while (0)
 #define KFBI_TRI_C(MBv, Lv)                 \
     switch (c) {                            \
         case 1: KFBI_TRI(MBv, Lv, 1); break;   \

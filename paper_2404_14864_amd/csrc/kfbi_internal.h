@@ -11,6 +11,9 @@
 
 namespace kfbi {
 
+// irregular nodes per segment of the sparse right-hand side build
+constexpr int kSegLen = 8;
+
 // ---------------------------------------------------------------------------
 // scalar types: real double, and an interleaved complex double that matches
 // torch's complex128 layout.
@@ -186,6 +189,17 @@ struct kfbi_domain {
     kfbi::IrrNode *irr = nullptr;       // n_irr, sorted by linear index
     int32_t *irr_row_ptr = nullptr;     // n+1: irregular nodes of interior row t (j = t+1)
     int32_t *irr_col = nullptr;         // n_irr: x index i of each irregular node
+    int32_t *row_order = nullptr;       // n_act_rows: interior rows holding irregular nodes,
+                                        // by decreasing node count
+    int n_act_rows = 0;
+    // the irregular nodes of each such row cut into segments of at most
+    // kSegLen consecutive nodes: first node seg_q0[s] and row seg_row[s]
+    // (a segment ends after kSegLen nodes or at its row's end) and, per row
+    // of row_order, its first segment row_seg[a] (n_act_rows + 1 entries)
+    int32_t *seg_q0 = nullptr;
+    int32_t *seg_row = nullptr;
+    int32_t *row_seg = nullptr;
+    int n_seg = 0;
     kfbi::Colloc *col = nullptr;        // Nb
     kfbi::Stencil *st = nullptr;        // Nb
     double *sine = nullptr;             // 2M: sin(pi m / M)
