@@ -28,6 +28,10 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (profiles/), filled in when the kernel has been counted at its
+# current version; None otherwise
+TRAFFIC = {}
 
 
 def parse():
@@ -39,6 +43,7 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--replay", type=int, default=200)
     return ap.parse_args()
 
 
@@ -123,16 +128,23 @@ def main():
     torch.cuda.synchronize()
     log("warmup done (%d steps)" % args.warmup)
 
-    lat, iters = [], []
+    # timed region: each call returns once GMRES has finished on the device
+    # (its final grid solve still queued), so the host enqueues the next
+    # step while the device completes this one; per-step device latency from
+    # HIP events on the domain's stream
+    aopts = {"async": True}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ts = time.perf_counter()
-        s = kfbi.kfbi_step_wave(st, g_all[args.warmup + k], u)
-        lat.append(time.perf_counter() - ts)
+        ev[k].record()
+        s = kfbi.kfbi_step_wave(st, g_all[args.warmup + k], u, opts=aopts)
         iters.append(s["iters"])
+    ev[args.steps].record()
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
+    lat = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(args.steps)]
     log("timed %d steps in %.3f s, %d GMRES iterations" % (args.steps, T, sum(iters)))
     U = u.cpu().numpy().reshape(M + 1, M + 1)
     finite = bool(np.all(np.isfinite(U)))
@@ -146,17 +158,19 @@ def main():
     for n in range(args.warmup):
         kfbi.kfbi_step_wave(st, g_all[n], u, opts=mopts)
     kfbi.kfbi_stepper_init(st, *init)
-    mlat, miters, mref = [], [], []
+    miters, mref = [], []
+    mopts_async = dict(mopts, **aopts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ts = time.perf_counter()
-        s = kfbi.kfbi_step_wave(st, g_all[k], u, opts=mopts)
-        mlat.append(time.perf_counter() - ts)
+        ev[k].record()
+        s = kfbi.kfbi_step_wave(st, g_all[k], u, opts=mopts_async)
         miters.append(s["iters"])
         mref.append(s["refinements"])
+    ev[args.steps].record()
     torch.cuda.synchronize()
     Tm = time.perf_counter() - t0
+    mlat = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(args.steps)]
     # FP64 reference of the same steps for the agreement figure
     Um = u.cpu().numpy().reshape(M + 1, M + 1)
     kfbi.kfbi_stepper_init(st, *init)
@@ -179,12 +193,23 @@ def main():
     kfbi.kfbi_profile_enable(dom, False)
     kdom = max(prof, key=lambda k: prof[k]["total_ms"])
     p = prof[kdom]
-    avg_ms = p["total_ms"] / max(p["launches"], 1)
-    achieved = p["bytes"] / max(p["launches"], 1) / (avg_ms * 1e-3) / 1e9
-    breakdown = {k: {"launches": v["launches"], "avg_us": 1e3 * v["total_ms"] / max(v["launches"], 1),
+    breakdown = {k: {"launches": v["launches"], "avg_us_events": 1e3 * v["total_ms"] / max(v["launches"], 1),
                      "share": v["total_ms"] / max(sum(q["total_ms"] for q in prof.values()), 1e-30)}
                  for k, v in prof.items() if v["launches"]}
-    log("dominant kernel %s: %d launches, avg %.2f us" % (kdom, p["launches"], 1e3 * avg_ms))
+    # launch duration of the dominant kernel: back-to-back replay between two
+    # HIP events where the kernel is idempotent (the grid-solve kernels),
+    # else the per-launch event average (which includes the event overhead)
+    if kdom in ("tridiag_sparse", "tridiag_dense", "eval_nodes"):
+        avg_ms, bytes_launch = kfbi.kfbi_profile_replay(dom, kdom, args.replay)
+        timing = "replay of %d back-to-back launches between two HIP events" % args.replay
+    else:
+        avg_ms = p["total_ms"] / max(p["launches"], 1)
+        bytes_launch = p["bytes"] / max(p["launches"], 1)
+        timing = "HIP events around each launch in %d profiled steps" % np_steps
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    # the grid solve of a matrix-vector product, the kernel the HBM target is about
+    gs_ms, gs_bytes = kfbi.kfbi_profile_replay(dom, "tridiag_sparse", args.replay)
+    log("dominant kernel %s: %d launches, avg %.2f us (%s)" % (kdom, p["launches"], 1e3 * avg_ms, timing))
 
     kfbi.kfbi_stepper_destroy(st)
     kfbi.kfbi_domain_destroy(dom)
@@ -214,17 +239,23 @@ def main():
                    "precision": "fp64", "parallelism": "single GPU"},
         "p50_step_ms": float(np.percentile(lat_ms, 50)),
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "latency": "device time per step from HIP events on the domain stream",
         "gmres_iters_per_step": float(np.mean(iters)),
         "solution_finite": finite,
         "roofline": {"bound": "hbm", "kernel": kdom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": 1e3 * avg_ms,
-                     "bytes_per_launch": p["bytes"] / max(p["launches"], 1),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get(kdom),
+                     "avg_launch_us": 1e3 * avg_ms, "bytes_per_launch": bytes_launch, "timing": timing,
                      "profiled_steps": np_steps},
+        "grid_solve_roofline": {"kernel": "tridiag_sparse", "avg_launch_us": 1e3 * gs_ms,
+                                "bytes_per_launch": gs_bytes,
+                                "achieved": gs_bytes / (gs_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": gs_bytes / (gs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                "timing": "replay of %d back-to-back launches between two HIP events" % args.replay},
         "kernels": breakdown,
         "mixed_precision": {"value": pts * sum(miters) / Tm, "ms_per_step": 1e3 * Tm / args.steps,
                             "p50_step_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
                             "p99_step_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
+                            "latency": "device time per step from HIP events",
                             "gmres_iters_per_step": float(np.mean(miters)),
                             "refinements_per_step": float(np.mean(mref)),
                             "grid_solve": "fp32", "refinement": "fp64",

@@ -99,7 +99,17 @@ typedef struct {
     int32_t restart;      /* GMRES restart length m, 1..64; default 50             */
     int32_t fixed_iters;  /* > 0: run exactly this many iterations (parity mode)   */
     int32_t precision;    /* -1: the domain's default; else kfbi_precision         */
+    int32_t flags;        /* KFBI_SOLVE_* bits; 0 by default                       */
+    int32_t pad;
 } kfbi_solve_opts;
+
+/* kfbi_solve_opts.flags: return as soon as GMRES has finished on the device.
+ * The final grid solve (u_grid_out, phi_inout) and the stepper's right-hand
+ * side update are then still queued on the domain stream: they complete in
+ * stream order before any later work on that stream, and the host must
+ * synchronise the stream before reading them.  stats are valid on return
+ * except device_ms, which is -1. */
+#define KFBI_SOLVE_ASYNC 1
 
 typedef struct {
     int32_t iters;        /* GMRES iterations (matrix-vector products in Arnoldi) */
@@ -203,6 +213,21 @@ int kfbi_stepper_init(kfbi_stepper *st, const void *u0_grid, const void *lap_u0_
                       const void *uprev_grid, const void *lap_uprev_grid,
                       const void *uprev_gamma, const void *lap_uprev_gamma);
 
+/* Checkpoint and restart of a stepper.  The state of the time scheme is the
+ * carried right-hand-side term of its recurrence on the grid and on Gamma
+ * (heat: G, eq. 3.4; wave: F^{n+1} and F^n, the recurrence after eq. 3.7;
+ * Schroedinger: u*, the algorithm after eq. 3.12) plus the density of the
+ * last solve, which warm-starts the next one.  The blob is opaque: a 64-byte
+ * header (equation, M, Nb, scalar type, tau, kappa) followed by those arrays
+ * in the domain's element type.  dst / src are caller-owned device buffers
+ * of at least kfbi_stepper_state_bytes() bytes.  get_state and set_state
+ * synchronise the domain stream.  set_state accepts only a blob written by
+ * a stepper with the same equation, grid, collocation count, scalar type and
+ * kappa (else KFBI_EINVAL). */
+int kfbi_stepper_state_bytes(const kfbi_stepper *st, uint64_t *bytes);
+int kfbi_stepper_get_state(kfbi_stepper *st, void *dst, uint64_t bytes);
+int kfbi_stepper_set_state(kfbi_stepper *st, const void *src, uint64_t bytes);
+
 /* One Crank-Nicolson step t^n -> t^{n+1} (eqs. 3.2-3.4): g_next is u on
  * Gamma at t^{n+1}; src_grid / src_gamma (nullable) hold s^n + s^{n+1}.
  * u_grid_out receives u^{n+1}. */
@@ -220,8 +245,10 @@ int kfbi_step_schrodinger(kfbi_stepper *st, const void *g_next_gamma, void *u_gr
 
 /* Per-kernel device timing (instrumentation for benchmarks).  When enabled,
  * every launch of the listed kernels of this domain is bracketed by two HIP
- * events on the domain stream; launches inside a GMRES chunk that found the
- * solve already finished are not counted.  kfbi_profile_enable(dom, 1)
+ * events on the domain stream; launches after the solve had finished on the
+ * device are not counted (in the mixed-precision schedule the grid-solve
+ * launches of the precision a slot did not use are counted as launches of
+ * near-zero length).  kfbi_profile_enable(dom, 1)
  * resets the counters; kfbi_profile_read waits for the outstanding events
  * and fills KFBI_K_COUNT entries: launches, summed event time and summed
  * algorithmic bytes (the bytes the kernel must move by design: its dense
@@ -245,6 +272,20 @@ typedef struct {
 
 int kfbi_profile_enable(kfbi_domain *dom, int32_t on);
 int kfbi_profile_read(kfbi_domain *dom, kfbi_kernel_prof *out);
+
+/* Replay timing: `reps` back-to-back launches of one FP64 grid-solve kernel
+ * of this domain on its current internal buffers, between two HIP events on
+ * the domain stream; writes the average launch duration (ms) and the
+ * algorithmic bytes of one launch.  kind: KFBI_K_TRIDIAG_SPARSE (corrections
+ * -> mode-space solution), KFBI_K_TRIDIAG_DENSE (dense right-hand side ->
+ * mode-space solution) or KFBI_K_EVAL_NODES (mode-space solution -> stencil
+ * values).  Needs a completed solve on the domain (it reuses the last
+ * kappa's coefficients and the last solve's data); overwrites the domain's
+ * internal scratch only.  Blocks until the launches have finished.
+ * Errors: KFBI_EINVAL (null pointer, reps outside 1..100000, other kind, no
+ * solve yet). */
+int kfbi_profile_replay(kfbi_domain *dom, int32_t kind, int32_t reps, double *avg_ms,
+                        double *bytes_per_launch);
 
 #ifdef __cplusplus
 }

@@ -72,10 +72,10 @@ void prof_end(kfbi_domain *d, int slot, int kind, double bytes) {
     (void)hipEventRecord(s.b, d->stream);
 }
 
-int prof_flush(kfbi_domain *d, int keep_tags_below) {
+int prof_flush(kfbi_domain *d, int keep_tags_below, int keep_tag) {
     for (auto &s : d->prof_live) {
         KFBI_HIP(hipEventSynchronize(s.b));
-        if (s.kind >= 0 && (s.tag < 0 || s.tag < keep_tags_below)) {
+        if (s.kind >= 0 && (s.tag < 0 || s.tag < keep_tags_below || s.tag == keep_tag)) {
             float ms = 0.f;
             KFBI_HIP(hipEventElapsedTime(&ms, s.a, s.b));
             d->prof_count[s.kind] += 1;
@@ -217,6 +217,55 @@ int kfbi_profile_enable(kfbi_domain *d, int32_t on) {
     return KFBI_OK;
 }
 
+int kfbi_profile_replay(kfbi_domain *d, int32_t kind, int32_t reps, double *avg_ms, double *bytes_per_launch) {
+    if (!d || !avg_ms || !bytes_per_launch) { set_error("null argument"); return KFBI_EINVAL; }
+    if (reps < 1 || reps > 100000) { set_error("reps must be in 1..100000"); return KFBI_EINVAL; }
+    if (kind != KFBI_K_TRIDIAG_SPARSE && kind != KFBI_K_TRIDIAG_DENSE && kind != KFBI_K_EVAL_NODES) {
+        set_error("replay supports the tridiagonal and stencil-evaluation kernels only");
+        return KFBI_EINVAL;
+    }
+    if (!d->coef_valid) { set_error("no solve has run on this domain"); return KFBI_EINVAL; }
+    auto launch = [&]() -> int {
+        if (kind == KFBI_K_TRIDIAG_SPARSE) return tridiag_solve(d, nullptr, d->corr, d->uhat);
+        if (kind == KFBI_K_TRIDIAG_DENSE) return tridiag_solve(d, d->rhat, d->corr, d->uhat);
+        return eval_stencil_nodes(d, d->uhat, d->ust);
+    };
+    // algorithmic bytes of one launch, through the profiler's own accounting
+    KFBI_TRY(prof_flush(d, 1 << 30));
+    const bool was_on = d->prof_on;
+    const int64_t c0 = d->prof_count[kind];
+    const double m0 = d->prof_ms[kind], b0 = d->prof_bytes[kind];
+    d->prof_on = true;
+    const int st = launch();
+    d->prof_on = was_on;
+    KFBI_TRY(st);
+    KFBI_TRY(prof_flush(d, 1 << 30));
+    *bytes_per_launch = d->prof_bytes[kind] - b0;
+    d->prof_count[kind] = c0;
+    d->prof_ms[kind] = m0;
+    d->prof_bytes[kind] = b0;
+    // timing: reps launches between two events
+    hipEvent_t e0, e1;
+    KFBI_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); set_error("hipEventCreate failed"); return KFBI_EDEVICE; }
+    int rc = KFBI_OK;
+    const bool was_on2 = d->prof_on;
+    d->prof_on = false;
+    if (hipEventRecord(e0, d->stream) != hipSuccess) rc = KFBI_EDEVICE;
+    for (int r = 0; r < reps && rc == KFBI_OK; ++r) rc = launch();
+    if (rc == KFBI_OK && hipEventRecord(e1, d->stream) != hipSuccess) rc = KFBI_EDEVICE;
+    if (rc == KFBI_OK && hipEventSynchronize(e1) != hipSuccess) rc = KFBI_EDEVICE;
+    float ms = 0.f;
+    if (rc == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = KFBI_EDEVICE;
+    d->prof_on = was_on2;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc == KFBI_EDEVICE) set_error("HIP event or launch failure during replay");
+    if (rc != KFBI_OK) return rc;
+    *avg_ms = ms / reps;
+    return KFBI_OK;
+}
+
 int kfbi_profile_read(kfbi_domain *d, kfbi_kernel_prof *out) {
     if (!d || !out) { set_error("null argument"); return KFBI_EINVAL; }
     KFBI_TRY(prof_flush(d, 1 << 30));
@@ -234,6 +283,7 @@ int kfbi_domain_destroy(kfbi_domain *d) {
     else hipDeviceSynchronize();
     for (auto &s : d->prof_live) { hipEventDestroy(s.a); hipEventDestroy(s.b); }
     for (hipEvent_t e : d->prof_pool) hipEventDestroy(e);
+    if (d->mirror_host) hipHostFree(d->mirror_host);
     if (d->ev0) hipEventDestroy(d->ev0);
     if (d->ev1) hipEventDestroy(d->ev1);
     for (void *p : d->allocs) hipFree(p);
@@ -370,6 +420,83 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
     if (st == KFBI_OK && hipMemsetAsync(s->phi, 0, Nb * es, d->stream) != hipSuccess) st = KFBI_EDEVICE;
     if (st != KFBI_OK) { kfbi_stepper_destroy(s); return st; }
     *out = s;
+    return KFBI_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t eq, M, Nb, cplx, initialized, pad;
+    double tau, kre, kim, pad2;
+};
+static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
+constexpr uint32_t kStateMagic = 0x5346424bu;  // "KBFS"
+
+size_t state_bytes(const kfbi_stepper *s) {
+    const kfbi_domain *d = s->dom;
+    const size_t es = elem_size(d), nodes = (size_t)(d->M + 1) * (d->M + 1), Nb = d->Nb;
+    return sizeof(StateHeader) + 2 * nodes * es + 3 * Nb * es;
+}
+}  // namespace
+
+int kfbi_stepper_state_bytes(const kfbi_stepper *s, uint64_t *bytes) {
+    if (!s || !bytes) { set_error("null argument"); return KFBI_EINVAL; }
+    *bytes = state_bytes(s);
+    return KFBI_OK;
+}
+
+int kfbi_stepper_get_state(kfbi_stepper *s, void *dst, uint64_t bytes) {
+    if (!s || !dst) { set_error("null argument"); return KFBI_EINVAL; }
+    if (bytes < state_bytes(s)) { set_error("state buffer too small"); return KFBI_EINVAL; }
+    kfbi_domain *d = s->dom;
+    const size_t es = elem_size(d), nodes = (size_t)(d->M + 1) * (d->M + 1), Nb = d->Nb;
+    StateHeader h{};
+    h.magic = kStateMagic;
+    h.version = 1;
+    h.eq = s->eq;
+    h.M = d->M;
+    h.Nb = d->Nb;
+    h.cplx = d->cplx ? 1 : 0;
+    h.initialized = s->initialized ? 1 : 0;
+    h.tau = s->p.tau;
+    h.kre = s->kre;
+    h.kim = s->kim;
+    char *p = (char *)dst;
+    KFBI_HIP(hipMemcpyAsync(p, &h, sizeof(h), hipMemcpyHostToDevice, d->stream));
+    p += sizeof(h);
+    const void *parts[5] = {s->A, s->B, s->Ag, s->Bg, s->phi};
+    const size_t sizes[5] = {nodes * es, nodes * es, Nb * es, Nb * es, Nb * es};
+    for (int q = 0; q < 5; ++q) {
+        KFBI_HIP(hipMemcpyAsync(p, parts[q], sizes[q], hipMemcpyDeviceToDevice, d->stream));
+        p += sizes[q];
+    }
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    return KFBI_OK;
+}
+
+int kfbi_stepper_set_state(kfbi_stepper *s, const void *src, uint64_t bytes) {
+    if (!s || !src) { set_error("null argument"); return KFBI_EINVAL; }
+    if (bytes < state_bytes(s)) { set_error("state buffer too small"); return KFBI_EINVAL; }
+    kfbi_domain *d = s->dom;
+    const size_t es = elem_size(d), nodes = (size_t)(d->M + 1) * (d->M + 1), Nb = d->Nb;
+    StateHeader h{};
+    KFBI_HIP(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    if (h.magic != kStateMagic || h.version != 1) { set_error("not a stepper state blob"); return KFBI_EINVAL; }
+    if (h.eq != s->eq || h.M != d->M || h.Nb != d->Nb || h.cplx != (d->cplx ? 1 : 0) || h.kre != s->kre ||
+        h.kim != s->kim) {
+        set_error("state blob belongs to a different stepper configuration");
+        return KFBI_EINVAL;
+    }
+    const char *p = (const char *)src + sizeof(h);
+    void *parts[5] = {s->A, s->B, s->Ag, s->Bg, s->phi};
+    const size_t sizes[5] = {nodes * es, nodes * es, Nb * es, Nb * es, Nb * es};
+    for (int q = 0; q < 5; ++q) {
+        KFBI_HIP(hipMemcpyAsync(parts[q], p, sizes[q], hipMemcpyDeviceToDevice, d->stream));
+        p += sizes[q];
+    }
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    s->initialized = h.initialized != 0;
     return KFBI_OK;
 }
 

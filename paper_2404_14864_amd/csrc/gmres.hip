@@ -16,7 +16,9 @@
 // basis as modified Gram-Schmidt up to rounding.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
+#include <string>
 #include <cstring>
 #include <vector>
 
@@ -27,11 +29,30 @@ namespace kfbi {
 // eta > 0 (mixed precision): a cycle runs until its residual estimate falls
 // below thresh = max(tol ||b||, eta beta); convergence is then decided only
 // by the FP64 residual computed at the start of the next cycle
+//
+// Device-driven schedule (merged-operator path): the solve is a sequence of
+// identical slots, each one grid solve followed by one control kernel that
+// acts on `state`: a cycle start (r = b - K x, stop test, v_0), an Arnoldi
+// step, or nothing once finished.  The control kernel sets the gate words
+// read by the next slot's grid-solve kernels (skip64 / skip32: FP64 / FP32
+// solve not needed) and by the final solve enqueued after the slots
+// (skip_tail, cleared when finished).
+constexpr int kStIter = 0, kStStart = 1, kStDone = 2;
+
 struct GmCtl {
     int j, done, iters, converged;
     int max_iter, m, fixed, breakdown;
     double tol, bnorm, beta, resid;
     double eta, thresh;
+    int state, skip64, skip32, skip_tail;
+    int slot, cycles, mixed, pad;
+};
+
+// host-visible copy of the control block's outcome, in pinned host memory;
+// written by every control kernel, seq last
+struct GmMirror {
+    int seq, state, iters, converged, cycles, pad;
+    double resid, bnorm;
 };
 
 namespace {
@@ -572,6 +593,311 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_update(GmCtl *ctl, const T *V
     }
 }
 
+// ---------------------------------------------------------------------------
+// Device-driven GMRES (merged-operator path)
+// ---------------------------------------------------------------------------
+
+// gate words of the next slot for a new state
+__device__ inline void gm_set_state(GmCtl *ctl, int st) {
+    ctl->state = st;
+    ctl->skip64 = (st == kStDone || (st == kStIter && ctl->mixed)) ? 1 : 0;
+    ctl->skip32 = (st == kStIter && ctl->mixed) ? 0 : 1;
+    ctl->skip_tail = st == kStDone ? 0 : 1;
+}
+
+__device__ inline void gm_publish(GmCtl *ctl, GmMirror *mir) {
+    mir->state = ctl->state;
+    mir->iters = ctl->iters;
+    mir->converged = ctl->converged;
+    mir->cycles = ctl->cycles;
+    mir->resid = ctl->resid;
+    mir->bnorm = ctl->bnorm;
+    __hip_atomic_store(&mir->seq, ctl->slot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// control block, ||b|| and the corrections of the initial iterate x_0
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_init(GmCtl *ctl, const T *__restrict__ b,
+                                                        const T *__restrict__ x, int Nb, int max_iter, int m,
+                                                        int fixed, double tol, double eta, int mixed, int n_irr,
+                                                        const T *__restrict__ mcoef,
+                                                        const int32_t *__restrict__ mbase, T *corr) {
+    extern __shared__ double dyn[];
+    T *sx = reinterpret_cast<T *>(dyn);
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
+        s += abs2(b[k]);
+        sx[k] = x[k];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        ctl->j = 0;
+        ctl->done = 0;
+        ctl->iters = 0;
+        ctl->converged = 0;
+        ctl->max_iter = max_iter;
+        ctl->m = m;
+        ctl->fixed = fixed;
+        ctl->breakdown = 0;
+        ctl->tol = tol;
+        ctl->bnorm = sqrt(s);
+        ctl->beta = 0.0;
+        ctl->resid = 0.0;
+        ctl->eta = eta;
+        ctl->thresh = 0.0;
+        ctl->slot = 0;
+        ctl->cycles = 0;
+        ctl->mixed = mixed;
+        ctl->pad = 0;
+        gm_set_state(ctl, kStStart);
+    }
+    corr_merged_block(sx, Nb, n_irr, mcoef, mbase, corr);
+}
+
+// The control kernel of one slot (see the schedule above).  Dynamic LDS:
+// [Nb: working vector][nvl*Nb: staged basis][m*m: triangular factor at a
+// cycle end].
+template <class T, int EPT>
+__global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mir, T *V, T *H, T *g, double *cs,
+                                                        T *sn, T *x, const T *__restrict__ b, int Nb, int m, int nvl,
+                                                        const T *__restrict__ ust, const double *__restrict__ w6,
+                                                        const T *__restrict__ bop, int n_irr,
+                                                        const T *__restrict__ mcoef,
+                                                        const int32_t *__restrict__ mbase, T *corr) {
+    extern __shared__ double dyn[];
+    T *sw = reinterpret_cast<T *>(dyn);
+    T *sV = sw + Nb;
+    T *sH = sV + (size_t)nvl * Nb;
+    __shared__ T red[kGmThreads / 64][65];
+    __shared__ T hcol[72];
+    __shared__ T hs[72];
+    __shared__ T ssn[72];
+    __shared__ T sgv[72];
+    __shared__ T ys[72];
+    __shared__ double scs[72];
+    __shared__ double redd[16];
+    __shared__ int sflag;
+    const int state = ctl->state;
+    if (state == kStDone) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int limit = ctl->fixed > 0 ? ctl->fixed : ctl->max_iter;
+
+    if (state == kStStart) {
+        // r = b - K x, stop test, v_0 = r / beta, corrections of v_0
+        double s = 0.0;
+        for (int k = tid; k < Nb; k += kGmThreads) {
+            const T r = b[k] - extract_k(k, Nb, ust, w6, bop, x);
+            sw[k] = r;
+            s += abs2(r);
+        }
+        s = block_sum(s, redd);
+        const double beta = sqrt(s);
+        const bool conv = beta <= ctl->tol * ctl->bnorm;
+        const bool stop = (ctl->fixed == 0 && conv) || beta == 0.0 || ctl->iters >= limit;
+        const double inv = stop ? 0.0 : 1.0 / beta;
+        for (int k = tid; k < Nb; k += kGmThreads) {
+            const T v = sw[k] * inv;
+            sw[k] = v;
+            V[k] = v;
+        }
+        if (tid <= m) g[tid] = tid == 0 ? scale_of<T>(beta) : zero<T>();
+        if (tid == 0) {
+            ctl->beta = beta;
+            ctl->resid = beta;
+            ctl->j = 0;
+            ctl->breakdown = 0;
+            ctl->converged = conv ? 1 : 0;
+            ctl->cycles += 1;
+            const double t0 = ctl->tol * ctl->bnorm, t1 = ctl->eta * beta;
+            ctl->thresh = t1 > t0 ? t1 : t0;
+            ctl->slot += 1;
+            gm_set_state(ctl, stop ? kStDone : kStIter);
+            gm_publish(ctl, mir);
+            sflag = stop ? 1 : 0;
+        }
+        __syncthreads();
+        if (!sflag) corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr);
+        return;
+    }
+
+    // Arnoldi step on column j: w = K v_j, CGS2, Givens
+    const int j = ctl->j;
+    const T *vj = V + (size_t)j * Nb;
+    T *w = V + (size_t)(j + 1) * Nb;
+    if (tid < j) {
+        scs[tid] = cs[tid];
+        ssn[tid] = sn[tid];
+    }
+    if (tid <= j) sgv[tid] = g[tid];
+    const int nst = j + 1 < nvl ? j + 1 : nvl;
+    for (int q = tid; q < nst * Nb; q += kGmThreads) sV[q] = V[q];
+    T cpre[kWin];
+    int bpre = 0;
+    if (tid < n_irr) {
+        bpre = mbase[tid];
+#pragma unroll
+        for (int o = 0; o < kWin; ++o) cpre[o] = mcoef[(size_t)o * n_irr + tid];
+    }
+    for (int k = tid; k < Nb; k += kGmThreads) sw[k] = extract_k(k, Nb, ust, w6, bop, vj);
+    __syncthreads();
+    T wl[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int k = tid + e * kGmThreads;
+        wl[e] = k < Nb ? sw[k] : zero<T>();
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = 0; i0 <= j; i0 += 16) {
+            T part[16];
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int idx = tid + e * kGmThreads;
+                if (idx < Nb) {
+#pragma unroll
+                    for (int ii = 0; ii < 16; ++ii)
+                        if (i0 + ii < nst) part[ii] += conjv(sV[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+#pragma unroll
+                    for (int ii = 0; ii < 16; ++ii)
+                        if (i0 + ii >= nst && i0 + ii <= j)
+                            part[ii] += conjv(V[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+                }
+            }
+            const T sum = wave_sum16(part, lane);
+            const int ii = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && i0 + ii <= j) red[wid][i0 + ii] = sum;
+        }
+        __syncthreads();
+        if (tid <= j) {
+            T sum = zero<T>();
+            for (int q = 0; q < (kGmThreads >> 6); ++q) sum += red[q][tid];
+            hs[tid] = sum;
+            hcol[tid] = pass == 0 ? sum : hcol[tid] + sum;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int idx = tid + e * kGmThreads;
+            if (idx < Nb) {
+                for (int i = 0; i < nst; ++i) wl[e] -= hs[i] * sV[(size_t)i * Nb + idx];
+                for (int i = nst; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+            }
+        }
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) s2 += abs2(wl[e]);
+    const double hn = sqrt(block_sum(s2, redd));
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + e * kGmThreads;
+        if (idx < Nb) {
+            const T v = wl[e] * inv;
+            w[idx] = v;
+            sw[idx] = v;
+        }
+    }
+    if (tid == 0) {
+        for (int i = 0; i < j; ++i) {
+            const T a = hcol[i], bb = hcol[i + 1];
+            hcol[i] = a * scs[i] + ssn[i] * bb;
+            hcol[i + 1] = bb * scs[i] - conjv(ssn[i]) * a;
+        }
+        const T a = hcol[j];
+        const double aa = absv(a);
+        const double rho = hypot(aa, hn);
+        double c;
+        T sr;
+        if (aa == 0.0) {
+            c = 0.0;
+            sr = scale_of<T>(1.0);
+        } else {
+            c = aa / rho;
+            sr = a * (hn / (aa * rho));
+        }
+        cs[j] = c;
+        sn[j] = sr;
+        hcol[j] = a * c + sr * hn;
+        hcol[j + 1] = zero<T>();
+        const T gj = sgv[j];
+        const T gj1 = -(conjv(sr) * gj);
+        g[j + 1] = gj1;
+        g[j] = gj * c;
+        sgv[j] = gj * c;
+        const double resid = absv(gj1);
+        ctl->resid = resid;
+        const int it = ctl->iters + 1;
+        ctl->iters = it;
+        ctl->j = j + 1;
+        const bool conv = resid <= ctl->thresh;
+        ctl->converged = (conv && ctl->eta == 0.0) ? 1 : 0;
+        if (hn == 0.0) ctl->breakdown = 1;
+        const bool end = (ctl->fixed == 0 && conv) || it >= limit || j + 1 >= m || hn == 0.0;
+        sflag = end ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid <= j + 1) H[(size_t)tid * m + j] = hcol[tid];
+    if (!sflag) {
+        // next Arnoldi step: corrections of v_{j+1}
+        if (tid < n_irr) {
+            T acc = zero<T>();
+#pragma unroll
+            for (int o = 0; o < kWin; ++o) {
+                int idx = bpre + o;
+                if (idx >= Nb) idx -= Nb;
+                acc += cpre[o] * sw[idx];
+            }
+            corr[tid] = acc;
+        }
+        corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr, kGmThreads);
+        if (tid == 0) {
+            ctl->slot += 1;
+            gm_set_state(ctl, kStIter);
+            gm_publish(ctl, mir);
+        }
+        return;
+    }
+    // end of the cycle: y = R^{-1} g on the leading (j+1) block (R is the
+    // rotated Hessenberg matrix: columns 0..j-1 from earlier steps, column j
+    // in hcol), x += V y, corrections of x
+    const int n1 = j + 1;
+    for (int q = tid; q < n1 * n1; q += kGmThreads) {
+        const int r = q / n1, c = q - r * n1;
+        sH[q] = c == j ? hcol[r] : H[(size_t)r * m + c];
+    }
+    __syncthreads();
+    for (int l = j; l >= 0; --l) {
+        if (tid == 0) ys[l] = sgv[l] / sH[l * n1 + l];
+        __syncthreads();
+        if (tid < l) sgv[tid] -= sH[tid * n1 + l] * ys[l];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + e * kGmThreads;
+        if (idx < Nb) {
+            T acc = x[idx];
+            for (int i = 0; i < nst; ++i) acc += sV[(size_t)i * Nb + idx] * ys[i];
+            for (int i = nst; i <= j; ++i) acc += V[(size_t)i * Nb + idx] * ys[i];
+            x[idx] = acc;
+            sw[idx] = acc;
+        }
+    }
+    __syncthreads();
+    corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr);
+    if (tid == 0) {
+        // FP64: the residual estimate decides; mixed: the FP64 residual of
+        // the next cycle start decides
+        const bool finished = ctl->converged || ctl->iters >= limit;
+        ctl->slot += 1;
+        gm_set_state(ctl, finished ? kStDone : kStStart);
+        gm_publish(ctl, mir);
+    }
+}
+
 struct GmPtrs {
     GmCtl *ctl;
     void *V, *H, *g, *sn, *y, *x, *b, *r;
@@ -784,6 +1110,148 @@ static int gmres_run(kfbi_domain *d, double kre, double kim, GmPtrs &P, const kf
     return KFBI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Host side of the device-driven schedule
+// ---------------------------------------------------------------------------
+constexpr int kTailTag = 1 << 20;
+
+template <class T>
+__global__ void k_copy_gated(int n, T *__restrict__ dst, const T *__restrict__ src, const int *done) {
+    if (*done) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// dynamic LDS of the control kernel; nvl basis vectors staged
+template <class T>
+static size_t slot_lds(int Nb, int m, int *nvl_out) {
+    const size_t es = sizeof(T), hb = (size_t)m * m * es, vb = (size_t)Nb * es;
+    int nvl = 0;
+    if (kGmIterLds >= hb + vb) nvl = (int)((kGmIterLds - hb - vb) / vb);
+    if (nvl > m + 1) nvl = m + 1;
+    *nvl_out = nvl;
+    return vb * (1 + nvl) + hb;
+}
+
+template <class T>
+static bool slots_supported(kfbi_domain *d, int m) {
+    int nvl;
+    return d->op_merged && (size_t)d->Nb * sizeof(T) <= 65536 && slot_lds<T>(d->Nb, m, &nvl) <= kGmIterLds;
+}
+
+template <class T>
+static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index, hipStream_t s) {
+    int nvl;
+    const size_t lds = slot_lds<T>(Nb, m, &nvl);
+    const int ept = (Nb + kGmThreads - 1) / kGmThreads;
+    GmMirror *mir = (GmMirror *)d->mirror_dev;
+    const int ps = prof_begin(d);
+#define KFBI_SLOT(E)                                                                                             \
+    k_gm_slot<T, E><<<1, kGmThreads, lds, s>>>(P.ctl, mir, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn,          \
+                                               (T *)P.x, (const T *)P.b, Nb, m, nvl, (const T *)d->ust, d->w6,   \
+                                               (const T *)d->bop, d->n_irr, (const T *)d->mcoef, d->mbase,       \
+                                               (T *)d->corr)
+    if (ept <= 1) KFBI_SLOT(1);
+    else if (ept <= 2) KFBI_SLOT(2);
+    else if (ept <= 4) KFBI_SLOT(4);
+    else if (ept <= 8) KFBI_SLOT(8);
+    else KFBI_SLOT(16);
+#undef KFBI_SLOT
+    KFBI_CHECK_LAUNCH();
+    // algorithmic bytes of an Arnoldi step at j = slot_index - 1 (one cycle
+    // start first): extraction inputs, both Gram-Schmidt sweeps, the new
+    // vector, the correction windows and the corrections written
+    int j = slot_index - 1;
+    if (j < 0) j = 0;
+    if (j > m - 1) j = m - 1;
+    const double es = (double)sizeof(T);
+    const double bytes = (double)Nb * (6.0 * es + 6.0 * 8.0 + 5.0 * es + es) + 2.0 * (j + 1) * Nb * es +
+                         (double)Nb * es + (double)d->n_irr * (kWin * es + 4.0 + es);
+    prof_end(d, ps, KFBI_K_ARNOLDI, bytes);
+    return KFBI_OK;
+}
+
+// Enqueue slots (and after each batch the caller's final solve, gated on the
+// finish flag) until the device reports the solve finished.  The host waits
+// on the pinned mirror of the control block, not on the stream, so it
+// returns while the final solve is still running.
+template <class T, class Tail>
+static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, bool mixed, Tail &&tail,
+                           int *iters_out, double *rel_out, int *conv_out, int *cycles_out) {
+    hipStream_t s = d->stream;
+    const int Nb = d->Nb, m = o.restart;
+    if (!d->mirror_host) {
+        KFBI_HIP(hipHostMalloc(&d->mirror_host, sizeof(GmMirror), hipHostMallocMapped | hipHostMallocCoherent));
+        memset(d->mirror_host, 0, sizeof(GmMirror));
+        KFBI_HIP(hipHostGetDevicePointer(&d->mirror_dev, d->mirror_host, 0));
+    }
+    GmMirror *mh = (GmMirror *)d->mirror_host;
+    __atomic_store_n(&mh->seq, 0, __ATOMIC_RELEASE);
+    const int fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
+    k_gm_init<T><<<1, kGmThreads, (size_t)Nb * sizeof(T), s>>>(
+        P.ctl, (const T *)P.b, (const T *)P.x, Nb, o.max_iter, m, fixed, o.tol, mixed ? 1e-5 : 0.0, mixed ? 1 : 0,
+        d->n_irr, (const T *)d->mcoef, d->mbase, (T *)d->corr);
+    KFBI_CHECK_LAUNCH();
+    const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
+    // first batch: the previous solve's slot count on this domain plus one
+    int want = d->last_slots > 0 ? d->last_slots + 1 : (fixed > 0 ? fixed + 2 : 12);
+    int n_enq = 0, last_batch = 0;
+    for (int batch = 0;; ++batch) {
+        last_batch = batch;
+        for (int c = 0; c < want; ++c) {
+            d->prof_tag = n_enq + c;
+            KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, skip64));
+            KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, skip64));
+            if (mixed) {
+                KFBI_TRY(tridiag_solve_low(d, d->corr, d->uhat32, skip32));
+                KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat32, d->ust, skip32, true));
+            }
+            KFBI_TRY(launch_slot<T>(d, P, Nb, m, n_enq + c, s));
+        }
+        n_enq += want;
+        d->prof_tag = kTailTag + batch;
+        KFBI_TRY(tail(skip_tail));
+        d->prof_tag = -1;
+        // wait until the device has finished or run every enqueued slot
+        const auto t0 = std::chrono::steady_clock::now();
+        int seq = 0, st = kStIter;
+        for (long spin = 1;; ++spin) {
+            seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
+            st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+            if (seq > 0 && (st == kStDone || seq >= n_enq)) break;
+            if ((spin & 255) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q != hipSuccess && q != hipErrorNotReady) {
+                    set_error(std::string("device error during GMRES: ") + hipGetErrorString(q));
+                    return KFBI_EDEVICE;
+                }
+                if (q == hipSuccess) {  // stream drained: the mirror must be final
+                    seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
+                    st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+                    if (seq > 0 && (st == kStDone || seq >= n_enq)) break;
+                    set_error("GMRES control block not published by the device");
+                    return KFBI_EDEVICE;
+                }
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(120)) {
+                    set_error("timed out waiting for the GMRES control block");
+                    return KFBI_EDEVICE;
+                }
+            }
+        }
+        if (st == kStDone) {
+            d->last_slots = seq;
+            break;
+        }
+        want = 4;
+    }
+    if (d->prof_on) KFBI_TRY(prof_flush(d, mh->seq, kTailTag + last_batch));
+    *iters_out = mh->iters;
+    *rel_out = mh->bnorm > 0 ? mh->resid / mh->bnorm : mh->resid;
+    *conv_out = mh->converged;
+    *cycles_out = mh->cycles;
+    return KFBI_OK;
+}
+
 int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
                     const void *g_gamma, void *u_grid_out, void *phi_inout, const kfbi_solve_opts *opts,
                     kfbi_solve_stats *stats) {
@@ -793,12 +1261,15 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     o.restart = 50;
     o.fixed_iters = 0;
     o.precision = -1;
+    o.flags = 0;
+    o.pad = 0;
     if (opts) {
         if (opts->tol > 0) o.tol = opts->tol;
         if (opts->max_iter > 0) o.max_iter = opts->max_iter;
         if (opts->restart > 0) o.restart = opts->restart;
         o.fixed_iters = opts->fixed_iters;
         o.precision = opts->precision;
+        o.flags = opts->flags;
     }
     if (o.restart > 64) {
         set_error("restart length must be at most 64");
@@ -845,18 +1316,41 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     int iters = 0, conv = 0, cycles = 0;
     double rel = 0.0;
     int st;
-    if (d->cplx) st = gmres_run<cd>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
-    else st = gmres_run<double>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
-    if (st != KFBI_OK) return st;
-    // U = IS(f, phi).U on the grid
-    KFBI_TRY(compute_corrections(d, kre, kim, P.x, f_gamma, d->corr));
-    KFBI_TRY(tridiag_solve(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat));
-    if (u_grid_out) KFBI_TRY(idst_rows_dense(d, d->uhat, u_grid_out));
-    if (phi_inout) KFBI_HIP(hipMemcpyAsync(phi_inout, P.x, vb, hipMemcpyDeviceToDevice, s));
+    // U = IS(f, phi).U on the grid (gate: null, or the finish flag of the
+    // device-driven schedule)
+    auto final_solve = [&](const int *gate) -> int {
+        KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
+        KFBI_TRY(tridiag_solve_ctl(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat, gate));
+        if (u_grid_out) KFBI_TRY(idst_rows_dense_ctl(d, d->uhat, u_grid_out, gate));
+        if (phi_inout) {
+            if (gate) {
+                const int n = (int)(vb / sizeof(double));
+                k_copy_gated<double><<<(n + 255) / 256, 256, 0, s>>>(n, (double *)phi_inout, (const double *)P.x,
+                                                                      gate);
+                KFBI_CHECK_LAUNCH();
+            } else {
+                KFBI_HIP(hipMemcpyAsync(phi_inout, P.x, vb, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        return KFBI_OK;
+    };
+    const bool slots = d->cplx ? slots_supported<cd>(d, o.restart) : slots_supported<double>(d, o.restart);
+    if (slots) {
+        if (d->cplx) st = gmres_run_slots<cd>(d, P, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
+        else st = gmres_run_slots<double>(d, P, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
+        if (st != KFBI_OK) return st;
+    } else {
+        if (d->cplx) st = gmres_run<cd>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
+        else st = gmres_run<double>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
+        if (st != KFBI_OK) return st;
+        KFBI_TRY(final_solve(nullptr));
+    }
     KFBI_HIP(hipEventRecord(e1, s));
-    KFBI_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    KFBI_HIP(hipEventElapsedTime(&ms, e0, e1));
+    float ms = -1.f;
+    if (!(o.flags & KFBI_SOLVE_ASYNC)) {
+        KFBI_HIP(hipEventSynchronize(e1));
+        KFBI_HIP(hipEventElapsedTime(&ms, e0, e1));
+    }
     if (stats) {
         stats->iters = iters;
         stats->converged = conv;

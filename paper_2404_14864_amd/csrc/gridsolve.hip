@@ -88,7 +88,8 @@ __device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (3
 template <class T>
 __global__ __launch_bounds__(256) void k_dst_rows(int M, int logN2, const T *in, bool in_grid,
                                                   const uint8_t *mask, T *out, bool out_grid,
-                                                  double scale, const double *twiddle) {
+                                                  double scale, const double *twiddle, const int *done) {
+    if (done && *done) return;
     extern __shared__ double lds[];
     double2 *a = reinterpret_cast<double2 *>(lds);
     const int n = M - 1, N2 = 2 * M;
@@ -163,7 +164,8 @@ __global__ __launch_bounds__(256) void k_dst_rows(int M, int logN2, const T *in,
 
 // first and last grid rows of a grid array: zero
 template <class T>
-__global__ void k_zero_edge_rows(int M, T *grid) {
+__global__ void k_zero_edge_rows(int M, T *grid, const int *done) {
+    if (done && *done) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > M) return;
     grid[i] = zero<T>();
@@ -481,7 +483,7 @@ __global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int
 
 template <class T>
 int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out,
-               bool out_grid, double scale) {
+               bool out_grid, double scale, const int *done = nullptr) {
     const int M = d->M, n = M - 1;
     int logN2 = 0;
     while ((1 << logN2) < 2 * M) ++logN2;
@@ -490,7 +492,7 @@ int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask
     size_t lds = (size_t)2 * M * sizeof(double2);
     const int ps = prof_begin(d);
     k_dst_rows<T><<<blocks, 256, lds, d->stream>>>(M, logN2, (const T *)in, in_grid, mask, (T *)out,
-                                                   out_grid, scale, d->twiddle);
+                                                   out_grid, scale, d->twiddle, done);
     KFBI_CHECK_LAUNCH();
     {
         const double es = sizeof(T), nn = (double)n * n, grid = (double)(M + 1) * (M + 1);
@@ -498,7 +500,7 @@ int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask
         prof_end(d, ps, in_grid ? KFBI_K_DST : KFBI_K_IDST, bytes);
     }
     if (out_grid) {
-        k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(M, (T *)out);
+        k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(M, (T *)out, done);
         KFBI_CHECK_LAUNCH();
     }
     return KFBI_OK;
@@ -653,9 +655,13 @@ int dst_rows_dense(kfbi_domain *d, const void *grid, bool mask_inside, void *rha
 }
 
 int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out) {
+    return idst_rows_dense_ctl(d, uhat, grid_out, nullptr);
+}
+
+int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done) {
     double scale = 2.0 / d->M;
-    if (d->cplx) return launch_dst<cd>(d, uhat, false, nullptr, grid_out, true, scale);
-    return launch_dst<double>(d, uhat, false, nullptr, grid_out, true, scale);
+    if (d->cplx) return launch_dst<cd>(d, uhat, false, nullptr, grid_out, true, scale, done);
+    return launch_dst<double>(d, uhat, false, nullptr, grid_out, true, scale, done);
 }
 
 int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out) {

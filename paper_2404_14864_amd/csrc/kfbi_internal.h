@@ -253,6 +253,9 @@ struct kfbi_domain {
     void *gm = nullptr;                 // device GmresState (+ basis)
     size_t gm_bytes = 0;
     int last_iters = 0;                 // iterations of the previous solve (chunk sizing)
+    int last_slots = 0;                 // grid solves of the previous device-driven solve
+    void *mirror_host = nullptr;        // pinned host copy of the GMRES control block
+    void *mirror_dev = nullptr;         //   and its device address
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // solve timing
 
     // optional per-kernel timing with HIP events (kfbi_profile_*)
@@ -288,6 +291,7 @@ int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat
 int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out, const int *done);
 // U on the full grid from Uhat
 int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out);
+int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done);
 // U at the 6 Nb stencil nodes
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out);
 int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low = false);
@@ -332,6 +336,6 @@ inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : si
 // dropped).
 int prof_begin(kfbi_domain *d);
 void prof_end(kfbi_domain *d, int slot, int kind, double bytes);
-int prof_flush(kfbi_domain *d, int keep_tags_below);
+int prof_flush(kfbi_domain *d, int keep_tags_below, int keep_tag = -1);
 
 }  // namespace kfbi

@@ -19,6 +19,7 @@ KFBI_OK, KFBI_EINVAL, KFBI_EDOMAIN, KFBI_ENOMEM, KFBI_ENOCONV, KFBI_EDEVICE, KFB
 CURVES = {"disk": 0, "ellipse": 1, "star": 2}
 KFBI_REAL, KFBI_COMPLEX = 0, 1
 KFBI_PREC_FP64, KFBI_PREC_MIXED = 0, 1
+KFBI_SOLVE_ASYNC = 1
 KFBI_HEAT, KFBI_WAVE, KFBI_SCHRODINGER = 0, 1, 2
 
 
@@ -48,7 +49,7 @@ class DomainInfo(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -107,6 +108,11 @@ def lib():
         "kfbi_step_schrodinger": ([_P, _P, _P, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
         "kfbi_profile_enable": ([_P, ctypes.c_int32], ctypes.c_int),
         "kfbi_profile_read": ([_P, ctypes.POINTER(KernelProf)], ctypes.c_int),
+        "kfbi_stepper_state_bytes": ([_P, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "kfbi_stepper_get_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
+        "kfbi_stepper_set_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
+        "kfbi_profile_replay": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -120,7 +126,8 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_domain_copy_classification", "kfbi_domain_copy_boundary", "kfbi_domain_copy_edges",
             "kfbi_grid_solve", "kfbi_interface_apply", "kfbi_helmholtz_solve", "kfbi_stepper_create",
             "kfbi_stepper_destroy", "kfbi_stepper_init", "kfbi_step_heat", "kfbi_step_wave",
-            "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read")
+            "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read", "kfbi_profile_replay",
+            "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state")
 
 
 def kfbi_profile_enable(h, on=True):
@@ -132,6 +139,15 @@ def kfbi_profile_read(h):
     _check(lib().kfbi_profile_read(h, arr))
     return {name: {"launches": int(arr[i].launches), "total_ms": arr[i].total_ms,
                    "bytes": arr[i].bytes} for i, name in enumerate(KERNELS)}
+
+
+def kfbi_profile_replay(h, kind, reps):
+    """Average launch duration (ms) of `reps` back-to-back launches of one
+    grid-solve kernel ("tridiag_sparse", "tridiag_dense" or "eval_nodes") and
+    its algorithmic bytes per launch."""
+    ms, by = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().kfbi_profile_replay(h, KERNELS.index(kind), int(reps), ctypes.byref(ms), ctypes.byref(by)))
+    return ms.value, by.value
 
 
 def _check(code, allow=()):
@@ -160,7 +176,8 @@ def _opts(opts):
         return None
     o = SolveOpts(tol=opts.get("tol", 0.0), max_iter=opts.get("max_iter", 0),
                   restart=opts.get("restart", 0), fixed_iters=opts.get("fixed_iters", 0),
-                  precision=opts.get("precision", -1))
+                  precision=opts.get("precision", -1),
+                  flags=KFBI_SOLVE_ASYNC if opts.get("async", False) else 0)
     return ctypes.byref(o)
 
 
@@ -252,6 +269,26 @@ def kfbi_stepper_create(h, equation, tau, theta=0.25, diffusivity=1.0, w=0.0, v_
 
 def kfbi_stepper_destroy(s):
     _check(lib().kfbi_stepper_destroy(s))
+
+
+def kfbi_stepper_state_bytes(s):
+    n = ctypes.c_uint64(0)
+    _check(lib().kfbi_stepper_state_bytes(s, ctypes.byref(n)))
+    return int(n.value)
+
+
+def kfbi_stepper_get_state(s, out=None):
+    """Checkpoint: the stepper's state as a uint8 device tensor (opaque)."""
+    n = kfbi_stepper_state_bytes(s)
+    if out is None:
+        out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    _check(lib().kfbi_stepper_get_state(s, _ptr(out, torch.uint8, None, "state"), out.numel()))
+    return out
+
+
+def kfbi_stepper_set_state(s, blob):
+    """Restart from a blob written by kfbi_stepper_get_state."""
+    _check(lib().kfbi_stepper_set_state(s, _ptr(blob, torch.uint8, None, "state"), blob.numel()))
 
 
 def kfbi_stepper_init(s, u0, lap_u0, u0_gamma, lap_u0_gamma, uprev=None, lap_uprev=None,

@@ -149,3 +149,71 @@ def test_schrodinger_free_closed_form():
         kfbi.kfbi_stepper_destroy(s)
     err = np.max(np.abs(U - mf.schr_free_u(X, Y, n * tau))[od.inside])
     assert err < 1e-3
+
+
+def _wave_stepper(desc, tau):
+    od = Domain(desc)
+    X, Y = od.X, od.Y
+    h = kfbi.kfbi_domain_create(desc)
+    gx, gy = kfbi.kfbi_domain_copy_boundary(h)
+    s = kfbi.kfbi_stepper_create(h, kfbi.KFBI_WAVE, tau, theta=0.25)
+    kfbi.kfbi_stepper_init(s, dev(mf.wave_u(X, Y, 0).ravel()), dev(mf.wave_lap(X, Y, 0).ravel()),
+                           dev(mf.wave_u(gx, gy, 0)), dev(mf.wave_lap(gx, gy, 0)),
+                           dev(mf.wave_u(X, Y, -tau).ravel()), dev(mf.wave_lap(X, Y, -tau).ravel()),
+                           dev(mf.wave_u(gx, gy, -tau)), dev(mf.wave_lap(gx, gy, -tau)))
+    return h, s, gx, gy
+
+
+def test_stepper_checkpoint_restart_is_exact():
+    """get_state / set_state: replaying steps from a checkpoint reproduces them
+    bit for bit (the state is the recurrence term and the warm-start density),
+    and a blob from another configuration is rejected."""
+    desc = W.domain_c2_wave(128)
+    tau = 2.0 / desc["M"]
+    h, s, gx, gy = _wave_stepper(desc, tau)
+    try:
+        u = empty_grid(desc["M"])
+        g = [dev(mf.wave_u(gx, gy, (n + 1) * tau)) for n in range(6)]
+        for n in range(3):
+            kfbi.kfbi_step_wave(s, g[n], u)
+        blob = kfbi.kfbi_stepper_get_state(s)
+        assert blob.numel() == kfbi.kfbi_stepper_state_bytes(s)
+        first = []
+        for n in range(3, 6):
+            kfbi.kfbi_step_wave(s, g[n], u)
+            first.append(host(u).copy())
+        kfbi.kfbi_stepper_set_state(s, blob)
+        for k, n in enumerate(range(3, 6)):
+            kfbi.kfbi_step_wave(s, g[n], u)
+            assert np.array_equal(host(u), first[k]), n
+        # a heat stepper on the same domain has another kappa and equation
+        hs = kfbi.kfbi_stepper_create(h, kfbi.KFBI_HEAT, tau)
+        with pytest.raises(kfbi.KfbiError):
+            kfbi.kfbi_stepper_set_state(hs, blob)
+        kfbi.kfbi_stepper_destroy(hs)
+        kfbi.kfbi_stepper_destroy(s)
+    finally:
+        kfbi.kfbi_domain_destroy(h)
+
+
+def test_async_steps_match_synchronous_steps():
+    """KFBI_SOLVE_ASYNC returns once GMRES has finished on the device; after a
+    stream synchronisation the results equal those of synchronous calls."""
+    desc = W.domain_c2_wave(256)
+    tau = 2.0 / desc["M"]
+    out = []
+    for mode in ({}, {"async": True}):
+        h, s, gx, gy = _wave_stepper(desc, tau)
+        try:
+            u = empty_grid(desc["M"])
+            its = []
+            for n in range(5):
+                st = kfbi.kfbi_step_wave(s, dev(mf.wave_u(gx, gy, (n + 1) * tau)), u, opts=dict(mode))
+                its.append(st["iters"])
+            torch.cuda.synchronize()
+            out.append((host(u).copy(), its))
+            kfbi.kfbi_stepper_destroy(s)
+        finally:
+            kfbi.kfbi_domain_destroy(h)
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
