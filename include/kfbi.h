@@ -276,8 +276,9 @@ int kfbi_profile_read(kfbi_domain *dom, kfbi_kernel_prof *out);
 /* Replay timing: `reps` back-to-back launches of one FP64 grid-solve kernel
  * of this domain on its current internal buffers, between two HIP events on
  * the domain stream; writes the average launch duration (ms) and the
- * algorithmic bytes of one launch.  kind: KFBI_K_TRIDIAG_SPARSE (corrections
- * -> mode-space solution), KFBI_K_TRIDIAG_DENSE (dense right-hand side ->
+ * algorithmic bytes of one launch.  kind: KFBI_K_TRIDIAG_SPARSE (the
+ * corrections of the last solve's density -> mode-space solution, the form
+ * used in every matrix-vector product), KFBI_K_TRIDIAG_DENSE (dense right-hand side ->
  * mode-space solution) or KFBI_K_EVAL_NODES (mode-space solution -> stencil
  * values).  Needs a completed solve on the domain (it reuses the last
  * kappa's coefficients and the last solve's data); overwrites the domain's

@@ -13,7 +13,9 @@
 // Arnoldi orthogonalisation is classical Gram-Schmidt applied twice (CGS2:
 // two passes of all inner products at once, so a step costs a fixed handful
 // of workgroup reductions instead of one per basis vector); it gives the same
-// basis as modified Gram-Schmidt up to rounding.
+// basis as modified Gram-Schmidt up to rounding.  (A conditional second pass
+// does not pay here: for the second-kind operator 1/2 I + W the projection
+// removes most of K v_j, so the reorthogonalisation test nearly always fires.)
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -285,22 +287,40 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_arnoldi(GmCtl *ctl, T *V, T *
 // ---------------------------------------------------------------------------
 constexpr int kWin = 16;
 
+// U nodes per thread per round: all their coefficient loads are issued
+// before the first use, so a round costs one memory latency
 template <class T>
 __device__ void corr_merged_block(const T *phi_lds, int Nb, int n_irr, const T *__restrict__ mcoef,
                                   const int32_t *__restrict__ mbase, T *__restrict__ corr, int q_first = 0) {
-    for (int q = q_first + threadIdx.x; q < n_irr; q += blockDim.x) {
-        const int b = mbase[q];
-        T c[kWin];
+    constexpr int U = sizeof(T) == 8 ? 4 : 2;
+    const int nt = blockDim.x;
+    for (int q0 = q_first + threadIdx.x; q0 < n_irr; q0 += U * nt) {
+        T c[U][kWin];
+        int b[U];
 #pragma unroll
-        for (int o = 0; o < kWin; ++o) c[o] = mcoef[(size_t)o * n_irr + q];
-        T acc = zero<T>();
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * nt;
+            b[u] = 0;
+            if (q < n_irr) {
+                b[u] = mbase[q];
 #pragma unroll
-        for (int o = 0; o < kWin; ++o) {
-            int idx = b + o;
-            if (idx >= Nb) idx -= Nb;
-            acc += c[o] * phi_lds[idx];
+                for (int o = 0; o < kWin; ++o) c[u][o] = mcoef[(size_t)o * n_irr + q];
+            }
         }
-        corr[q] = acc;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * nt;
+            if (q < n_irr) {
+                T acc = zero<T>();
+#pragma unroll
+                for (int o = 0; o < kWin; ++o) {
+                    int idx = b[u] + o;
+                    if (idx >= Nb) idx -= Nb;
+                    acc += c[u][o] * phi_lds[idx];
+                }
+                corr[q] = acc;
+            }
+        }
     }
 }
 
@@ -605,6 +625,10 @@ __device__ inline void gm_set_state(GmCtl *ctl, int st) {
     ctl->skip_tail = st == kStDone ? 0 : 1;
 }
 
+// The mirror is fine-grained (uncached) host memory: the fields are plain
+// stores, and waiting for their completion before the store of seq orders
+// them for the host without a release fence (which would write back the
+// whole L2 of the XCD).
 __device__ inline void gm_publish(GmCtl *ctl, GmMirror *mir) {
     mir->state = ctl->state;
     mir->iters = ctl->iters;
@@ -612,23 +636,21 @@ __device__ inline void gm_publish(GmCtl *ctl, GmMirror *mir) {
     mir->cycles = ctl->cycles;
     mir->resid = ctl->resid;
     mir->bnorm = ctl->bnorm;
-    __hip_atomic_store(&mir->seq, ctl->slot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_store(&mir->seq, ctl->slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// control block, ||b|| and the corrections of the initial iterate x_0
+// control block, ||b||, and x_0 as the first slot's density
 template <class T>
 __global__ __launch_bounds__(kGmThreads) void k_gm_init(GmCtl *ctl, const T *__restrict__ b,
-                                                        const T *__restrict__ x, int Nb, int max_iter, int m,
-                                                        int fixed, double tol, double eta, int mixed, int n_irr,
-                                                        const T *__restrict__ mcoef,
-                                                        const int32_t *__restrict__ mbase, T *corr) {
-    extern __shared__ double dyn[];
-    T *sx = reinterpret_cast<T *>(dyn);
+                                                        const T *__restrict__ x, T *__restrict__ vcur, int Nb,
+                                                        int max_iter, int m, int fixed, double tol, double eta,
+                                                        int mixed) {
     __shared__ double red[16];
     double s = 0.0;
     for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
         s += abs2(b[k]);
-        sx[k] = x[k];
+        vcur[k] = x[k];
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
@@ -652,19 +674,16 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_init(GmCtl *ctl, const T *__r
         ctl->pad = 0;
         gm_set_state(ctl, kStStart);
     }
-    corr_merged_block(sx, Nb, n_irr, mcoef, mbase, corr);
 }
 
-// The control kernel of one slot (see the schedule above).  Dynamic LDS:
-// [Nb: working vector][nvl*Nb: staged basis][m*m: triangular factor at a
-// cycle end].
+// The control kernel of one slot (see the schedule above).  kv holds K vcur
+// from the slot's grid solve; the kernel ends by writing the density of the
+// next product to vcur.  Dynamic LDS: [Nb: working vector][nvl*Nb: staged
+// basis][m*m: triangular factor at a cycle end].
 template <class T, int EPT>
 __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mir, T *V, T *H, T *g, double *cs,
-                                                        T *sn, T *x, const T *__restrict__ b, int Nb, int m, int nvl,
-                                                        const T *__restrict__ ust, const double *__restrict__ w6,
-                                                        const T *__restrict__ bop, int n_irr,
-                                                        const T *__restrict__ mcoef,
-                                                        const int32_t *__restrict__ mbase, T *corr) {
+                                                        T *sn, T *x, const T *__restrict__ b, T *__restrict__ vcur,
+                                                        const T *__restrict__ kv, int Nb, int m, int nvl) {
     extern __shared__ double dyn[];
     T *sw = reinterpret_cast<T *>(dyn);
     T *sV = sw + Nb;
@@ -677,29 +696,32 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
     __shared__ T ys[72];
     __shared__ double scs[72];
     __shared__ double redd[16];
-    __shared__ int sflag;
-    const int state = ctl->state;
+    __shared__ int sflag, sconv, sit;
+    // one read of the control block (uniform); thread 0 writes back what
+    // changes, so no control field is re-read from memory on the critical path
+    const GmCtl c = *ctl;
+    const int state = c.state;
     if (state == kStDone) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int limit = ctl->fixed > 0 ? ctl->fixed : ctl->max_iter;
+    const int limit = c.fixed > 0 ? c.fixed : c.max_iter;
 
     if (state == kStStart) {
         // r = b - K x, stop test, v_0 = r / beta, corrections of v_0
         double s = 0.0;
         for (int k = tid; k < Nb; k += kGmThreads) {
-            const T r = b[k] - extract_k(k, Nb, ust, w6, bop, x);
+            const T r = b[k] - kv[k];
             sw[k] = r;
             s += abs2(r);
         }
         s = block_sum(s, redd);
         const double beta = sqrt(s);
-        const bool conv = beta <= ctl->tol * ctl->bnorm;
-        const bool stop = (ctl->fixed == 0 && conv) || beta == 0.0 || ctl->iters >= limit;
+        const bool conv = beta <= c.tol * c.bnorm;
+        const bool stop = (c.fixed == 0 && conv) || beta == 0.0 || c.iters >= limit;
         const double inv = stop ? 0.0 : 1.0 / beta;
         for (int k = tid; k < Nb; k += kGmThreads) {
             const T v = sw[k] * inv;
-            sw[k] = v;
             V[k] = v;
+            vcur[k] = v;
         }
         if (tid <= m) g[tid] = tid == 0 ? scale_of<T>(beta) : zero<T>();
         if (tid == 0) {
@@ -708,22 +730,18 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
             ctl->j = 0;
             ctl->breakdown = 0;
             ctl->converged = conv ? 1 : 0;
-            ctl->cycles += 1;
-            const double t0 = ctl->tol * ctl->bnorm, t1 = ctl->eta * beta;
+            ctl->cycles = c.cycles + 1;
+            const double t0 = c.tol * c.bnorm, t1 = c.eta * beta;
             ctl->thresh = t1 > t0 ? t1 : t0;
-            ctl->slot += 1;
+            ctl->slot = c.slot + 1;
             gm_set_state(ctl, stop ? kStDone : kStIter);
             gm_publish(ctl, mir);
-            sflag = stop ? 1 : 0;
         }
-        __syncthreads();
-        if (!sflag) corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr);
         return;
     }
 
     // Arnoldi step on column j: w = K v_j, CGS2, Givens
-    const int j = ctl->j;
-    const T *vj = V + (size_t)j * Nb;
+    const int j = c.j;
     T *w = V + (size_t)(j + 1) * Nb;
     if (tid < j) {
         scs[tid] = cs[tid];
@@ -732,14 +750,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
     if (tid <= j) sgv[tid] = g[tid];
     const int nst = j + 1 < nvl ? j + 1 : nvl;
     for (int q = tid; q < nst * Nb; q += kGmThreads) sV[q] = V[q];
-    T cpre[kWin];
-    int bpre = 0;
-    if (tid < n_irr) {
-        bpre = mbase[tid];
-#pragma unroll
-        for (int o = 0; o < kWin; ++o) cpre[o] = mcoef[(size_t)o * n_irr + tid];
-    }
-    for (int k = tid; k < Nb; k += kGmThreads) sw[k] = extract_k(k, Nb, ust, w6, bop, vj);
+    for (int k = tid; k < Nb; k += kGmThreads) sw[k] = kv[k];
     __syncthreads();
     T wl[EPT];
 #pragma unroll
@@ -747,8 +758,35 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
         const int k = tid + e * kGmThreads;
         wl[e] = k < Nb ? sw[k] : zero<T>();
     }
+    // CGS2 against v_0..v_j.  All of v_0..v_j staged: branch-free dot
+    // products (clamped LDS reads, masked terms) so that every read is in
+    // flight before the first use.
+    const bool staged = j + 1 <= nst;
     for (int pass = 0; pass < 2; ++pass) {
-        for (int i0 = 0; i0 <= j; i0 += 16) {
+        for (int i0 = 0; i0 <= j && staged; i0 += 16) {
+            T part[16];
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int idx = tid + e * kGmThreads;
+                if (idx < Nb) {
+                    T vv[16];
+#pragma unroll
+                    for (int ii = 0; ii < 16; ++ii) {
+                        const int i = i0 + ii <= j ? i0 + ii : j;
+                        vv[ii] = sV[(size_t)i * Nb + idx];
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < 16; ++ii)
+                        part[ii] += (i0 + ii <= j ? conjv(vv[ii]) : zero<T>()) * wl[e];
+                }
+            }
+            const T sum = wave_sum16(part, lane);
+            const int ii = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && i0 + ii <= j) red[wid][i0 + ii] = sum;
+        }
+        for (int i0 = 0; i0 <= j && !staged; i0 += 16) {
             T part[16];
 #pragma unroll
             for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
@@ -781,8 +819,22 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
         for (int e = 0; e < EPT; ++e) {
             const int idx = tid + e * kGmThreads;
             if (idx < Nb) {
-                for (int i = 0; i < nst; ++i) wl[e] -= hs[i] * sV[(size_t)i * Nb + idx];
-                for (int i = nst; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+                if (staged) {
+                    for (int i0 = 0; i0 <= j; i0 += 8) {
+                        T vv[8], hh[8];
+#pragma unroll
+                        for (int ii = 0; ii < 8; ++ii) {
+                            const int i = i0 + ii <= j ? i0 + ii : j;
+                            vv[ii] = sV[(size_t)i * Nb + idx];
+                            hh[ii] = i0 + ii <= j ? hs[i] : zero<T>();
+                        }
+#pragma unroll
+                        for (int ii = 0; ii < 8; ++ii) wl[e] -= hh[ii] * vv[ii];
+                    }
+                } else {
+                    for (int i = 0; i < nst; ++i) wl[e] -= hs[i] * sV[(size_t)i * Nb + idx];
+                    for (int i = nst; i <= j; ++i) wl[e] -= hs[i] * V[(size_t)i * Nb + idx];
+                }
             }
         }
     }
@@ -797,7 +849,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
         if (idx < Nb) {
             const T v = wl[e] * inv;
             w[idx] = v;
-            sw[idx] = v;
+            vcur[idx] = v;
         }
     }
     if (tid == 0) {
@@ -809,52 +861,44 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
         const T a = hcol[j];
         const double aa = absv(a);
         const double rho = hypot(aa, hn);
-        double c;
+        double cg;
         T sr;
         if (aa == 0.0) {
-            c = 0.0;
+            cg = 0.0;
             sr = scale_of<T>(1.0);
         } else {
-            c = aa / rho;
+            cg = aa / rho;
             sr = a * (hn / (aa * rho));
         }
-        cs[j] = c;
+        cs[j] = cg;
         sn[j] = sr;
-        hcol[j] = a * c + sr * hn;
+        hcol[j] = a * cg + sr * hn;
         hcol[j + 1] = zero<T>();
         const T gj = sgv[j];
         const T gj1 = -(conjv(sr) * gj);
         g[j + 1] = gj1;
-        g[j] = gj * c;
-        sgv[j] = gj * c;
+        g[j] = gj * cg;
+        sgv[j] = gj * cg;
         const double resid = absv(gj1);
         ctl->resid = resid;
-        const int it = ctl->iters + 1;
+        const int it = c.iters + 1;
         ctl->iters = it;
         ctl->j = j + 1;
-        const bool conv = resid <= ctl->thresh;
-        ctl->converged = (conv && ctl->eta == 0.0) ? 1 : 0;
+        const bool conv = resid <= c.thresh;
+        const int converged = (conv && c.eta == 0.0) ? 1 : 0;
+        ctl->converged = converged;
         if (hn == 0.0) ctl->breakdown = 1;
-        const bool end = (ctl->fixed == 0 && conv) || it >= limit || j + 1 >= m || hn == 0.0;
+        const bool end = (c.fixed == 0 && conv) || it >= limit || j + 1 >= m || hn == 0.0;
         sflag = end ? 1 : 0;
+        sconv = converged;
+        sit = it;
     }
     __syncthreads();
     if (tid <= j + 1) H[(size_t)tid * m + j] = hcol[tid];
     if (!sflag) {
-        // next Arnoldi step: corrections of v_{j+1}
-        if (tid < n_irr) {
-            T acc = zero<T>();
-#pragma unroll
-            for (int o = 0; o < kWin; ++o) {
-                int idx = bpre + o;
-                if (idx >= Nb) idx -= Nb;
-                acc += cpre[o] * sw[idx];
-            }
-            corr[tid] = acc;
-        }
-        corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr, kGmThreads);
+        // next Arnoldi step on v_{j+1} (already in vcur)
         if (tid == 0) {
-            ctl->slot += 1;
+            ctl->slot = c.slot + 1;
             gm_set_state(ctl, kStIter);
             gm_publish(ctl, mir);
         }
@@ -883,16 +927,14 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
             for (int i = 0; i < nst; ++i) acc += sV[(size_t)i * Nb + idx] * ys[i];
             for (int i = nst; i <= j; ++i) acc += V[(size_t)i * Nb + idx] * ys[i];
             x[idx] = acc;
-            sw[idx] = acc;
+            vcur[idx] = acc;
         }
     }
-    __syncthreads();
-    corr_merged_block(sw, Nb, n_irr, mcoef, mbase, corr);
     if (tid == 0) {
         // FP64: the residual estimate decides; mixed: the FP64 residual of
         // the next cycle start decides
-        const bool finished = ctl->converged || ctl->iters >= limit;
-        ctl->slot += 1;
+        const bool finished = sconv || sit >= limit;
+        ctl->slot = c.slot + 1;
         gm_set_state(ctl, finished ? kStDone : kStStart);
         gm_publish(ctl, mir);
     }
@@ -901,6 +943,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
 struct GmPtrs {
     GmCtl *ctl;
     void *V, *H, *g, *sn, *y, *x, *b, *r;
+    void *vcur;  // the density whose product the next slot computes
     double *cs;
 };
 
@@ -924,10 +967,18 @@ GmPtrs gm_layout(kfbi_domain *d, int mmax) {
     P.x = take(Nb * es);
     P.b = take(Nb * es);
     P.r = take(Nb * es);
+    P.vcur = take(Nb * es);
     return P;
 }
 
 }  // namespace
+
+// the density of the last solve on this domain (Nb values, device)
+const void *gmres_last_density(kfbi_domain *d) {
+    if (!d->gm) return nullptr;
+    GmPtrs P = gm_layout(d, 64);
+    return P.x;
+}
 
 size_t gmres_bytes(kfbi_domain *d) {
     const size_t es = elem_size(d), Nb = d->Nb, mmax = 64;
@@ -940,6 +991,7 @@ size_t gmres_bytes(kfbi_domain *d) {
     add(mmax * sizeof(double));
     add(mmax * es);
     add(mmax * es);
+    add(Nb * es);
     add(Nb * es);
     add(Nb * es);
     add(Nb * es);
@@ -1148,9 +1200,7 @@ static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index,
     const int ps = prof_begin(d);
 #define KFBI_SLOT(E)                                                                                             \
     k_gm_slot<T, E><<<1, kGmThreads, lds, s>>>(P.ctl, mir, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn,          \
-                                               (T *)P.x, (const T *)P.b, Nb, m, nvl, (const T *)d->ust, d->w6,   \
-                                               (const T *)d->bop, d->n_irr, (const T *)d->mcoef, d->mbase,       \
-                                               (T *)d->corr)
+                                               (T *)P.x, (const T *)P.b, (T *)P.vcur, (const T *)P.r, Nb, m, nvl)
     if (ept <= 1) KFBI_SLOT(1);
     else if (ept <= 2) KFBI_SLOT(2);
     else if (ept <= 4) KFBI_SLOT(4);
@@ -1159,14 +1209,13 @@ static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index,
 #undef KFBI_SLOT
     KFBI_CHECK_LAUNCH();
     // algorithmic bytes of an Arnoldi step at j = slot_index - 1 (one cycle
-    // start first): extraction inputs, both Gram-Schmidt sweeps, the new
-    // vector, the correction windows and the corrections written
+    // start first): K v_j, both Gram-Schmidt sweeps over the basis, the new
+    // vector (basis and vcur)
     int j = slot_index - 1;
     if (j < 0) j = 0;
     if (j > m - 1) j = m - 1;
     const double es = (double)sizeof(T);
-    const double bytes = (double)Nb * (6.0 * es + 6.0 * 8.0 + 5.0 * es + es) + 2.0 * (j + 1) * Nb * es +
-                         (double)Nb * es + (double)d->n_irr * (kWin * es + 4.0 + es);
+    const double bytes = (double)Nb * es + 2.0 * (j + 1) * Nb * es + 2.0 * Nb * es;
     prof_end(d, ps, KFBI_K_ARNOLDI, bytes);
     return KFBI_OK;
 }
@@ -1188,9 +1237,8 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, 
     GmMirror *mh = (GmMirror *)d->mirror_host;
     __atomic_store_n(&mh->seq, 0, __ATOMIC_RELEASE);
     const int fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
-    k_gm_init<T><<<1, kGmThreads, (size_t)Nb * sizeof(T), s>>>(
-        P.ctl, (const T *)P.b, (const T *)P.x, Nb, o.max_iter, m, fixed, o.tol, mixed ? 1e-5 : 0.0, mixed ? 1 : 0,
-        d->n_irr, (const T *)d->mcoef, d->mbase, (T *)d->corr);
+    k_gm_init<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.b, (const T *)P.x, (T *)P.vcur, Nb, o.max_iter, m,
+                                          fixed, o.tol, mixed ? 1e-5 : 0.0, mixed ? 1 : 0);
     KFBI_CHECK_LAUNCH();
     const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
     // first batch: the previous solve's slot count on this domain plus one
@@ -1200,11 +1248,12 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, 
         last_batch = batch;
         for (int c = 0; c < want; ++c) {
             d->prof_tag = n_enq + c;
-            KFBI_TRY(tridiag_solve_ctl(d, nullptr, d->corr, d->uhat, skip64));
-            KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, skip64));
+            // P.r receives K vcur
+            KFBI_TRY(tridiag_solve_phi(d, P.vcur, d->uhat, skip64, false));
+            KFBI_TRY(eval_extract_ctl(d, d->uhat, P.vcur, P.r, skip64, false));
             if (mixed) {
-                KFBI_TRY(tridiag_solve_low(d, d->corr, d->uhat32, skip32));
-                KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat32, d->ust, skip32, true));
+                KFBI_TRY(tridiag_solve_phi(d, P.vcur, d->uhat32, skip32, true));
+                KFBI_TRY(eval_extract_ctl(d, d->uhat32, P.vcur, P.r, skip32, true));
             }
             KFBI_TRY(launch_slot<T>(d, P, Nb, m, n_enq + c, s));
         }

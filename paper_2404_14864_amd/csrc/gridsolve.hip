@@ -30,6 +30,8 @@
 //                   the inverse transform of its row.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "kfbi_internal.h"
 
 namespace kfbi {
@@ -234,6 +236,8 @@ struct TriSparse {
     int nnz, n_act, n_seg;
 };
 
+constexpr int kCorrWin = 16;
+
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
 __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T *__restrict__ rhat,
                                                        const TC *__restrict__ corr, TriSparse sp,
@@ -254,7 +258,8 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T
     T *spart = tile + tile_len;                          // n_seg*MB partial sums
     // staged sparse right-hand side: values, columns, row pointers, row
     // order, segment tables
-    T *sval = spart + (corr ? n_seg * MB : 0);
+    const bool sparse = corr != nullptr;
+    T *sval = spart + (sparse ? n_seg * MB : 0);
     int32_t *scol = reinterpret_cast<int32_t *>(sval + (STAGE ? nnz : 0));
     int32_t *srp = scol + (STAGE ? nnz : 0);
     int32_t *srow = srp + (STAGE ? n + 1 : 0);
@@ -303,6 +308,8 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T
                 }
             }
         }
+    }
+    if (STAGE && sparse) {
         for (int q = threadIdx.x; q <= n; q += NT) srp[q] = sp.row_ptr[q];
         for (int q = threadIdx.x; q < n_seg; q += NT) {
             ssq0[q] = sp.seg_q0[q];
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T
     // several LDS round trips in flight.  Then one thread per row adds its
     // segments' partial sums in order, so the result does not depend on
     // the schedule.
-    if (corr) {
+    if (sparse) {
         for (int sg = threadIdx.x; sg < n_seg; sg += NT) {
             const int t = STAGE ? ssrow[sg] : sp.seg_row[sg];
             int q = STAGE ? ssq0[sg] : sp.seg_q0[sg];
@@ -481,6 +488,67 @@ __global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int
     if (lane == 0) out[p] = to_high(acc * (R)(2.0 / M));
 }
 
+// corrections of a density with the merged operator, one thread per node
+template <class TC>
+__global__ void k_corr_phi(const TC *__restrict__ phi, int Nb, int nnz, const TC *__restrict__ mcoef,
+                           const int32_t *__restrict__ mbase, TC *__restrict__ corr, const int *done) {
+    if (done && *done) return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int b = mbase[q];
+    TC acc = zero<TC>();
+#pragma unroll
+    for (int o = 0; o < kCorrWin; ++o) {
+        int idx = b + o;
+        if (idx >= Nb) idx -= Nb;
+        acc += mcoef[(size_t)o * nnz + q] * phi[idx];
+    }
+    corr[q] = acc;
+}
+
+// K phi at the collocation points, one workgroup of six wavefronts per
+// point: wavefront p evaluates the grid solution at stencil node p (as
+// k_eval_nodes: U = (2/M) sum_k U^[t][k] sin(pi i k / M), summed in the
+// precision of U^ and stored in FP64), then one thread forms the extraction
+// U+(z_k) = sum_p w6[k][p] U_p + sum_o bop[k][o] phi[k-2+o] in FP64 (the
+// compact form of the six-point rule with the jump terms of the outside
+// nodes, eq. 3.36).
+template <class T, class TO>
+__global__ __launch_bounds__(384) void k_eval_extract(int M, int Nb, const int32_t *__restrict__ nodes,
+                                                      int node_stride, const T *__restrict__ uhat,
+                                                      const typename Real<T>::type *__restrict__ sine,
+                                                      const double *__restrict__ w6, const TO *__restrict__ bop,
+                                                      const TO *__restrict__ phi, TO *__restrict__ kv,
+                                                      const int *__restrict__ done) {
+    typedef typename Real<T>::type R;
+    __shared__ TO su[6];
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int k = blockIdx.x;
+    const int n = M - 1, mask2M = 2 * M - 1;
+    const int node = nodes[(size_t)k * node_stride + p];
+    const int i = node % (M + 1);
+    const T *row = uhat + (size_t)(node / (M + 1) - 1) * n;
+    T acc = zero<T>();
+    for (int kk = lane; kk < n; kk += 64) acc += row[kk] * sine[(i * (kk + 1)) & mask2M];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+    if (lane == 0) su[p] = to_high(acc * (R)(2.0 / M));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        TO r = zero<TO>();
+#pragma unroll
+        for (int q = 0; q < 6; ++q) r += su[q] * w6[6 * k + q];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            int idx = k - 2 + o;
+            idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
+            r += bop[5 * k + o] * phi[idx];
+        }
+        kv[k] = r;
+    }
+}
+
 template <class T>
 int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out,
                bool out_grid, double scale, const int *done = nullptr) {
@@ -539,11 +607,11 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
     sp.nnz = d->n_irr;
     sp.n_act = d->n_act_rows;
     sp.n_seg = d->n_seg;
+    typedef typename High<T>::type TC;
     const size_t stage_bytes = (size_t)sp.nnz * (sizeof(T) + sizeof(int32_t)) +
                                (size_t)(n + 1 + 2 * sp.n_act + 1 + 2 * sp.n_seg) * sizeof(int32_t);
     const bool stage = corr && lds + stage_bytes <= kTriLdsMax;
     if (stage) lds += stage_bytes;
-    typedef typename High<T>::type TC;
     typedef typename Real<T>::type R;
     const bool low = sizeof(T) < sizeof(TC);
     const T *etab = (const T *)(low ? d->etab32 : d->etab);
@@ -643,6 +711,38 @@ int ensure_coefficients_low(kfbi_domain *d, double kre, double kim) {
     return KFBI_OK;
 }
 
+int tridiag_solve_phi(kfbi_domain *d, const void *phi, void *uhat_out, const int *done, bool low) {
+    if (!d->op_merged) {
+        set_error("the density form of the grid solve needs the merged correction operator");
+        return KFBI_ENOTSUP;
+    }
+    // corrections once, by many workgroups (every tridiagonal workgroup
+    // needs all of them), then the sparse grid solve
+    KFBI_TRY(corrections_of_density(d, phi, d->corr, done));
+    if (low) {
+        if (d->cplx) return launch_tridiag<cf>(d, nullptr, d->corr, uhat_out, done);
+        return launch_tridiag<float>(d, nullptr, d->corr, uhat_out, done);
+    }
+    if (d->cplx) return launch_tridiag<cd>(d, nullptr, d->corr, uhat_out, done);
+    return launch_tridiag<double>(d, nullptr, d->corr, uhat_out, done);
+}
+
+int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done) {
+    const int nnz = d->n_irr;
+    const int ps = prof_begin(d);
+    if (d->cplx)
+        k_corr_phi<cd><<<(nnz + 63) / 64, 64, 0, d->stream>>>((const cd *)phi, d->Nb, nnz, (const cd *)d->mcoef,
+                                                             d->mbase, (cd *)corr_out, done);
+    else
+        k_corr_phi<double><<<(nnz + 63) / 64, 64, 0, d->stream>>>((const double *)phi, d->Nb, nnz,
+                                                                 (const double *)d->mcoef, d->mbase,
+                                                                 (double *)corr_out, done);
+    KFBI_CHECK_LAUNCH();
+    const double es = elem_size(d);
+    prof_end(d, ps, KFBI_K_CORRECTIONS, (double)nnz * (kCorrWin * es + 4.0 + es) + (double)d->Nb * es);
+    return KFBI_OK;
+}
+
 int tridiag_solve_low(kfbi_domain *d, const void *corr, void *uhat32_out, const int *done) {
     if (d->cplx) return launch_tridiag<cf>(d, nullptr, corr, uhat32_out, done);
     return launch_tridiag<float>(d, nullptr, corr, uhat32_out, done);
@@ -675,6 +775,39 @@ int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *
 
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out) {
     return eval_stencil_nodes_ctl(d, uhat, ust_out, nullptr, false);
+}
+
+int eval_extract_ctl(kfbi_domain *d, const void *uhat, const void *phi, void *kv_out, const int *done, bool low) {
+    const int Nb = d->Nb;
+    const int stride = (int)(sizeof(Stencil) / sizeof(int32_t));
+    const int32_t *nodes = reinterpret_cast<const int32_t *>(d->st);
+    const int grid = Nb;
+    const int ps = prof_begin(d);
+    if (d->cplx) {
+        if (low)
+            k_eval_extract<cf, cd><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride, (const cf *)uhat, d->sine32,
+                                                                d->w6, (const cd *)d->bop, (const cd *)phi,
+                                                                (cd *)kv_out, done);
+        else
+            k_eval_extract<cd, cd><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride, (const cd *)uhat, d->sine,
+                                                                d->w6, (const cd *)d->bop, (const cd *)phi,
+                                                                (cd *)kv_out, done);
+    } else {
+        if (low)
+            k_eval_extract<float, double><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride, (const float *)uhat,
+                                                                       d->sine32, d->w6, (const double *)d->bop,
+                                                                       (const double *)phi, (double *)kv_out, done);
+        else
+            k_eval_extract<double, double><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride,
+                                                                        (const double *)uhat, d->sine, d->w6,
+                                                                        (const double *)d->bop, (const double *)phi,
+                                                                        (double *)kv_out, done);
+    }
+    KFBI_CHECK_LAUNCH();
+    const double es = low ? elem_size(d) / 2.0 : elem_size(d), eo = elem_size(d);
+    prof_end(d, ps, KFBI_K_EVAL_NODES,
+             (double)Nb * (6.0 * ((d->M - 1) * es + 4.0) + 6.0 * 8.0 + 5.0 * eo + 2.0 * eo));
+    return KFBI_OK;
 }
 
 int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low) {

@@ -295,9 +295,19 @@ int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const 
 // U at the 6 Nb stencil nodes
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out);
 int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low = false);
+// K phi at the collocation points from the mode-space solution of phi's
+// corrections (merged operator form: stencil weights w6, jump terms bop)
+int eval_extract_ctl(kfbi_domain *d, const void *uhat, const void *phi, void *kv_out, const int *done, bool low);
 // mixed precision: FP32 / complex64 coefficient tables and grid solve
 int ensure_coefficients_low(kfbi_domain *d, double kre, double kim);
 int tridiag_solve_low(kfbi_domain *d, const void *corr, void *uhat32_out, const int *done);
+// grid solve of the corrections of a density phi (FP64 / complex128, Nb
+// values; corrections with the merged operator); low: FP32 / complex64 solve
+int tridiag_solve_phi(kfbi_domain *d, const void *phi, void *uhat_out, const int *done, bool low);
+// the density of the last solve on the domain (null before the first)
+const void *gmres_last_density(kfbi_domain *d);
+// corrections of a density with the merged operator (many workgroups)
+int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done);
 
 // interface pieces (interface.hip)
 int compute_corrections(kfbi_domain *d, double kre, double kim, const void *phi,
