@@ -14,9 +14,11 @@ final grid solve.
 Metric: grid-pts * GMRES-iters / s = sum over steps of (M-1)^2 * iterations,
 divided by the wall time of the timed steps (inputs resident in HBM).
 
-Also reported: p50/p99 step latency, the dominant kernel's achieved
-algorithmic bandwidth against the 8 TB/s HBM peak (HIP events around its
-launches), and the CPU oracle timed on a bounded sample of the same workload.
+Also reported: p50/p99 step latency (device time per step from HIP events),
+the dominant kernel's achieved algorithmic bandwidth against the 8 TB/s HBM
+peak (its launch duration from back-to-back replay launches between two HIP
+events), its measured HBM traffic, and the CPU oracle timed on a bounded
+sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 3]
 """
@@ -28,10 +30,12 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (profiles/), filled in when the kernel has been counted at its
-# current version; None otherwise
-TRAFFIC = {}
+# HBM bytes per launch of the kernel at its current version, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
+# on a 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); the
+# counts and the commands are in profiles/tridiag_wave512_fp64_hbm_traffic.md.
+# Kernels not listed (or changed since they were counted) report null.
+TRAFFIC = {"tridiag_sparse": 2596418.0}
 
 
 def parse():
@@ -44,6 +48,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--replay", type=int, default=200)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device three times (the reference transfer "
+                         "for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -213,6 +220,15 @@ def main():
 
     kfbi.kfbi_stepper_destroy(st)
     kfbi.kfbi_domain_destroy(dom)
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nb, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB three times" % args.calibrate_copy)
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -222,6 +222,18 @@ __global__ void k_coef(int M, double kh2_re, double kh2_im, S *etab, S *elim, in
 // LDS per workgroup on gfx950: 160 KB
 constexpr size_t kTriLdsMax = 163840;
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
+// b mod 8).  xcd_tile maps workgroup b to a tile index so that each XCD
+// owns one contiguous run of tiles (a bijection on [0, G) for any G): the
+// mode groups written by one XCD are then adjacent, and the partial rows
+// each workgroup writes merge into whole cache lines in that XCD's L2
+// before they go to HBM.
+__device__ inline int xcd_tile(int b, int G) {
+    const int x = b & 7, i = b >> 3, per = G >> 3, rem = G & 7;
+    const int first = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return first + i;
+}
+
 template <int MB, int C>
 __device__ inline int tidx(int t, int m) {
     return t * MB + m + t / C;
@@ -266,7 +278,7 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T
     int32_t *ssq0 = srow + (STAGE ? n_act : 0);
     int32_t *ssrow = ssq0 + (STAGE ? n_seg : 0);
     int32_t *srseg = ssrow + (STAGE ? n_seg : 0);
-    const int k0 = blockIdx.x * MB;
+    const int k0 = xcd_tile(blockIdx.x, gridDim.x) * MB;
     const int lane = threadIdx.x % LANES;
     const int m = threadIdx.x / LANES;
     const int k = k0 + m;
