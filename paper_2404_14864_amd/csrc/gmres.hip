@@ -642,10 +642,23 @@ __device__ inline void gm_publish(GmCtl *ctl, GmMirror *mir) {
 
 // control block, ||b||, and x_0 as the first slot's density
 template <class T>
-__global__ __launch_bounds__(kGmThreads) void k_gm_init(GmCtl *ctl, const T *__restrict__ b,
-                                                        const T *__restrict__ x, T *__restrict__ vcur, int Nb,
-                                                        int max_iter, int m, int fixed, double tol, double eta,
-                                                        int mixed) {
+struct GmInitArgs {
+    GmCtl *ctl;
+    const T *b, *x;
+    T *vcur;
+    int Nb, max_iter, m, fixed;
+    double tol, eta;
+    int mixed;
+};
+
+template <class T>
+__device__ void gm_init_body(const GmInitArgs<T> &A, int) {
+    GmCtl *ctl = A.ctl;
+    const T *__restrict__ b = A.b;
+    const T *__restrict__ x = A.x;
+    T *__restrict__ vcur = A.vcur;
+    const int Nb = A.Nb, max_iter = A.max_iter, m = A.m, fixed = A.fixed, mixed = A.mixed;
+    const double tol = A.tol, eta = A.eta;
     __shared__ double red[16];
     double s = 0.0;
     for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
@@ -676,14 +689,38 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_init(GmCtl *ctl, const T *__r
     }
 }
 
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_gm_init(GmInitArgs<T> A) {
+    gm_init_body(A, 0);
+}
+
 // The control kernel of one slot (see the schedule above).  kv holds K vcur
 // from the slot's grid solve; the kernel ends by writing the density of the
 // next product to vcur.  Dynamic LDS: [Nb: working vector][nvl*Nb: staged
 // basis][m*m: triangular factor at a cycle end].
+template <class T>
+struct SlotArgs {
+    GmCtl *ctl;
+    GmMirror *mir;
+    T *V, *H, *g;
+    double *cs;
+    T *sn, *x;
+    const T *b;
+    T *vcur;
+    const T *kv;
+    int Nb, m, nvl;
+};
+
 template <class T, int EPT>
-__global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mir, T *V, T *H, T *g, double *cs,
-                                                        T *sn, T *x, const T *__restrict__ b, T *__restrict__ vcur,
-                                                        const T *__restrict__ kv, int Nb, int m, int nvl) {
+__device__ void gm_slot_body(const SlotArgs<T> &A, int) {
+    GmCtl *ctl = A.ctl;
+    GmMirror *mir = A.mir;
+    T *V = A.V, *H = A.H, *g = A.g, *sn = A.sn, *x = A.x;
+    double *cs = A.cs;
+    const T *__restrict__ b = A.b;
+    T *__restrict__ vcur = A.vcur;
+    const T *__restrict__ kv = A.kv;
+    const int Nb = A.Nb, m = A.m, nvl = A.nvl;
     extern __shared__ double dyn[];
     T *sw = reinterpret_cast<T *>(dyn);
     T *sV = sw + Nb;
@@ -940,6 +977,11 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(GmCtl *ctl, GmMirror *mi
     }
 }
 
+template <class T, int EPT>
+__global__ __launch_bounds__(kGmThreads) void k_gm_slot(SlotArgs<T> A) {
+    gm_slot_body<T, EPT>(A, 0);
+}
+
 struct GmPtrs {
     GmCtl *ctl;
     void *V, *H, *g, *sn, *y, *x, *b, *r;
@@ -1186,6 +1228,43 @@ static size_t slot_lds(int Nb, int m, int *nvl_out) {
 }
 
 template <class T>
+GmInitArgs<T> gm_init_args(GmPtrs &P, int Nb, const kfbi_solve_opts &o, bool mixed) {
+    GmInitArgs<T> A;
+    A.ctl = P.ctl;
+    A.b = (const T *)P.b;
+    A.x = (const T *)P.x;
+    A.vcur = (T *)P.vcur;
+    A.Nb = Nb;
+    A.max_iter = o.max_iter;
+    A.m = o.restart;
+    A.fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
+    A.tol = o.tol;
+    A.eta = mixed ? 1e-5 : 0.0;
+    A.mixed = mixed ? 1 : 0;
+    return A;
+}
+
+template <class T>
+SlotArgs<T> slot_args(GmPtrs &P, GmMirror *mir, int Nb, int m, int nvl) {
+    SlotArgs<T> A;
+    A.ctl = P.ctl;
+    A.mir = mir;
+    A.V = (T *)P.V;
+    A.H = (T *)P.H;
+    A.g = (T *)P.g;
+    A.cs = P.cs;
+    A.sn = (T *)P.sn;
+    A.x = (T *)P.x;
+    A.b = (const T *)P.b;
+    A.vcur = (T *)P.vcur;
+    A.kv = (const T *)P.r;
+    A.Nb = Nb;
+    A.m = m;
+    A.nvl = nvl;
+    return A;
+}
+
+template <class T>
 static bool slots_supported(kfbi_domain *d, int m) {
     int nvl;
     return d->op_merged && (size_t)d->Nb * sizeof(T) <= 65536 && slot_lds<T>(d->Nb, m, &nvl) <= kGmIterLds;
@@ -1198,9 +1277,8 @@ static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index,
     const int ept = (Nb + kGmThreads - 1) / kGmThreads;
     GmMirror *mir = (GmMirror *)d->mirror_dev;
     const int ps = prof_begin(d);
-#define KFBI_SLOT(E)                                                                                             \
-    k_gm_slot<T, E><<<1, kGmThreads, lds, s>>>(P.ctl, mir, (T *)P.V, (T *)P.H, (T *)P.g, P.cs, (T *)P.sn,          \
-                                               (T *)P.x, (const T *)P.b, (T *)P.vcur, (const T *)P.r, Nb, m, nvl)
+    const SlotArgs<T> A = slot_args<T>(P, mir, Nb, m, nvl);
+#define KFBI_SLOT(E) k_gm_slot<T, E><<<1, kGmThreads, lds, s>>>(A)
     if (ept <= 1) KFBI_SLOT(1);
     else if (ept <= 2) KFBI_SLOT(2);
     else if (ept <= 4) KFBI_SLOT(4);
@@ -1237,8 +1315,7 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, 
     GmMirror *mh = (GmMirror *)d->mirror_host;
     __atomic_store_n(&mh->seq, 0, __ATOMIC_RELEASE);
     const int fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
-    k_gm_init<T><<<1, kGmThreads, 0, s>>>(P.ctl, (const T *)P.b, (const T *)P.x, (T *)P.vcur, Nb, o.max_iter, m,
-                                          fixed, o.tol, mixed ? 1e-5 : 0.0, mixed ? 1 : 0);
+    k_gm_init<T><<<1, kGmThreads, 0, s>>>(gm_init_args<T>(P, Nb, o, mixed));
     KFBI_CHECK_LAUNCH();
     const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
     // first batch: the previous solve's slot count on this domain plus one

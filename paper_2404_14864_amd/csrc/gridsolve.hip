@@ -71,10 +71,6 @@ template <> __device__ inline cd one<cd>() { return make_cd(1.0, 0.0); }
 template <> __device__ inline float one<float>() { return 1.0f; }
 template <> __device__ inline cf one<cf>() { return make_cf(1.0f, 0.0f); }
 
-// real scalar type of an element type (sine tables, scale factors)
-template <class T> struct Real { typedef double type; };
-template <> struct Real<float> { typedef float type; };
-template <> struct Real<cf> { typedef float type; };
 
 __device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (32 - bits); }
 
@@ -88,16 +84,21 @@ __device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (3
 // 2i S1_k; a complex row's transform is Y_k = -2i S_k.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256) void k_dst_rows(int M, int logN2, const T *in, bool in_grid,
-                                                  const uint8_t *mask, T *out, bool out_grid,
-                                                  double scale, const double *twiddle, const int *done) {
-    if (done && *done) return;
+__device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
+    const int M = A.M, logN2 = A.logN2;
+    const T *in = A.in;
+    const bool in_grid = A.in_grid, out_grid = A.out_grid;
+    const uint8_t *mask = A.mask;
+    T *out = A.out;
+    const double scale = A.scale;
+    const double *twiddle = A.twiddle;
+    if (A.done && *A.done) return;
     extern __shared__ double lds[];
     double2 *a = reinterpret_cast<double2 *>(lds);
     const int n = M - 1, N2 = 2 * M;
     constexpr bool CPLX = sizeof(T) == sizeof(cd);
     const int rows_per = CPLX ? 1 : 2;
-    const int t_first = blockIdx.x * rows_per;
+    const int t_first = blk * rows_per;
     // load the odd extension, bit-reversed
     for (int m = threadIdx.x; m < N2; m += blockDim.x) {
         double re = 0.0, im = 0.0;
@@ -164,14 +165,25 @@ __global__ __launch_bounds__(256) void k_dst_rows(int M, int logN2, const T *in,
     }
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_dst_rows(DstArgs<T> A) {
+    dst_rows_body(A, blockIdx.x);
+}
+
 // first and last grid rows of a grid array: zero
 template <class T>
-__global__ void k_zero_edge_rows(int M, T *grid, const int *done) {
-    if (done && *done) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void zero_edge_body(const ZeroArgs<T> &A, int blk) {
+    if (A.done && *A.done) return;
+    const int M = A.M;
+    int i = blk * blockDim.x + threadIdx.x;
     if (i > M) return;
-    grid[i] = zero<T>();
-    grid[(size_t)M * (M + 1) + i] = zero<T>();
+    A.grid[i] = zero<T>();
+    A.grid[(size_t)M * (M + 1) + i] = zero<T>();
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_zero_edge_rows(ZeroArgs<T> A) {
+    zero_edge_body(A, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,21 +255,23 @@ __device__ inline int tidx(int t, int m) {
 // the corrections arrive in FP64 (TC) and are rounded once when staged.
 // STAGE: the sparse right-hand side and its segment tables are copied to
 // LDS first; otherwise they are read from global memory.
-struct TriSparse {
-    const int32_t *irr_col, *row_ptr, *row_order, *seg_q0, *seg_row, *row_seg;
-    int nnz, n_act, n_seg;
-};
 
 constexpr int kCorrWin = 16;
 
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
-__global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T *__restrict__ rhat,
-                                                       const TC *__restrict__ corr, TriSparse sp,
-                                                       const typename Real<T>::type *__restrict__ sine,
-                                                       const T *__restrict__ etab, const T *__restrict__ elim,
-                                                       const int32_t *__restrict__ tconv, T *__restrict__ uhat,
-                                                       const int *__restrict__ done) {
+__device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     typedef typename Real<T>::type R;
+    const int M = A.M;
+    const double h2 = A.h2;
+    const T *__restrict__ rhat = A.rhat;
+    const TC *__restrict__ corr = A.corr;
+    const TriSparse &sp = A.sp;
+    const R *__restrict__ sine = A.sine;
+    const T *__restrict__ etab = A.etab;
+    const T *__restrict__ elim = A.elim;
+    const int32_t *__restrict__ tconv = A.tconv;
+    T *__restrict__ uhat = A.uhat;
+    const int *__restrict__ done = A.done;
     extern __shared__ double lds[];
     constexpr int NT = MB * LANES;
     const int n = M - 1;
@@ -278,7 +292,7 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T
     int32_t *ssq0 = srow + (STAGE ? n_act : 0);
     int32_t *ssrow = ssq0 + (STAGE ? n_seg : 0);
     int32_t *srseg = ssrow + (STAGE ? n_seg : 0);
-    const int k0 = xcd_tile(blockIdx.x, gridDim.x) * MB;
+    const int k0 = tile_idx * MB;
     const int lane = threadIdx.x % LANES;
     const int m = threadIdx.x / LANES;
     const int k = k0 + m;
@@ -472,20 +486,27 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(int M, double h2, const T
     }
 }
 
+template <class T, class TC, int MB, int LANES, int C, bool STAGE>
+__global__ __launch_bounds__(MB *LANES) void k_tridiag(TriArgs<T, TC> A) {
+    tridiag_body<T, TC, MB, LANES, C, STAGE>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // U at listed nodes: one wavefront per node, U = (2/M) sum_k U^[t][k]
 // sin(pi i k / M).  nodes: linear grid indices (interior nodes only).
 // ---------------------------------------------------------------------------
 // T: precision of U^ and of the sum; the result is stored in FP64 (TO)
 template <class T, class TO>
-__global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int32_t *__restrict__ nodes,
-                                                    int node_stride, const T *__restrict__ uhat,
-                                                    const typename Real<T>::type *__restrict__ sine,
-                                                    TO *__restrict__ out, const int *__restrict__ done) {
+__device__ void eval_nodes_body(const EvalArgs<T, TO> &A, int blk) {
     typedef typename Real<T>::type R;
-    if (done && *done) return;
+    const int M = A.M, nnodes = A.nnodes, node_stride = A.node_stride;
+    const int32_t *__restrict__ nodes = A.nodes;
+    const T *__restrict__ uhat = A.uhat;
+    const R *__restrict__ sine = A.sine;
+    TO *__restrict__ out = A.out;
+    if (A.done && *A.done) return;
     const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int p = blk * 4 + (threadIdx.x >> 6);
     if (p >= nnodes) return;
     const int n = M - 1, mask2M = 2 * M - 1;
     // nodes of a stencil record are 6 consecutive int32 followed by the rest of
@@ -500,12 +521,21 @@ __global__ __launch_bounds__(256) void k_eval_nodes(int M, int nnodes, const int
     if (lane == 0) out[p] = to_high(acc * (R)(2.0 / M));
 }
 
+template <class T, class TO>
+__global__ __launch_bounds__(256) void k_eval_nodes(EvalArgs<T, TO> A) {
+    eval_nodes_body(A, blockIdx.x);
+}
+
 // corrections of a density with the merged operator, one thread per node
 template <class TC>
-__global__ void k_corr_phi(const TC *__restrict__ phi, int Nb, int nnz, const TC *__restrict__ mcoef,
-                           const int32_t *__restrict__ mbase, TC *__restrict__ corr, const int *done) {
-    if (done && *done) return;
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void corr_phi_body(const CorrPhiArgs<TC> &A, int blk) {
+    const TC *__restrict__ phi = A.phi;
+    const int Nb = A.Nb, nnz = A.nnz;
+    const TC *__restrict__ mcoef = A.mcoef;
+    const int32_t *__restrict__ mbase = A.mbase;
+    TC *__restrict__ corr = A.corr;
+    if (A.done && *A.done) return;
+    const int q = blk * blockDim.x + threadIdx.x;
     if (q >= nnz) return;
     const int b = mbase[q];
     TC acc = zero<TC>();
@@ -518,6 +548,11 @@ __global__ void k_corr_phi(const TC *__restrict__ phi, int Nb, int nnz, const TC
     corr[q] = acc;
 }
 
+template <class TC>
+__global__ __launch_bounds__(64) void k_corr_phi(CorrPhiArgs<TC> A) {
+    corr_phi_body(A, blockIdx.x);
+}
+
 // K phi at the collocation points, one workgroup of six wavefronts per
 // point: wavefront p evaluates the grid solution at stencil node p (as
 // k_eval_nodes: U = (2/M) sum_k U^[t][k] sin(pi i k / M), summed in the
@@ -526,17 +561,20 @@ __global__ void k_corr_phi(const TC *__restrict__ phi, int Nb, int nnz, const TC
 // compact form of the six-point rule with the jump terms of the outside
 // nodes, eq. 3.36).
 template <class T, class TO>
-__global__ __launch_bounds__(384) void k_eval_extract(int M, int Nb, const int32_t *__restrict__ nodes,
-                                                      int node_stride, const T *__restrict__ uhat,
-                                                      const typename Real<T>::type *__restrict__ sine,
-                                                      const double *__restrict__ w6, const TO *__restrict__ bop,
-                                                      const TO *__restrict__ phi, TO *__restrict__ kv,
-                                                      const int *__restrict__ done) {
+__device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     typedef typename Real<T>::type R;
+    const int M = A.M, Nb = A.Nb, node_stride = A.node_stride;
+    const int32_t *__restrict__ nodes = A.nodes;
+    const T *__restrict__ uhat = A.uhat;
+    const R *__restrict__ sine = A.sine;
+    const double *__restrict__ w6 = A.w6;
+    const TO *__restrict__ bop = A.bop;
+    const TO *__restrict__ phi = A.phi;
+    TO *__restrict__ kv = A.kv;
     __shared__ TO su[6];
-    if (done && *done) return;
+    if (A.done && *A.done) return;
     const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
-    const int k = blockIdx.x;
+    const int k = blk;
     const int n = M - 1, mask2M = 2 * M - 1;
     const int node = nodes[(size_t)k * node_stride + p];
     const int i = node % (M + 1);
@@ -561,18 +599,42 @@ __global__ __launch_bounds__(384) void k_eval_extract(int M, int Nb, const int32
     }
 }
 
+template <class T, class TO>
+__global__ __launch_bounds__(384) void k_eval_extract(EvxArgs<T, TO> A) {
+    eval_extract_body(A, blockIdx.x);
+}
+
+// argument blocks and launch shapes shared by the single and batched paths
+template <class T>
+DstArgs<T> dst_args(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out, bool out_grid,
+                    double scale, const int *done) {
+    DstArgs<T> A;
+    A.M = d->M;
+    A.logN2 = 0;
+    while ((1 << A.logN2) < 2 * d->M) ++A.logN2;
+    A.in = (const T *)in;
+    A.in_grid = in_grid ? 1 : 0;
+    A.mask = mask;
+    A.out = (T *)out;
+    A.out_grid = out_grid ? 1 : 0;
+    A.scale = scale;
+    A.twiddle = d->twiddle;
+    A.done = done;
+    return A;
+}
+template <class T>
+int dst_blocks(int M) {
+    return sizeof(T) == sizeof(cd) ? M - 1 : M / 2;
+}
+inline size_t dst_lds(int M) { return (size_t)2 * M * sizeof(double2); }
+
 template <class T>
 int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out,
                bool out_grid, double scale, const int *done = nullptr) {
     const int M = d->M, n = M - 1;
-    int logN2 = 0;
-    while ((1 << logN2) < 2 * M) ++logN2;
-    const bool cplx = sizeof(T) == sizeof(cd);
-    int blocks = cplx ? n : (n + 1) / 2;
-    size_t lds = (size_t)2 * M * sizeof(double2);
+    const DstArgs<T> A = dst_args<T>(d, in, in_grid, mask, out, out_grid, scale, done);
     const int ps = prof_begin(d);
-    k_dst_rows<T><<<blocks, 256, lds, d->stream>>>(M, logN2, (const T *)in, in_grid, mask, (T *)out,
-                                                   out_grid, scale, d->twiddle, done);
+    k_dst_rows<T><<<dst_blocks<T>(M), 256, dst_lds(M), d->stream>>>(A);
     KFBI_CHECK_LAUNCH();
     {
         const double es = sizeof(T), nn = (double)n * n, grid = (double)(M + 1) * (M + 1);
@@ -580,67 +642,155 @@ int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask
         prof_end(d, ps, in_grid ? KFBI_K_DST : KFBI_K_IDST, bytes);
     }
     if (out_grid) {
-        k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(M, (T *)out, done);
+        k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(ZeroArgs<T>{M, (T *)out, done});
         KFBI_CHECK_LAUNCH();
     }
     return KFBI_OK;
 }
 
+template <class TC>
+CorrPhiArgs<TC> corr_phi_args(kfbi_domain *d, const void *phi, void *corr, const int *done) {
+    return CorrPhiArgs<TC>{(const TC *)phi, d->Nb, d->n_irr, (const TC *)d->mcoef, d->mbase, (TC *)corr, done};
+}
+
+template <class T, class TO>
+EvxArgs<T, TO> evx_args(kfbi_domain *d, const void *uhat, const void *phi, void *kv, const int *done) {
+    typedef typename Real<T>::type R;
+    const bool low = sizeof(T) < sizeof(TO);
+    EvxArgs<T, TO> A;
+    A.M = d->M;
+    A.Nb = d->Nb;
+    A.node_stride = (int)(sizeof(Stencil) / sizeof(int32_t));
+    A.nodes = reinterpret_cast<const int32_t *>(d->st);
+    A.uhat = (const T *)uhat;
+    A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.w6 = d->w6;
+    A.bop = (const TO *)d->bop;
+    A.phi = (const TO *)phi;
+    A.kv = (TO *)kv;
+    A.done = done;
+    return A;
+}
+
+template <class T, class TO>
+EvalArgs<T, TO> eval_args(kfbi_domain *d, const void *uhat, void *out, const int *done) {
+    typedef typename Real<T>::type R;
+    const bool low = sizeof(T) < sizeof(TO);
+    EvalArgs<T, TO> A;
+    A.M = d->M;
+    A.nnodes = 6 * d->Nb;
+    A.node_stride = (int)(sizeof(Stencil) / sizeof(int32_t));
+    A.nodes = reinterpret_cast<const int32_t *>(d->st);
+    A.uhat = (const T *)uhat;
+    A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.out = (TO *)out;
+    A.done = done;
+    return A;
+}
+
+// launch shape of the tridiagonal kernel for one domain: modes per
+// workgroup (the largest power of two <= 4 whose LDS tile stays within
+// 32 KB, unless the domain fixes it; eight modes use 32-lane groups, fewer
+// use 64), rows per lane, LDS and whether the sparse input is staged
+struct TriShape {
+    int mb, lanes, c, blocks;
+    size_t lds, lds_base, stage_bytes;
+};
+
 template <class T>
-int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
-    const int M = d->M, n = M - 1;
-    const double h2 = d->h * d->h;
-    // modes per workgroup: the largest power of two (<= 4) whose LDS tile
-    // stays within 32 KB (a domain may fix it); eight modes use 32-lane
-    // groups, fewer use 64
+TriShape tri_shape(const kfbi_domain *d, bool sparse) {
+    TriShape S;
+    const int n = d->M - 1;
     int mb = d->tri_mb;
     if (mb <= 0) {
         mb = 4;
         while (mb > 1 && (size_t)n * mb * sizeof(T) > 32768) mb >>= 1;
     }
-    const int lanes = mb == 8 ? 32 : 64;
-    int c = 1;
-    while (lanes * c < n) c <<= 1;
-    const int blocks = (n + mb - 1) / mb;
-    size_t lds = (size_t)2 * M * sizeof(double) + ((size_t)n * mb + n / c + 1) * sizeof(T);
-    if (corr) lds += (size_t)d->n_seg * mb * sizeof(T);
-    if (c > 32 || lds > kTriLdsMax) {
-        set_error("grid too large for the tridiagonal kernel");
-        return KFBI_ENOTSUP;
-    }
-    // stage the sparse right-hand side in LDS when it fits
-    TriSparse sp;
-    sp.irr_col = d->irr_col;
-    sp.row_ptr = d->irr_row_ptr;
-    sp.row_order = d->row_order;
-    sp.seg_q0 = d->seg_q0;
-    sp.seg_row = d->seg_row;
-    sp.row_seg = d->row_seg;
-    sp.nnz = d->n_irr;
-    sp.n_act = d->n_act_rows;
-    sp.n_seg = d->n_seg;
+    S.mb = mb;
+    S.lanes = mb == 8 ? 32 : 64;
+    S.c = 1;
+    while (S.lanes * S.c < n) S.c <<= 1;
+    S.blocks = (n + mb - 1) / mb;
+    S.lds_base = (size_t)2 * d->M * sizeof(double) + ((size_t)n * mb + n / S.c + 1) * sizeof(T);
+    if (sparse) S.lds_base += (size_t)d->n_seg * mb * sizeof(T);
+    S.stage_bytes = sparse ? (size_t)d->n_irr * (sizeof(T) + sizeof(int32_t)) +
+                                 (size_t)(n + 1 + 2 * d->n_act_rows + 1 + 2 * d->n_seg) * sizeof(int32_t)
+                           : 0;
+    S.lds = S.lds_base;
+    return S;
+}
+
+template <class T>
+TriArgs<T, typename High<T>::type> tri_args(kfbi_domain *d, const void *rhat, const void *corr, void *uhat,
+                                            const int *done) {
     typedef typename High<T>::type TC;
-    const size_t stage_bytes = (size_t)sp.nnz * (sizeof(T) + sizeof(int32_t)) +
-                               (size_t)(n + 1 + 2 * sp.n_act + 1 + 2 * sp.n_seg) * sizeof(int32_t);
-    const bool stage = corr && lds + stage_bytes <= kTriLdsMax;
-    if (stage) lds += stage_bytes;
     typedef typename Real<T>::type R;
+    TriArgs<T, TC> A;
+    A.M = d->M;
+    A.h2 = d->h * d->h;
+    A.rhat = (const T *)rhat;
+    A.corr = (const TC *)corr;
+    A.sp.irr_col = d->irr_col;
+    A.sp.row_ptr = d->irr_row_ptr;
+    A.sp.row_order = d->row_order;
+    A.sp.seg_q0 = d->seg_q0;
+    A.sp.seg_row = d->seg_row;
+    A.sp.row_seg = d->row_seg;
+    A.sp.nnz = d->n_irr;
+    A.sp.n_act = d->n_act_rows;
+    A.sp.n_seg = d->n_seg;
     const bool low = sizeof(T) < sizeof(TC);
-    const T *etab = (const T *)(low ? d->etab32 : d->etab);
-    const T *elim = (const T *)(low ? d->elim32 : d->elim);
-    const int32_t *tconv = low ? d->tconv32 : d->tconv;
-    const R *sine = low ? (const R *)d->sine32 : (const R *)d->sine;
-#define KFBI_TRI(MBv, Lv, CC)                                                                                 \
-    do {                                                                                                      \
-        if (stage)                                                                                            \
-            k_tridiag<T, TC, MBv, Lv, CC, true><<<blocks, MBv * Lv, lds, d->stream>>>(                        \
-                M, h2, (const T *)rhat, (const TC *)corr, sp, sine, etab, elim, tconv, (T *)uhat, done);      \
-        else                                                                                                  \
-            k_tridiag<T, TC, MBv, Lv, CC, false><<<blocks, MBv * Lv, lds, d->stream>>>(                       \
-                M, h2, (const T *)rhat, (const TC *)corr, sp, sine, etab, elim, tconv, (T *)uhat, done);      \
+    A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.etab = (const T *)(low ? d->etab32 : d->etab);
+    A.elim = (const T *)(low ? d->elim32 : d->elim);
+    A.tconv = low ? d->tconv32 : d->tconv;
+    A.uhat = (T *)uhat;
+    A.done = done;
+    return A;
+}
+
+// one launch of a tridiagonal-kernel instantiation, single or batched
+template <class T, class TC>
+struct TriLaunchOne {
+    TriArgs<T, TC> A;
+    int blocks;
+    size_t lds;
+    hipStream_t s;
+    template <int MB, int L, int C, bool ST>
+    void go() const {
+        k_tridiag<T, TC, MB, L, C, ST><<<blocks, MB * L, lds, s>>>(A);
+    }
+};
+
+template <class T, class TC, int MB, int LANES, int C, bool STAGE>
+__global__ __launch_bounds__(MB *LANES) void kb_tridiag(const TriArgs<T, TC> *__restrict__ A,
+                                                        const BlkMap *__restrict__ map) {
+    const BlkMap e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    tridiag_body<T, TC, MB, LANES, C, STAGE>(A[e.inst], e.local);
+}
+
+template <class T, class TC>
+struct TriLaunchBatch {
+    const TriArgs<T, TC> *A;
+    const BlkMap *map;
+    int blocks;
+    size_t lds;
+    hipStream_t s;
+    template <int MB, int L, int C, bool ST>
+    void go() const {
+        kb_tridiag<T, TC, MB, L, C, ST><<<blocks, MB * L, lds, s>>>(A, map);
+    }
+};
+
+template <class F>
+void tri_dispatch(int mb, int c, bool stage, const F &f) {
+#define KFBI_TRI(MBv, Lv, CC)                                  \
+    do {                                                       \
+        if (stage) f.template go<MBv, Lv, CC, true>();         \
+        else f.template go<MBv, Lv, CC, false>();              \
     } while (0)
-#define KFBI_TRI_C(MBv, Lv)                 \
-    switch (c) {                            \
+#define KFBI_TRI_C(MBv, Lv)                    \
+    switch (c) {                               \
         case 1: KFBI_TRI(MBv, Lv, 1); break;   \
         case 2: KFBI_TRI(MBv, Lv, 2); break;   \
         case 4: KFBI_TRI(MBv, Lv, 4); break;   \
@@ -648,7 +798,6 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
         case 16: KFBI_TRI(MBv, Lv, 16); break; \
         default: KFBI_TRI(MBv, Lv, 32); break; \
     }
-    const int ps = prof_begin(d);
     switch (mb) {
         case 8: KFBI_TRI_C(8, 32); break;
         case 4: KFBI_TRI_C(4, 64); break;
@@ -657,6 +806,23 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
     }
 #undef KFBI_TRI_C
 #undef KFBI_TRI
+}
+
+template <class T>
+int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
+    typedef typename High<T>::type TC;
+    const int n = d->M - 1;
+    TriShape S = tri_shape<T>(d, corr != nullptr);
+    if (S.c > 32 || S.lds > kTriLdsMax) {
+        set_error("grid too large for the tridiagonal kernel");
+        return KFBI_ENOTSUP;
+    }
+    // stage the sparse right-hand side in LDS when it fits
+    const bool stage = corr && S.lds + S.stage_bytes <= kTriLdsMax;
+    if (stage) S.lds += S.stage_bytes;
+    TriLaunchOne<T, TC> L{tri_args<T>(d, rhat, corr, uhat, done), S.blocks, S.lds, d->stream};
+    const int ps = prof_begin(d);
+    tri_dispatch(S.mb, S.c, stage, L);
     KFBI_CHECK_LAUNCH();
     {
         // algorithmic bytes: write U^ (and read R^ when dense) plus the sparse input
@@ -739,21 +905,6 @@ int tridiag_solve_phi(kfbi_domain *d, const void *phi, void *uhat_out, const int
     return launch_tridiag<double>(d, nullptr, d->corr, uhat_out, done);
 }
 
-int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done) {
-    const int nnz = d->n_irr;
-    const int ps = prof_begin(d);
-    if (d->cplx)
-        k_corr_phi<cd><<<(nnz + 63) / 64, 64, 0, d->stream>>>((const cd *)phi, d->Nb, nnz, (const cd *)d->mcoef,
-                                                             d->mbase, (cd *)corr_out, done);
-    else
-        k_corr_phi<double><<<(nnz + 63) / 64, 64, 0, d->stream>>>((const double *)phi, d->Nb, nnz,
-                                                                 (const double *)d->mcoef, d->mbase,
-                                                                 (double *)corr_out, done);
-    KFBI_CHECK_LAUNCH();
-    const double es = elem_size(d);
-    prof_end(d, ps, KFBI_K_CORRECTIONS, (double)nnz * (kCorrWin * es + 4.0 + es) + (double)d->Nb * es);
-    return KFBI_OK;
-}
 
 int tridiag_solve_low(kfbi_domain *d, const void *corr, void *uhat32_out, const int *done) {
     if (d->cplx) return launch_tridiag<cf>(d, nullptr, corr, uhat32_out, done);
@@ -789,31 +940,34 @@ int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out) {
     return eval_stencil_nodes_ctl(d, uhat, ust_out, nullptr, false);
 }
 
+
+
+int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done) {
+    const int nnz = d->n_irr;
+    const int ps = prof_begin(d);
+    if (d->cplx)
+        k_corr_phi<cd><<<(nnz + 63) / 64, 64, 0, d->stream>>>(corr_phi_args<cd>(d, phi, corr_out, done));
+    else
+        k_corr_phi<double><<<(nnz + 63) / 64, 64, 0, d->stream>>>(corr_phi_args<double>(d, phi, corr_out, done));
+    KFBI_CHECK_LAUNCH();
+    const double es = elem_size(d);
+    prof_end(d, ps, KFBI_K_CORRECTIONS, (double)nnz * (kCorrWin * es + 4.0 + es) + (double)d->Nb * es);
+    return KFBI_OK;
+}
+
 int eval_extract_ctl(kfbi_domain *d, const void *uhat, const void *phi, void *kv_out, const int *done, bool low) {
     const int Nb = d->Nb;
-    const int stride = (int)(sizeof(Stencil) / sizeof(int32_t));
-    const int32_t *nodes = reinterpret_cast<const int32_t *>(d->st);
-    const int grid = Nb;
     const int ps = prof_begin(d);
     if (d->cplx) {
-        if (low)
-            k_eval_extract<cf, cd><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride, (const cf *)uhat, d->sine32,
-                                                                d->w6, (const cd *)d->bop, (const cd *)phi,
-                                                                (cd *)kv_out, done);
-        else
-            k_eval_extract<cd, cd><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride, (const cd *)uhat, d->sine,
-                                                                d->w6, (const cd *)d->bop, (const cd *)phi,
-                                                                (cd *)kv_out, done);
+        if (low) k_eval_extract<cf, cd><<<Nb, 384, 0, d->stream>>>(evx_args<cf, cd>(d, uhat, phi, kv_out, done));
+        else k_eval_extract<cd, cd><<<Nb, 384, 0, d->stream>>>(evx_args<cd, cd>(d, uhat, phi, kv_out, done));
     } else {
         if (low)
-            k_eval_extract<float, double><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride, (const float *)uhat,
-                                                                       d->sine32, d->w6, (const double *)d->bop,
-                                                                       (const double *)phi, (double *)kv_out, done);
+            k_eval_extract<float, double><<<Nb, 384, 0, d->stream>>>(
+                evx_args<float, double>(d, uhat, phi, kv_out, done));
         else
-            k_eval_extract<double, double><<<grid, 384, 0, d->stream>>>(d->M, Nb, nodes, stride,
-                                                                        (const double *)uhat, d->sine, d->w6,
-                                                                        (const double *)d->bop, (const double *)phi,
-                                                                        (double *)kv_out, done);
+            k_eval_extract<double, double><<<Nb, 384, 0, d->stream>>>(
+                evx_args<double, double>(d, uhat, phi, kv_out, done));
     }
     KFBI_CHECK_LAUNCH();
     const double es = low ? elem_size(d) / 2.0 : elem_size(d), eo = elem_size(d);
@@ -824,26 +978,18 @@ int eval_extract_ctl(kfbi_domain *d, const void *uhat, const void *phi, void *kv
 
 int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low) {
     const int nn = 6 * d->Nb;
-    const int stride = (int)(sizeof(Stencil) / sizeof(int32_t));
-    const int32_t *nodes = reinterpret_cast<const int32_t *>(d->st);
     const int grid = (nn + 3) / 4;
     const int ps = prof_begin(d);
     if (d->cplx) {
-        if (low)
-            k_eval_nodes<cf, cd><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cf *)uhat,
-                                                              d->sine32, (cd *)ust_out, done);
-        else
-            k_eval_nodes<cd, cd><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride, (const cd *)uhat, d->sine,
-                                                              (cd *)ust_out, done);
+        if (low) k_eval_nodes<cf, cd><<<grid, 256, 0, d->stream>>>(eval_args<cf, cd>(d, uhat, ust_out, done));
+        else k_eval_nodes<cd, cd><<<grid, 256, 0, d->stream>>>(eval_args<cd, cd>(d, uhat, ust_out, done));
     } else {
         if (low)
-            k_eval_nodes<float, double><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride,
-                                                                     (const float *)uhat, d->sine32,
-                                                                     (double *)ust_out, done);
+            k_eval_nodes<float, double><<<grid, 256, 0, d->stream>>>(
+                eval_args<float, double>(d, uhat, ust_out, done));
         else
-            k_eval_nodes<double, double><<<grid, 256, 0, d->stream>>>(d->M, nn, nodes, stride,
-                                                                      (const double *)uhat, d->sine,
-                                                                      (double *)ust_out, done);
+            k_eval_nodes<double, double><<<grid, 256, 0, d->stream>>>(
+                eval_args<double, double>(d, uhat, ust_out, done));
     }
     KFBI_CHECK_LAUNCH();
     const double es = low ? elem_size(d) / 2.0 : elem_size(d);

@@ -70,11 +70,18 @@ __device__ inline const T *at_slot(const T *base, const int *jptr, int add, size
 }
 
 template <class T>
-__global__ void k_corrections(int n_irr, const IrrNode *__restrict__ irr, const Edge *__restrict__ edges,
-                              int Nb, double dth, double h, T kappa, const T *phi_base, const int *jptr,
-                              const T *__restrict__ fg, T *__restrict__ corr, const int *done) {
-    if (done && *done) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void corrections_body(const CorrArgs<T> &A, int blk) {
+    const int n_irr = A.n_irr, Nb = A.Nb;
+    const IrrNode *__restrict__ irr = A.irr;
+    const Edge *__restrict__ edges = A.edges;
+    const double dth = A.dth, h = A.h;
+    const T kappa = A.kappa;
+    const T *phi_base = A.phi_base;
+    const int *jptr = A.jptr;
+    const T *__restrict__ fg = A.fg;
+    T *__restrict__ corr = A.corr;
+    if (A.done && *A.done) return;
+    int q = blk * blockDim.x + threadIdx.x;
     if (q >= n_irr) return;
     const T *phi = at_slot(phi_base, jptr, 0, (size_t)Nb);
     const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
@@ -104,14 +111,27 @@ __global__ void k_corrections(int n_irr, const IrrNode *__restrict__ irr, const 
     corr[q] = acc * (-R.sgn / (h * h));
 }
 
+template <class T>
+__global__ __launch_bounds__(128) void k_corrections(CorrArgs<T> A) {
+    corrections_body(A, blockIdx.x);
+}
+
 // U+(z_k) = sum_p w_p (U(p) + [p outside] J_k(p)); out = g + scale U+
 template <class T>
-__global__ void k_extract(int Nb, double dth, const Colloc *__restrict__ col, const Stencil *__restrict__ st,
-                          T kappa, const T *__restrict__ ust, const T *phi_base, const int *jptr,
-                          const T *__restrict__ fg, const T *__restrict__ g, double scale, T *out_base,
-                          int out_add, const int *done) {
-    if (done && *done) return;
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void extract_body(const ExtArgs<T> &A, int blk) {
+    const int Nb = A.Nb, out_add = A.out_add;
+    const double dth = A.dth, scale = A.scale;
+    const Colloc *__restrict__ col = A.col;
+    const Stencil *__restrict__ st = A.st;
+    const T kappa = A.kappa;
+    const T *__restrict__ ust = A.ust;
+    const T *phi_base = A.phi_base;
+    const int *jptr = A.jptr;
+    const T *__restrict__ fg = A.fg;
+    const T *__restrict__ g = A.g;
+    T *out_base = A.out_base;
+    if (A.done && *A.done) return;
+    int k = blk * blockDim.x + threadIdx.x;
     if (k >= Nb) return;
     const T *phi = at_slot(phi_base, jptr, 0, (size_t)Nb);
     T *out = out_base + (jptr ? (size_t)(*jptr + out_add) * Nb : 0);
@@ -134,6 +154,11 @@ __global__ void k_extract(int Nb, double dth, const Colloc *__restrict__ col, co
     T res = up * scale;
     if (g) res += g[k];
     out[k] = res;
+}
+
+template <class T>
+__global__ __launch_bounds__(128) void k_extract(ExtArgs<T> A) {
+    extract_body(A, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,13 +287,51 @@ template <> double kappa_of<double>(double kre, double) { return kre; }
 template <> cd kappa_of<cd>(double kre, double kim) { return make_cd(kre, kim); }
 
 template <class T>
+CorrArgs<T> corr_args(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
+                      const void *fg, void *corr, const int *done) {
+    CorrArgs<T> A;
+    A.n_irr = d->n_irr;
+    A.Nb = d->Nb;
+    A.irr = d->irr;
+    A.edges = d->edges;
+    A.dth = 6.283185307179586476925286766559 / d->Nb;
+    A.h = d->h;
+    A.kappa = kappa_of<T>(kre, kim);
+    A.phi_base = (const T *)phi_base;
+    A.jptr = jptr;
+    A.fg = (const T *)fg;
+    A.corr = (T *)corr;
+    A.done = done;
+    return A;
+}
+
+template <class T>
+ExtArgs<T> ext_args(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi_base, const int *jptr,
+                    const void *fg, const void *g, double scale, void *out_base, int out_add, const int *done) {
+    ExtArgs<T> A;
+    A.Nb = d->Nb;
+    A.out_add = out_add;
+    A.dth = 6.283185307179586476925286766559 / d->Nb;
+    A.scale = scale;
+    A.col = d->col;
+    A.st = d->st;
+    A.kappa = kappa_of<T>(kre, kim);
+    A.ust = (const T *)ust;
+    A.phi_base = (const T *)phi_base;
+    A.jptr = jptr;
+    A.fg = (const T *)fg;
+    A.g = (const T *)g;
+    A.out_base = (T *)out_base;
+    A.done = done;
+    return A;
+}
+
+template <class T>
 int launch_corr(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
                 const void *fg, void *corr, const int *done) {
-    const double dth = 6.283185307179586476925286766559 / d->Nb;
     const int ps = prof_begin(d);
     k_corrections<T><<<(d->n_irr + 127) / 128, 128, 0, d->stream>>>(
-        d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kappa_of<T>(kre, kim), (const T *)phi_base, jptr,
-        (const T *)fg, (T *)corr, done);
+        corr_args<T>(d, kre, kim, phi_base, jptr, fg, corr, done));
     KFBI_CHECK_LAUNCH();
     prof_end(d, ps, KFBI_K_CORRECTIONS, (double)d->n_irr * (sizeof(IrrNode) + sizeof(T)));
     return KFBI_OK;
@@ -278,11 +341,9 @@ template <class T>
 int launch_extract(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi_base,
                    const int *jptr, const void *fg, const void *g, double scale, void *out_base,
                    int out_add, const int *done) {
-    const double dth = 6.283185307179586476925286766559 / d->Nb;
     const int ps = prof_begin(d);
     k_extract<T><<<(d->Nb + 127) / 128, 128, 0, d->stream>>>(
-        d->Nb, dth, d->col, d->st, kappa_of<T>(kre, kim), (const T *)ust, (const T *)phi_base, jptr,
-        (const T *)fg, (const T *)g, scale, (T *)out_base, out_add, done);
+        ext_args<T>(d, kre, kim, ust, phi_base, jptr, fg, g, scale, out_base, out_add, done));
     KFBI_CHECK_LAUNCH();
     prof_end(d, ps, KFBI_K_EXTRACT, (double)d->Nb * (sizeof(Colloc) + sizeof(Stencil) + 8.0 * sizeof(T)));
     return KFBI_OK;

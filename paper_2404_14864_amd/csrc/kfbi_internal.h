@@ -339,6 +339,124 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
 
 inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : sizeof(double); }
 
+// ---------------------------------------------------------------------------
+// Kernel argument blocks.  Each device kernel body takes one of these and its
+// block index; a single-instance launch passes the block by value, a batched
+// launch reads one per instance from device memory (see BlkMap).
+// ---------------------------------------------------------------------------
+// real scalar type of an element type (sine tables, scale factors)
+template <class T> struct Real { typedef double type; };
+template <> struct Real<float> { typedef float type; };
+template <> struct Real<cf> { typedef float type; };
+
+template <class T>
+struct DstArgs {
+    int M, logN2;
+    const T *in;
+    int in_grid;
+    const uint8_t *mask;
+    T *out;
+    int out_grid;
+    double scale;
+    const double *twiddle;
+    const int *done;
+};
+
+template <class T>
+struct ZeroArgs {
+    int M;
+    T *grid;
+    const int *done;
+};
+
+struct TriSparse {
+    const int32_t *irr_col, *row_ptr, *row_order, *seg_q0, *seg_row, *row_seg;
+    int nnz, n_act, n_seg;
+};
+
+template <class T, class TC>
+struct TriArgs {
+    int M;
+    double h2;
+    const T *rhat;
+    const TC *corr;
+    TriSparse sp;
+    const typename Real<T>::type *sine;
+    const T *etab, *elim;
+    const int32_t *tconv;
+    T *uhat;
+    const int *done;
+};
+
+template <class T, class TO>
+struct EvalArgs {
+    int M, nnodes, node_stride;
+    const int32_t *nodes;
+    const T *uhat;
+    const typename Real<T>::type *sine;
+    TO *out;
+    const int *done;
+};
+
+template <class TC>
+struct CorrPhiArgs {
+    const TC *phi;
+    int Nb, nnz;
+    const TC *mcoef;
+    const int32_t *mbase;
+    TC *corr;
+    const int *done;
+};
+
+template <class T, class TO>
+struct EvxArgs {
+    int M, Nb, node_stride;
+    const int32_t *nodes;
+    const T *uhat;
+    const typename Real<T>::type *sine;
+    const double *w6;
+    const TO *bop;
+    const TO *phi;
+    TO *kv;
+    const int *done;
+};
+
+template <class T>
+struct CorrArgs {
+    int n_irr, Nb;
+    const IrrNode *irr;
+    const Edge *edges;
+    double dth, h;
+    T kappa;
+    const T *phi_base;
+    const int *jptr;
+    const T *fg;
+    T *corr;
+    const int *done;
+};
+
+template <class T>
+struct ExtArgs {
+    int Nb, out_add;
+    double dth, scale;
+    const Colloc *col;
+    const Stencil *st;
+    T kappa;
+    const T *ust;
+    const T *phi_base;
+    const int *jptr;
+    const T *fg;
+    const T *g;
+    T *out_base;
+    const int *done;
+};
+
+// batched launches: workgroup b of the launch runs local block `local` of
+// instance `inst`
+struct BlkMap {
+    int inst, local;
+};
+
 // kernel timing: prof_begin returns a slot (or -1 when profiling is off);
 // prof_end closes it with the launch's algorithmic bytes; prof_flush waits
 // for the recorded events and accumulates every slot whose tag is -1 or
