@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--replay", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=256, help="instances of the batched Helmholtz run (0: skip)")
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device three times (the reference transfer "
                          "for HBM byte counters)")
@@ -87,6 +89,81 @@ def cpu_baseline(M, seconds):
             "cores": 1, "kind": "oracle",
             "sample": "first %d time steps of the same wave workload (%d GMRES iterations) in %.1f s; "
                       "numpy/scipy oracle, single-threaded FFTs" % (n, iters, el)}
+
+
+def batched_helmholtz(n, reps):
+    """Batched modified-Helmholtz solves: n seeded instances (star domains,
+    grids drawn from {128, 256, 512, 1024}, kappa ~ U[1, 1e4], smooth random
+    f and g), solved plain (one call per instance, in turn) and batched (one
+    call for all), in FP64 and with FP32 inner solves.  Throughput in
+    grid-pts * GMRES-iters / s over all instances."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from workloads.fields import SmoothField
+    from paper_2404_14864_amd import kfbi
+    dev = "cuda:0"
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    t0 = time.perf_counter()
+    mem = []
+    for i in range(n):
+        desc, kappa, rng = W.domain_c4_instance(i)
+        f, g = SmoothField(rng), SmoothField(rng)
+        h = kfbi.kfbi_domain_create(desc)
+        zx, zy = kfbi.kfbi_domain_copy_boundary(h)
+        x = W.grid_coords(1.0, desc["M"])
+        M = desc["M"]
+        mem.append({"h": h, "M": M, "Nb": desc["Nb"], "kappa": kappa, "f": d(f.grid(x, x).ravel()), "fg": d(f(zx, zy)),
+                    "g": d(g(zx, zy)), "u": torch.zeros((M + 1) ** 2, dtype=torch.float64, device=dev)})
+    torch.cuda.synchronize()
+    log("batch: %d instances created in %.1f s (grids %s)" % (
+        n, time.perf_counter() - t0, dict(zip(*np.unique([m["M"] for m in mem], return_counts=True)))))
+    pts = np.array([(m["M"] - 1) ** 2 for m in mem], dtype=np.float64)
+    out = {"workload": "%d batched Helmholtz instances, star r0~U[0.3,0.6] lobes 3..8 amp 0.2 r0, grids "
+                       "U{128,256,512,1024}, Nb=M, kappa~U[1,1e4], smooth random f and g, tol 1e-10" % n}
+    for label, prec in (("fp64", kfbi.KFBI_PREC_FP64), ("mixed", kfbi.KFBI_PREC_MIXED)):
+        opts = {"tol": 1e-10, "precision": prec}
+        # plain: one solve per instance in turn (first pass warms coefficients)
+        for m in mem:
+            kfbi.kfbi_helmholtz_solve(m["h"], m["kappa"], m["f"], m["fg"], m["g"], m["u"], opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = []
+        for m in mem:
+            s = kfbi.kfbi_helmholtz_solve(m["h"], m["kappa"], m["f"], m["fg"], m["g"], m["u"], opts=opts)
+            its.append(s["iters"])
+        torch.cuda.synchronize()
+        Tp = time.perf_counter() - t0
+        plain = float(np.dot(pts, its) / Tp)
+        ref = [m["u"].clone() for m in mem]
+        # batched
+        b = kfbi.kfbi_batch_create([m["h"] for m in mem])
+        args = ([m["kappa"] for m in mem], [m["f"] for m in mem], [m["fg"] for m in mem], [m["g"] for m in mem],
+                [m["u"] for m in mem])
+        kfbi.kfbi_batch_helmholtz(b, *args, opts=opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bits = None
+        for _ in range(reps):
+            st = kfbi.kfbi_batch_helmholtz(b, *args, opts=opts)
+            bits = [x["iters"] for x in st]
+        torch.cuda.synchronize()
+        Tb = (time.perf_counter() - t0) / reps
+        batched = float(np.dot(pts, bits) / Tb)
+        diff = max(float((m["u"] - r).abs().max() / max(r.abs().max(), 1e-300)) for m, r in zip(mem, ref))
+        kfbi.kfbi_batch_destroy(b)
+        out[label] = {"plain_value": plain, "plain_ms": 1e3 * Tp, "batched_value": batched, "batched_ms": 1e3 * Tb,
+                      "speedup": batched / plain, "gmres_iters_total": int(sum(bits)),
+                      "max_rel_diff_batched_vs_plain": diff}
+        log("batch %s: plain %.3g (%.1f ms), batched %.3g (%.1f ms), x%.1f, %d iterations" % (
+            label, plain, 1e3 * Tp, batched, 1e3 * Tb, batched / plain, sum(bits)))
+    out["unit"] = "grid-pts*GMRES-iters/s"
+    for m in mem:
+        kfbi.kfbi_domain_destroy(m["h"])
+    return out
 
 
 def main():
@@ -230,6 +307,8 @@ def main():
         log("copied %d MiB three times" % args.calibrate_copy)
         del src, dst
 
+    batched = batched_helmholtz(args.batch, args.batch_reps) if args.batch > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (~%.0f s)" % args.cpu_seconds)
@@ -276,6 +355,7 @@ def main():
                             "refinements_per_step": float(np.mean(mref)),
                             "grid_solve": "fp32", "refinement": "fp64",
                             "rel_diff_vs_fp64_after_steps": mixed_err},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -122,6 +122,7 @@ typedef struct {
 
 typedef struct kfbi_domain kfbi_domain;
 typedef struct kfbi_stepper kfbi_stepper;
+typedef struct kfbi_batch kfbi_batch;
 
 /* Thread-local description of the last failure. */
 const char *kfbi_last_error(void);
@@ -242,6 +243,34 @@ int kfbi_step_wave(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
 /* One Strang-splitting step (the three-step algorithm after eq. 3.12). */
 int kfbi_step_schrodinger(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
                           const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+/* Batched modified-Helmholtz solves (eq. 3.13 through eqs. 3.17-3.18, one
+ * problem per member domain).  A batch holds n REAL domains that share one
+ * stream; every kernel launch of a batched solve runs the blocks of all
+ * members, each member with its own GMRES state, so members of different
+ * grid sizes, curves and kappa advance together and finished members drop
+ * out on the device.  Members must have Nb <= 8192; a domain may belong to
+ * several batches but must not be used by two calls at once.
+ * kfbi_batch_create copies the launch tables to the device (it
+ * synchronises the stream); kfbi_batch_destroy frees only the batch's own
+ * memory.  Errors: KFBI_EINVAL (null or empty, mixed streams),
+ * KFBI_ENOTSUP (complex member, too large), KFBI_ENOMEM. */
+int kfbi_batch_create(kfbi_domain *const *doms, int32_t n, kfbi_batch **out);
+int kfbi_batch_destroy(kfbi_batch *b);
+
+/* n solves, member q with kappa[q] and the device arrays f_grid[q] (grid,
+ * f at inside nodes), f_gamma[q] and g_gamma[q] (Nb values on Gamma);
+ * u_grid_out[q] (grid) and phi_inout[q] (density: warm start in, result
+ * out) may be NULL as arrays or entries.  kappa, f_grid, ... are host
+ * arrays of n entries.  opts as for kfbi_helmholtz_solve (the precision
+ * field selects FP64 or the FP32 inner solves for all members); stats, if
+ * not NULL, receives n entries, device_ms the time of the whole batch.
+ * Returns KFBI_ENOCONV when some member reached max_iter (all outputs are
+ * still written). */
+int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid,
+                         const void *const *f_gamma, const void *const *g_gamma,
+                         void *const *u_grid_out, void *const *phi_inout,
+                         const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
 /* Per-kernel device timing (instrumentation for benchmarks).  When enabled,
  * every launch of the listed kernels of this domain is bracketed by two HIP

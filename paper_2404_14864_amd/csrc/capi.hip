@@ -217,6 +217,21 @@ int kfbi_profile_enable(kfbi_domain *d, int32_t on) {
     return KFBI_OK;
 }
 
+int kfbi_batch_create(kfbi_domain *const *doms, int32_t n, kfbi_batch **out) {
+    return batch_create(doms, n, out);
+}
+
+int kfbi_batch_destroy(kfbi_batch *b) {
+    batch_destroy(b);
+    return KFBI_OK;
+}
+
+int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
+                         const void *const *g_gamma, void *const *u_grid_out, void *const *phi_inout,
+                         const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+    return batch_helmholtz(b, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
+}
+
 int kfbi_profile_replay(kfbi_domain *d, int32_t kind, int32_t reps, double *avg_ms, double *bytes_per_launch) {
     if (!d || !avg_ms || !bytes_per_launch) { set_error("null argument"); return KFBI_EINVAL; }
     if (reps < 1 || reps > 100000) { set_error("reps must be in 1..100000"); return KFBI_EINVAL; }

@@ -513,6 +513,44 @@ int build_domain(kfbi_domain *d) {
         set_error("an extraction stencil reaches the box boundary");
         return KFBI_EDOMAIN;
     }
+    // the stencil nodes grouped by grid row: for each interior row holding
+    // stencil nodes, the entries (index 6k+p into the stencil values, column)
+    std::vector<Stencil> hst(Nb);
+    KFBI_HIP(hipMemcpyAsync(hst.data(), d->st, (size_t)Nb * sizeof(Stencil), hipMemcpyDeviceToHost, s));
+    KFBI_HIP(hipStreamSynchronize(s));
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> per_row(d->n);
+    for (int k = 0; k < Nb; ++k)
+        for (int p = 0; p < 6; ++p) {
+            const int node = hst[k].node[p];
+            const int t = node / (M + 1) - 1, i = node % (M + 1);
+            per_row[t].push_back({6 * k + p, i});
+        }
+    std::vector<int32_t> erow_t, erow_ptr, erow_ent, erow_col;
+    for (int t = 0; t < d->n; ++t) {
+        if (per_row[t].empty()) continue;
+        erow_t.push_back(t);
+        erow_ptr.push_back((int32_t)erow_ent.size());
+        for (auto &e : per_row[t]) {
+            erow_ent.push_back(e.first);
+            erow_col.push_back(e.second);
+        }
+    }
+    erow_ptr.push_back((int32_t)erow_ent.size());
+    d->n_erows = (int)erow_t.size();
+    d->erow_lo = erow_t.front();
+    d->erow_hi = erow_t.back();
+    KFBI_TRY(dalloc(d, (void **)&d->erow_t, erow_t.size() * sizeof(int32_t)));
+    KFBI_TRY(dalloc(d, (void **)&d->erow_ptr, erow_ptr.size() * sizeof(int32_t)));
+    KFBI_TRY(dalloc(d, (void **)&d->erow_ent, erow_ent.size() * sizeof(int32_t)));
+    KFBI_TRY(dalloc(d, (void **)&d->erow_col, erow_col.size() * sizeof(int32_t)));
+    KFBI_HIP(hipMemcpyAsync(d->erow_t, erow_t.data(), erow_t.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    KFBI_HIP(hipMemcpyAsync(d->erow_ptr, erow_ptr.data(), erow_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                            s));
+    KFBI_HIP(hipMemcpyAsync(d->erow_ent, erow_ent.data(), erow_ent.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                            s));
+    KFBI_HIP(hipMemcpyAsync(d->erow_col, erow_col.data(), erow_col.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                            s));
+    KFBI_HIP(hipStreamSynchronize(s));
     return KFBI_OK;
 }
 

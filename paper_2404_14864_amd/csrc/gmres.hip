@@ -1492,4 +1492,440 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     return KFBI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched solves: many real domains advance through the same launches.  Each
+// member keeps its own device-driven GMRES state (control block, gates,
+// mirror); a batched kernel runs every member's blocks and each block obeys
+// its own member's gate, so members that finish early cost only the early
+// exit of their blocks.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CopyArgs {
+    double *dst;
+    const double *src;  // null: zero
+    int n;
+    const int *done;
+};
+
+__device__ void copy_body(const CopyArgs &A, int blk) {
+    if (A.done && *A.done) return;
+    const int i = blk * blockDim.x + threadIdx.x;
+    if (i < A.n) A.dst[i] = A.src ? A.src[i] : 0.0;
+}
+
+struct FinalArgs {
+    int *skip_tail;
+};
+
+__global__ __launch_bounds__(256) void kb_copy(const CopyArgs *__restrict__ A, const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    copy_body(A[e.inst], e.local);
+}
+
+// a member whose final solve has just run (skip_tail 0) is marked done (2),
+// so later rounds of the same solve skip it
+__global__ void kb_final(const FinalArgs *__restrict__ A, int n) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n && *A[q].skip_tail == 0) *A[q].skip_tail = 2;
+}
+
+__global__ __launch_bounds__(kGmThreads) void kb_gm_init(const GmInitArgs<double> *__restrict__ A) {
+    gm_init_body(A[blockIdx.x], 0);
+}
+
+template <int EPT>
+__global__ __launch_bounds__(kGmThreads) void kb_gm_slot(const SlotArgs<double> *__restrict__ A) {
+    gm_slot_body<double, EPT>(A[blockIdx.x], 0);
+}
+
+// argument arrays of one batched solve, one entry per member each
+enum {
+    kUDstF = 0, kUCorrB, kUTriB, kUErowB, kUExtB, kUCopyX, kUInit,
+    kUCorrPhi64, kUTri64, kUErow64, kUExm64, kUCorrPhi32, kUTri32, kUErow32, kUExm32, kUSlot,
+    kUCorrF, kUTriF, kUIdst, kUZero, kUCopyF, kUFinal, kUses
+};
+
+}  // namespace
+
+struct BatchClass {
+    int M;
+    std::vector<int> members;
+    int map64, blocks64, map32, blocks32;
+    BatchTriShape dense, sparse64, sparse32;
+};
+
+}  // namespace kfbi
+
+struct kfbi_batch {
+    std::vector<kfbi_domain *> doms;
+    hipStream_t stream = nullptr;
+    // workgroup maps, one array for all kinds and classes
+    kfbi::BlkMap *d_map = nullptr;
+    int map_off[kfbi::kBaKinds] = {}, map_blocks[kfbi::kBaKinds] = {};
+    std::vector<kfbi::BatchClass> classes;
+    // argument staging
+    char *h_args = nullptr, *d_args = nullptr;
+    size_t use_off[kfbi::kUses] = {}, use_size[kfbi::kUses] = {}, args_bytes = 0;
+    int last_slots = 0;
+    int nb_max = 0, m_lds = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace kfbi {
+
+void batch_destroy(kfbi_batch *b) {
+    if (!b) return;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->d_map) hipFree(b->d_map);
+    if (b->d_args) hipFree(b->d_args);
+    if (b->h_args) hipHostFree(b->h_args);
+    if (b->ev0) hipEventDestroy(b->ev0);
+    if (b->ev1) hipEventDestroy(b->ev1);
+    delete b;
+}
+
+int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
+    if (!doms || n < 1 || !out) { set_error("null argument or empty batch"); return KFBI_EINVAL; }
+    *out = nullptr;
+    kfbi_batch *b = new kfbi_batch();
+    b->stream = doms[0]->stream;
+    for (int q = 0; q < n; ++q) {
+        kfbi_domain *d = doms[q];
+        if (!d) { batch_destroy(b); set_error("null domain in batch"); return KFBI_EINVAL; }
+        if (d->cplx) { batch_destroy(b); set_error("batched solves support real domains only"); return KFBI_ENOTSUP; }
+        if (d->stream != b->stream) {
+            batch_destroy(b);
+            set_error("batch members must share one stream");
+            return KFBI_EINVAL;
+        }
+        if ((size_t)d->Nb * sizeof(double) > 65536) {
+            batch_destroy(b);
+            set_error("batch members need Nb <= 8192");
+            return KFBI_ENOTSUP;
+        }
+        b->doms.push_back(d);
+        b->nb_max = std::max(b->nb_max, d->Nb);
+    }
+    // workgroup maps: per kind over all members (the tridiagonal kinds per
+    // class of equal M, in XCD tile order inside the kernel)
+    std::vector<BlkMap> map;
+    const int kinds[] = {kBaDst, kBaZero, kBaErow64, kBaExm, kBaCorrPhi, kBaCorr, kBaExt, kBaCopy};
+    for (int kind : kinds) {
+        b->map_off[kind] = (int)map.size();
+        for (int q = 0; q < n; ++q) {
+            int nbk;
+            if (kind == kBaCorr || kind == kBaExt) nbk = batch_blocks_iface(doms[q], kind);
+            else if (kind == kBaCopy) nbk = (doms[q]->Nb + 255) / 256;
+            else nbk = batch_blocks(doms[q], kind);
+            for (int l = 0; l < nbk; ++l) map.push_back(BlkMap{q, l});
+        }
+        b->map_blocks[kind] = (int)map.size() - b->map_off[kind];
+    }
+    std::vector<int> Ms;
+    for (int q = 0; q < n; ++q)
+        if (std::find(Ms.begin(), Ms.end(), doms[q]->M) == Ms.end()) Ms.push_back(doms[q]->M);
+    std::sort(Ms.begin(), Ms.end());
+    for (int M : Ms) {
+        BatchClass C;
+        C.M = M;
+        for (int q = 0; q < n; ++q)
+            if (doms[q]->M == M) C.members.push_back(q);
+        std::vector<kfbi_domain *> cd;
+        for (int q : C.members) cd.push_back(doms[q]);
+        int st = batch_tri_shape(cd.data(), (int)cd.size(), true, false, &C.sparse64);
+        if (st == KFBI_OK) st = batch_tri_shape(cd.data(), (int)cd.size(), true, false, &C.dense);
+        if (st == KFBI_OK) st = batch_tri_shape(cd.data(), (int)cd.size(), true, true, &C.sparse32);
+        if (st != KFBI_OK) { batch_destroy(b); return st; }
+        C.map64 = (int)map.size();
+        for (int q : C.members)
+            for (int l = 0; l < batch_blocks(doms[q], kBaTri64); ++l) map.push_back(BlkMap{q, l});
+        C.blocks64 = (int)map.size() - C.map64;
+        C.map32 = (int)map.size();
+        for (int q : C.members)
+            for (int l = 0; l < batch_blocks(doms[q], kBaTri32); ++l) map.push_back(BlkMap{q, l});
+        C.blocks32 = (int)map.size() - C.map32;
+        b->classes.push_back(C);
+    }
+    // argument arrays
+    auto use_size = [&](int u) -> size_t {
+        switch (u) {
+            case kUDstF: case kUIdst: return batch_args_size(kBaDst);
+            case kUZero: return batch_args_size(kBaZero);
+            case kUCorrB: case kUCorrF: return batch_args_size_iface(kBaCorr);
+            case kUExtB: return batch_args_size_iface(kBaExt);
+            case kUTriB: case kUTriF: case kUTri64: return batch_args_size(kBaTri64);
+            case kUTri32: return batch_args_size(kBaTri32);
+            case kUErowB: case kUErow64: return batch_args_size(kBaErow64);
+            case kUErow32: return batch_args_size(kBaErow32);
+            case kUExm64: case kUExm32: return batch_args_size(kBaExm);
+            case kUCorrPhi64: case kUCorrPhi32: return batch_args_size(kBaCorrPhi);
+            case kUCopyX: case kUCopyF: return sizeof(CopyArgs);
+            case kUInit: return sizeof(GmInitArgs<double>);
+            case kUSlot: return sizeof(SlotArgs<double>);
+            case kUFinal: return sizeof(FinalArgs);
+            default: return 0;
+        }
+    };
+    size_t off = 0;
+    for (int u = 0; u < kUses; ++u) {
+        b->use_size[u] = use_size(u);
+        b->use_off[u] = off;
+        off += ((b->use_size[u] * n) + 255) & ~(size_t)255;
+    }
+    b->args_bytes = off;
+    if (hipHostMalloc((void **)&b->h_args, off, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&b->d_args, off) != hipSuccess ||
+        hipMalloc((void **)&b->d_map, map.size() * sizeof(BlkMap)) != hipSuccess) {
+        batch_destroy(b);
+        set_error("out of device memory for the batch tables");
+        return KFBI_ENOMEM;
+    }
+    if (hipMemcpyAsync(b->d_map, map.data(), map.size() * sizeof(BlkMap), hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+        batch_destroy(b);
+        set_error("copy of the batch tables failed");
+        return KFBI_EDEVICE;
+    }
+    if (hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
+        batch_destroy(b);
+        set_error("hipEventCreate failed");
+        return KFBI_EDEVICE;
+    }
+    *out = b;
+    return KFBI_OK;
+}
+
+int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
+                    const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
+                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+    if (!b || !kappa || !f_grid || !f_gamma || !g_gamma) { set_error("null argument"); return KFBI_EINVAL; }
+    const int n = (int)b->doms.size();
+    kfbi_solve_opts o;
+    o.tol = 1e-10;
+    o.max_iter = 500;
+    o.restart = 50;
+    o.fixed_iters = 0;
+    o.precision = -1;
+    o.flags = 0;
+    o.pad = 0;
+    if (opts) {
+        if (opts->tol > 0) o.tol = opts->tol;
+        if (opts->max_iter > 0) o.max_iter = opts->max_iter;
+        if (opts->restart > 0) o.restart = opts->restart;
+        o.fixed_iters = opts->fixed_iters;
+        o.precision = opts->precision;
+        o.flags = opts->flags;
+    }
+    if (o.restart > 64) { set_error("restart length must be at most 64"); return KFBI_EINVAL; }
+    const bool mixed = (o.precision >= 0 ? o.precision : b->doms[0]->desc.precision) == KFBI_PREC_MIXED;
+    hipStream_t s = b->stream;
+    // per-member setup: coefficients and operators for this kappa
+    for (int q = 0; q < n; ++q) {
+        kfbi_domain *d = b->doms[q];
+        if (!f_grid[q] || !f_gamma[q] || !g_gamma[q]) { set_error("null member array"); return KFBI_EINVAL; }
+        KFBI_TRY(ensure_coefficients(d, kappa[q], 0.0));
+        KFBI_TRY(ensure_operators(d, kappa[q], 0.0));
+        if (mixed) KFBI_TRY(ensure_coefficients_low(d, kappa[q], 0.0));
+        if (!slots_supported<double>(d, o.restart)) {
+            set_error("batch member without the merged operators or too large for the control kernel");
+            return KFBI_ENOTSUP;
+        }
+        if (!d->mirror_host) {
+            KFBI_HIP(hipHostMalloc(&d->mirror_host, sizeof(GmMirror), hipHostMallocMapped | hipHostMallocCoherent));
+            memset(d->mirror_host, 0, sizeof(GmMirror));
+            KFBI_HIP(hipHostGetDevicePointer(&d->mirror_dev, d->mirror_host, 0));
+        }
+    }
+    // argument blocks
+    int nvl_min = 1 << 30;
+    size_t slot_lds_max = 0;
+    for (int q = 0; q < n; ++q) {
+        kfbi_domain *d = b->doms[q];
+        GmPtrs P = gm_layout(d, 64);
+        const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
+        auto at = [&](int u) { return b->h_args + b->use_off[u] + (size_t)q * b->use_size[u]; };
+        batch_fill_dst(d, f_grid[q], true, true, d->rhat, false, 1.0, nullptr, at(kUDstF));
+        batch_fill_corr(d, kappa[q], nullptr, f_gamma[q], d->corr, nullptr, at(kUCorrB));
+        batch_fill_tri(d, d->rhat, d->corr, d->uhat, nullptr, false, at(kUTriB));
+        batch_fill_erow(d, d->uhat, d->ust, nullptr, false, at(kUErowB));
+        batch_fill_ext(d, kappa[q], d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, nullptr, at(kUExtB));
+        *(CopyArgs *)at(kUCopyX) = CopyArgs{(double *)P.x, phi_inout ? (const double *)phi_inout[q] : nullptr,
+                                            d->Nb, nullptr};
+        *(GmInitArgs<double> *)at(kUInit) = gm_init_args<double>(P, d->Nb, o, mixed);
+        batch_fill_corr_phi(d, P.vcur, d->corr, skip64, at(kUCorrPhi64));
+        batch_fill_tri(d, nullptr, d->corr, d->uhat, skip64, false, at(kUTri64));
+        batch_fill_erow(d, d->uhat, d->ust, skip64, false, at(kUErow64));
+        batch_fill_exm(d, d->ust, P.vcur, P.r, skip64, at(kUExm64));
+        batch_fill_corr_phi(d, P.vcur, d->corr, skip32, at(kUCorrPhi32));
+        batch_fill_tri(d, nullptr, d->corr, d->uhat32, skip32, true, at(kUTri32));
+        batch_fill_erow(d, d->uhat32, d->ust, skip32, true, at(kUErow32));
+        batch_fill_exm(d, d->ust, P.vcur, P.r, skip32, at(kUExm32));
+        int nvl;
+        const size_t lds = slot_lds<double>(d->Nb, o.restart, &nvl);
+        slot_lds_max = std::max(slot_lds_max, lds);
+        nvl_min = std::min(nvl_min, nvl);
+        *(SlotArgs<double> *)at(kUSlot) = slot_args<double>(P, (GmMirror *)d->mirror_dev, d->Nb, o.restart, nvl);
+        batch_fill_corr(d, kappa[q], P.x, f_gamma[q], d->corr, skip_tail, at(kUCorrF));
+        batch_fill_tri(d, d->rhat, d->corr, d->uhat, skip_tail, false, at(kUTriF));
+        void *uo = u_out ? u_out[q] : nullptr;
+        batch_fill_dst(d, d->uhat, false, false, uo, true, 2.0 / d->M, skip_tail, at(kUIdst));
+        batch_fill_zero(d, uo, skip_tail, at(kUZero));
+        *(CopyArgs *)at(kUCopyF) = CopyArgs{phi_inout ? (double *)phi_inout[q] : nullptr, (const double *)P.x,
+                                            d->Nb, skip_tail};
+        *(FinalArgs *)at(kUFinal) = FinalArgs{&P.ctl->skip_tail};
+        GmMirror *mh = (GmMirror *)d->mirror_host;
+        __atomic_store_n(&mh->seq, 0, __ATOMIC_RELEASE);
+    }
+    // the dynamic LDS of a batched control launch must hold every member's
+    // layout, with nvl staged vectors of the largest Nb
+    for (int q = 0; q < n; ++q) {
+        SlotArgs<double> *A = (SlotArgs<double> *)(b->h_args + b->use_off[kUSlot] + (size_t)q * b->use_size[kUSlot]);
+        A->nvl = nvl_min;
+    }
+    slot_lds_max = (size_t)b->nb_max * sizeof(double) * (1 + nvl_min) + (size_t)o.restart * o.restart * sizeof(double);
+    KFBI_HIP(hipEventRecord(b->ev0, s));
+    KFBI_HIP(hipMemcpyAsync(b->d_args, b->h_args, b->args_bytes, hipMemcpyHostToDevice, s));
+    auto dargs = [&](int u) { return (const void *)(b->d_args + b->use_off[u]); };
+    auto mapk = [&](int kind) { return b->d_map + b->map_off[kind]; };
+    auto launch = [&](int kind, int use) -> int {
+        return batch_launch(kind, dargs(use), mapk(kind), b->map_blocks[kind], 0, nullptr, s);
+    };
+    // DST launches: LDS for the largest grid (each block uses its own M)
+    int m_max = 0;
+    for (auto *d : b->doms) m_max = std::max(m_max, d->M);
+    auto launch_dst = [&](int use) -> int {
+        return batch_launch(kBaDst, dargs(use), mapk(kBaDst), b->map_blocks[kBaDst], m_max, nullptr, s);
+    };
+    auto launch_erow = [&](int use, bool low) -> int {
+        return batch_launch(low ? kBaErow32 : kBaErow64, dargs(use), mapk(kBaErow64), b->map_blocks[kBaErow64],
+                            m_max, nullptr, s);
+    };
+    auto launch_tri = [&](int use, bool low, bool dense) -> int {
+        for (auto &C : b->classes) {
+            const BatchTriShape &S = low ? C.sparse32 : (dense ? C.dense : C.sparse64);
+            KFBI_TRY(batch_launch(low ? kBaTri32 : kBaTri64, dargs(use), b->d_map + (low ? C.map32 : C.map64),
+                                  low ? C.blocks32 : C.blocks64, C.M, &S, s));
+        }
+        return KFBI_OK;
+    };
+    // b-solve for every member
+    KFBI_TRY(launch_dst(kUDstF));
+    KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrB), mapk(kBaCorr), b->map_blocks[kBaCorr], s));
+    KFBI_TRY(launch_tri(kUTriB, false, true));
+    KFBI_TRY(launch_erow(kUErowB, false));
+    KFBI_TRY(batch_launch_iface(kBaExt, dargs(kUExtB), mapk(kBaExt), b->map_blocks[kBaExt], s));
+    kb_copy<<<b->map_blocks[kBaCopy], 256, 0, s>>>((const CopyArgs *)dargs(kUCopyX), mapk(kBaCopy));
+    KFBI_CHECK_LAUNCH();
+    kb_gm_init<<<n, kGmThreads, 0, s>>>((const GmInitArgs<double> *)dargs(kUInit));
+    KFBI_CHECK_LAUNCH();
+    // slots until every member has finished
+    const int ept = (b->nb_max + kGmThreads - 1) / kGmThreads;
+    int want = b->last_slots > 0 ? b->last_slots + 1 : (o.fixed_iters > 0 ? o.fixed_iters + 2 : 16);
+    int n_enq = 0;
+    for (;;) {
+        for (int c = 0; c < want; ++c) {
+            KFBI_TRY(launch(kBaCorrPhi, kUCorrPhi64));
+            KFBI_TRY(launch_tri(kUTri64, false, false));
+            KFBI_TRY(launch_erow(kUErow64, false));
+            KFBI_TRY(launch(kBaExm, kUExm64));
+            if (mixed) {
+                KFBI_TRY(launch(kBaCorrPhi, kUCorrPhi32));
+                KFBI_TRY(launch_tri(kUTri32, true, false));
+                KFBI_TRY(launch_erow(kUErow32, true));
+                KFBI_TRY(launch(kBaExm, kUExm32));
+            }
+            const SlotArgs<double> *SA = (const SlotArgs<double> *)dargs(kUSlot);
+            if (ept <= 1) kb_gm_slot<1><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else if (ept <= 2) kb_gm_slot<2><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else if (ept <= 4) kb_gm_slot<4><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else if (ept <= 8) kb_gm_slot<8><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else kb_gm_slot<16><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            KFBI_CHECK_LAUNCH();
+        }
+        n_enq += want;
+        // final solve of the members that have finished (gated per member)
+        KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrF), mapk(kBaCorr), b->map_blocks[kBaCorr], s));
+        KFBI_TRY(launch_tri(kUTriF, false, true));
+        if (u_out) {
+            KFBI_TRY(launch_dst(kUIdst));
+            KFBI_TRY(launch(kBaZero, kUZero));
+        }
+        if (phi_inout) {
+            kb_copy<<<b->map_blocks[kBaCopy], 256, 0, s>>>((const CopyArgs *)dargs(kUCopyF), mapk(kBaCopy));
+            KFBI_CHECK_LAUNCH();
+        }
+        kb_final<<<(n + 255) / 256, 256, 0, s>>>((const FinalArgs *)dargs(kUFinal), n);
+        KFBI_CHECK_LAUNCH();
+        // wait until every member has finished or run every enqueued slot
+        const auto t0 = std::chrono::steady_clock::now();
+        bool all_done = true;
+        for (long spin = 1;; ++spin) {
+            all_done = true;
+            bool settled = true;
+            for (int q = 0; q < n; ++q) {
+                GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
+                const int seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
+                const int st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+                const bool done = seq > 0 && st == kStDone;
+                if (!done) all_done = false;
+                if (!(done || seq >= n_enq)) settled = false;
+            }
+            if (settled) break;
+            if ((spin & 255) == 0) {
+                const hipError_t qe = hipStreamQuery(s);
+                if (qe != hipSuccess && qe != hipErrorNotReady) {
+                    set_error(std::string("device error during batched GMRES: ") + hipGetErrorString(qe));
+                    return KFBI_EDEVICE;
+                }
+                if (qe == hipSuccess) {
+                    // drained: one more look at the mirrors, then give up
+                    bool ok = true;
+                    for (int q = 0; q < n; ++q) {
+                        GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
+                        const int seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
+                        const int st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+                        if (!((seq > 0 && st == kStDone) || seq >= n_enq)) ok = false;
+                    }
+                    if (ok) continue;
+                    set_error("batched GMRES control blocks not published by the device");
+                    return KFBI_EDEVICE;
+                }
+                if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(300)) {
+                    set_error("timed out waiting for the batched GMRES control blocks");
+                    return KFBI_EDEVICE;
+                }
+            }
+        }
+        if (all_done) break;
+        want = 4;
+    }
+    int max_seq = 0, st = KFBI_OK;
+    for (int q = 0; q < n; ++q) {
+        GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
+        max_seq = std::max(max_seq, mh->seq);
+        if (stats) {
+            stats[q].iters = mh->iters;
+            stats[q].converged = mh->converged;
+            stats[q].rel_resid = mh->bnorm > 0 ? mh->resid / mh->bnorm : mh->resid;
+            stats[q].refinements = mixed ? mh->cycles : 0;
+            stats[q].pad = 0;
+            stats[q].device_ms = -1.0;
+        }
+        if (!mh->converged && o.fixed_iters <= 0) st = KFBI_ENOCONV;
+    }
+    b->last_slots = max_seq;
+    KFBI_HIP(hipEventRecord(b->ev1, s));
+    if (!(o.flags & KFBI_SOLVE_ASYNC)) {
+        KFBI_HIP(hipEventSynchronize(b->ev1));
+        float ms = 0.f;
+        KFBI_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        if (stats)
+            for (int q = 0; q < n; ++q) stats[q].device_ms = ms;
+    }
+    if (st == KFBI_ENOCONV) set_error("GMRES reached max_iter before the tolerance for a batch member");
+    return st;
+}
+
 }  // namespace kfbi

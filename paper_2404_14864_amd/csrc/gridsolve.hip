@@ -30,6 +30,7 @@
 //                   the inverse transform of its row.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kfbi_internal.h"
@@ -604,6 +605,65 @@ __global__ __launch_bounds__(384) void k_eval_extract(EvxArgs<T, TO> A) {
     eval_extract_body(A, blockIdx.x);
 }
 
+// Grid values at the stencil nodes by rows: one workgroup per interior row
+// holding stencil nodes stages that row of U^ and the sine table in LDS
+// once, then one wavefront per node of the row forms U = (2/M) sum_k
+// U^[t][k] sin(pi i k / M) (same sum and reduction order as k_eval_nodes).
+// Reads each needed row once instead of once per node.
+template <class T, class TO>
+__device__ void eval_rows_body(const ErowArgs<T, TO> &A, int blk) {
+    typedef typename Real<T>::type R;
+    if (A.done && *A.done) return;
+    extern __shared__ double lds[];
+    const int M = A.M, n = M - 1, mask2M = 2 * M - 1;
+    R *S = reinterpret_cast<R *>(lds);
+    T *row = reinterpret_cast<T *>(S + 2 * M);
+    const int t = A.erow_t[blk];
+    const T *src = A.uhat + (size_t)t * n;
+    for (int q = threadIdx.x; q < 2 * M; q += blockDim.x) S[q] = A.sine[q];
+    for (int q = threadIdx.x; q < n; q += blockDim.x) row[q] = src[q];
+    __syncthreads();
+    const int e0 = A.erow_ptr[blk], e1 = A.erow_ptr[blk + 1];
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int e = e0 + (int)(threadIdx.x >> 6); e < e1; e += nw) {
+        const int i = A.erow_col[e];
+        T acc = zero<T>();
+        for (int k = lane; k < n; k += 64) acc += row[k] * S[(i * (k + 1)) & mask2M];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+        if (lane == 0) A.ust[A.erow_ent[e]] = to_high(acc * (R)(2.0 / M));
+    }
+}
+
+template <class T, class TO>
+__global__ __launch_bounds__(256) void k_eval_rows(ErowArgs<T, TO> A) {
+    eval_rows_body(A, blockIdx.x);
+}
+
+// K phi at collocation point k from its six stencil values: the extraction
+// sum_p w6[k][p] U_p + sum_o bop[k][o] phi[k-2+o] (as in k_eval_extract)
+template <class T>
+__device__ void extract_merged_body(const ExmArgs<T> &A, int blk) {
+    if (A.done && *A.done) return;
+    const int k = blk * blockDim.x + threadIdx.x, Nb = A.Nb;
+    if (k >= Nb) return;
+    T r = zero<T>();
+#pragma unroll
+    for (int q = 0; q < 6; ++q) r += A.ust[6 * k + q] * A.w6[6 * k + q];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+        int idx = k - 2 + o;
+        idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
+        r += A.bop[5 * k + o] * A.phi[idx];
+    }
+    A.kv[k] = r;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_extract_merged(ExmArgs<T> A) {
+    extract_merged_body(A, blockIdx.x);
+}
+
 // argument blocks and launch shapes shared by the single and batched paths
 template <class T>
 DstArgs<T> dst_args(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out, bool out_grid,
@@ -670,6 +730,32 @@ EvxArgs<T, TO> evx_args(kfbi_domain *d, const void *uhat, const void *phi, void 
     A.kv = (TO *)kv;
     A.done = done;
     return A;
+}
+
+template <class T, class TO>
+ErowArgs<T, TO> erow_args(kfbi_domain *d, const void *uhat, void *ust, const int *done) {
+    typedef typename Real<T>::type R;
+    const bool low = sizeof(T) < sizeof(TO);
+    ErowArgs<T, TO> A;
+    A.M = d->M;
+    A.erow_t = d->erow_t;
+    A.erow_ptr = d->erow_ptr;
+    A.erow_ent = d->erow_ent;
+    A.erow_col = d->erow_col;
+    A.uhat = (const T *)uhat;
+    A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.ust = (TO *)ust;
+    A.done = done;
+    return A;
+}
+template <class T, class TO>
+size_t erow_lds(int M) {
+    return (size_t)2 * M * sizeof(typename Real<T>::type) + (size_t)(M - 1) * sizeof(T);
+}
+
+template <class T>
+ExmArgs<T> exm_args(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done) {
+    return ExmArgs<T>{d->Nb, (const T *)ust, d->w6, (const T *)d->bop, (const T *)phi, (T *)kv, done};
 }
 
 template <class T, class TO>
@@ -994,6 +1080,200 @@ int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, cons
     KFBI_CHECK_LAUNCH();
     const double es = low ? elem_size(d) / 2.0 : elem_size(d);
     prof_end(d, ps, KFBI_K_EVAL_NODES, (double)nn * ((d->M - 1) * es + 4.0 + elem_size(d)));
+    return KFBI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches: one grid runs the blocks of many instances; workgroup b
+// looks up (instance, local block) in a map and reads that instance's
+// argument block.  Only real instances (FP64 with FP32 inner solves).
+// ---------------------------------------------------------------------------
+namespace {
+template <class T>
+__global__ __launch_bounds__(256) void kb_dst_rows(const DstArgs<T> *__restrict__ A, const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    dst_rows_body(A[e.inst], e.local);
+}
+template <class T>
+__global__ __launch_bounds__(256) void kb_zero_edge_rows(const ZeroArgs<T> *__restrict__ A,
+                                                         const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    zero_edge_body(A[e.inst], e.local);
+}
+template <class T, class TO>
+__global__ __launch_bounds__(256) void kb_eval_nodes(const EvalArgs<T, TO> *__restrict__ A,
+                                                     const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    eval_nodes_body(A[e.inst], e.local);
+}
+template <class T, class TO>
+__global__ __launch_bounds__(384) void kb_eval_extract(const EvxArgs<T, TO> *__restrict__ A,
+                                                       const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    eval_extract_body(A[e.inst], e.local);
+}
+template <class TC>
+__global__ __launch_bounds__(64) void kb_corr_phi(const CorrPhiArgs<TC> *__restrict__ A,
+                                                  const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    corr_phi_body(A[e.inst], e.local);
+}
+template <class T, class TO>
+__global__ __launch_bounds__(256) void kb_eval_rows(const ErowArgs<T, TO> *__restrict__ A,
+                                                    const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    eval_rows_body(A[e.inst], e.local);
+}
+__global__ __launch_bounds__(256) void kb_extract_merged(const ExmArgs<double> *__restrict__ A,
+                                                         const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    extract_merged_body(A[e.inst], e.local);
+}
+}  // namespace
+
+// argument blocks of one member, written to host memory
+size_t batch_args_size(int kind) {
+    switch (kind) {
+        case kBaDst: return sizeof(DstArgs<double>);
+        case kBaZero: return sizeof(ZeroArgs<double>);
+        case kBaTri64: return sizeof(TriArgs<double, double>);
+        case kBaTri32: return sizeof(TriArgs<float, double>);
+        case kBaEval: return sizeof(EvalArgs<double, double>);
+        case kBaEvx64: return sizeof(EvxArgs<double, double>);
+        case kBaEvx32: return sizeof(EvxArgs<float, double>);
+        case kBaCorrPhi: return sizeof(CorrPhiArgs<double>);
+        case kBaErow64: return sizeof(ErowArgs<double, double>);
+        case kBaErow32: return sizeof(ErowArgs<float, double>);
+        case kBaExm: return sizeof(ExmArgs<double>);
+        default: return 0;
+    }
+}
+
+void batch_fill_dst(kfbi_domain *d, const void *in, bool in_grid, bool mask_inside, void *out, bool out_grid,
+                    double scale, const int *done, void *dst) {
+    *(DstArgs<double> *)dst = dst_args<double>(d, in, in_grid, mask_inside ? d->flags : nullptr, out, out_grid,
+                                               scale, done);
+}
+void batch_fill_zero(kfbi_domain *d, void *grid, const int *done, void *dst) {
+    *(ZeroArgs<double> *)dst = ZeroArgs<double>{d->M, (double *)grid, done};
+}
+void batch_fill_tri(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done, bool low,
+                    void *dst) {
+    if (low) *(TriArgs<float, double> *)dst = tri_args<float>(d, rhat, corr, uhat, done);
+    else *(TriArgs<double, double> *)dst = tri_args<double>(d, rhat, corr, uhat, done);
+}
+void batch_fill_eval(kfbi_domain *d, const void *uhat, void *out, const int *done, void *dst) {
+    *(EvalArgs<double, double> *)dst = eval_args<double, double>(d, uhat, out, done);
+}
+void batch_fill_evx(kfbi_domain *d, const void *uhat, const void *phi, void *kv, const int *done, bool low,
+                    void *dst) {
+    if (low) *(EvxArgs<float, double> *)dst = evx_args<float, double>(d, uhat, phi, kv, done);
+    else *(EvxArgs<double, double> *)dst = evx_args<double, double>(d, uhat, phi, kv, done);
+}
+void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst) {
+    *(CorrPhiArgs<double> *)dst = corr_phi_args<double>(d, phi, corr, done);
+}
+void batch_fill_erow(kfbi_domain *d, const void *uhat, void *ust, const int *done, bool low, void *dst) {
+    if (low) *(ErowArgs<float, double> *)dst = erow_args<float, double>(d, uhat, ust, done);
+    else *(ErowArgs<double, double> *)dst = erow_args<double, double>(d, uhat, ust, done);
+}
+void batch_fill_exm(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done, void *dst) {
+    *(ExmArgs<double> *)dst = exm_args<double>(d, ust, phi, kv, done);
+}
+
+int batch_blocks(const kfbi_domain *d, int kind) {
+    switch (kind) {
+        case kBaDst: return dst_blocks<double>(d->M);
+        case kBaZero: return (d->M + 1 + 255) / 256;
+        case kBaTri64: return tri_shape<double>(d, true).blocks;
+        case kBaTri32: return tri_shape<float>(d, true).blocks;
+        case kBaEval: return (6 * d->Nb + 3) / 4;
+        case kBaEvx64:
+        case kBaEvx32: return d->Nb;
+        case kBaCorrPhi: return (d->n_irr + 63) / 64;
+        case kBaErow64:
+        case kBaErow32: return d->n_erows;
+        case kBaExm: return (d->Nb + 255) / 256;
+        default: return 0;
+    }
+}
+
+// launch shape of the tridiagonal kernel shared by a batch class (equal M,
+// mb and c; LDS the largest over the members; staged when all fit)
+int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out) {
+    for (int q = 0; q < n; ++q) {
+        const TriShape S = low ? tri_shape<float>(doms[q], sparse) : tri_shape<double>(doms[q], sparse);
+        if (q == 0) {
+            out->mb = S.mb;
+            out->c = S.c;
+            out->lds = S.lds_base;
+            out->stage_lds = S.lds_base + S.stage_bytes;
+        } else {
+            if (S.mb != out->mb || S.c != out->c) {
+                set_error("batch class members differ in tridiagonal launch shape");
+                return KFBI_EINVAL;
+            }
+            out->lds = std::max(out->lds, S.lds_base);
+            out->stage_lds = std::max(out->stage_lds, S.lds_base + S.stage_bytes);
+        }
+    }
+    if (out->c > 32 || out->lds > kTriLdsMax) {
+        set_error("grid too large for the tridiagonal kernel");
+        return KFBI_ENOTSUP;
+    }
+    out->stage = sparse && out->stage_lds <= kTriLdsMax;
+    if (out->stage) out->lds = out->stage_lds;
+    return KFBI_OK;
+}
+
+int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
+                 hipStream_t s) {
+    if (blocks <= 0) return KFBI_OK;
+    switch (kind) {
+        case kBaDst:
+            kb_dst_rows<double><<<blocks, 256, dst_lds(M), s>>>((const DstArgs<double> *)args, map);
+            break;
+        case kBaZero:
+            kb_zero_edge_rows<double><<<blocks, 256, 0, s>>>((const ZeroArgs<double> *)args, map);
+            break;
+        case kBaTri64: {
+            TriLaunchBatch<double, double> L{(const TriArgs<double, double> *)args, map, blocks, shape->lds, s};
+            tri_dispatch(shape->mb, shape->c, shape->stage, L);
+            break;
+        }
+        case kBaTri32: {
+            TriLaunchBatch<float, double> L{(const TriArgs<float, double> *)args, map, blocks, shape->lds, s};
+            tri_dispatch(shape->mb, shape->c, shape->stage, L);
+            break;
+        }
+        case kBaEval:
+            kb_eval_nodes<double, double><<<blocks, 256, 0, s>>>((const EvalArgs<double, double> *)args, map);
+            break;
+        case kBaEvx64:
+            kb_eval_extract<double, double><<<blocks, 384, 0, s>>>((const EvxArgs<double, double> *)args, map);
+            break;
+        case kBaEvx32:
+            kb_eval_extract<float, double><<<blocks, 384, 0, s>>>((const EvxArgs<float, double> *)args, map);
+            break;
+        case kBaCorrPhi:
+            kb_corr_phi<double><<<blocks, 64, 0, s>>>((const CorrPhiArgs<double> *)args, map);
+            break;
+        case kBaErow64:
+            kb_eval_rows<double, double><<<blocks, 256, erow_lds<double, double>(M), s>>>(
+                (const ErowArgs<double, double> *)args, map);
+            break;
+        case kBaErow32:
+            kb_eval_rows<float, double><<<blocks, 256, erow_lds<float, double>(M), s>>>(
+                (const ErowArgs<float, double> *)args, map);
+            break;
+        case kBaExm:
+            kb_extract_merged<<<blocks, 256, 0, s>>>((const ExmArgs<double> *)args, map);
+            break;
+        default:
+            set_error("unknown batched kernel");
+            return KFBI_EINVAL;
+    }
+    KFBI_CHECK_LAUNCH();
     return KFBI_OK;
 }
 

@@ -437,4 +437,52 @@ int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     return KFBI_OK;
 }
 
+// batched launches (real members)
+namespace {
+__global__ __launch_bounds__(128) void kb_corrections(const CorrArgs<double> *__restrict__ A,
+                                                      const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    corrections_body(A[e.inst], e.local);
+}
+__global__ __launch_bounds__(128) void kb_extract(const ExtArgs<double> *__restrict__ A,
+                                                  const BlkMap *__restrict__ map) {
+    const BlkMap e = map[blockIdx.x];
+    extract_body(A[e.inst], e.local);
+}
+}  // namespace
+
+size_t batch_args_size_iface(int kind) {
+    if (kind == kBaCorr) return sizeof(CorrArgs<double>);
+    if (kind == kBaExt) return sizeof(ExtArgs<double>);
+    return 0;
+}
+
+int batch_blocks_iface(const kfbi_domain *d, int kind) {
+    if (kind == kBaCorr) return (d->n_irr + 127) / 128;
+    if (kind == kBaExt) return (d->Nb + 127) / 128;
+    return 0;
+}
+
+void batch_fill_corr(kfbi_domain *d, double kre, const void *phi, const void *fg, void *corr, const int *done,
+                     void *dst) {
+    *(CorrArgs<double> *)dst = corr_args<double>(d, kre, 0.0, phi, nullptr, fg, corr, done);
+}
+
+void batch_fill_ext(kfbi_domain *d, double kre, const void *ust, const void *phi, const void *fg, const void *g,
+                    double scale, void *out, const int *done, void *dst) {
+    *(ExtArgs<double> *)dst = ext_args<double>(d, kre, 0.0, ust, phi, nullptr, fg, g, scale, out, 0, done);
+}
+
+int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s) {
+    if (blocks <= 0) return KFBI_OK;
+    if (kind == kBaCorr) kb_corrections<<<blocks, 128, 0, s>>>((const CorrArgs<double> *)args, map);
+    else if (kind == kBaExt) kb_extract<<<blocks, 128, 0, s>>>((const ExtArgs<double> *)args, map);
+    else {
+        set_error("unknown batched kernel");
+        return KFBI_EINVAL;
+    }
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
 }  // namespace kfbi

@@ -200,6 +200,11 @@ struct kfbi_domain {
     int32_t *seg_row = nullptr;
     int32_t *row_seg = nullptr;
     int n_seg = 0;
+    // the stencil nodes grouped by interior grid row (rows erow_t[r],
+    // entries erow_ptr[r] .. erow_ptr[r+1]: stencil-value index 6k+p and
+    // column); erow_lo .. erow_hi spans every such row
+    int32_t *erow_t = nullptr, *erow_ptr = nullptr, *erow_ent = nullptr, *erow_col = nullptr;
+    int n_erows = 0, erow_lo = 0, erow_hi = 0;
     kfbi::Colloc *col = nullptr;        // Nb
     kfbi::Stencil *st = nullptr;        // Nb
     double *sine = nullptr;             // 2M: sin(pi m / M)
@@ -451,11 +456,98 @@ struct ExtArgs {
     const int *done;
 };
 
+// stencil values by rows: one workgroup per row that holds stencil nodes
+template <class T, class TO>
+struct ErowArgs {
+    int M;
+    const int32_t *erow_t, *erow_ptr, *erow_ent, *erow_col;
+    const T *uhat;
+    const typename Real<T>::type *sine;
+    TO *ust;
+    const int *done;
+};
+
+// K phi at the collocation points from the stencil values (merged form)
+template <class T>
+struct ExmArgs {
+    int Nb;
+    const T *ust;
+    const double *w6;
+    const T *bop;
+    const T *phi;
+    T *kv;
+    const int *done;
+};
+
 // batched launches: workgroup b of the launch runs local block `local` of
 // instance `inst`
 struct BlkMap {
     int inst, local;
 };
+
+// ---------------------------------------------------------------------------
+// Batched solves (many real domains per launch).  Each kernel kind has an
+// argument block per member and a block count per member; the batch driver
+// lays the members' blocks out in a BlkMap and launches one grid.
+// ---------------------------------------------------------------------------
+enum {
+    kBaDst = 0,       // DST rows (dense forward or inverse)
+    kBaZero,          // first / last grid rows of an output grid
+    kBaTri64,         // tridiagonal solve, FP64
+    kBaTri32,         // tridiagonal solve, FP32 inner
+    kBaEval,          // grid values at the stencil nodes
+    kBaEvx64,         // K phi at the collocation points, FP64 grid values
+    kBaEvx32,         //   from FP32 grid values
+    kBaCorrPhi,       // corrections of a density (merged operator)
+    kBaCorr,          // corrections, general form
+    kBaExt,           // extraction, general form
+    kBaInit,          // GMRES control block init
+    kBaSlot,          // GMRES control kernel
+    kBaCopy,          // gated copy of the density
+    kBaFinal,         // marks a finished member's final solve done
+    kBaErow64,        // stencil values by rows, FP64 grid values
+    kBaErow32,        //   from FP32 grid values
+    kBaExm,           // K phi from stencil values (merged operator)
+    kBaKinds
+};
+
+struct BatchTriShape {
+    int mb, c;
+    bool stage;
+    size_t lds, stage_lds;
+};
+
+size_t batch_args_size(int kind);
+int batch_blocks(const kfbi_domain *d, int kind);
+int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out);
+int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
+                 hipStream_t s);
+void batch_fill_dst(kfbi_domain *d, const void *in, bool in_grid, bool mask_inside, void *out, bool out_grid,
+                    double scale, const int *done, void *dst);
+void batch_fill_zero(kfbi_domain *d, void *grid, const int *done, void *dst);
+void batch_fill_tri(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done, bool low,
+                    void *dst);
+void batch_fill_eval(kfbi_domain *d, const void *uhat, void *out, const int *done, void *dst);
+void batch_fill_evx(kfbi_domain *d, const void *uhat, const void *phi, void *kv, const int *done, bool low,
+                    void *dst);
+void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst);
+void batch_fill_erow(kfbi_domain *d, const void *uhat, void *ust, const int *done, bool low, void *dst);
+void batch_fill_exm(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done, void *dst);
+// interface.hip
+size_t batch_args_size_iface(int kind);
+int batch_blocks_iface(const kfbi_domain *d, int kind);
+void batch_fill_corr(kfbi_domain *d, double kre, const void *phi, const void *fg, void *corr, const int *done,
+                     void *dst);
+void batch_fill_ext(kfbi_domain *d, double kre, const void *ust, const void *phi, const void *fg, const void *g,
+                    double scale, void *out, const int *done, void *dst);
+int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s);
+
+// batched Helmholtz solves (gmres.hip)
+int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out);
+void batch_destroy(kfbi_batch *b);
+int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
+                    const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
+                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
 // kernel timing: prof_begin returns a slot (or -1 when profiling is off);
 // prof_end closes it with the launch's algorithmic bytes; prof_flush waits

@@ -111,6 +111,11 @@ def lib():
         "kfbi_stepper_state_bytes": ([_P, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "kfbi_stepper_get_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
         "kfbi_stepper_set_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
+        "kfbi_batch_create": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
+        "kfbi_batch_destroy": ([_P], ctypes.c_int),
+        "kfbi_batch_helmholtz": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                  ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                  ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
         "kfbi_profile_replay": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -127,7 +132,8 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_grid_solve", "kfbi_interface_apply", "kfbi_helmholtz_solve", "kfbi_stepper_create",
             "kfbi_stepper_destroy", "kfbi_stepper_init", "kfbi_step_heat", "kfbi_step_wave",
             "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read", "kfbi_profile_replay",
-            "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state")
+            "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state",
+            "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz")
 
 
 def kfbi_profile_enable(h, on=True):
@@ -139,6 +145,42 @@ def kfbi_profile_read(h):
     _check(lib().kfbi_profile_read(h, arr))
     return {name: {"launches": int(arr[i].launches), "total_ms": arr[i].total_ms,
                    "bytes": arr[i].bytes} for i, name in enumerate(KERNELS)}
+
+
+# ---- batches ---------------------------------------------------------------
+def kfbi_batch_create(domains):
+    """A batch of real domain handles (same stream) solved together."""
+    n = len(domains)
+    arr = (_P * n)(*[d.value if isinstance(d, ctypes.c_void_p) else d for d in domains])
+    out = _P()
+    _check(lib().kfbi_batch_create(arr, n, ctypes.byref(out)))
+    return out
+
+
+def kfbi_batch_destroy(b):
+    _check(lib().kfbi_batch_destroy(b))
+
+
+def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, phi_inout=None, opts=None):
+    """Member q solves lap u - kappas[q] u = f_grid[q] with u = g_gamma[q] on
+    Gamma; all arguments are lists of float64 CUDA tensors (u_grid_out and
+    phi_inout may be None or contain None).  Returns the per-member stats."""
+    n = len(kappas)
+    if not (len(f_grid) == len(f_gamma) == len(g_gamma) == n):
+        raise ValueError("one entry per member is required")
+    kap = (ctypes.c_double * n)(*[float(k) for k in kappas])
+
+    def ptrs(lst, name):
+        if lst is None:
+            return None
+        return (_P * n)(*[(_ptr(t, torch.float64, None, name).value if t is not None else None) for t in lst])
+
+    stats = (SolveStats * n)()
+    code = lib().kfbi_batch_helmholtz(b, kap, ptrs(f_grid, "f_grid"), ptrs(f_gamma, "f_gamma"),
+                                      ptrs(g_gamma, "g_gamma"), ptrs(u_grid_out, "u_grid_out"),
+                                      ptrs(phi_inout, "phi_inout"), _opts(opts), stats)
+    _check(code, allow=(KFBI_ENOCONV,))
+    return [stats[q].as_dict() for q in range(n)]
 
 
 def kfbi_profile_replay(h, kind, reps):

@@ -16,6 +16,21 @@ class SmoothField:
         self.alpha = rng.uniform(0.0, 2.0 * np.pi, (n, n))
         self.beta = rng.uniform(0.0, 2.0 * np.pi, (n, n))
 
+    def grid(self, x, y):
+        """The field on the tensor grid F[j, i] = f(x[i], y[j]): each term is a
+        product of a function of x and a function of y, so the sum is one
+        (len(y) x n^2) @ (n^2 x len(x)) product."""
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        p = np.arange(self.n)[:, None]
+        q = np.arange(self.n)[None, :]
+        amp = (self.g * np.exp(-(p * p + q * q) / 8.0)).ravel()
+        cx = np.cos(np.pi / 2.0 * np.multiply.outer(np.repeat(np.arange(self.n), self.n), x)
+                    + self.alpha.ravel()[:, None])
+        cy = np.cos(np.pi / 2.0 * np.multiply.outer(np.tile(np.arange(self.n), self.n), y)
+                    + self.beta.ravel()[:, None])
+        return (cy.T * amp) @ cx
+
     def __call__(self, x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
