@@ -154,12 +154,28 @@ def batched_helmholtz(n, reps):
         Tb = (time.perf_counter() - t0) / reps
         batched = float(np.dot(pts, bits) / Tb)
         diff = max(float((m["u"] - r).abs().max() / max(r.abs().max(), 1e-300)) for m, r in zip(mem, ref))
+        tuning = [r for r in kfbi.kfbi_batch_tuning(b) if r["tuned"]]
+        kfbi.kfbi_batch_destroy(b)
+        # the same batch with the default tridiagonal launch shapes
+        b = kfbi.kfbi_batch_create([m["h"] for m in mem])
+        opts_nt = dict(opts, no_tune=True)
+        kfbi.kfbi_batch_helmholtz(b, *args, opts=opts_nt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            kfbi.kfbi_batch_helmholtz(b, *args, opts=opts_nt)
+        torch.cuda.synchronize()
+        Tu = (time.perf_counter() - t0) / reps
         kfbi.kfbi_batch_destroy(b)
         out[label] = {"plain_value": plain, "plain_ms": 1e3 * Tp, "batched_value": batched, "batched_ms": 1e3 * Tb,
-                      "speedup": batched / plain, "gmres_iters_total": int(sum(bits)),
-                      "max_rel_diff_batched_vs_plain": diff}
-        log("batch %s: plain %.3g (%.1f ms), batched %.3g (%.1f ms), x%.1f, %d iterations" % (
-            label, plain, 1e3 * Tp, batched, 1e3 * Tb, batched / plain, sum(bits)))
+                      "batched_untuned_ms": 1e3 * Tu, "speedup": batched / plain, "gmres_iters_total": int(sum(bits)),
+                      "max_rel_diff_batched_vs_plain": diff,
+                      "tridiag_shapes": ["M%d %s: %d modes/wg%s, %.1f us" % (
+                          r["M"], r["kind"], r["modes_per_wg"], " staged" if r["staged"] else "", r["us"])
+                          for r in tuning]}
+        log("batch %s: plain %.3g (%.1f ms), batched %.3g (%.1f ms; default shapes %.1f ms), x%.1f, %d iterations" % (
+            label, plain, 1e3 * Tp, batched, 1e3 * Tb, 1e3 * Tu, batched / plain, sum(bits)))
+        log("batch %s tridiagonal shapes: %s" % (label, "; ".join(out[label]["tridiag_shapes"])))
     out["unit"] = "grid-pts*GMRES-iters/s"
     for m in mem:
         kfbi.kfbi_domain_destroy(m["h"])

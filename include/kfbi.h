@@ -111,6 +111,11 @@ typedef struct {
  * except device_ms, which is -1. */
 #define KFBI_SOLVE_ASYNC 1
 
+/* kfbi_solve_opts.flags, batched solves only: keep the default launch shape
+ * of the tridiagonal kernel instead of timing the candidates (see
+ * kfbi_batch_tuning).  The choice never changes results. */
+#define KFBI_BATCH_NO_TUNE 2
+
 typedef struct {
     int32_t iters;        /* GMRES iterations (matrix-vector products in Arnoldi) */
     int32_t converged;
@@ -271,6 +276,19 @@ int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *
                          const void *const *f_gamma, const void *const *g_gamma,
                          void *const *u_grid_out, void *const *phi_inout,
                          const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
+/* Launch shape of the tridiagonal kernel (the y-direction solves of the
+ * five-point system, section 3.4) per class of members with equal M.  The
+ * first kfbi_batch_helmholtz of each precision (unless KFBI_BATCH_NO_TUNE)
+ * times, on the members' own tables, every shape that computes the same
+ * values (1, 2 or 4 sine modes per 256-, 128- or 64-lane workgroup; the
+ * sparse input staged in LDS or read from HBM) and keeps the fastest.
+ * Writes min(cap, rows) rows of 5 int32 {M, kind (0: sparse FP64, 1: with
+ * dense input FP64, 2: sparse FP32), modes per workgroup, staged, tuned}
+ * to rows (may be NULL when cap is 0), the time of the kept shape in
+ * microseconds per launch of the class (or -1 when untuned) to us (may be
+ * NULL), and the row count to n_rows.  Errors: KFBI_EINVAL. */
+int kfbi_batch_tuning(const kfbi_batch *b, int32_t cap, int32_t *rows, double *us, int32_t *n_rows);
 
 /* Per-kernel device timing (instrumentation for benchmarks).  When enabled,
  * every launch of the listed kernels of this domain is bracketed by two HIP

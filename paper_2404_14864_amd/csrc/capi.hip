@@ -232,6 +232,10 @@ int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *
     return batch_helmholtz(b, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
 }
 
+int kfbi_batch_tuning(const kfbi_batch *b, int32_t cap, int32_t *rows, double *us, int32_t *n_rows) {
+    return batch_tuning(b, cap, rows, us, n_rows);
+}
+
 int kfbi_profile_replay(kfbi_domain *d, int32_t kind, int32_t reps, double *avg_ms, double *bytes_per_launch) {
     if (!d || !avg_ms || !bytes_per_launch) { set_error("null argument"); return KFBI_EINVAL; }
     if (reps < 1 || reps > 100000) { set_error("reps must be in 1..100000"); return KFBI_EINVAL; }

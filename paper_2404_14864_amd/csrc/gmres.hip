@@ -1548,12 +1548,19 @@ enum {
 
 }  // namespace
 
+// members of equal M share the tridiagonal launches: one workgroup map per
+// choice of 1, 2, 4 or 8 modes per workgroup, and the shape in use for the
+// sparse FP64, dense-input FP64 and sparse FP32 solves
 struct BatchClass {
     int M;
     std::vector<int> members;
-    int map64, blocks64, map32, blocks32;
-    BatchTriShape dense, sparse64, sparse32;
+    int map_mb[4], blocks_mb[4];
+    BatchTriShape shape[3];
+    bool tuned[3];
+    double us[3];
 };
+
+inline int mb_log2(int mb) { return mb >= 8 ? 3 : mb >= 4 ? 2 : mb >= 2 ? 1 : 0; }
 
 }  // namespace kfbi
 
@@ -1633,18 +1640,18 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
             if (doms[q]->M == M) C.members.push_back(q);
         std::vector<kfbi_domain *> cd;
         for (int q : C.members) cd.push_back(doms[q]);
-        int st = batch_tri_shape(cd.data(), (int)cd.size(), true, false, &C.sparse64);
-        if (st == KFBI_OK) st = batch_tri_shape(cd.data(), (int)cd.size(), true, false, &C.dense);
-        if (st == KFBI_OK) st = batch_tri_shape(cd.data(), (int)cd.size(), true, true, &C.sparse32);
-        if (st != KFBI_OK) { batch_destroy(b); return st; }
-        C.map64 = (int)map.size();
-        for (int q : C.members)
-            for (int l = 0; l < batch_blocks(doms[q], kBaTri64); ++l) map.push_back(BlkMap{q, l});
-        C.blocks64 = (int)map.size() - C.map64;
-        C.map32 = (int)map.size();
-        for (int q : C.members)
-            for (int l = 0; l < batch_blocks(doms[q], kBaTri32); ++l) map.push_back(BlkMap{q, l});
-        C.blocks32 = (int)map.size() - C.map32;
+        for (int kind = 0; kind < 3; ++kind) {
+            const int st = batch_tri_shape(cd.data(), (int)cd.size(), true, kind == 2, &C.shape[kind]);
+            if (st != KFBI_OK) { batch_destroy(b); return st; }
+            C.tuned[kind] = false;
+            C.us[kind] = -1.0;
+        }
+        for (int lm = 0; lm < 4; ++lm) {
+            C.map_mb[lm] = (int)map.size();
+            for (int q : C.members)
+                for (int l = 0; l < batch_tri_blocks(doms[q], 1 << lm); ++l) map.push_back(BlkMap{q, l});
+            C.blocks_mb[lm] = (int)map.size() - C.map_mb[lm];
+        }
         b->classes.push_back(C);
     }
     // argument arrays
@@ -1697,6 +1704,121 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
     return KFBI_OK;
 }
 
+// microseconds per launch of one class's tridiagonal solves in shape S: one
+// launch to warm up, one to size the run, then about 2 ms of launches
+int tune_time(kfbi_batch *b, int kind, const void *args, const BatchClass &C, const BatchTriShape &S, double *us) {
+    hipStream_t s = b->stream;
+    const int lm = mb_log2(S.mb);
+    auto go = [&]() { return batch_launch(kind, args, b->d_map + C.map_mb[lm], C.blocks_mb[lm], C.M, &S, s); };
+    KFBI_TRY(go());
+    float ms = 0.f;
+    KFBI_HIP(hipEventRecord(b->ev0, s));
+    KFBI_TRY(go());
+    KFBI_HIP(hipEventRecord(b->ev1, s));
+    KFBI_HIP(hipEventSynchronize(b->ev1));
+    KFBI_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    const int reps = std::min(20, std::max(2, (int)(2.0 / std::max(ms, 1e-3f)) + 1));
+    KFBI_HIP(hipEventRecord(b->ev0, s));
+    for (int r = 0; r < reps; ++r) KFBI_TRY(go());
+    KFBI_HIP(hipEventRecord(b->ev1, s));
+    KFBI_HIP(hipEventSynchronize(b->ev1));
+    KFBI_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    *us = 1e3 * ms / reps;
+    return KFBI_OK;
+}
+
+// Times the tridiagonal launch shapes of every class once per precision and
+// keeps the fastest.  Only shapes with 64-lane mode groups (1, 2 or 4 modes
+// per workgroup) are candidates: for a given mode they run the same
+// operations in the same order, so the choice never changes the values.
+// Inputs are the members' own tables with the scratch right-hand sides
+// cleared; the launches write only the scratch transforms.
+int batch_tune_run(kfbi_batch *b, bool low, char *d_buf) {
+    const int n = (int)b->doms.size();
+    const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64);
+    for (auto &C : b->classes) {
+        std::vector<kfbi_domain *> cd;
+        for (int q : C.members) cd.push_back(b->doms[q]);
+        const int kinds_hi[] = {0, 1}, kinds_lo[] = {2};
+        const int *kinds = low ? kinds_lo : kinds_hi;
+        const int nk = low ? 1 : 2;
+        for (int ik = 0; ik < nk; ++ik) {
+            const int kind = kinds[ik];
+            if (C.tuned[kind] || C.shape[kind].mb > 4) continue;
+            const void *args = d_buf + (kind == 1 ? (size_t)n * as : 0);
+            BatchTriShape best = C.shape[kind];
+            double best_us = 1e300;
+            for (int mb : {1, 2, 4}) {
+                for (int stage : {0, 1}) {
+                    BatchTriShape S;
+                    if (batch_tri_shape(cd.data(), (int)cd.size(), true, low, &S, mb, stage) != KFBI_OK) continue;
+                    double us = 0.0;
+                    KFBI_TRY(tune_time(b, low ? kBaTri32 : kBaTri64, args, C, S, &us));
+                    if (us < best_us) {
+                        best_us = us;
+                        best = S;
+                    }
+                }
+            }
+            C.shape[kind] = best;
+            C.us[kind] = best_us;
+            C.tuned[kind] = true;
+        }
+    }
+    return KFBI_OK;
+}
+
+int batch_tune(kfbi_batch *b, bool low) {
+    bool need = false;
+    for (auto &C : b->classes)
+        for (int kind : {0, 1, 2})
+            if ((kind == 2) == low && !C.tuned[kind] && C.shape[kind].mb <= 4) need = true;
+    if (!need) return KFBI_OK;
+    const int n = (int)b->doms.size();
+    hipStream_t s = b->stream;
+    const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64);
+    std::vector<char> h(2 * as * n);
+    for (int q = 0; q < n; ++q) {
+        kfbi_domain *d = b->doms[q];
+        const int nn = d->M - 1;
+        KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * sizeof(double), s));
+        KFBI_HIP(hipMemsetAsync(d->rhat, 0, (size_t)nn * nn * sizeof(double), s));
+        batch_fill_tri(d, nullptr, d->corr, low ? d->uhat32 : d->uhat, nullptr, low, h.data() + (size_t)q * as);
+        if (!low) batch_fill_tri(d, d->rhat, d->corr, d->uhat, nullptr, false, h.data() + (size_t)(n + q) * as);
+    }
+    char *d_buf = nullptr;
+    KFBI_HIP(hipMalloc((void **)&d_buf, h.size()));
+    int st = hipMemcpyAsync(d_buf, h.data(), h.size(), hipMemcpyHostToDevice, s) == hipSuccess ? KFBI_OK
+                                                                                                 : KFBI_EDEVICE;
+    if (st != KFBI_OK) set_error("copy of the tuning arguments failed");
+    if (st == KFBI_OK) st = batch_tune_run(b, low, d_buf);
+    const bool synced = hipStreamSynchronize(s) == hipSuccess;
+    hipFree(d_buf);
+    if (st == KFBI_OK && !synced) {
+        set_error("stream failed while tuning the batch");
+        st = KFBI_EDEVICE;
+    }
+    return st;
+}
+
+int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows) {
+    if (!b || !n_rows || cap < 0 || (cap > 0 && !rows)) { set_error("null argument"); return KFBI_EINVAL; }
+    int r = 0;
+    for (const auto &C : b->classes)
+        for (int kind = 0; kind < 3; ++kind, ++r) {
+            if (r >= cap) continue;
+            int32_t *o = rows + 5 * r;
+            o[0] = C.M;
+            o[1] = kind;
+            o[2] = C.shape[kind].mb;
+            o[3] = C.shape[kind].stage ? 1 : 0;
+            o[4] = C.tuned[kind] ? 1 : 0;
+            if (us) us[r] = C.tuned[kind] ? C.us[kind] : -1.0;
+        }
+    *n_rows = r;
+    return KFBI_OK;
+}
+
 int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
                     const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
                     const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
@@ -1737,6 +1859,10 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
             memset(d->mirror_host, 0, sizeof(GmMirror));
             KFBI_HIP(hipHostGetDevicePointer(&d->mirror_dev, d->mirror_host, 0));
         }
+    }
+    if (!(o.flags & KFBI_BATCH_NO_TUNE)) {
+        KFBI_TRY(batch_tune(b, false));
+        if (mixed) KFBI_TRY(batch_tune(b, true));
     }
     // argument blocks
     int nvl_min = 1 << 30;
@@ -1804,9 +1930,10 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     };
     auto launch_tri = [&](int use, bool low, bool dense) -> int {
         for (auto &C : b->classes) {
-            const BatchTriShape &S = low ? C.sparse32 : (dense ? C.dense : C.sparse64);
-            KFBI_TRY(batch_launch(low ? kBaTri32 : kBaTri64, dargs(use), b->d_map + (low ? C.map32 : C.map64),
-                                  low ? C.blocks32 : C.blocks64, C.M, &S, s));
+            const BatchTriShape &S = C.shape[low ? 2 : (dense ? 1 : 0)];
+            const int lm = mb_log2(S.mb);
+            KFBI_TRY(batch_launch(low ? kBaTri32 : kBaTri64, dargs(use), b->d_map + C.map_mb[lm], C.blocks_mb[lm],
+                                  C.M, &S, s));
         }
         return KFBI_OK;
     };

@@ -784,10 +784,10 @@ struct TriShape {
 };
 
 template <class T>
-TriShape tri_shape(const kfbi_domain *d, bool sparse) {
+TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0) {
     TriShape S;
     const int n = d->M - 1;
-    int mb = d->tri_mb;
+    int mb = mb_force > 0 ? mb_force : d->tri_mb;
     if (mb <= 0) {
         mb = 4;
         while (mb > 1 && (size_t)n * mb * sizeof(T) > 32768) mb >>= 1;
@@ -1200,9 +1200,9 @@ int batch_blocks(const kfbi_domain *d, int kind) {
 
 // launch shape of the tridiagonal kernel shared by a batch class (equal M,
 // mb and c; LDS the largest over the members; staged when all fit)
-int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out) {
+int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb, int stage_pref) {
     for (int q = 0; q < n; ++q) {
-        const TriShape S = low ? tri_shape<float>(doms[q], sparse) : tri_shape<double>(doms[q], sparse);
+        const TriShape S = low ? tri_shape<float>(doms[q], sparse, mb) : tri_shape<double>(doms[q], sparse, mb);
         if (q == 0) {
             out->mb = S.mb;
             out->c = S.c;
@@ -1221,9 +1221,18 @@ int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, Batc
         set_error("grid too large for the tridiagonal kernel");
         return KFBI_ENOTSUP;
     }
-    out->stage = sparse && out->stage_lds <= kTriLdsMax;
+    out->stage = sparse && out->stage_lds <= kTriLdsMax && stage_pref != 0;
+    if (stage_pref == 1 && !out->stage) {
+        set_error("staged sparse input does not fit");
+        return KFBI_ENOTSUP;
+    }
     if (out->stage) out->lds = out->stage_lds;
+    out->blocks_per = 0;
     return KFBI_OK;
+}
+
+int batch_tri_blocks(const kfbi_domain *d, int mb) {
+    return (d->M - 1 + mb - 1) / mb;
 }
 
 int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,

@@ -515,11 +515,16 @@ struct BatchTriShape {
     int mb, c;
     bool stage;
     size_t lds, stage_lds;
+    int blocks_per;
 };
 
 size_t batch_args_size(int kind);
 int batch_blocks(const kfbi_domain *d, int kind);
-int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out);
+// mb: modes per workgroup (0: each domain's default); stage_pref: -1 stage
+// the sparse input when it fits, 0 never, 1 always (error if it does not fit)
+int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb = 0,
+                    int stage_pref = -1);
+int batch_tri_blocks(const kfbi_domain *d, int mb);
 int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
                  hipStream_t s);
 void batch_fill_dst(kfbi_domain *d, const void *in, bool in_grid, bool mask_inside, void *out, bool out_grid,
@@ -545,6 +550,7 @@ int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks
 // batched Helmholtz solves (gmres.hip)
 int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out);
 void batch_destroy(kfbi_batch *b);
+int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows);
 int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
                     const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
                     const kfbi_solve_opts *opts, kfbi_solve_stats *stats);

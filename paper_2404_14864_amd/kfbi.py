@@ -20,6 +20,7 @@ CURVES = {"disk": 0, "ellipse": 1, "star": 2}
 KFBI_REAL, KFBI_COMPLEX = 0, 1
 KFBI_PREC_FP64, KFBI_PREC_MIXED = 0, 1
 KFBI_SOLVE_ASYNC = 1
+KFBI_BATCH_NO_TUNE = 2
 KFBI_HEAT, KFBI_WAVE, KFBI_SCHRODINGER = 0, 1, 2
 
 
@@ -116,6 +117,8 @@ def lib():
         "kfbi_batch_helmholtz": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                   ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_batch_tuning": ([_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "kfbi_profile_replay": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -133,7 +136,7 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_stepper_destroy", "kfbi_stepper_init", "kfbi_step_heat", "kfbi_step_wave",
             "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read", "kfbi_profile_replay",
             "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state",
-            "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz")
+            "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz", "kfbi_batch_tuning")
 
 
 def kfbi_profile_enable(h, on=True):
@@ -183,6 +186,25 @@ def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, p
     return [stats[q].as_dict() for q in range(n)]
 
 
+TUNING_KINDS = ("sparse64", "dense64", "sparse32")
+
+
+def kfbi_batch_tuning(b):
+    """Tridiagonal launch shape per class of equal M and solve kind:
+    dicts {M, kind, modes_per_wg, staged, tuned, us}."""
+    n = ctypes.c_int32(0)
+    _check(lib().kfbi_batch_tuning(b, 0, None, None, ctypes.byref(n)))
+    rows = (ctypes.c_int32 * (5 * max(n.value, 1)))()
+    us = (ctypes.c_double * max(n.value, 1))()
+    _check(lib().kfbi_batch_tuning(b, n.value, rows, us, ctypes.byref(n)))
+    out = []
+    for r in range(n.value):
+        M, kind, mb, st, tuned = rows[5 * r:5 * r + 5]
+        out.append({"M": M, "kind": TUNING_KINDS[kind], "modes_per_wg": mb, "staged": bool(st),
+                    "tuned": bool(tuned), "us": us[r] if tuned else None})
+    return out
+
+
 def kfbi_profile_replay(h, kind, reps):
     """Average launch duration (ms) of `reps` back-to-back launches of one
     grid-solve kernel ("tridiag_sparse", "tridiag_dense" or "eval_nodes") and
@@ -219,7 +241,8 @@ def _opts(opts):
     o = SolveOpts(tol=opts.get("tol", 0.0), max_iter=opts.get("max_iter", 0),
                   restart=opts.get("restart", 0), fixed_iters=opts.get("fixed_iters", 0),
                   precision=opts.get("precision", -1),
-                  flags=KFBI_SOLVE_ASYNC if opts.get("async", False) else 0)
+                  flags=(KFBI_SOLVE_ASYNC if opts.get("async", False) else 0)
+                  | (KFBI_BATCH_NO_TUNE if opts.get("no_tune", False) else 0))
     return ctypes.byref(o)
 
 

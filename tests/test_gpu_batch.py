@@ -125,3 +125,39 @@ def test_batch_mixed_precision_and_warm_start():
     finally:
         for m in ms:
             m.close()
+
+
+def test_batch_tuning_keeps_values_bitwise():
+    ms = _members(6, (64, 128, 256))
+    try:
+        args = ([m.kappa for m in ms], [m.f_grid for m in ms], [m.f_gamma for m in ms], [m.g_gamma for m in ms])
+        outs = {}
+        for tune in (False, True):
+            b = kfbi.kfbi_batch_create([m.h for m in ms])
+            rows0 = kfbi.kfbi_batch_tuning(b)
+            assert not any(r["tuned"] for r in rows0)
+            for prec in (kfbi.KFBI_PREC_FP64, kfbi.KFBI_PREC_MIXED):
+                us = [empty_grid(m.M) for m in ms]
+                phis = [empty_gamma(m.Nb) for m in ms]
+                st = kfbi.kfbi_batch_helmholtz(b, *args, us, phis,
+                                               opts={"tol": 1e-10, "precision": prec, "no_tune": not tune})
+                outs[tune, prec] = ([host(u) for u in us], [host(p) for p in phis], [s["iters"] for s in st])
+            rows = kfbi.kfbi_batch_tuning(b)
+            kfbi.kfbi_batch_destroy(b)
+            grids = sorted({m.M for m in ms})
+            assert sorted({r["M"] for r in rows}) == grids
+            assert len(rows) == 3 * len(grids)
+            for r in rows:
+                assert r["tuned"] == tune, r
+                assert r["modes_per_wg"] in (1, 2, 4), r
+                if tune:
+                    assert r["us"] > 0, r
+        for prec in (kfbi.KFBI_PREC_FP64, kfbi.KFBI_PREC_MIXED):
+            a, t = outs[False, prec], outs[True, prec]
+            assert a[2] == t[2]
+            for q in range(len(ms)):
+                assert np.array_equal(a[0][q], t[0][q]), (prec, q)
+                assert np.array_equal(a[1][q], t[1][q]), (prec, q)
+    finally:
+        for m in ms:
+            m.close()
