@@ -525,28 +525,38 @@ int build_domain(kfbi_domain *d) {
             const int t = node / (M + 1) - 1, i = node % (M + 1);
             per_row[t].push_back({6 * k + p, i});
         }
-    std::vector<int32_t> erow_t, erow_ptr, erow_ent, erow_col;
+    std::vector<int32_t> erow_t, erow_ptr, erow_col, erow_nid((size_t)6 * Nb, -1);
     for (int t = 0; t < d->n; ++t) {
         if (per_row[t].empty()) continue;
+        auto &pr = per_row[t];
+        std::stable_sort(pr.begin(), pr.end(),
+                         [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &b) {
+                             return a.second < b.second;
+                         });
         erow_t.push_back(t);
-        erow_ptr.push_back((int32_t)erow_ent.size());
-        for (auto &e : per_row[t]) {
-            erow_ent.push_back(e.first);
-            erow_col.push_back(e.second);
+        erow_ptr.push_back((int32_t)erow_col.size());
+        for (size_t q = 0; q < pr.size(); ++q) {
+            if (q == 0 || pr[q].second != pr[q - 1].second) erow_col.push_back(pr[q].second);
+            erow_nid[pr[q].first] = (int32_t)erow_col.size() - 1;
         }
     }
-    erow_ptr.push_back((int32_t)erow_ent.size());
+    erow_ptr.push_back((int32_t)erow_col.size());
     d->n_erows = (int)erow_t.size();
+    d->n_enodes = (int)erow_col.size();
+    for (size_t r = 0; r < erow_t.size(); r += kErowRows) {
+        const size_t r1 = std::min(erow_t.size(), r + kErowRows);
+        d->erow_blk_max = std::max(d->erow_blk_max, erow_ptr[r1] - erow_ptr[r]);
+    }
     d->erow_lo = erow_t.front();
     d->erow_hi = erow_t.back();
     KFBI_TRY(dalloc(d, (void **)&d->erow_t, erow_t.size() * sizeof(int32_t)));
     KFBI_TRY(dalloc(d, (void **)&d->erow_ptr, erow_ptr.size() * sizeof(int32_t)));
-    KFBI_TRY(dalloc(d, (void **)&d->erow_ent, erow_ent.size() * sizeof(int32_t)));
     KFBI_TRY(dalloc(d, (void **)&d->erow_col, erow_col.size() * sizeof(int32_t)));
+    KFBI_TRY(dalloc(d, (void **)&d->erow_nid, erow_nid.size() * sizeof(int32_t)));
+    KFBI_HIP(hipMemcpyAsync(d->erow_nid, erow_nid.data(), erow_nid.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                            s));
     KFBI_HIP(hipMemcpyAsync(d->erow_t, erow_t.data(), erow_t.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KFBI_HIP(hipMemcpyAsync(d->erow_ptr, erow_ptr.data(), erow_ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                            s));
-    KFBI_HIP(hipMemcpyAsync(d->erow_ent, erow_ent.data(), erow_ent.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                             s));
     KFBI_HIP(hipMemcpyAsync(d->erow_col, erow_col.data(), erow_col.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                             s));

@@ -1555,6 +1555,7 @@ struct BatchClass {
     int M;
     std::vector<int> members;
     int map_mb[4], blocks_mb[4];
+    int map_erow, blocks_erow;
     BatchTriShape shape[3];
     bool tuned[3];
     double us[3];
@@ -1611,13 +1612,18 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
             set_error("batch members need Nb <= 8192");
             return KFBI_ENOTSUP;
         }
+        if (d->erow_blk_max > kErowCols) {
+            batch_destroy(b);
+            set_error("batch member with too many stencil nodes on consecutive rows");
+            return KFBI_ENOTSUP;
+        }
         b->doms.push_back(d);
         b->nb_max = std::max(b->nb_max, d->Nb);
     }
     // workgroup maps: per kind over all members (the tridiagonal kinds per
     // class of equal M, in XCD tile order inside the kernel)
     std::vector<BlkMap> map;
-    const int kinds[] = {kBaDst, kBaZero, kBaErow64, kBaExm, kBaCorrPhi, kBaCorr, kBaExt, kBaCopy};
+    const int kinds[] = {kBaDst, kBaZero, kBaExm, kBaCorrPhi, kBaCorr, kBaExt, kBaCopy};
     for (int kind : kinds) {
         b->map_off[kind] = (int)map.size();
         for (int q = 0; q < n; ++q) {
@@ -1652,6 +1658,10 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
                 for (int l = 0; l < batch_tri_blocks(doms[q], 1 << lm); ++l) map.push_back(BlkMap{q, l});
             C.blocks_mb[lm] = (int)map.size() - C.map_mb[lm];
         }
+        C.map_erow = (int)map.size();
+        for (int q : C.members)
+            for (int l = 0; l < batch_blocks(doms[q], kBaErow64); ++l) map.push_back(BlkMap{q, l});
+        C.blocks_erow = (int)map.size() - C.map_erow;
         b->classes.push_back(C);
     }
     // argument arrays
@@ -1924,9 +1934,12 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     auto launch_dst = [&](int use) -> int {
         return batch_launch(kBaDst, dargs(use), mapk(kBaDst), b->map_blocks[kBaDst], m_max, nullptr, s);
     };
+    // stencil evaluation per class of equal M (register rows sized to M)
     auto launch_erow = [&](int use, bool low) -> int {
-        return batch_launch(low ? kBaErow32 : kBaErow64, dargs(use), mapk(kBaErow64), b->map_blocks[kBaErow64],
-                            m_max, nullptr, s);
+        for (auto &C : b->classes)
+            KFBI_TRY(batch_launch(low ? kBaErow32 : kBaErow64, dargs(use), b->d_map + C.map_erow, C.blocks_erow, C.M,
+                                  nullptr, s));
+        return KFBI_OK;
     };
     auto launch_tri = [&](int use, bool low, bool dense) -> int {
         for (auto &C : b->classes) {

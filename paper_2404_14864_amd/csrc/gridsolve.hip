@@ -264,15 +264,21 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     typedef typename Real<T>::type R;
     const int M = A.M;
     const double h2 = A.h2;
-    const T *__restrict__ rhat = A.rhat;
-    const TC *__restrict__ corr = A.corr;
+    const gmem<T> *__restrict__ rhat = gview(A.rhat);
+    const gmem<TC> *__restrict__ corr = gview(A.corr);
     const TriSparse &sp = A.sp;
-    const R *__restrict__ sine = A.sine;
-    const T *__restrict__ etab = A.etab;
-    const T *__restrict__ elim = A.elim;
-    const int32_t *__restrict__ tconv = A.tconv;
-    T *__restrict__ uhat = A.uhat;
-    const int *__restrict__ done = A.done;
+    const gmem<int32_t> *__restrict__ irr_col = gview(sp.irr_col);
+    const gmem<int32_t> *__restrict__ row_ptr = gview(sp.row_ptr);
+    const gmem<int32_t> *__restrict__ row_order = gview(sp.row_order);
+    const gmem<int32_t> *__restrict__ seg_q0 = gview(sp.seg_q0);
+    const gmem<int32_t> *__restrict__ seg_row = gview(sp.seg_row);
+    const gmem<int32_t> *__restrict__ row_seg = gview(sp.row_seg);
+    const gmem<R> *__restrict__ sine = gview(A.sine);
+    const gmem<T> *__restrict__ etab = gview(A.etab);
+    const gmem<T> *__restrict__ elim = gview(A.elim);
+    const gmem<int32_t> *__restrict__ tconv = gview(A.tconv);
+    gmem<T> *__restrict__ uhat = gview(A.uhat);
+    const gmem<int> *__restrict__ done = gview(A.done);
     extern __shared__ double lds[];
     constexpr int NT = MB * LANES;
     const int n = M - 1;
@@ -302,7 +308,7 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     T lim = zero<T>();
     if (k < n) {
         tc = tconv[k];
-        lim = elim[k];
+        lim = gld(elim + k);
     }
     // sine table and staging: loads batched so that several are in flight
     for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * NT) {
@@ -322,8 +328,8 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
             for (int u = 0; u < 4; ++u) {
                 const int q = q0 + u * NT;
                 if (q < nnz) {
-                    v[u] = corr[q];
-                    c[u] = sp.irr_col[q];
+                    v[u] = gld(corr + (q));
+                    c[u] = irr_col[q];
                 }
             }
 #pragma unroll
@@ -337,21 +343,21 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
         }
     }
     if (STAGE && sparse) {
-        for (int q = threadIdx.x; q <= n; q += NT) srp[q] = sp.row_ptr[q];
+        for (int q = threadIdx.x; q <= n; q += NT) srp[q] = row_ptr[q];
         for (int q = threadIdx.x; q < n_seg; q += NT) {
-            ssq0[q] = sp.seg_q0[q];
-            ssrow[q] = sp.seg_row[q];
+            ssq0[q] = seg_q0[q];
+            ssrow[q] = seg_row[q];
         }
         for (int q = threadIdx.x; q < n_act; q += NT) {
-            srow[q] = sp.row_order[q];
-            srseg[q] = sp.row_seg[q];
+            srow[q] = row_order[q];
+            srseg[q] = row_seg[q];
         }
-        if (threadIdx.x == 0) srseg[n_act] = sp.row_seg[n_act];
+        if (threadIdx.x == 0) srseg[n_act] = row_seg[n_act];
     }
     // dense part (or zero) of the right-hand side
     for (int p = threadIdx.x; p < n * MB; p += NT) {
         const int t = p / MB, mm = p - t * MB;
-        tile[tidx<MB, C>(t, mm)] = (rhat && k0 + mm < n) ? rhat[(size_t)t * n + k0 + mm] : zero<T>();
+        tile[tidx<MB, C>(t, mm)] = (rhat && k0 + mm < n) ? gld(rhat + (size_t)t * n + k0 + mm) : zero<T>();
     }
     __syncthreads();
     // Thomas coefficients of phase B: loads in flight during phase A
@@ -359,7 +365,7 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int t = t0 + c;
-        e[c] = (t < tc && t < n) ? etab[(size_t)t * n + k] : lim;
+        e[c] = (t < tc && t < n) ? gld(etab + (size_t)t * n + k) : lim;
     }
     // phase A: sparse sums.  Each thread sums one segment (at most kSegLen
     // irregular nodes of one row) for all MB modes; four nodes per step keep
@@ -368,9 +374,9 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     // the schedule.
     if (sparse) {
         for (int sg = threadIdx.x; sg < n_seg; sg += NT) {
-            const int t = STAGE ? ssrow[sg] : sp.seg_row[sg];
-            int q = STAGE ? ssq0[sg] : sp.seg_q0[sg];
-            const int rend = STAGE ? srp[t + 1] : sp.row_ptr[t + 1];
+            const int t = STAGE ? ssrow[sg] : seg_row[sg];
+            int q = STAGE ? ssq0[sg] : seg_q0[sg];
+            const int rend = STAGE ? srp[t + 1] : row_ptr[t + 1];
             const int q1 = q + kSegLen < rend ? q + kSegLen : rend;
             T acc[MB];
 #pragma unroll
@@ -380,8 +386,8 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
                 int col[4], idx[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    cv[u] = STAGE ? sval[q + u] : Conv<T>::from(corr[q + u]);
-                    col[u] = STAGE ? scol[q + u] : sp.irr_col[q + u];
+                    cv[u] = STAGE ? sval[q + u] : Conv<T>::from(gld(corr + (q + u)));
+                    col[u] = STAGE ? scol[q + u] : irr_col[q + u];
                     idx[u] = (col[u] * (k0 + 1)) & mask2M;
                 }
 #pragma unroll
@@ -394,8 +400,8 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
                 }
             }
             for (; q < q1; ++q) {
-                const T cv = STAGE ? sval[q] : Conv<T>::from(corr[q]);
-                const int col = STAGE ? scol[q] : sp.irr_col[q];
+                const T cv = STAGE ? sval[q] : Conv<T>::from(gld(corr + (q)));
+                const int col = STAGE ? scol[q] : irr_col[q];
                 int idx = (col * (k0 + 1)) & mask2M;
 #pragma unroll
                 for (int mm = 0; mm < MB; ++mm) {
@@ -408,9 +414,9 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
         }
         __syncthreads();
         for (int a = threadIdx.x; a < n_act; a += NT) {
-            const int t = STAGE ? srow[a] : sp.row_order[a];
-            const int s0 = STAGE ? srseg[a] : sp.row_seg[a];
-            const int s1 = STAGE ? srseg[a + 1] : sp.row_seg[a + 1];
+            const int t = STAGE ? srow[a] : row_order[a];
+            const int s0 = STAGE ? srseg[a] : row_seg[a];
+            const int s1 = STAGE ? srseg[a + 1] : row_seg[a + 1];
             T acc[MB];
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) acc[mm] = spart[s0 * MB + mm];
@@ -483,7 +489,7 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     // phase C
     for (int p = threadIdx.x; p < n * MB; p += NT) {
         const int t = p / MB, mm = p - t * MB;
-        if (k0 + mm < n) uhat[(size_t)t * n + k0 + mm] = tile[tidx<MB, C>(t, mm)];
+        if (k0 + mm < n) gst(uhat + (size_t)t * n + k0 + mm, tile[tidx<MB, C>(t, mm)]);
     }
 }
 
@@ -497,6 +503,41 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(TriArgs<T, TC> A) {
 // sin(pi i k / M).  nodes: linear grid indices (interior nodes only).
 // ---------------------------------------------------------------------------
 // T: precision of U^ and of the sum; the result is stored in FP64 (TO)
+// Sum over modes of one row against the sine of one column i:
+// sum_k row[k] sin(pi i (k+1) / M), lanes taking k = lane + 64 j in turn
+// (the order of every stencil evaluation, so all of them agree bit for
+// bit).  The table S holds sin(pi q / M), q < 2M (M a power of two).  The
+// sine of the lane's angle a_j = a + b_j, a = (lane+1) i and b_j = 64 j i,
+// is sin a cos b_j + cos a sin b_j: two lane-dependent table reads per
+// column and two uniform ones per step instead of a scattered read per
+// mode (cos x read as sin(x + pi/2)).  get(j) returns row[lane + 64 j];
+// KR > 0 unrolls KR steps (values held in registers), KR = 0 loops.
+template <int KR, class T, class SP, class G>
+__device__ __forceinline__ T mode_sum(SP S, int M, int n, int i, int lane, const G &get) {
+    typedef typename Real<T>::type R;
+    const int mask2M = 2 * M - 1, quarter = M >> 1;
+    const int ia = (i * (lane + 1)) & mask2M;
+    const R sa = S[ia], ca = S[(ia + quarter) & mask2M];
+    T acc = zero<T>();
+    if constexpr (KR > 0) {
+        // get(j) is zero past the last mode, so every step adds exactly what
+        // the guarded loop adds
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+            const int ib = (64 * i * j) & mask2M;
+            const R sv = fma(ca, (R)S[ib], sa * (R)S[(ib + quarter) & mask2M]);
+            acc += get(j) * sv;
+        }
+    } else {
+        for (int j = 0; 64 * j < n; ++j) {
+            const int ib = (64 * i * j) & mask2M;
+            const R sv = fma(ca, (R)S[ib], sa * (R)S[(ib + quarter) & mask2M]);
+            if (lane + 64 * j < n) acc += get(j) * sv;
+        }
+    }
+    return acc;
+}
+
 template <class T, class TO>
 __device__ void eval_nodes_body(const EvalArgs<T, TO> &A, int blk) {
     typedef typename Real<T>::type R;
@@ -509,14 +550,13 @@ __device__ void eval_nodes_body(const EvalArgs<T, TO> &A, int blk) {
     const int lane = threadIdx.x & 63;
     const int p = blk * 4 + (threadIdx.x >> 6);
     if (p >= nnodes) return;
-    const int n = M - 1, mask2M = 2 * M - 1;
+    const int n = M - 1;
     // nodes of a stencil record are 6 consecutive int32 followed by the rest of
     // the record; node_stride is the record size in int32 units
     int node = nodes[(size_t)(p / 6) * node_stride + (p % 6)];
     int i = node % (M + 1), j = node / (M + 1);
     const T *row = uhat + (size_t)(j - 1) * n;
-    T acc = zero<T>();
-    for (int k = lane; k < n; k += 64) acc += row[k] * sine[(i * (k + 1)) & mask2M];
+    T acc = mode_sum<0, T>(gview(sine), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
     if (lane == 0) out[p] = to_high(acc * (R)(2.0 / M));
@@ -576,12 +616,11 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     if (A.done && *A.done) return;
     const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
     const int k = blk;
-    const int n = M - 1, mask2M = 2 * M - 1;
+    const int n = M - 1;
     const int node = nodes[(size_t)k * node_stride + p];
     const int i = node % (M + 1);
     const T *row = uhat + (size_t)(node / (M + 1) - 1) * n;
-    T acc = zero<T>();
-    for (int kk = lane; kk < n; kk += 64) acc += row[kk] * sine[(i * (kk + 1)) & mask2M];
+    T acc = mode_sum<0, T>(gview(sine), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
     if (lane == 0) su[p] = to_high(acc * (R)(2.0 / M));
@@ -605,58 +644,109 @@ __global__ __launch_bounds__(384) void k_eval_extract(EvxArgs<T, TO> A) {
     eval_extract_body(A, blockIdx.x);
 }
 
-// Grid values at the stencil nodes by rows: one workgroup per interior row
-// holding stencil nodes stages that row of U^ and the sine table in LDS
-// once, then one wavefront per node of the row forms U = (2/M) sum_k
-// U^[t][k] sin(pi i k / M) (same sum and reduction order as k_eval_nodes).
-// Reads each needed row once instead of once per node.
-template <class T, class TO>
+// Grid values at the stencil nodes by rows: U = (2/M) sum_k U^[t][k]
+// sin(pi i k / M) at each distinct stencil node (t, i), in the same sum and
+// reduction order as k_eval_nodes.  Each wavefront takes kErowRows/4 rows
+// in turn: it holds the row's n modes in registers (mode k = lane + 64 j in
+// slot j, KR >= n/64 slots), forms the sum for each node of the row, and
+// writes it to every stencil entry of that node.  Each needed row is read
+// once and the sine table is staged once per workgroup.
+template <class T, class TO, int KR>
 __device__ void eval_rows_body(const ErowArgs<T, TO> &A, int blk) {
     typedef typename Real<T>::type R;
-    if (A.done && *A.done) return;
+    constexpr int RW = kErowRows / 4;  // rows per wavefront
+    if (A.done && *gview(A.done)) return;
     extern __shared__ double lds[];
-    const int M = A.M, n = M - 1, mask2M = 2 * M - 1;
+    const int M = A.M, n = M - 1, n_rows = A.n_rows;
+    const gmem<int32_t> *__restrict__ erow_t = gview(A.erow_t);
+    const gmem<int32_t> *__restrict__ erow_ptr = gview(A.erow_ptr);
+    const gmem<int32_t> *__restrict__ erow_col = gview(A.erow_col);
+    const gmem<T> *__restrict__ uhat = gview(A.uhat);
+    const gmem<R> *__restrict__ sine = gview(A.sine);
+    gmem<TO> *__restrict__ ust = gview(A.ust);
     R *S = reinterpret_cast<R *>(lds);
-    T *row = reinterpret_cast<T *>(S + 2 * M);
-    const int t = A.erow_t[blk];
-    const T *src = A.uhat + (size_t)t * n;
-    for (int q = threadIdx.x; q < 2 * M; q += blockDim.x) S[q] = A.sine[q];
-    for (int q = threadIdx.x; q < n; q += blockDim.x) row[q] = src[q];
-    __syncthreads();
-    const int e0 = A.erow_ptr[blk], e1 = A.erow_ptr[blk + 1];
-    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int e = e0 + (int)(threadIdx.x >> 6); e < e1; e += nw) {
-        const int i = A.erow_col[e];
-        T acc = zero<T>();
-        for (int k = lane; k < n; k += 64) acc += row[k] * S[(i * (k + 1)) & mask2M];
+    int32_t *scol = reinterpret_cast<int32_t *>(S + 2 * M);  // kErowCols node columns
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = blk * kErowRows + w;  // the wavefront's rows: r0 + 4 q, q < RW
+    // Every global load below is issued unconditionally at a clamped,
+    // in-bounds index and masked afterwards, and the sums read only LDS:
+    // loads under a branch, or loads between the row prefetch and its use,
+    // make the compiler wait for all outstanding loads (the counter is in
+    // order), which would serialise the prefetch.  Row indices and node
+    // ranges of the wavefront's rows, one per lane (n_rows >= 1):
+    const int rl = min(r0 + 4 * min(lane, RW - 1), n_rows - 1);
+    const int t_l = erow_t[rl], p0_l = erow_ptr[rl], p1_l = erow_ptr[rl + 1];
+    // the workgroup's nodes are the contiguous range [P0, P1)
+    const int P0 = erow_ptr[min(blk * kErowRows, n_rows - 1)];
+    const int P1 = erow_ptr[min((blk + 1) * kErowRows, n_rows)];
+    auto load_row = [&](int q, T (&dst)[KR]) {
+        const gmem<T> *src = uhat + (size_t)__shfl(t_l, q) * n;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
-        if (lane == 0) A.ust[A.erow_ent[e]] = to_high(acc * (R)(2.0 / M));
+        for (int j = 0; j < KR; ++j) {
+            const int k = lane + 64 * j;
+            const T x = gld(src + min(k, n - 1));
+            dst[j] = k < n ? x : zero<T>();
+        }
+    };
+    T v[KR], vn[KR];
+    load_row(0, v);
+    // sine table and node columns, loads batched so that several are in flight
+    for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * 256) {
+        R s4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s4[u] = sine[min(q0 + u * 256, 2 * M - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u * 256 < 2 * M) S[q0 + u * 256] = s4[u];
     }
-}
-
-template <class T, class TO>
-__global__ __launch_bounds__(256) void k_eval_rows(ErowArgs<T, TO> A) {
-    eval_rows_body(A, blockIdx.x);
+    for (int q = threadIdx.x; q < P1 - P0; q += 256) scol[q] = erow_col[P0 + q];
+    __syncthreads();
+    const R scale = (R)(2.0 / M);
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        if (r0 + 4 * q >= n_rows) break;
+        // next row's modes load during this row's sums (the last row reloads
+        // a clamped row, unused)
+        const bool more = q + 1 < RW && r0 + 4 * (q + 1) < n_rows;
+        if (q + 1 < RW) load_row(q + 1, vn);
+        const int p0 = __shfl(p0_l, q), p1 = __shfl(p1_l, q);
+        for (int c = p0; c < p1; ++c) {
+            const int i = scol[c - P0];
+            T acc = mode_sum<KR, T>(S, M, n, i, lane, [&](int jj) { return v[jj]; });
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+            // every lane holds the sum: all write the same value
+            gst(ust + c, to_high(acc * scale));
+        }
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < KR; ++j) v[j] = vn[j];
+        }
+    }
 }
 
 // K phi at collocation point k from its six stencil values: the extraction
 // sum_p w6[k][p] U_p + sum_o bop[k][o] phi[k-2+o] (as in k_eval_extract)
 template <class T>
 __device__ void extract_merged_body(const ExmArgs<T> &A, int blk) {
-    if (A.done && *A.done) return;
+    if (A.done && *gview(A.done)) return;
     const int k = blk * blockDim.x + threadIdx.x, Nb = A.Nb;
     if (k >= Nb) return;
+    const gmem<T> *__restrict__ ust = gview(A.ust);
+    const gmem<int32_t> *__restrict__ nid = gview(A.nid);
+    const gmem<double> *__restrict__ w6 = gview(A.w6);
+    const gmem<T> *__restrict__ bop = gview(A.bop);
+    const gmem<T> *__restrict__ phi = gview(A.phi);
     T r = zero<T>();
 #pragma unroll
-    for (int q = 0; q < 6; ++q) r += A.ust[6 * k + q] * A.w6[6 * k + q];
+    for (int q = 0; q < 6; ++q) r += gld(ust + nid[6 * k + q]) * w6[6 * k + q];
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
         int idx = k - 2 + o;
         idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
-        r += A.bop[5 * k + o] * A.phi[idx];
+        r += gld(bop + 5 * k + o) * gld(phi + idx);
     }
-    A.kv[k] = r;
+    gst(gview(A.kv) + k, r);
 }
 
 template <class T>
@@ -738,9 +828,9 @@ ErowArgs<T, TO> erow_args(kfbi_domain *d, const void *uhat, void *ust, const int
     const bool low = sizeof(T) < sizeof(TO);
     ErowArgs<T, TO> A;
     A.M = d->M;
+    A.n_rows = d->n_erows;
     A.erow_t = d->erow_t;
     A.erow_ptr = d->erow_ptr;
-    A.erow_ent = d->erow_ent;
     A.erow_col = d->erow_col;
     A.uhat = (const T *)uhat;
     A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
@@ -750,12 +840,29 @@ ErowArgs<T, TO> erow_args(kfbi_domain *d, const void *uhat, void *ust, const int
 }
 template <class T, class TO>
 size_t erow_lds(int M) {
-    return (size_t)2 * M * sizeof(typename Real<T>::type) + (size_t)(M - 1) * sizeof(T);
+    return (size_t)2 * M * sizeof(typename Real<T>::type) + (size_t)kErowCols * sizeof(int32_t);
+}
+inline int erow_blocks(const kfbi_domain *d) { return (d->n_erows + kErowRows - 1) / kErowRows; }
+
+// register slots per lane for rows of up to M - 1 modes
+template <class F>
+int erow_dispatch(int M, const F &f) {
+    const int n = M - 1;
+    if (n <= 128) f.template go<2>();
+    else if (n <= 256) f.template go<4>();
+    else if (n <= 512) f.template go<8>();
+    else if (n <= 1024) f.template go<16>();
+    else if (n <= 2048) f.template go<32>();
+    else {
+        set_error("grid too large for the row-wise stencil evaluation");
+        return KFBI_ENOTSUP;
+    }
+    return KFBI_OK;
 }
 
 template <class T>
 ExmArgs<T> exm_args(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done) {
-    return ExmArgs<T>{d->Nb, (const T *)ust, d->w6, (const T *)d->bop, (const T *)phi, (T *)kv, done};
+    return ExmArgs<T>{d->Nb, (const T *)ust, d->erow_nid, d->w6, (const T *)d->bop, (const T *)phi, (T *)kv, done};
 }
 
 template <class T, class TO>
@@ -1119,10 +1226,25 @@ __global__ __launch_bounds__(64) void kb_corr_phi(const CorrPhiArgs<TC> *__restr
     corr_phi_body(A[e.inst], e.local);
 }
 template <class T, class TO>
+struct ErowLaunchBatch {
+    const ErowArgs<T, TO> *A;
+    const BlkMap *map;
+    int blocks;
+    size_t lds;
+    hipStream_t s;
+    template <int KR>
+    void go() const;
+};
+template <class T, class TO, int KR>
 __global__ __launch_bounds__(256) void kb_eval_rows(const ErowArgs<T, TO> *__restrict__ A,
                                                     const BlkMap *__restrict__ map) {
     const BlkMap e = map[blockIdx.x];
-    eval_rows_body(A[e.inst], e.local);
+    eval_rows_body<T, TO, KR>(A[e.inst], e.local);
+}
+template <class T, class TO>
+template <int KR>
+void ErowLaunchBatch<T, TO>::go() const {
+    kb_eval_rows<T, TO, KR><<<blocks, 256, lds, s>>>(A, map);
 }
 __global__ __launch_bounds__(256) void kb_extract_merged(const ExmArgs<double> *__restrict__ A,
                                                          const BlkMap *__restrict__ map) {
@@ -1192,7 +1314,7 @@ int batch_blocks(const kfbi_domain *d, int kind) {
         case kBaEvx32: return d->Nb;
         case kBaCorrPhi: return (d->n_irr + 63) / 64;
         case kBaErow64:
-        case kBaErow32: return d->n_erows;
+        case kBaErow32: return erow_blocks(d);
         case kBaExm: return (d->Nb + 255) / 256;
         default: return 0;
     }
@@ -1267,14 +1389,18 @@ int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int 
         case kBaCorrPhi:
             kb_corr_phi<double><<<blocks, 64, 0, s>>>((const CorrPhiArgs<double> *)args, map);
             break;
-        case kBaErow64:
-            kb_eval_rows<double, double><<<blocks, 256, erow_lds<double, double>(M), s>>>(
-                (const ErowArgs<double, double> *)args, map);
+        case kBaErow64: {
+            ErowLaunchBatch<double, double> L{(const ErowArgs<double, double> *)args, map, blocks,
+                                              erow_lds<double, double>(M), s};
+            KFBI_TRY(erow_dispatch(M, L));
             break;
-        case kBaErow32:
-            kb_eval_rows<float, double><<<blocks, 256, erow_lds<float, double>(M), s>>>(
-                (const ErowArgs<float, double> *)args, map);
+        }
+        case kBaErow32: {
+            ErowLaunchBatch<float, double> L{(const ErowArgs<float, double> *)args, map, blocks,
+                                             erow_lds<float, double>(M), s};
+            KFBI_TRY(erow_dispatch(M, L));
             break;
+        }
         case kBaExm:
             kb_extract_merged<<<blocks, 256, 0, s>>>((const ExmArgs<double> *)args, map);
             break;

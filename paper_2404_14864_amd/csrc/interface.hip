@@ -125,6 +125,7 @@ __device__ void extract_body(const ExtArgs<T> &A, int blk) {
     const Stencil *__restrict__ st = A.st;
     const T kappa = A.kappa;
     const T *__restrict__ ust = A.ust;
+    const int32_t *__restrict__ nid = A.nid;
     const T *phi_base = A.phi_base;
     const int *jptr = A.jptr;
     const T *__restrict__ fg = A.fg;
@@ -143,7 +144,7 @@ __device__ void extract_body(const ExtArgs<T> &A, int blk) {
     const Stencil &S = st[k];
     T up = zero<T>();
     for (int q = 0; q < 6; ++q) {
-        T val = ust[6 * k + q];
+        T val = ust[nid ? nid[6 * k + q] : 6 * k + q];
         if ((S.out_mask >> q) & 1) {
             const double xi = S.xi[q], eta = S.eta[q];
             val += J.u + J.ux * xi + J.uy * eta + J.uxx * (0.5 * xi * xi) + J.uxy * (xi * eta) +
@@ -317,6 +318,7 @@ ExtArgs<T> ext_args(kfbi_domain *d, double kre, double kim, const void *ust, con
     A.st = d->st;
     A.kappa = kappa_of<T>(kre, kim);
     A.ust = (const T *)ust;
+    A.nid = nullptr;
     A.phi_base = (const T *)phi_base;
     A.jptr = jptr;
     A.fg = (const T *)fg;
@@ -470,7 +472,9 @@ void batch_fill_corr(kfbi_domain *d, double kre, const void *phi, const void *fg
 
 void batch_fill_ext(kfbi_domain *d, double kre, const void *ust, const void *phi, const void *fg, const void *g,
                     double scale, void *out, const int *done, void *dst) {
-    *(ExtArgs<double> *)dst = ext_args<double>(d, kre, 0.0, ust, phi, nullptr, fg, g, scale, out, 0, done);
+    ExtArgs<double> A = ext_args<double>(d, kre, 0.0, ust, phi, nullptr, fg, g, scale, out, 0, done);
+    A.nid = d->erow_nid;  // batched stencil values come one per distinct node
+    *(ExtArgs<double> *)dst = A;
 }
 
 int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s) {

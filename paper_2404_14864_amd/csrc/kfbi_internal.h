@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -200,11 +201,13 @@ struct kfbi_domain {
     int32_t *seg_row = nullptr;
     int32_t *row_seg = nullptr;
     int n_seg = 0;
-    // the stencil nodes grouped by interior grid row (rows erow_t[r],
-    // entries erow_ptr[r] .. erow_ptr[r+1]: stencil-value index 6k+p and
-    // column); erow_lo .. erow_hi spans every such row
-    int32_t *erow_t = nullptr, *erow_ptr = nullptr, *erow_ent = nullptr, *erow_col = nullptr;
-    int n_erows = 0, erow_lo = 0, erow_hi = 0;
+    // the distinct stencil nodes grouped by interior grid row: rows
+    // erow_t[r] hold nodes erow_ptr[r] .. erow_ptr[r+1] (column erow_col[j]);
+    // stencil value 6k+p is the value of distinct node erow_nid[6k+p];
+    // erow_lo .. erow_hi spans every such row
+    int32_t *erow_t = nullptr, *erow_ptr = nullptr, *erow_col = nullptr, *erow_nid = nullptr;
+    int n_erows = 0, erow_lo = 0, erow_hi = 0, n_enodes = 0;
+    int erow_blk_max = 0;  // most nodes in kErowRows consecutive rows
     kfbi::Colloc *col = nullptr;        // Nb
     kfbi::Stencil *st = nullptr;        // Nb
     double *sine = nullptr;             // 2M: sin(pi m / M)
@@ -349,6 +352,35 @@ inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : si
 // block index; a single-instance launch passes the block by value, a batched
 // launch reads one per instance from device memory (see BlkMap).
 // ---------------------------------------------------------------------------
+// Global-memory view of a pointer held in an argument block.  Batched
+// kernels read their argument blocks from device memory, so the compiler
+// cannot tell those pointers from LDS ones and would access them with flat
+// instructions, whose completion also gates every later LDS wait.  Loads
+// and stores through these views are global ones.
+template <class T> using gmem = __attribute__((address_space(1))) T;
+template <class T> __device__ __forceinline__ const gmem<T> *gview(const T *p) { return (const gmem<T> *)p; }
+template <class T> __device__ __forceinline__ gmem<T> *gview(T *p) { return (gmem<T> *)p; }
+// element loads and stores through global views (complex elements move as
+// one two-lane vector)
+typedef double gdv2 __attribute__((ext_vector_type(2)));
+typedef float gfv2 __attribute__((ext_vector_type(2)));
+template <class T> __device__ __forceinline__ T gld(const gmem<T> *p) {
+    if constexpr (std::is_same<T, cd>::value) {
+        const gdv2 v = *(const gmem<gdv2> *)p;
+        return make_cd(v.x, v.y);
+    } else if constexpr (std::is_same<T, cf>::value) {
+        const gfv2 v = *(const gmem<gfv2> *)p;
+        return make_cf(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+template <class T> __device__ __forceinline__ void gst(gmem<T> *p, T v) {
+    if constexpr (std::is_same<T, cd>::value) *(gmem<gdv2> *)p = gdv2{v.x, v.y};
+    else if constexpr (std::is_same<T, cf>::value) *(gmem<gfv2> *)p = gfv2{v.x, v.y};
+    else *p = v;
+}
+
 // real scalar type of an element type (sine tables, scale factors)
 template <class T> struct Real { typedef double type; };
 template <> struct Real<float> { typedef float type; };
@@ -448,6 +480,8 @@ struct ExtArgs {
     const Stencil *st;
     T kappa;
     const T *ust;
+    const int32_t *nid;   // null: ust holds the 6 Nb stencil values in order;
+                          // else one value per distinct node, 6k+p -> nid[6k+p]
     const T *phi_base;
     const int *jptr;
     const T *fg;
@@ -456,11 +490,14 @@ struct ExtArgs {
     const int *done;
 };
 
-// stencil values by rows: one workgroup per row that holds stencil nodes
+// stencil values by rows: one wavefront per row that holds stencil nodes,
+// kErowRows rows per workgroup
+constexpr int kErowRows = 8;
+constexpr int kErowCols = 1024;  // node columns of a workgroup staged in LDS
 template <class T, class TO>
 struct ErowArgs {
-    int M;
-    const int32_t *erow_t, *erow_ptr, *erow_ent, *erow_col;
+    int M, n_rows;
+    const int32_t *erow_t, *erow_ptr, *erow_col;
     const T *uhat;
     const typename Real<T>::type *sine;
     TO *ust;
@@ -471,7 +508,8 @@ struct ErowArgs {
 template <class T>
 struct ExmArgs {
     int Nb;
-    const T *ust;
+    const T *ust;         // one value per distinct stencil node
+    const int32_t *nid;   // stencil value 6k+p -> distinct node
     const double *w6;
     const T *bop;
     const T *phi;
