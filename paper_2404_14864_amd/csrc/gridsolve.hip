@@ -512,26 +512,37 @@ __global__ __launch_bounds__(MB *LANES) void k_tridiag(TriArgs<T, TC> A) {
 // column and two uniform ones per step instead of a scattered read per
 // mode (cos x read as sin(x + pi/2)).  get(j) returns row[lane + 64 j];
 // KR > 0 unrolls KR steps (values held in registers), KR = 0 loops.
-template <int KR, class T, class SP, class G>
-__device__ __forceinline__ T mode_sum(SP S, int M, int n, int i, int lane, const G &get) {
-    typedef typename Real<T>::type R;
+template <int KR, class T, class SP, class R, class G>
+__device__ __forceinline__ T mode_sum(SP S, const cmem<R> *scu, int M, int n, int i, int lane, const G &get) {
     const int mask2M = 2 * M - 1, quarter = M >> 1;
     const int ia = (i * (lane + 1)) & mask2M;
-    const R sa = S[ia], ca = S[(ia + quarter) & mask2M];
+    R sa, ca;
+    if constexpr (KR > 0) {
+        // M = 64 KR, and S extends a quarter period past 2M
+        sa = S[ia];
+        ca = S[ia + 32 * KR];
+    } else {
+        sa = S[ia];
+        ca = S[(ia + quarter) & mask2M];
+    }
+    // the step angle 64 i j (mod 2M) is 64 m with m = i j mod max(1, M/32):
+    // its sine and cosine come from the step table, the same for every lane
+    // of the wavefront (i is uniform), so they load into scalar registers
+    const int mu = (KR > 0 ? 2 * KR : max(1, M >> 5)) - 1;
     T acc = zero<T>();
     if constexpr (KR > 0) {
         // get(j) is zero past the last mode, so every step adds exactly what
         // the guarded loop adds
 #pragma unroll
         for (int j = 0; j < KR; ++j) {
-            const int ib = (64 * i * j) & mask2M;
-            const R sv = fma(ca, (R)S[ib], sa * (R)S[(ib + quarter) & mask2M]);
+            const int m = (i * j) & mu;
+            const R sv = fma(ca, (R)scu[2 * m], sa * (R)scu[2 * m + 1]);
             acc += get(j) * sv;
         }
     } else {
         for (int j = 0; 64 * j < n; ++j) {
-            const int ib = (64 * i * j) & mask2M;
-            const R sv = fma(ca, (R)S[ib], sa * (R)S[(ib + quarter) & mask2M]);
+            const int m = (i * j) & mu;
+            const R sv = fma(ca, (R)scu[2 * m], sa * (R)scu[2 * m + 1]);
             if (lane + 64 * j < n) acc += get(j) * sv;
         }
     }
@@ -553,10 +564,11 @@ __device__ void eval_nodes_body(const EvalArgs<T, TO> &A, int blk) {
     const int n = M - 1;
     // nodes of a stencil record are 6 consecutive int32 followed by the rest of
     // the record; node_stride is the record size in int32 units
-    int node = nodes[(size_t)(p / 6) * node_stride + (p % 6)];
+    // one node per wavefront: uniform, kept in scalar registers
+    int node = __builtin_amdgcn_readfirstlane(nodes[(size_t)(p / 6) * node_stride + (p % 6)]);
     int i = node % (M + 1), j = node / (M + 1);
     const T *row = uhat + (size_t)(j - 1) * n;
-    T acc = mode_sum<0, T>(gview(sine), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
+    T acc = mode_sum<0, T>(gview(sine), cview(A.scu), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
     if (lane == 0) out[p] = to_high(acc * (R)(2.0 / M));
@@ -617,10 +629,10 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
     const int k = blk;
     const int n = M - 1;
-    const int node = nodes[(size_t)k * node_stride + p];
+    const int node = __builtin_amdgcn_readfirstlane(nodes[(size_t)k * node_stride + p]);
     const int i = node % (M + 1);
     const T *row = uhat + (size_t)(node / (M + 1) - 1) * n;
-    T acc = mode_sum<0, T>(gview(sine), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
+    T acc = mode_sum<0, T>(gview(sine), cview(A.scu), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
     if (lane == 0) su[p] = to_high(acc * (R)(2.0 / M));
@@ -657,15 +669,17 @@ __device__ void eval_rows_body(const ErowArgs<T, TO> &A, int blk) {
     constexpr int RW = kErowRows / 4;  // rows per wavefront
     if (A.done && *gview(A.done)) return;
     extern __shared__ double lds[];
-    const int M = A.M, n = M - 1, n_rows = A.n_rows;
+    constexpr int M = 64 * KR, n = M - 1;  // the launch is per class of equal M
+    const int n_rows = A.n_rows;
     const gmem<int32_t> *__restrict__ erow_t = gview(A.erow_t);
     const gmem<int32_t> *__restrict__ erow_ptr = gview(A.erow_ptr);
     const gmem<int32_t> *__restrict__ erow_col = gview(A.erow_col);
     const gmem<T> *__restrict__ uhat = gview(A.uhat);
     const gmem<R> *__restrict__ sine = gview(A.sine);
+    const cmem<R> *__restrict__ scu = cview(A.scu);
     gmem<TO> *__restrict__ ust = gview(A.ust);
     R *S = reinterpret_cast<R *>(lds);
-    int32_t *scol = reinterpret_cast<int32_t *>(S + 2 * M);  // kErowCols node columns
+    int32_t *scol = reinterpret_cast<int32_t *>(S + 2 * M + M / 2);  // kErowCols node columns
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = blk * kErowRows + w;  // the wavefront's rows: r0 + 4 q, q < RW
     // Every global load below is issued unconditionally at a clamped,
@@ -691,13 +705,15 @@ __device__ void eval_rows_body(const ErowArgs<T, TO> &A, int blk) {
     T v[KR], vn[KR];
     load_row(0, v);
     // sine table and node columns, loads batched so that several are in flight
-    for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * 256) {
+    // (the table repeats its first quarter period after 2M)
+    constexpr int SL = 2 * M + M / 2;
+    for (int q0 = threadIdx.x; q0 < SL; q0 += 4 * 256) {
         R s4[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s4[u] = sine[min(q0 + u * 256, 2 * M - 1)];
+        for (int u = 0; u < 4; ++u) s4[u] = sine[min(q0 + u * 256, SL - 1) & (2 * M - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (q0 + u * 256 < 2 * M) S[q0 + u * 256] = s4[u];
+            if (q0 + u * 256 < SL) S[q0 + u * 256] = s4[u];
     }
     for (int q = threadIdx.x; q < P1 - P0; q += 256) scol[q] = erow_col[P0 + q];
     __syncthreads();
@@ -711,8 +727,9 @@ __device__ void eval_rows_body(const ErowArgs<T, TO> &A, int blk) {
         if (q + 1 < RW) load_row(q + 1, vn);
         const int p0 = __shfl(p0_l, q), p1 = __shfl(p1_l, q);
         for (int c = p0; c < p1; ++c) {
-            const int i = scol[c - P0];
-            T acc = mode_sum<KR, T>(S, M, n, i, lane, [&](int jj) { return v[jj]; });
+            // uniform over the wavefront: scalar index arithmetic
+            const int i = __builtin_amdgcn_readfirstlane(scol[c - P0]);
+            T acc = mode_sum<KR, T>(S, scu, M, n, i, lane, [&](int jj) { return v[jj]; });
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
             // every lane holds the sum: all write the same value
@@ -814,6 +831,7 @@ EvxArgs<T, TO> evx_args(kfbi_domain *d, const void *uhat, const void *phi, void 
     A.nodes = reinterpret_cast<const int32_t *>(d->st);
     A.uhat = (const T *)uhat;
     A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.scu = low ? (const R *)d->scu32 : (const R *)d->scu;
     A.w6 = d->w6;
     A.bop = (const TO *)d->bop;
     A.phi = (const TO *)phi;
@@ -834,28 +852,30 @@ ErowArgs<T, TO> erow_args(kfbi_domain *d, const void *uhat, void *ust, const int
     A.erow_col = d->erow_col;
     A.uhat = (const T *)uhat;
     A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.scu = low ? (const R *)d->scu32 : (const R *)d->scu;
     A.ust = (TO *)ust;
     A.done = done;
     return A;
 }
 template <class T, class TO>
 size_t erow_lds(int M) {
-    return (size_t)2 * M * sizeof(typename Real<T>::type) + (size_t)kErowCols * sizeof(int32_t);
+    return (size_t)(2 * M + M / 2) * sizeof(typename Real<T>::type) + (size_t)kErowCols * sizeof(int32_t);
 }
 inline int erow_blocks(const kfbi_domain *d) { return (d->n_erows + kErowRows - 1) / kErowRows; }
 
-// register slots per lane for rows of up to M - 1 modes
+// register slots per lane, M / 64 (one instantiation per grid size)
 template <class F>
 int erow_dispatch(int M, const F &f) {
-    const int n = M - 1;
-    if (n <= 128) f.template go<2>();
-    else if (n <= 256) f.template go<4>();
-    else if (n <= 512) f.template go<8>();
-    else if (n <= 1024) f.template go<16>();
-    else if (n <= 2048) f.template go<32>();
-    else {
-        set_error("grid too large for the row-wise stencil evaluation");
-        return KFBI_ENOTSUP;
+    switch (M) {
+        case 64: f.template go<1>(); break;
+        case 128: f.template go<2>(); break;
+        case 256: f.template go<4>(); break;
+        case 512: f.template go<8>(); break;
+        case 1024: f.template go<16>(); break;
+        case 2048: f.template go<32>(); break;
+        default:
+            set_error("the row-wise stencil evaluation supports grids of 64 to 2048");
+            return KFBI_ENOTSUP;
     }
     return KFBI_OK;
 }
@@ -876,6 +896,7 @@ EvalArgs<T, TO> eval_args(kfbi_domain *d, const void *uhat, void *out, const int
     A.nodes = reinterpret_cast<const int32_t *>(d->st);
     A.uhat = (const T *)uhat;
     A.sine = low ? (const R *)d->sine32 : (const R *)d->sine;
+    A.scu = low ? (const R *)d->scu32 : (const R *)d->scu;
     A.out = (TO *)out;
     A.done = done;
     return A;
@@ -1047,9 +1068,14 @@ int ensure_coefficients(kfbi_domain *d, double kre, double kim) {
 }
 
 namespace {
-__global__ void k_sine32(int M, float *s) {
+__global__ void k_sine32(int M, float *s, float *scu) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m < 2 * M) s[m] = (float)sinpi((double)m / (double)M);
+    if (m < max(1, M / 32)) {
+        const int q = (64 * m) & (2 * M - 1), qc = (64 * m + M / 2) & (2 * M - 1);
+        scu[2 * m] = (float)sinpi((double)q / (double)M);
+        scu[2 * m + 1] = (float)sinpi((double)qc / (double)M);
+    }
 }
 }  // namespace
 
@@ -1065,7 +1091,8 @@ int ensure_coefficients_low(kfbi_domain *d, double kre, double kim) {
         KFBI_TRY(dalloc(d, &d->elim32, (size_t)n * ls));
         KFBI_TRY(dalloc(d, (void **)&d->tconv32, (size_t)n * sizeof(int32_t)));
         KFBI_TRY(dalloc(d, (void **)&d->sine32, (size_t)2 * M * sizeof(float)));
-        k_sine32<<<(2 * M + 255) / 256, 256, 0, d->stream>>>(M, d->sine32);
+        KFBI_TRY(dalloc(d, (void **)&d->scu32, (size_t)2 * std::max(1, M / 32) * sizeof(float)));
+        k_sine32<<<(2 * M + 255) / 256, 256, 0, d->stream>>>(M, d->sine32, d->scu32);
         KFBI_CHECK_LAUNCH();
     }
     const double h2 = d->h * d->h;

@@ -211,6 +211,9 @@ struct kfbi_domain {
     kfbi::Colloc *col = nullptr;        // Nb
     kfbi::Stencil *st = nullptr;        // Nb
     double *sine = nullptr;             // 2M: sin(pi m / M)
+    // the sine table at the angles 64 m (sin, cos pairs): a mode sum's
+    // uniform step angles, m < max(1, M / 32)
+    double *scu = nullptr;
     double *twiddle = nullptr;          // 2M complex: exp(-2 pi i m / 2M), m < M
 
     // scratch for solves (element type T = double or cd; sized for cd)
@@ -229,7 +232,7 @@ struct kfbi_domain {
     void *etab32 = nullptr;
     void *elim32 = nullptr;
     int32_t *tconv32 = nullptr;
-    float *sine32 = nullptr;
+    float *sine32 = nullptr, *scu32 = nullptr;
     bool coef32_valid = false;
     double coef32_kre = 0, coef32_kim = 0;
 
@@ -360,6 +363,11 @@ inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : si
 template <class T> using gmem = __attribute__((address_space(1))) T;
 template <class T> __device__ __forceinline__ const gmem<T> *gview(const T *p) { return (const gmem<T> *)p; }
 template <class T> __device__ __forceinline__ gmem<T> *gview(T *p) { return (gmem<T> *)p; }
+// Constant-memory view for tables that no kernel writes: a load through it
+// at a wavefront-uniform index becomes a scalar load into SGPRs.
+template <class T> using cmem = __attribute__((address_space(4))) T;
+template <class T> __device__ __forceinline__ const cmem<T> *cview(const T *p) { return (const cmem<T> *)p; }
+
 // element loads and stores through global views (complex elements move as
 // one two-lane vector)
 typedef double gdv2 __attribute__((ext_vector_type(2)));
@@ -430,7 +438,7 @@ struct EvalArgs {
     int M, nnodes, node_stride;
     const int32_t *nodes;
     const T *uhat;
-    const typename Real<T>::type *sine;
+    const typename Real<T>::type *sine, *scu;
     TO *out;
     const int *done;
 };
@@ -450,7 +458,7 @@ struct EvxArgs {
     int M, Nb, node_stride;
     const int32_t *nodes;
     const T *uhat;
-    const typename Real<T>::type *sine;
+    const typename Real<T>::type *sine, *scu;
     const double *w6;
     const TO *bop;
     const TO *phi;
@@ -499,7 +507,7 @@ struct ErowArgs {
     int M, n_rows;
     const int32_t *erow_t, *erow_ptr, *erow_col;
     const T *uhat;
-    const typename Real<T>::type *sine;
+    const typename Real<T>::type *sine, *scu;
     TO *ust;
     const int *done;
 };
