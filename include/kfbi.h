@@ -277,6 +277,24 @@ int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *
                          void *const *u_grid_out, void *const *phi_inout,
                          const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
+/* One time step of every active member stepper: the Crank-Nicolson step of
+ * kfbi_step_heat (eq. 3.4) or the theta-scheme step of kfbi_step_wave
+ * (eqs. 3.5-3.7), with the members' modified-Helmholtz solves batched as in
+ * kfbi_batch_helmholtz.  st[q] is an initialised REAL heat or wave stepper
+ * on member q's domain.  active (host, n bytes; NULL: all) selects the
+ * members that step; for each, g_next[q] is g on Gamma at the new time and
+ * u_grid_out[q] (grid) receives u; a heat member may pass its sources as
+ * kfbi_step_heat does (src_grid[q], src_gamma[q]; the arrays or entries may
+ * be NULL).  Members not active are untouched (state and outputs).  st,
+ * g_next, ... are host arrays of n entries; the results are on the batch
+ * stream in stream order.  stats (n entries, zero for members not active)
+ * as kfbi_batch_helmholtz.  Errors: KFBI_EINVAL (null, stepper not on the
+ * member's domain, not initialised, Schroedinger stepper), KFBI_ENOCONV
+ * (some member reached max_iter; its step still completes). */
+int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *active,
+                    const void *const *g_next, const void *const *src_grid, const void *const *src_gamma,
+                    void *const *u_grid_out, const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
 /* Launch shape of the tridiagonal kernel (the y-direction solves of the
  * five-point system, section 3.4) per class of members with equal M.  The
  * first kfbi_batch_helmholtz of each precision (unless KFBI_BATCH_NO_TUNE)

@@ -232,6 +232,70 @@ int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *
     return batch_helmholtz(b, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
 }
 
+int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *active, const void *const *g_next,
+                    const void *const *src_grid, const void *const *src_gamma, void *const *u_out,
+                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+    if (!b || !st || !g_next || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
+    const int n = batch_size(b);
+    auto on = [&](int q) { return !active || active[q] != 0; };
+    std::vector<double> kap(n, 0.0);
+    std::vector<const void *> f(n, nullptr), fg(n, nullptr), g(n, nullptr);
+    std::vector<void *> u(n, nullptr), phi(n, nullptr);
+    for (int q = 0; q < n; ++q) {
+        if (!on(q)) continue;
+        kfbi_stepper *s = st[q];
+        if (!s || !g_next[q] || !u_out[q]) { set_error("null stepper or array of an active member"); return KFBI_EINVAL; }
+        if (s->dom != batch_domain(b, q)) { set_error("stepper is not on the batch member's domain"); return KFBI_EINVAL; }
+        if ((s->eq != KFBI_HEAT && s->eq != KFBI_WAVE) || !s->initialized) {
+            set_error("batched steps take initialised heat or wave steppers");
+            return KFBI_EINVAL;
+        }
+    }
+    // right-hand sides of the members' solves (as kfbi_step_heat / kfbi_step_wave)
+    for (int q = 0; q < n; ++q) {
+        if (!on(q)) continue;
+        kfbi_stepper *s = st[q];
+        kfbi_domain *d = s->dom;
+        const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+        if (s->eq == KFBI_HEAT) {
+            const void *sg = src_grid ? src_grid[q] : nullptr, *sgg = src_gamma ? src_gamma[q] : nullptr;
+            KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A, -1.0, sg));
+            KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag, -1.0, sgg));
+        } else {
+            KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A));
+            KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag));
+        }
+        kap[q] = s->kre;
+        f[q] = s->f;
+        fg[q] = s->fg;
+        g[q] = g_next[q];
+        u[q] = u_out[q];
+        phi[q] = s->phi;
+    }
+    const int rc = batch_helmholtz(b, kap.data(), f.data(), fg.data(), g.data(), u.data(), phi.data(), opts, stats,
+                                   active);
+    if (rc != KFBI_OK && rc != KFBI_ENOCONV) return rc;
+    // state updates (as the single steps)
+    for (int q = 0; q < n; ++q) {
+        if (!on(q)) continue;
+        kfbi_stepper *s = st[q];
+        kfbi_domain *d = s->dom;
+        const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+        if (s->eq == KFBI_HEAT) {
+            KFBI_TRY(lin4<double>(d, ng, s->A, 2.0 * s->kre, u_out[q], 1.0, s->f));
+            KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * s->kre, g_next[q], 1.0, s->fg));
+        } else {
+            const double th = s->p.theta, c1 = (1.0 - 2.0 * th) / th, a = s->kre / th;
+            KFBI_TRY(lin4<double>(d, ng, s->B, a, u_out[q], -c1, s->A, -1.0, s->B));
+            KFBI_TRY(lin4<double>(d, Nb, s->Bg, a, g_next[q], -c1, s->Ag, -1.0, s->Bg));
+            std::swap(s->A, s->B);
+            std::swap(s->Ag, s->Bg);
+        }
+    }
+    if (rc == KFBI_ENOCONV) set_error("GMRES reached max_iter before the tolerance for a batch member");
+    return rc;
+}
+
 int kfbi_batch_tuning(const kfbi_batch *b, int32_t cap, int32_t *rows, double *us, int32_t *n_rows) {
     return batch_tuning(b, cap, rows, us, n_rows);
 }
@@ -441,7 +505,12 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
     if (st == KFBI_OK) st = st_alloc(s, &s->f, nodes * es);
     if (st == KFBI_OK) st = st_alloc(s, &s->fg, Nb * es);
     if (st == KFBI_OK) st = st_alloc(s, &s->phi, Nb * es);
-    if (st == KFBI_OK && hipMemsetAsync(s->phi, 0, Nb * es, d->stream) != hipSuccess) st = KFBI_EDEVICE;
+    // every state buffer starts at zero (the checkpoint of a stepper is then
+    // a function of its steps alone, also for buffers its equation leaves unused)
+    void *zero_bufs[5] = {s->A, s->Ag, s->B, s->Bg, s->phi};
+    const size_t zero_sizes[5] = {nodes * es, Nb * es, nodes * es, Nb * es, Nb * es};
+    for (int q = 0; q < 5 && st == KFBI_OK; ++q)
+        if (hipMemsetAsync(zero_bufs[q], 0, zero_sizes[q], d->stream) != hipSuccess) st = KFBI_EDEVICE;
     if (st != KFBI_OK) { kfbi_stepper_destroy(s); return st; }
     *out = s;
     return KFBI_OK;

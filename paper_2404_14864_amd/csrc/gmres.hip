@@ -643,6 +643,7 @@ __device__ inline void gm_publish(GmCtl *ctl, GmMirror *mir) {
 // control block, ||b||, and x_0 as the first slot's density
 template <class T>
 struct GmInitArgs {
+    const int *off;  // nonzero: member not solved in this call (batched solves)
     GmCtl *ctl;
     const T *b, *x;
     T *vcur;
@@ -653,6 +654,7 @@ struct GmInitArgs {
 
 template <class T>
 __device__ void gm_init_body(const GmInitArgs<T> &A, int) {
+    if (A.off && *A.off) return;
     GmCtl *ctl = A.ctl;
     const T *__restrict__ b = A.b;
     const T *__restrict__ x = A.x;
@@ -700,6 +702,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_init(GmInitArgs<T> A) {
 // basis][m*m: triangular factor at a cycle end].
 template <class T>
 struct SlotArgs {
+    const int *off;  // nonzero: member not solved in this call (batched solves)
     GmCtl *ctl;
     GmMirror *mir;
     T *V, *H, *g;
@@ -713,6 +716,7 @@ struct SlotArgs {
 
 template <class T, int EPT>
 __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
+    if (A.off && *A.off) return;
     GmCtl *ctl = A.ctl;
     GmMirror *mir = A.mir;
     T *V = A.V, *H = A.H, *g = A.g, *sn = A.sn, *x = A.x;
@@ -1230,6 +1234,7 @@ static size_t slot_lds(int Nb, int m, int *nvl_out) {
 template <class T>
 GmInitArgs<T> gm_init_args(GmPtrs &P, int Nb, const kfbi_solve_opts &o, bool mixed) {
     GmInitArgs<T> A;
+    A.off = nullptr;
     A.ctl = P.ctl;
     A.b = (const T *)P.b;
     A.x = (const T *)P.x;
@@ -1247,6 +1252,7 @@ GmInitArgs<T> gm_init_args(GmPtrs &P, int Nb, const kfbi_solve_opts &o, bool mix
 template <class T>
 SlotArgs<T> slot_args(GmPtrs &P, GmMirror *mir, int Nb, int m, int nvl) {
     SlotArgs<T> A;
+    A.off = nullptr;
     A.ctl = P.ctl;
     A.mir = mir;
     A.V = (T *)P.V;
@@ -1578,6 +1584,7 @@ struct kfbi_batch {
     int last_slots = 0;
     int nb_max = 0, m_lds = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int *d_one = nullptr;  // a device word holding 1: the gate of members not solved in a call
 };
 
 namespace kfbi {
@@ -1587,6 +1594,7 @@ void batch_destroy(kfbi_batch *b) {
     if (b->stream) hipStreamSynchronize(b->stream);
     if (b->d_map) hipFree(b->d_map);
     if (b->d_args) hipFree(b->d_args);
+    if (b->d_one) hipFree(b->d_one);
     if (b->h_args) hipHostFree(b->h_args);
     if (b->ev0) hipEventDestroy(b->ev0);
     if (b->ev1) hipEventDestroy(b->ev1);
@@ -1693,13 +1701,16 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
     b->args_bytes = off;
     if (hipHostMalloc((void **)&b->h_args, off, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void **)&b->d_args, off) != hipSuccess ||
-        hipMalloc((void **)&b->d_map, map.size() * sizeof(BlkMap)) != hipSuccess) {
+        hipMalloc((void **)&b->d_map, map.size() * sizeof(BlkMap)) != hipSuccess ||
+        hipMalloc((void **)&b->d_one, sizeof(int)) != hipSuccess) {
         batch_destroy(b);
         set_error("out of device memory for the batch tables");
         return KFBI_ENOMEM;
     }
+    static const int one = 1;
     if (hipMemcpyAsync(b->d_map, map.data(), map.size() * sizeof(BlkMap), hipMemcpyHostToDevice, b->stream) !=
             hipSuccess ||
+        hipMemcpyAsync(b->d_one, &one, sizeof(int), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess) {
         batch_destroy(b);
         set_error("copy of the batch tables failed");
@@ -1743,12 +1754,17 @@ int tune_time(kfbi_batch *b, int kind, const void *args, const BatchClass &C, co
 // operations in the same order, so the choice never changes the values.
 // Inputs are the members' own tables with the scratch right-hand sides
 // cleared; the launches write only the scratch transforms.
-int batch_tune_run(kfbi_batch *b, bool low, char *d_buf) {
+int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) {
     const int n = (int)b->doms.size();
     const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64);
     for (auto &C : b->classes) {
         std::vector<kfbi_domain *> cd;
-        for (int q : C.members) cd.push_back(b->doms[q]);
+        bool any = false;
+        for (int q : C.members) {
+            cd.push_back(b->doms[q]);
+            any = any || !active || active[q];
+        }
+        if (!any) continue;  // timed once some member of the class is solved
         const int kinds_hi[] = {0, 1}, kinds_lo[] = {2};
         const int *kinds = low ? kinds_lo : kinds_hi;
         const int nk = low ? 1 : 2;
@@ -1778,7 +1794,7 @@ int batch_tune_run(kfbi_batch *b, bool low, char *d_buf) {
     return KFBI_OK;
 }
 
-int batch_tune(kfbi_batch *b, bool low) {
+int batch_tune(kfbi_batch *b, bool low, const uint8_t *active) {
     bool need = false;
     for (auto &C : b->classes)
         for (int kind : {0, 1, 2})
@@ -1791,17 +1807,21 @@ int batch_tune(kfbi_batch *b, bool low) {
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = b->doms[q];
         const int nn = d->M - 1;
-        KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * sizeof(double), s));
-        KFBI_HIP(hipMemsetAsync(d->rhat, 0, (size_t)nn * nn * sizeof(double), s));
-        batch_fill_tri(d, nullptr, d->corr, low ? d->uhat32 : d->uhat, nullptr, low, h.data() + (size_t)q * as);
-        if (!low) batch_fill_tri(d, d->rhat, d->corr, d->uhat, nullptr, false, h.data() + (size_t)(n + q) * as);
+        // members not solved in this call may lack their coefficients: gated off
+        const int *one = (!active || active[q]) ? nullptr : b->d_one;
+        if (!one) {
+            KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * sizeof(double), s));
+            KFBI_HIP(hipMemsetAsync(d->rhat, 0, (size_t)nn * nn * sizeof(double), s));
+        }
+        batch_fill_tri(d, nullptr, d->corr, low ? d->uhat32 : d->uhat, one, low, h.data() + (size_t)q * as);
+        if (!low) batch_fill_tri(d, d->rhat, d->corr, d->uhat, one, false, h.data() + (size_t)(n + q) * as);
     }
     char *d_buf = nullptr;
     KFBI_HIP(hipMalloc((void **)&d_buf, h.size()));
     int st = hipMemcpyAsync(d_buf, h.data(), h.size(), hipMemcpyHostToDevice, s) == hipSuccess ? KFBI_OK
                                                                                                  : KFBI_EDEVICE;
     if (st != KFBI_OK) set_error("copy of the tuning arguments failed");
-    if (st == KFBI_OK) st = batch_tune_run(b, low, d_buf);
+    if (st == KFBI_OK) st = batch_tune_run(b, low, d_buf, active);
     const bool synced = hipStreamSynchronize(s) == hipSuccess;
     hipFree(d_buf);
     if (st == KFBI_OK && !synced) {
@@ -1810,6 +1830,9 @@ int batch_tune(kfbi_batch *b, bool low) {
     }
     return st;
 }
+
+int batch_size(const kfbi_batch *b) { return (int)b->doms.size(); }
+kfbi_domain *batch_domain(const kfbi_batch *b, int q) { return b->doms[q]; }
 
 int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows) {
     if (!b || !n_rows || cap < 0 || (cap > 0 && !rows)) { set_error("null argument"); return KFBI_EINVAL; }
@@ -1831,9 +1854,15 @@ int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_
 
 int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
                     const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
-                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats, const uint8_t *active) {
     if (!b || !kappa || !f_grid || !f_gamma || !g_gamma) { set_error("null argument"); return KFBI_EINVAL; }
     const int n = (int)b->doms.size();
+    auto on = [&](int q) { return !active || active[q] != 0; };
+    int n_on = 0;
+    for (int q = 0; q < n; ++q) n_on += on(q) ? 1 : 0;
+    if (stats)
+        for (int q = 0; q < n; ++q) stats[q] = kfbi_solve_stats{0, 1, 0.0, 0, 0, 0.0};
+    if (n_on == 0) return KFBI_OK;
     kfbi_solve_opts o;
     o.tol = 1e-10;
     o.max_iter = 500;
@@ -1856,6 +1885,7 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     // per-member setup: coefficients and operators for this kappa
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = b->doms[q];
+        if (!on(q)) continue;
         if (!f_grid[q] || !f_gamma[q] || !g_gamma[q]) { set_error("null member array"); return KFBI_EINVAL; }
         KFBI_TRY(ensure_coefficients(d, kappa[q], 0.0));
         KFBI_TRY(ensure_operators(d, kappa[q], 0.0));
@@ -1871,8 +1901,8 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         }
     }
     if (!(o.flags & KFBI_BATCH_NO_TUNE)) {
-        KFBI_TRY(batch_tune(b, false));
-        if (mixed) KFBI_TRY(batch_tune(b, true));
+        KFBI_TRY(batch_tune(b, false, active));
+        if (mixed) KFBI_TRY(batch_tune(b, true, active));
     }
     // argument blocks
     int nvl_min = 1 << 30;
@@ -1880,16 +1910,21 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = b->doms[q];
         GmPtrs P = gm_layout(d, 64);
-        const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
+        // a member not solved in this call has every gate on the word that holds 1
+        const int *one = on(q) ? nullptr : b->d_one;
+        const int *skip64 = one ? one : &P.ctl->skip64, *skip32 = one ? one : &P.ctl->skip32,
+                  *skip_tail = one ? one : &P.ctl->skip_tail;
         auto at = [&](int u) { return b->h_args + b->use_off[u] + (size_t)q * b->use_size[u]; };
-        batch_fill_dst(d, f_grid[q], true, true, d->rhat, false, 1.0, nullptr, at(kUDstF));
-        batch_fill_corr(d, kappa[q], nullptr, f_gamma[q], d->corr, nullptr, at(kUCorrB));
-        batch_fill_tri(d, d->rhat, d->corr, d->uhat, nullptr, false, at(kUTriB));
-        batch_fill_erow(d, d->uhat, d->ust, nullptr, false, at(kUErowB));
-        batch_fill_ext(d, kappa[q], d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, nullptr, at(kUExtB));
+        batch_fill_dst(d, f_grid[q], true, true, d->rhat, false, 1.0, one, at(kUDstF));
+        batch_fill_corr(d, kappa[q], nullptr, f_gamma[q], d->corr, one, at(kUCorrB));
+        batch_fill_tri(d, d->rhat, d->corr, d->uhat, one, false, at(kUTriB));
+        batch_fill_erow(d, d->uhat, d->ust, one, false, at(kUErowB));
+        batch_fill_ext(d, kappa[q], d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, one, at(kUExtB));
         *(CopyArgs *)at(kUCopyX) = CopyArgs{(double *)P.x, phi_inout ? (const double *)phi_inout[q] : nullptr,
-                                            d->Nb, nullptr};
-        *(GmInitArgs<double> *)at(kUInit) = gm_init_args<double>(P, d->Nb, o, mixed);
+                                            d->Nb, one};
+        GmInitArgs<double> ia = gm_init_args<double>(P, d->Nb, o, mixed);
+        ia.off = one;
+        *(GmInitArgs<double> *)at(kUInit) = ia;
         batch_fill_corr_phi(d, P.vcur, d->corr, skip64, at(kUCorrPhi64));
         batch_fill_tri(d, nullptr, d->corr, d->uhat, skip64, false, at(kUTri64));
         batch_fill_erow(d, d->uhat, d->ust, skip64, false, at(kUErow64));
@@ -1902,7 +1937,9 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         const size_t lds = slot_lds<double>(d->Nb, o.restart, &nvl);
         slot_lds_max = std::max(slot_lds_max, lds);
         nvl_min = std::min(nvl_min, nvl);
-        *(SlotArgs<double> *)at(kUSlot) = slot_args<double>(P, (GmMirror *)d->mirror_dev, d->Nb, o.restart, nvl);
+        SlotArgs<double> sa = slot_args<double>(P, (GmMirror *)d->mirror_dev, d->Nb, o.restart, nvl);
+        sa.off = one;
+        *(SlotArgs<double> *)at(kUSlot) = sa;
         batch_fill_corr(d, kappa[q], P.x, f_gamma[q], d->corr, skip_tail, at(kUCorrF));
         batch_fill_tri(d, d->rhat, d->corr, d->uhat, skip_tail, false, at(kUTriF));
         void *uo = u_out ? u_out[q] : nullptr;
@@ -1910,9 +1947,8 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         batch_fill_zero(d, uo, skip_tail, at(kUZero));
         *(CopyArgs *)at(kUCopyF) = CopyArgs{phi_inout ? (double *)phi_inout[q] : nullptr, (const double *)P.x,
                                             d->Nb, skip_tail};
-        *(FinalArgs *)at(kUFinal) = FinalArgs{&P.ctl->skip_tail};
-        GmMirror *mh = (GmMirror *)d->mirror_host;
-        __atomic_store_n(&mh->seq, 0, __ATOMIC_RELEASE);
+        *(FinalArgs *)at(kUFinal) = FinalArgs{one ? b->d_one : &P.ctl->skip_tail};
+        if (on(q)) __atomic_store_n(&((GmMirror *)d->mirror_host)->seq, 0, __ATOMIC_RELEASE);
     }
     // the dynamic LDS of a batched control launch must hold every member's
     // layout, with nvl staged vectors of the largest Nb
@@ -2005,6 +2041,7 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
             all_done = true;
             bool settled = true;
             for (int q = 0; q < n; ++q) {
+                if (!on(q)) continue;
                 GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
                 const int seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
                 const int st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
@@ -2023,6 +2060,7 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
                     // drained: one more look at the mirrors, then give up
                     bool ok = true;
                     for (int q = 0; q < n; ++q) {
+                        if (!on(q)) continue;
                         GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
                         const int seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
                         const int st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
@@ -2043,6 +2081,7 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     }
     int max_seq = 0, st = KFBI_OK;
     for (int q = 0; q < n; ++q) {
+        if (!on(q)) continue;
         GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
         max_seq = std::max(max_seq, mh->seq);
         if (stats) {
@@ -2062,7 +2101,8 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         float ms = 0.f;
         KFBI_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
         if (stats)
-            for (int q = 0; q < n; ++q) stats[q].device_ms = ms;
+            for (int q = 0; q < n; ++q)
+                if (on(q)) stats[q].device_ms = ms;
     }
     if (st == KFBI_ENOCONV) set_error("GMRES reached max_iter before the tolerance for a batch member");
     return st;

@@ -87,13 +87,13 @@ __device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (3
 template <class T>
 __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
     const int M = A.M, logN2 = A.logN2;
-    const T *in = A.in;
+    const gmem<T> *in = gview(A.in);
     const bool in_grid = A.in_grid, out_grid = A.out_grid;
-    const uint8_t *mask = A.mask;
-    T *out = A.out;
+    const gmem<uint8_t> *mask = gview(A.mask);
+    gmem<T> *out = gview(A.out);
     const double scale = A.scale;
-    const double *twiddle = A.twiddle;
-    if (A.done && *A.done) return;
+    const gmem<double> *twiddle = gview(A.twiddle);
+    if (A.done && *gview(A.done)) return;
     extern __shared__ double lds[];
     double2 *a = reinterpret_cast<double2 *>(lds);
     const int n = M - 1, N2 = 2 * M;
@@ -113,11 +113,11 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
                 bool keep = (mask == nullptr) || (mask[(size_t)(t + 1) * (M + 1) + i] & 1);
                 if (!keep) continue;
                 if constexpr (CPLX) {
-                    const cd v = reinterpret_cast<const cd *>(in)[idx];
+                    const cd v = gld(in + idx);
                     re = sgn * v.x;
                     im = sgn * v.y;
                 } else {
-                    double v = reinterpret_cast<const double *>(in)[idx];
+                    double v = gld(in + idx);
                     if (r == 0) re = sgn * v; else im = sgn * v;
                 }
             }
@@ -131,7 +131,7 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
         for (int b = threadIdx.x; b < M; b += blockDim.x) {
             int grp = b / half, pos = b - grp * half;
             int i0 = grp * len + pos, i1 = i0 + half;
-            double wr = twiddle[2 * pos * tstep], wi = twiddle[2 * pos * tstep + 1];
+            const double wr = twiddle[2 * pos * tstep], wi = twiddle[2 * pos * tstep + 1];
             double2 u = a[i0], v = a[i1];
             double vr = v.x * wr - v.y * wi, vi = v.x * wi + v.y * wr;
             a[i0] = make_double2(u.x + vr, u.y + vi);
@@ -148,10 +148,10 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
             size_t idx = out_grid ? (size_t)(t + 1) * (M + 1) + k : (size_t)t * n + (k - 1);
             if constexpr (CPLX) {
                 // S_k = i Y_k / 2
-                reinterpret_cast<cd *>(out)[idx] = make_cd(-0.5 * scale * Z.y, 0.5 * scale * Z.x);
+                gst(out + idx, make_cd(-0.5 * scale * Z.y, 0.5 * scale * Z.x));
             } else {
                 double v = (r == 0) ? -0.5 * Z.y : 0.5 * Z.x;
-                reinterpret_cast<double *>(out)[idx] = scale * v;
+                gst(out + idx, scale * v);
             }
         }
     }
@@ -160,8 +160,8 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
             int t = t_first + r;
             if (t >= n) continue;
             size_t base = (size_t)(t + 1) * (M + 1);
-            reinterpret_cast<T *>(out)[base] = zero<T>();
-            reinterpret_cast<T *>(out)[base + M] = zero<T>();
+            gst(out + base, zero<T>());
+            gst(out + base + M, zero<T>());
         }
     }
 }

@@ -596,10 +596,12 @@ int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks
 // batched Helmholtz solves (gmres.hip)
 int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out);
 void batch_destroy(kfbi_batch *b);
+int batch_size(const kfbi_batch *b);
+kfbi_domain *batch_domain(const kfbi_batch *b, int q);
 int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows);
 int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
                     const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
-                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats, const uint8_t *active = nullptr);
 
 // kernel timing: prof_begin returns a slot (or -1 when profiling is off);
 // prof_end closes it with the launch's algorithmic bytes; prof_flush waits

@@ -117,6 +117,9 @@ def lib():
         "kfbi_batch_helmholtz": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                   ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_batch_step": ([_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_P),
+                             ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(SolveOpts),
+                             ctypes.POINTER(SolveStats)], ctypes.c_int),
         "kfbi_batch_tuning": ([_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "kfbi_profile_replay": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -136,7 +139,8 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_stepper_destroy", "kfbi_stepper_init", "kfbi_step_heat", "kfbi_step_wave",
             "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read", "kfbi_profile_replay",
             "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state",
-            "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz", "kfbi_batch_tuning")
+            "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz", "kfbi_batch_tuning",
+            "kfbi_batch_step")
 
 
 def kfbi_profile_enable(h, on=True):
@@ -182,6 +186,30 @@ def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, p
     code = lib().kfbi_batch_helmholtz(b, kap, ptrs(f_grid, "f_grid"), ptrs(f_gamma, "f_gamma"),
                                       ptrs(g_gamma, "g_gamma"), ptrs(u_grid_out, "u_grid_out"),
                                       ptrs(phi_inout, "phi_inout"), _opts(opts), stats)
+    _check(code, allow=(KFBI_ENOCONV,))
+    return [stats[q].as_dict() for q in range(n)]
+
+
+def kfbi_batch_step(b, steppers, g_next, u_out, active=None, src_grid=None, src_gamma=None, opts=None):
+    """One time step of the active member steppers (heat or wave, member q
+    on the batch's domain q) with their solves batched.  g_next, u_out,
+    src_grid, src_gamma: lists of float64 CUDA tensors (None entries for
+    members not active or without sources); active: booleans (None: all).
+    Returns the per-member stats."""
+    n = len(steppers)
+    if len(g_next) != n or len(u_out) != n:
+        raise ValueError("one entry per member is required")
+    st = (_P * n)(*[(x.value if isinstance(x, ctypes.c_void_p) else x) for x in steppers])
+    act = None if active is None else (ctypes.c_uint8 * n)(*[1 if a else 0 for a in active])
+
+    def ptrs(lst, name):
+        if lst is None:
+            return None
+        return (_P * n)(*[(_ptr(t, torch.float64, None, name).value if t is not None else None) for t in lst])
+
+    stats = (SolveStats * n)()
+    code = lib().kfbi_batch_step(b, st, act, ptrs(g_next, "g_next"), ptrs(src_grid, "src_grid"),
+                                 ptrs(src_gamma, "src_gamma"), ptrs(u_out, "u_out"), _opts(opts), stats)
     _check(code, allow=(KFBI_ENOCONV,))
     return [stats[q].as_dict() for q in range(n)]
 
