@@ -91,6 +91,10 @@ typedef struct {
     int32_t n_edges;      /* grid edges crossed by Gamma                    */
     int32_t pad;
     uint64_t device_bytes;/* device memory held by the domain               */
+    uint64_t device_bytes_max; /* what it holds once every solve has run:
+                             the per-kappa operator tables and the FP32 tables
+                             of mixed precision, allocated on first use,
+                             included (the figure for admission budgets)    */
 } kfbi_domain_info;
 
 typedef struct {

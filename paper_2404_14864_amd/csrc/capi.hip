@@ -390,6 +390,7 @@ int kfbi_domain_get_info(const kfbi_domain *d, kfbi_domain_info *out) {
     out->n_irregular = d->n_irr;
     out->n_edges = d->n_edges;
     out->device_bytes = d->bytes;
+    out->device_bytes_max = d->bytes + operators_bytes_pending(d) + low_tables_bytes_pending(d);
     return KFBI_OK;
 }
 

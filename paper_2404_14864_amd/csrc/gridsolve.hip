@@ -1079,6 +1079,13 @@ __global__ void k_sine32(int M, float *s, float *scu) {
 }
 }  // namespace
 
+size_t low_tables_bytes_pending(const kfbi_domain *d) {
+    if (d->uhat32) return 0;
+    const size_t M = (size_t)d->M, n = M - 1, ls = d->cplx ? sizeof(cf) : sizeof(float);
+    return 2 * n * n * ls + n * ls + n * sizeof(int32_t) + 2 * M * sizeof(float) +
+           2 * (size_t)std::max(1, d->M / 32) * sizeof(float);
+}
+
 // FP32 / complex64 coefficient table and scratch for the mixed-precision
 // grid solve (allocated on first use)
 int ensure_coefficients_low(kfbi_domain *d, double kre, double kim) {

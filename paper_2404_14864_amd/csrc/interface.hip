@@ -377,6 +377,13 @@ int extract_boundary(kfbi_domain *d, double kre, double kim, const void *ust, co
     return extract_boundary_ctl(d, kre, kim, ust, phi, nullptr, f_gamma, g_minus, scale, out, 0, nullptr);
 }
 
+size_t operators_bytes_pending(const kfbi_domain *d) {
+    if (d->cop_coef) return 0;
+    const size_t es = elem_size(d), ni = (size_t)d->n_irr, Nb = (size_t)d->Nb;
+    return ni * 32 * es + ni * 4 * sizeof(int32_t) + ni * kCorrWin * es + ni * sizeof(int32_t) + 256 + Nb * 5 * es +
+           Nb * 6 * sizeof(double);
+}
+
 int ensure_operators(kfbi_domain *d, double kre, double kim) {
     if (d->op_valid && d->op_kre == kre && d->op_kim == kim) return KFBI_OK;
     const size_t es = elem_size(d);

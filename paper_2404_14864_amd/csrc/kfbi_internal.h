@@ -596,6 +596,9 @@ int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks
 // batched Helmholtz solves (gmres.hip)
 int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out);
 void batch_destroy(kfbi_batch *b);
+// device bytes of the tables a domain allocates on first use, while not yet allocated
+size_t operators_bytes_pending(const kfbi_domain *d);
+size_t low_tables_bytes_pending(const kfbi_domain *d);
 int batch_size(const kfbi_batch *b);
 kfbi_domain *batch_domain(const kfbi_batch *b, int q);
 int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows);

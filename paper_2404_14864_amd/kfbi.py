@@ -44,7 +44,8 @@ class DomainInfo(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("Nb", ctypes.c_int32), ("L", ctypes.c_double),
                 ("h", ctypes.c_double), ("n_inside", ctypes.c_int32),
                 ("n_irregular", ctypes.c_int32), ("n_edges", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+                ("pad", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("device_bytes_max", ctypes.c_uint64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -299,7 +300,7 @@ def kfbi_domain_get_info(h):
     _check(lib().kfbi_domain_get_info(h, ctypes.byref(info)))
     return {"M": info.M, "Nb": info.Nb, "L": info.L, "h": info.h, "n_inside": info.n_inside,
             "n_irregular": info.n_irregular, "n_edges": info.n_edges,
-            "device_bytes": int(info.device_bytes)}
+            "device_bytes": int(info.device_bytes), "device_bytes_max": int(info.device_bytes_max)}
 
 
 def kfbi_domain_copy_classification(h):
