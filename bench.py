@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # on a 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); the
 # counts and the commands are in profiles/tridiag_wave512_fp64_hbm_traffic.md.
 # Kernels not listed (or changed since they were counted) report null.
-TRAFFIC = {"tridiag_sparse": 2596418.0}
+TRAFFIC = {"tridiag_sparse": 2588265.0}
 
 
 def parse():
@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--replay", type=int, default=200)
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched Helmholtz run (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-jobs", type=int, default=32, help="jobs of the serving sample (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device three times (the reference transfer "
                          "for HBM byte counters)")
@@ -180,6 +181,30 @@ def batched_helmholtz(n, reps):
     for m in mem:
         kfbi.kfbi_domain_destroy(m["h"])
     return out
+
+
+def serving(n_jobs):
+    """The serving workload on a bounded sample: n_jobs seeded jobs (heat,
+    wave, Schroedinger 40/40/20; star or ellipse domains; grids uniform over
+    {256, 512, 1024}; 20..60 steps each), Poisson arrivals at 0.5 job per
+    tick, admitted within 0.8 of the free device memory.  Step latency is
+    the device time of the tick that advanced the job."""
+    import torch
+    from workloads.serving import job_fields, job_stream
+    from paper_2404_14864_amd.serving import Server
+    free, _ = torch.cuda.mem_get_info()
+    specs = job_stream(20240423, n_jobs, rate=0.5, grids=(256, 512, 1024), steps=(20, 60))
+    srv = Server(int(0.8 * free), job_fields, {"tol": 1e-10})
+    rep = srv.run(specs, tick=1.0)
+    rep["workload"] = ("%d jobs, heat/wave/Schroedinger 40/40/20, star (heat, wave) and ellipse (Schroedinger) "
+                       "domains, grids U{256,512,1024}, Nb=M, 20-60 steps, Poisson arrivals 0.5/tick, "
+                       "tol 1e-10" % n_jobs)
+    rep["n_finished"] = len(rep.pop("finished"))
+    rep["n_rejected"] = len(rep.pop("rejected"))
+    log("serving: %d jobs in %d ticks, p50 %.2f ms, p99 %.2f ms per step, %.3g %s, up to %d jobs at once" % (
+        rep["n_finished"], rep["ticks"], rep["p50_step_ms"], rep["p99_step_ms"], rep["throughput"], rep["unit"],
+        rep["max_concurrent_jobs"]))
+    return rep
 
 
 def main():
@@ -324,6 +349,7 @@ def main():
         del src, dst
 
     batched = batched_helmholtz(args.batch, args.batch_reps) if args.batch > 0 else None
+    served = serving(args.serve_jobs) if args.serve_jobs > 0 else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -372,6 +398,7 @@ def main():
                             "grid_solve": "fp32", "refinement": "fp64",
                             "rel_diff_vs_fp64_after_steps": mixed_err},
         "batched": batched,
+        "serving": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
