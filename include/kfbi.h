@@ -105,6 +105,7 @@ typedef struct {
     int32_t precision;    /* -1: the domain's default; else kfbi_precision         */
     int32_t flags;        /* KFBI_SOLVE_* bits; 0 by default                       */
     int32_t pad;
+    double gamma;         /* Richardson parameter (KFBI_SOLVE_RICHARDSON); <= 0: 1  */
 } kfbi_solve_opts;
 
 /* kfbi_solve_opts.flags: return as soon as GMRES has finished on the device.
@@ -119,6 +120,16 @@ typedef struct {
  * of the tridiagonal kernel instead of timing the candidates (see
  * kfbi_batch_tuning).  The choice never changes results. */
 #define KFBI_BATCH_NO_TUNE 2
+
+/* kfbi_solve_opts.flags: solve the second-kind equation (eq. 3.17) by the
+ * Richardson iteration of eq. 3.21, phi_{k+1} = (1 - gamma/2) phi_k +
+ * gamma (g - Yf - W phi_k) = phi_k + gamma (b - K phi_k), instead of GMRES,
+ * from the same initial density and to the same stopping test
+ * (||b - K phi|| <= tol ||b||; fixed_iters > 0: exactly that many updates).
+ * stats.iters counts the updates.  FP64 (complex128) only: with the mixed
+ * precision the call returns KFBI_ENOTSUP; single solves and steps only
+ * (batched calls return KFBI_ENOTSUP). */
+#define KFBI_SOLVE_RICHARDSON 4
 
 typedef struct {
     int32_t iters;        /* GMRES iterations (matrix-vector products in Arnoldi) */

@@ -16,6 +16,7 @@ IS(f, phi) the interface solve of oracle.interface (reading R2):
 import numpy as np
 
 from . import gmres as _gmres
+from . import richardson as _richardson
 from .interface import interface_solve
 
 
@@ -42,15 +43,21 @@ def dense_operator(dom, kappa):
 
 
 def helmholtz_solve(dom, kappa, f_grid, f_gamma, g, phi0=None, tol=1e-10,
-                    restart=50, max_iter=500, fixed_iters=None):
-    """Solve the Dirichlet problem.  Returns (U, phi, stats)."""
+                    restart=50, max_iter=500, fixed_iters=None, solver="gmres", gamma=1.0):
+    """Solve the Dirichlet problem.  Returns (U, phi, stats).  solver:
+    "gmres" (reading R1) or "richardson" (eq. 3.21 with parameter gamma)."""
     cplx = any(np.iscomplexobj(v) for v in (kappa, f_grid, f_gamma, g, phi0)
                if v is not None)
     dtype = np.complex128 if cplx else np.float64
     g = np.asarray(g, dtype=dtype)
     b = rhs(dom, kappa, f_grid, f_gamma, g)
-    phi, iters, rel, conv = _gmres.gmres(
-        lambda v: matvec(dom, kappa, v), b, phi0, tol=tol, restart=restart,
-        max_iter=max_iter, fixed_iters=fixed_iters)
+    if solver == "richardson":
+        phi, iters, rel, conv = _richardson.richardson(
+            lambda v: matvec(dom, kappa, v), b, phi0, gamma=gamma, tol=tol,
+            max_iter=max_iter, fixed_iters=fixed_iters)
+    else:
+        phi, iters, rel, conv = _gmres.gmres(
+            lambda v: matvec(dom, kappa, v), b, phi0, tol=tol, restart=restart,
+            max_iter=max_iter, fixed_iters=fixed_iters)
     U, _ = interface_solve(dom, kappa, f_grid, f_gamma, phi)
     return U, phi, {"iters": iters, "rel_resid": rel, "converged": conv}

@@ -986,6 +986,49 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_slot(SlotArgs<T> A) {
     gm_slot_body<T, EPT>(A, 0);
 }
 
+// The control kernel of one Richardson slot (eq. 3.21 as x + gamma (b - K x)).
+// kv holds K x from the slot's grid solve, x the current density (equal to
+// vcur).  The residual of x decides the stop; otherwise x and vcur advance.
+template <class T>
+struct RichArgs {
+    GmCtl *ctl;
+    GmMirror *mir;
+    T *x, *vcur;
+    const T *b, *kv;
+    int Nb;
+    double gamma;
+};
+
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void k_rich_slot(RichArgs<T> A) {
+    GmCtl *ctl = A.ctl;
+    const GmCtl c = *ctl;
+    if (c.state == kStDone) return;
+    __shared__ double red[16];
+    const int Nb = A.Nb;
+    double s = 0.0;
+    for (int k = threadIdx.x; k < Nb; k += blockDim.x) s += abs2(A.b[k] - A.kv[k]);
+    const double resid = sqrt(block_sum(s, red));
+    const bool conv = resid <= c.tol * c.bnorm;
+    const bool stop = c.fixed > 0 ? c.iters >= c.fixed : (conv || c.iters >= c.max_iter);
+    if (!stop) {
+        for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
+            const T xn = A.x[k] + (A.b[k] - A.kv[k]) * A.gamma;
+            A.x[k] = xn;
+            A.vcur[k] = xn;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->iters = c.iters + (stop ? 0 : 1);
+        ctl->resid = resid;
+        ctl->converged = conv ? 1 : 0;
+        ctl->slot = c.slot + 1;
+        gm_set_state(ctl, stop ? kStDone : kStIter);
+        gm_publish(ctl, A.mir);
+    }
+}
+
 struct GmPtrs {
     GmCtl *ctl;
     void *V, *H, *g, *sn, *y, *x, *b, *r;
@@ -1311,6 +1354,7 @@ static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index,
 template <class T, class Tail>
 static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, bool mixed, Tail &&tail,
                            int *iters_out, double *rel_out, int *conv_out, int *cycles_out) {
+    const bool rich = (o.flags & KFBI_SOLVE_RICHARDSON) != 0;
     hipStream_t s = d->stream;
     const int Nb = d->Nb, m = o.restart;
     if (!d->mirror_host) {
@@ -1338,7 +1382,16 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, 
                 KFBI_TRY(tridiag_solve_phi(d, P.vcur, d->uhat32, skip32, true));
                 KFBI_TRY(eval_extract_ctl(d, d->uhat32, P.vcur, P.r, skip32, true));
             }
-            KFBI_TRY(launch_slot<T>(d, P, Nb, m, n_enq + c, s));
+            if (rich) {
+                const RichArgs<T> RA{P.ctl, (GmMirror *)d->mirror_dev, (T *)P.x, (T *)P.vcur, (const T *)P.b,
+                                     (const T *)P.r, Nb, o.gamma > 0 ? o.gamma : 1.0};
+                const int ps = prof_begin(d);
+                k_rich_slot<T><<<1, kGmThreads, 0, s>>>(RA);
+                KFBI_CHECK_LAUNCH();
+                prof_end(d, ps, KFBI_K_ARNOLDI, 6.0 * Nb * sizeof(T));
+            } else {
+                KFBI_TRY(launch_slot<T>(d, P, Nb, m, n_enq + c, s));
+            }
         }
         n_enq += want;
         d->prof_tag = kTailTag + batch;
@@ -1395,6 +1448,7 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     o.precision = -1;
     o.flags = 0;
     o.pad = 0;
+    o.gamma = 0.0;
     if (opts) {
         if (opts->tol > 0) o.tol = opts->tol;
         if (opts->max_iter > 0) o.max_iter = opts->max_iter;
@@ -1402,6 +1456,7 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
         o.fixed_iters = opts->fixed_iters;
         o.precision = opts->precision;
         o.flags = opts->flags;
+        o.gamma = opts->gamma;
     }
     if (o.restart > 64) {
         set_error("restart length must be at most 64");
@@ -1421,6 +1476,11 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
         return KFBI_EINVAL;
     }
     const bool mixed = prec == KFBI_PREC_MIXED;
+    const bool rich = (o.flags & KFBI_SOLVE_RICHARDSON) != 0;
+    if (rich && mixed) {
+        set_error("the Richardson iteration runs in FP64 only");
+        return KFBI_ENOTSUP;
+    }
     hipStream_t s = d->stream;
     if (!d->ev0) {
         KFBI_HIP(hipEventCreate(&d->ev0));
@@ -1467,6 +1527,10 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
         return KFBI_OK;
     };
     const bool slots = d->cplx ? slots_supported<cd>(d, o.restart) : slots_supported<double>(d, o.restart);
+    if (rich && !slots) {
+        set_error("the Richardson iteration needs the device-driven schedule (merged operators)");
+        return KFBI_ENOTSUP;
+    }
     if (slots) {
         if (d->cplx) st = gmres_run_slots<cd>(d, P, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
         else st = gmres_run_slots<double>(d, P, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
@@ -1492,7 +1556,8 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     }
     const bool fixed = o.fixed_iters > 0;
     if (!conv && !fixed) {
-        set_error("GMRES reached max_iter before the tolerance");
+        set_error(rich ? "the Richardson iteration reached max_iter before the tolerance"
+                       : "GMRES reached max_iter before the tolerance");
         return KFBI_ENOCONV;
     }
     return KFBI_OK;
@@ -1871,6 +1936,7 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     o.precision = -1;
     o.flags = 0;
     o.pad = 0;
+    o.gamma = 0.0;
     if (opts) {
         if (opts->tol > 0) o.tol = opts->tol;
         if (opts->max_iter > 0) o.max_iter = opts->max_iter;
@@ -1878,8 +1944,10 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         o.fixed_iters = opts->fixed_iters;
         o.precision = opts->precision;
         o.flags = opts->flags;
+        o.gamma = opts->gamma;
     }
     if (o.restart > 64) { set_error("restart length must be at most 64"); return KFBI_EINVAL; }
+    if (o.flags & KFBI_SOLVE_RICHARDSON) { set_error("batched solves use GMRES"); return KFBI_ENOTSUP; }
     const bool mixed = (o.precision >= 0 ? o.precision : b->doms[0]->desc.precision) == KFBI_PREC_MIXED;
     hipStream_t s = b->stream;
     // per-member setup: coefficients and operators for this kappa

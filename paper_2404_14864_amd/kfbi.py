@@ -21,6 +21,7 @@ KFBI_REAL, KFBI_COMPLEX = 0, 1
 KFBI_PREC_FP64, KFBI_PREC_MIXED = 0, 1
 KFBI_SOLVE_ASYNC = 1
 KFBI_BATCH_NO_TUNE = 2
+KFBI_SOLVE_RICHARDSON = 4
 KFBI_HEAT, KFBI_WAVE, KFBI_SCHRODINGER = 0, 1, 2
 
 
@@ -51,7 +52,8 @@ class DomainInfo(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("gamma", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -271,7 +273,9 @@ def _opts(opts):
                   restart=opts.get("restart", 0), fixed_iters=opts.get("fixed_iters", 0),
                   precision=opts.get("precision", -1),
                   flags=(KFBI_SOLVE_ASYNC if opts.get("async", False) else 0)
-                  | (KFBI_BATCH_NO_TUNE if opts.get("no_tune", False) else 0))
+                  | (KFBI_BATCH_NO_TUNE if opts.get("no_tune", False) else 0)
+                  | (KFBI_SOLVE_RICHARDSON if opts.get("solver", "gmres") == "richardson" else 0),
+                  gamma=float(opts.get("gamma", 0.0)))
     return ctypes.byref(o)
 
 

@@ -38,6 +38,6 @@ def test_binding_struct_sizes_match_header_layout():
     from paper_2404_14864_amd import kfbi
     # sizes implied by the header's field order on LP64
     assert ctypes.sizeof(kfbi.DomainDesc) == 8 + 4 * 4 + 8 * 7 + 4 * 2 + 8
-    assert ctypes.sizeof(kfbi.SolveOpts) == 8 + 4 * 6
+    assert ctypes.sizeof(kfbi.SolveOpts) == 8 + 4 * 6 + 8
     assert ctypes.sizeof(kfbi.SolveStats) == 4 * 2 + 8 + 4 * 2 + 8
     assert ctypes.sizeof(kfbi.DomainInfo) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8
