@@ -307,6 +307,27 @@ def main():
     log("mixed: %d steps in %.3f s, %d iterations, rel diff vs FP64 %.2e" % (args.steps, Tm, sum(miters),
                                                                           mixed_err))
 
+    # the paper's Richardson iteration (eq. 3.21) on the first steps of the
+    # same workload, beside GMRES: products per step and device time
+    rich = {}
+    rsteps = min(args.steps, 20)
+    for label, ropts in (("gmres", {}), ("richardson_gamma1", {"solver": "richardson", "gamma": 1.0}),
+                         ("richardson_gamma0.9", {"solver": "richardson", "gamma": 0.9})):
+        kfbi.kfbi_stepper_init(st, *init)
+        its = []
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(rsteps):
+            its.append(kfbi.kfbi_step_wave(st, g_all[k], u, opts=dict(ropts, tol=1e-10))["iters"])
+        ev[1].record()
+        torch.cuda.synchronize()
+        rich[label] = {"products_per_step": float(np.mean(its)),
+                       "ms_per_step": ev[0].elapsed_time(ev[1]) / rsteps}
+    rich["steps"] = rsteps
+    rich["tol"] = 1e-10
+    log("solvers: " + ", ".join("%s %.1f products %.3f ms" % (k, v["products_per_step"], v["ms_per_step"])
+                                for k, v in rich.items() if isinstance(v, dict)))
+
     # profiled pass: HIP events around every kernel launch of the same steps
     kfbi.kfbi_stepper_init(st, *init)
     kfbi.kfbi_profile_enable(dom, True)
@@ -397,6 +418,7 @@ def main():
                             "refinements_per_step": float(np.mean(mref)),
                             "grid_solve": "fp32", "refinement": "fp64",
                             "rel_diff_vs_fp64_after_steps": mixed_err},
+        "solvers": rich,
         "batched": batched,
         "serving": served,
         "cpu_baseline": cpu,
