@@ -790,8 +790,21 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     }
     if (tid <= j) sgv[tid] = g[tid];
     const int nst = j + 1 < nvl ? j + 1 : nvl;
-    for (int q = tid; q < nst * Nb; q += kGmThreads) sV[q] = V[q];
+    // stage the basis: eight loads in flight per thread (clamped, in
+    // bounds), then the LDS writes, so the copy costs about one memory
+    // round trip rather than one per element
     for (int k = tid; k < Nb; k += kGmThreads) sw[k] = kv[k];
+    {
+        const int total = nst * Nb;
+        for (int q0 = tid; q0 < total; q0 += 8 * kGmThreads) {
+            T v8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v8[u] = V[min(q0 + u * kGmThreads, total - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u * kGmThreads < total) sV[q0 + u * kGmThreads] = v8[u];
+        }
+    }
     __syncthreads();
     T wl[EPT];
 #pragma unroll
@@ -1491,6 +1504,7 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     GmPtrs P = gm_layout(d, 64);
     const size_t vb = (size_t)d->Nb * elem_size(d);
     KFBI_TRY(ensure_coefficients(d, kre, kim));
+    KFBI_TRY(tune_tridiag(d));
     KFBI_TRY(ensure_operators(d, kre, kim));
     if (mixed) KFBI_TRY(ensure_coefficients_low(d, kre, kim));
     // b = g - IS(f, 0).U+

@@ -911,15 +911,20 @@ struct TriShape {
     size_t lds, lds_base, stage_bytes;
 };
 
+// the largest power of two <= 4 modes whose LDS tile stays within 32 KB
+template <class T>
+int tri_default_mb(int n) {
+    int mb = 4;
+    while (mb > 1 && (size_t)n * mb * sizeof(T) > 32768) mb >>= 1;
+    return mb;
+}
+
 template <class T>
 TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0) {
     TriShape S;
     const int n = d->M - 1;
     int mb = mb_force > 0 ? mb_force : d->tri_mb;
-    if (mb <= 0) {
-        mb = 4;
-        while (mb > 1 && (size_t)n * mb * sizeof(T) > 32768) mb >>= 1;
-    }
+    if (mb <= 0) mb = tri_default_mb<T>(n);
     S.mb = mb;
     S.lanes = mb == 8 ? 32 : 64;
     S.c = 1;
@@ -1031,8 +1036,9 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
         set_error("grid too large for the tridiagonal kernel");
         return KFBI_ENOTSUP;
     }
-    // stage the sparse right-hand side in LDS when it fits
-    const bool stage = corr && S.lds + S.stage_bytes <= kTriLdsMax;
+    // stage the sparse right-hand side in LDS when it fits (unless timing
+    // found the unstaged kernel faster)
+    const bool stage = corr && S.lds + S.stage_bytes <= kTriLdsMax && d->tri_stage != 0;
     if (stage) S.lds += S.stage_bytes;
     TriLaunchOne<T, TC> L{tri_args<T>(d, rhat, corr, uhat, done), S.blocks, S.lds, d->stream};
     const int ps = prof_begin(d);
@@ -1049,6 +1055,65 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
 }
 
 }  // namespace
+
+// Times the sparse-input tridiagonal launch of this domain for 1, 2 and 4
+// modes per workgroup (64-lane mode groups: the same operations in the same
+// order for every mode) with and without LDS staging, on the domain's own
+// tables, and keeps the fastest.  Writes only the scratch transforms.
+template <class T>
+int tune_tridiag_t(kfbi_domain *d) {
+    typedef typename High<T>::type TC;
+    hipStream_t s = d->stream;
+    const int n = d->M - 1;
+    KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * sizeof(TC), s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KFBI_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        set_error("hipEventCreate failed");
+        return KFBI_EDEVICE;
+    }
+    int best_mb = tri_default_mb<T>(n), best_stage = -1, st = KFBI_OK;
+    float best = 1e30f;
+    for (int mb : {1, 2, 4}) {
+        const TriShape S = tri_shape<T>(d, true, mb);
+        if (S.c > 32 || S.lds > kTriLdsMax) continue;
+        for (int stage : {0, 1}) {
+            if (stage && S.lds + S.stage_bytes > kTriLdsMax) continue;
+            const size_t lds = S.lds + (stage ? S.stage_bytes : 0);
+            TriLaunchOne<T, TC> L{tri_args<T>(d, nullptr, d->corr, d->uhat, nullptr), S.blocks, lds, s};
+            tri_dispatch(S.mb, S.c, stage != 0, L);
+            if (hipEventRecord(e0, s) != hipSuccess) st = KFBI_EDEVICE;
+            for (int r = 0; r < 20; ++r) tri_dispatch(S.mb, S.c, stage != 0, L);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = KFBI_EDEVICE;
+            float ms = 0.f;
+            if (st == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = KFBI_EDEVICE;
+            if (st != KFBI_OK) break;
+            if (ms < best) {
+                best = ms;
+                best_mb = mb;
+                best_stage = stage ? -1 : 0;
+            }
+        }
+        if (st != KFBI_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != KFBI_OK) {
+        set_error("timing the tridiagonal launch shapes failed");
+        return st;
+    }
+    d->tri_mb = best_mb;
+    d->tri_stage = best_stage;
+    return KFBI_OK;
+}
+
+int tune_tridiag(kfbi_domain *d) {
+    if (d->tri_tuned) return KFBI_OK;
+    d->tri_tuned = true;
+    if (d->tri_mb > 0) return KFBI_OK;
+    return d->cplx ? tune_tridiag_t<cd>(d) : tune_tridiag_t<double>(d);
+}
 
 int ensure_coefficients(kfbi_domain *d, double kre, double kim) {
     if (d->coef_valid && d->coef_kre == kre && d->coef_kim == kim) return KFBI_OK;
@@ -1357,6 +1422,8 @@ int batch_blocks(const kfbi_domain *d, int kind) {
 // launch shape of the tridiagonal kernel shared by a batch class (equal M,
 // mb and c; LDS the largest over the members; staged when all fit)
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb, int stage_pref) {
+    // the static default, not a member's own timed choice, when none is given
+    if (mb <= 0) mb = low ? tri_default_mb<float>(doms[0]->M - 1) : tri_default_mb<double>(doms[0]->M - 1);
     for (int q = 0; q < n; ++q) {
         const TriShape S = low ? tri_shape<float>(doms[q], sparse, mb) : tri_shape<double>(doms[q], sparse, mb);
         if (q == 0) {

@@ -225,7 +225,10 @@ struct kfbi_domain {
     void *vec = nullptr;                // scratch boundary vectors (8*Nb)
 
     // launch shape of the tridiagonal kernel: modes per workgroup (0: default)
-    int tri_mb = 0;
+    // and LDS staging of the sparse input (-1: when it fits, 0: never), set by
+    // timing at the first solve (the candidates compute the same values)
+    int tri_mb = 0, tri_stage = -1;
+    bool tri_tuned = false;
 
     // mixed precision (FP32 / complex64 grid solve), allocated on first use
     void *uhat32 = nullptr;
@@ -599,6 +602,7 @@ void batch_destroy(kfbi_batch *b);
 // device bytes of the tables a domain allocates on first use, while not yet allocated
 size_t operators_bytes_pending(const kfbi_domain *d);
 size_t low_tables_bytes_pending(const kfbi_domain *d);
+int tune_tridiag(kfbi_domain *d);
 int batch_size(const kfbi_batch *b);
 kfbi_domain *batch_domain(const kfbi_batch *b, int q);
 int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows);
