@@ -360,11 +360,16 @@ int kfbi_profile_read(kfbi_domain *dom, kfbi_kernel_prof *out);
  * corrections of the last solve's density -> mode-space solution, the form
  * used in every matrix-vector product), KFBI_K_TRIDIAG_DENSE (dense right-hand side ->
  * mode-space solution) or KFBI_K_EVAL_NODES (mode-space solution -> stencil
- * values).  Needs a completed solve on the domain (it reuses the last
- * kappa's coefficients and the last solve's data); overwrites the domain's
- * internal scratch only.  Blocks until the launches have finished.
+ * values), KFBI_K_CORRECTIONS (the corrections of the last solve's density
+ * by the merged per-kappa operator, as in every matrix-vector product) or
+ * KFBI_K_ARNOLDI (the GMRES control kernel: the same Arnoldi
+ * step on column min(5, last column) of the last solve's basis, repeated in
+ * a replay mode that leaves the control block as it was).  Needs a completed solve on the domain (it reuses
+ * the last kappa's coefficients and the last solve's data); overwrites the
+ * domain's internal scratch only.  Blocks until the launches have finished.
  * Errors: KFBI_EINVAL (null pointer, reps outside 1..100000, other kind, no
- * solve yet). */
+ * solve yet), KFBI_ENOTSUP (corrections or control kernel of a domain
+ * without the device-driven schedule). */
 int kfbi_profile_replay(kfbi_domain *dom, int32_t kind, int32_t reps, double *avg_ms,
                         double *bytes_per_launch);
 

@@ -303,9 +303,15 @@ int kfbi_batch_tuning(const kfbi_batch *b, int32_t cap, int32_t *rows, double *u
 int kfbi_profile_replay(kfbi_domain *d, int32_t kind, int32_t reps, double *avg_ms, double *bytes_per_launch) {
     if (!d || !avg_ms || !bytes_per_launch) { set_error("null argument"); return KFBI_EINVAL; }
     if (reps < 1 || reps > 100000) { set_error("reps must be in 1..100000"); return KFBI_EINVAL; }
-    if (kind != KFBI_K_TRIDIAG_SPARSE && kind != KFBI_K_TRIDIAG_DENSE && kind != KFBI_K_EVAL_NODES) {
-        set_error("replay supports the tridiagonal and stencil-evaluation kernels only");
+    if (kind == KFBI_K_ARNOLDI) return replay_slot(d, reps, avg_ms, bytes_per_launch);
+    if (kind != KFBI_K_TRIDIAG_SPARSE && kind != KFBI_K_TRIDIAG_DENSE && kind != KFBI_K_EVAL_NODES &&
+        kind != KFBI_K_CORRECTIONS) {
+        set_error("replay supports the tridiagonal, stencil-evaluation, corrections and control kernels only");
         return KFBI_EINVAL;
+    }
+    if (kind == KFBI_K_CORRECTIONS && !d->op_merged) {
+        set_error("the corrections replay needs the merged operators of the device-driven schedule");
+        return KFBI_ENOTSUP;
     }
     if (!d->coef_valid) { set_error("no solve has run on this domain"); return KFBI_EINVAL; }
     const void *phi = gmres_last_density(d);
@@ -316,6 +322,7 @@ int kfbi_profile_replay(kfbi_domain *d, int32_t kind, int32_t reps, double *avg_
     auto launch = [&]() -> int {
         if (kind == KFBI_K_TRIDIAG_SPARSE) return tridiag_solve(d, nullptr, d->corr, d->uhat);
         if (kind == KFBI_K_TRIDIAG_DENSE) return tridiag_solve(d, d->rhat, d->corr, d->uhat);
+        if (kind == KFBI_K_CORRECTIONS) return corrections_of_density(d, phi, d->corr, nullptr);
         return eval_stencil_nodes(d, d->uhat, d->ust);
     };
     // algorithmic bytes of one launch, through the profiler's own accounting

@@ -703,6 +703,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_init(GmInitArgs<T> A) {
 template <class T>
 struct SlotArgs {
     const int *off;  // nonzero: member not solved in this call (batched solves)
+    int replay;      // nonzero: timing replay, the control block is not advanced
     GmCtl *ctl;
     GmMirror *mir;
     T *V, *H, *g;
@@ -934,14 +935,16 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
         g[j] = gj * cg;
         sgv[j] = gj * cg;
         const double resid = absv(gj1);
-        ctl->resid = resid;
         const int it = c.iters + 1;
-        ctl->iters = it;
-        ctl->j = j + 1;
         const bool conv = resid <= c.thresh;
         const int converged = (conv && c.eta == 0.0) ? 1 : 0;
-        ctl->converged = converged;
-        if (hn == 0.0) ctl->breakdown = 1;
+        if (!A.replay) {
+            ctl->resid = resid;
+            ctl->iters = it;
+            ctl->j = j + 1;
+            ctl->converged = converged;
+            if (hn == 0.0) ctl->breakdown = 1;
+        }
         const bool end = (c.fixed == 0 && conv) || it >= limit || j + 1 >= m || hn == 0.0;
         sflag = end ? 1 : 0;
         sconv = converged;
@@ -951,7 +954,7 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     if (tid <= j + 1) H[(size_t)tid * m + j] = hcol[tid];
     if (!sflag) {
         // next Arnoldi step on v_{j+1} (already in vcur)
-        if (tid == 0) {
+        if (tid == 0 && !A.replay) {
             ctl->slot = c.slot + 1;
             gm_set_state(ctl, kStIter);
             gm_publish(ctl, mir);
@@ -1309,6 +1312,7 @@ template <class T>
 SlotArgs<T> slot_args(GmPtrs &P, GmMirror *mir, int Nb, int m, int nvl) {
     SlotArgs<T> A;
     A.off = nullptr;
+    A.replay = 0;
     A.ctl = P.ctl;
     A.mir = mir;
     A.V = (T *)P.V;
@@ -1333,13 +1337,15 @@ static bool slots_supported(kfbi_domain *d, int m) {
 }
 
 template <class T>
-static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index, hipStream_t s) {
+static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index, hipStream_t s,
+                       bool replay = false) {
     int nvl;
     const size_t lds = slot_lds<T>(Nb, m, &nvl);
     const int ept = (Nb + kGmThreads - 1) / kGmThreads;
     GmMirror *mir = (GmMirror *)d->mirror_dev;
     const int ps = prof_begin(d);
-    const SlotArgs<T> A = slot_args<T>(P, mir, Nb, m, nvl);
+    SlotArgs<T> A = slot_args<T>(P, mir, Nb, m, nvl);
+    A.replay = replay ? 1 : 0;
 #define KFBI_SLOT(E) k_gm_slot<T, E><<<1, kGmThreads, lds, s>>>(A)
     if (ept <= 1) KFBI_SLOT(1);
     else if (ept <= 2) KFBI_SLOT(2);
@@ -1448,6 +1454,82 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, 
     *conv_out = mh->converged;
     *cycles_out = mh->cycles;
     return KFBI_OK;
+}
+
+// Replay timing of the control kernel: back-to-back Arnoldi steps on column
+// j_r = min(5, last column of the last solve) of the last solve's basis, in
+// replay mode (the control block set once to a step at j_r that cannot stop,
+// and not advanced by the launches).  The basis columns above j_r, H, the
+// rotations, g and vcur are overwritten (every solve starts by rewriting
+// them); the density x and the control block are left as the last solve
+// ended.
+template <class T>
+int replay_slot_t(kfbi_domain *d, int reps, double *avg_ms, double *bytes) {
+    hipStream_t s = d->stream;
+    GmPtrs P = gm_layout(d, 64);
+    const int Nb = d->Nb;
+    GmCtl c;
+    KFBI_HIP(hipMemcpyAsync(&c, P.ctl, sizeof(GmCtl), hipMemcpyDeviceToHost, s));
+    KFBI_HIP(hipStreamSynchronize(s));
+    const int m = c.m > 1 ? c.m : 2;
+    int jr = c.j - 1 < 5 ? c.j - 1 : 5;
+    if (jr < 0) jr = 0;
+    if (jr > m - 2) jr = m - 2;
+    GmCtl r = c;
+    r.state = kStIter;
+    r.j = jr;
+    r.iters = 0;
+    r.fixed = 0;
+    r.max_iter = 1 << 30;
+    r.thresh = -1.0;  // never converged: the step cannot end the cycle
+    r.eta = 0.0;
+    r.mixed = 0;
+    r.slot = 0;
+    r.skip64 = 0;
+    r.skip32 = 1;
+    r.skip_tail = 1;
+    KFBI_HIP(hipMemcpyAsync(P.ctl, &r, sizeof(GmCtl), hipMemcpyHostToDevice, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = KFBI_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = KFBI_EDEVICE;
+    const bool was_on = d->prof_on;
+    d->prof_on = false;
+    if (rc == KFBI_OK) rc = launch_slot<T>(d, P, Nb, m, jr + 1, s, true);  // warm-up
+    if (rc == KFBI_OK && hipEventRecord(e0, s) != hipSuccess) rc = KFBI_EDEVICE;
+    for (int q = 0; q < reps && rc == KFBI_OK; ++q) rc = launch_slot<T>(d, P, Nb, m, jr + 1, s, true);
+    if (rc == KFBI_OK && hipEventRecord(e1, s) != hipSuccess) rc = KFBI_EDEVICE;
+    if (rc == KFBI_OK && hipEventSynchronize(e1) != hipSuccess) rc = KFBI_EDEVICE;
+    float ms = 0.f;
+    if (rc == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = KFBI_EDEVICE;
+    d->prof_on = was_on;
+    // leave the control block as the last solve ended
+    if (hipMemcpyAsync(P.ctl, &c, sizeof(GmCtl), hipMemcpyHostToDevice, s) != hipSuccess && rc == KFBI_OK)
+        rc = KFBI_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess && rc == KFBI_OK) rc = KFBI_EDEVICE;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (rc != KFBI_OK) {
+        set_error("replay of the control kernel failed");
+        return rc;
+    }
+    *avg_ms = (double)ms / reps;
+    // the algorithmic bytes of launch_slot's accounting at column jr
+    const double es = (double)sizeof(T);
+    *bytes = (double)Nb * es + 2.0 * (jr + 1) * Nb * es + 2.0 * Nb * es;
+    return KFBI_OK;
+}
+
+int replay_slot(kfbi_domain *d, int reps, double *avg_ms, double *bytes) {
+    if (!d->gm || !d->mirror_dev) {
+        set_error("no device-driven solve has run on this domain");
+        return KFBI_EINVAL;
+    }
+    const bool slots = d->cplx ? slots_supported<cd>(d, 50) : slots_supported<double>(d, 50);
+    if (!slots) {
+        set_error("the domain does not use the device-driven schedule");
+        return KFBI_ENOTSUP;
+    }
+    return d->cplx ? replay_slot_t<cd>(d, reps, avg_ms, bytes) : replay_slot_t<double>(d, reps, avg_ms, bytes);
 }
 
 int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,

@@ -603,6 +603,7 @@ void batch_destroy(kfbi_batch *b);
 size_t operators_bytes_pending(const kfbi_domain *d);
 size_t low_tables_bytes_pending(const kfbi_domain *d);
 int tune_tridiag(kfbi_domain *d);
+int replay_slot(kfbi_domain *d, int reps, double *avg_ms, double *bytes);
 int batch_size(const kfbi_batch *b);
 kfbi_domain *batch_domain(const kfbi_batch *b, int q);
 int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows);

@@ -217,3 +217,31 @@ def test_async_steps_match_synchronous_steps():
             kfbi.kfbi_domain_destroy(h)
     assert out[0][1] == out[1][1]
     assert np.array_equal(out[0][0], out[1][0])
+
+
+def test_replay_timing_leaves_steps_unchanged():
+    """kfbi_profile_replay of the grid-solve and control kernels returns a
+    positive launch time and byte count, and the steps after it equal the
+    steps of a stepper that was never replayed, bit for bit."""
+    desc = W.domain_c2_wave(128)
+    tau = 2.0 / desc["M"]
+    runs = []
+    for replay in (False, True):
+        h, s, gx, gy = _wave_stepper(desc, tau)
+        try:
+            u = empty_grid(desc["M"])
+            g = [dev(mf.wave_u(gx, gy, (n + 1) * tau)) for n in range(4)]
+            outs = []
+            for n in range(4):
+                kfbi.kfbi_step_wave(s, g[n], u)
+                outs.append(host(u).copy())
+                if replay and n == 1:
+                    for kind in ("tridiag_sparse", "tridiag_dense", "eval_nodes", "corrections", "arnoldi"):
+                        ms, by = kfbi.kfbi_profile_replay(h, kind, 20)
+                        assert 0 < ms < 1.0 and by > 0, kind
+            runs.append(outs)
+            kfbi.kfbi_stepper_destroy(s)
+        finally:
+            kfbi.kfbi_domain_destroy(h)
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
