@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the kernel at its current version, from two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
 # on a 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); the
-# counts and the commands are in profiles/tridiag_wave512_fp64_hbm_traffic.md.
+# counts and the commands are in profiles/*_wave512_fp64_hbm_traffic.md.
 # Kernels not listed (or changed since they were counted) report null.
-TRAFFIC = {"tridiag_sparse": 2588265.0}
+TRAFFIC = {"tridiag_sparse": 2676719.0, "arnoldi": 64186.0}
 
 
 def parse():
