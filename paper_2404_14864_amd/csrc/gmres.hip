@@ -64,18 +64,51 @@ constexpr int kGmThreads = 512;
 constexpr size_t kGmIterLds = 131072;
 
 
-template <class T> struct WS;
-template <> struct WS<double> {
-    __device__ static double xr(double v, int o) { return __shfl_xor(v, o, 64); }
-};
-template <> struct WS<cd> {
-    __device__ static cd xr(cd v, int o) { return make_cd(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64)); }
-};
+// Cross-lane exchanges of the wavefront reductions on the VALU (gfx950),
+// not through the LDS unit: the partner of lane l differs from l in bit B,
+// and for the row mirrors also in lower bits, which the later levels of a
+// reduction cover anyway.
+//   B = 5, 4: permlane32 / permlane16 swaps (l ^ 32, l ^ 16);
+//   B = 3, 2: row mirror (i -> 15 - i in each row of 16), half-row mirror
+//             (i -> 7 - i in each half row);
+//   B = 1, 0: quad permutations (l ^ 2, l ^ 1).
+template <int B>
+__device__ __forceinline__ unsigned xl32(unsigned u) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (B == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return lane < 32 ? r[1] : r[0];
+    } else if constexpr (B == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else if constexpr (B == 3) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x140, 0xf, 0xf, false);
+    } else if constexpr (B == 2) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x141, 0xf, 0xf, false);
+    } else if constexpr (B == 1) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x4E, 0xf, 0xf, false);
+    } else {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xf, 0xf, false);
+    }
+}
+template <int B>
+__device__ __forceinline__ double xl(double v) {
+    return __hiloint2double((int)xl32<B>((unsigned)__double2hiint(v)), (int)xl32<B>((unsigned)__double2loint(v)));
+}
+template <int B>
+__device__ __forceinline__ cd xl(cd v) {
+    return make_cd(xl<B>(v.x), xl<B>(v.y));
+}
 
+// sum over the wavefront, in every lane (all 64 lanes active)
 template <class T>
 __device__ inline T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += WS<T>::xr(v, o);
+    v += xl<5>(v);
+    v += xl<4>(v);
+    v += xl<3>(v);
+    v += xl<2>(v);
+    v += xl<1>(v);
+    v += xl<0>(v);
     return v;
 }
 
@@ -89,30 +122,30 @@ __device__ inline T wave_sum16(T (&v)[16], int lane) {
         const bool hi = lane & 32;
         const T send = hi ? v[i] : v[i + 8];
         const T keep = hi ? v[i + 8] : v[i];
-        v[i] = keep + WS<T>::xr(send, 32);
+        v[i] = keep + xl<5>(send);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const bool hi = lane & 16;
         const T send = hi ? v[i] : v[i + 4];
         const T keep = hi ? v[i + 4] : v[i];
-        v[i] = keep + WS<T>::xr(send, 16);
+        v[i] = keep + xl<4>(send);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const bool hi = lane & 8;
         const T send = hi ? v[i] : v[i + 2];
         const T keep = hi ? v[i + 2] : v[i];
-        v[i] = keep + WS<T>::xr(send, 8);
+        v[i] = keep + xl<3>(send);
     }
     {
         const bool hi = lane & 4;
         const T send = hi ? v[0] : v[1];
         const T keep = hi ? v[1] : v[0];
-        v[0] = keep + WS<T>::xr(send, 4);
+        v[0] = keep + xl<2>(send);
     }
-    v[0] += WS<T>::xr(v[0], 2);
-    v[0] += WS<T>::xr(v[0], 1);
+    v[0] += xl<1>(v[0]);
+    v[0] += xl<0>(v[0]);
     return v[0];
 }
 
