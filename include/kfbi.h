@@ -198,6 +198,9 @@ int kfbi_interface_apply(kfbi_domain *dom, double kappa_re, double kappa_im,
  * Dirichlet data at the collocation points; u_grid_out the grid solution
  * (meaningful at inside nodes); phi_inout (nullable) the warm start on
  * entry and the density on exit.  opts nullable (defaults), stats nullable.
+ * The Krylov vectors of one domain are held by one workgroup of 512 threads,
+ * 16 entries each: solves (and steps) need Nb <= 8192 and return
+ * KFBI_ENOTSUP above it.
  * Returns ENOCONV when max_iter is reached first (outputs still written). */
 int kfbi_helmholtz_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
                          const void *f_grid, const void *f_gamma,
