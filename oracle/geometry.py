@@ -267,6 +267,12 @@ class Domain:
         e0[:, 0] = 1.0
         # U+(z) = e0^T A^{-1} U~  ->  weights w solve A^T w = e0
         self.st_weight = np.linalg.solve(np.transpose(A, (0, 2, 1)), e0[:, :, None])[:, :, 0]
+        # the interior normal derivative n . (U_x+, U_y+) = (nx e1 + ny e2)^T
+        # A^{-1} U~ (rows 1 and 2 of the same expansion; the Neumann problem)
+        en = np.zeros((Nb, 6))
+        en[:, 1] = self.colloc["nx"]
+        en[:, 2] = self.colloc["ny"]
+        self.st_weight_n = np.linalg.solve(np.transpose(A, (0, 2, 1)), en[:, :, None])[:, :, 0]
         del M, h
 
     def counts(self):

@@ -9,7 +9,9 @@ the box boundary,
   b. correction of the five-point equations at irregular nodes (section
      3.2.4, C^+/C^- terms) and the grid solve (eq. 3.31),
   c. extraction of the interior limit U^+ at the collocation points
-     (section 3.2.6, eq. 3.36).
+     (section 3.2.6, eq. 3.36), and for the Neumann problem of the interior
+     normal derivative n . grad U^+ from the same expansion (its first-order
+     coefficients).
 
 Readings taken:
   R8  correction at node P for a crossing edge (P, Q) with intersection X on
@@ -148,24 +150,27 @@ def corrections(dom, je):
     return C.reshape(M + 1, M + 1)
 
 
-def extract(dom, U, jz):
+def extract(dom, U, jz, weights=None):
     """U^+ at the collocation points from the grid solution U and the jumps
-    at the collocation points (section 3.2.6)."""
+    at the collocation points (section 3.2.6).  weights: the six-point
+    weights (default: those of U^+; dom.st_weight_n gives the interior
+    normal derivative from the same corrected values)."""
     xi, eta = dom.st_xi, dom.st_eta
     J = (jz["u"][:, None] + jz["ux"][:, None] * xi + jz["uy"][:, None] * eta
          + 0.5 * jz["uxx"][:, None] * xi * xi + jz["uxy"][:, None] * xi * eta
          + 0.5 * jz["uyy"][:, None] * eta * eta)
     Ut = U.ravel()[dom.st_node] + np.where(dom.st_outside, J, 0.0)
-    return np.sum(dom.st_weight * Ut, axis=1)
+    return np.sum((dom.st_weight if weights is None else weights) * Ut, axis=1)
 
 
-def interface_solve(dom, kappa, f_grid, f_gamma, phi, psi=None):
+def interface_solve(dom, kappa, f_grid, f_gamma, phi, psi=None, normal=False):
     """Solve the interface problem (3.30) with F = f~, [u] = phi, [u_n] = psi.
 
     f_grid: (M+1)x(M+1) array or None (f = 0); f_gamma: trace of f on Gamma at
     the collocation points (None when f = 0).  Returns (U, Uplus): the grid
     solution on all (M+1)^2 nodes (zero on the box boundary) and the interior
-    limit U^+ at the collocation points.
+    limit U^+ at the collocation points; with normal=True also the interior
+    normal derivative dU^+/dn there (U, Uplus, Unplus).
     """
     M, h = dom.M, dom.h
     cplx = any(np.iscomplexobj(v) for v in (kappa, f_grid, f_gamma, phi, psi)
@@ -183,4 +188,6 @@ def interface_solve(dom, kappa, f_grid, f_gamma, phi, psi=None):
         R = R + np.where(dom.inside, f_grid, 0.0)          # f~ (R23)
     U = np.zeros((M + 1, M + 1), dtype=dtype)
     U[1:-1, 1:-1] = boxsolve.solve(R[1:-1, 1:-1], h, kappa)
+    if normal:
+        return U, extract(dom, U, jz), extract(dom, U, jz, dom.st_weight_n)
     return U, extract(dom, U, jz)

@@ -1,10 +1,12 @@
 """Oracle time steppers (TEST INFRASTRUCTURE ONLY).
 
-Each implicit step is one modified-Helmholtz Dirichlet solve (oracle.bie)
-whose right-hand side comes from a recurrence, so that no discrete
-Laplacian of the numerical solution is ever formed (section 3.1).  The same
-recurrence is carried on Gamma with u = g there (reading R11), giving the
-trace of f needed by the jump conditions.
+Each implicit step is one modified-Helmholtz solve (oracle.bie), Dirichlet
+or Neumann, whose right-hand side comes from a recurrence, so that no
+discrete Laplacian of the numerical solution is ever formed (section 3.1).
+The same recurrence is carried on Gamma (reading R11), giving the trace of f
+needed by the jump conditions; it takes u = g there for the Dirichlet
+problem and the extracted interior limit U+ for the Neumann problem (g is
+then du/dn).
 
 Heat, Crank-Nicolson (eqs. 3.1-3.4, with a source s and diffusivity c,
 reading R13):  kappa = 2c/tau,
@@ -30,33 +32,46 @@ after them; i u_t = lap u + v u + w|u|^2 u as in eq. 2.2; reading R16):
 
 import numpy as np
 
-from .bie import helmholtz_solve
+from .bie import helmholtz_solve, neumann_solve
 
 
 class _Base:
-    def __init__(self, dom, tol, restart, max_iter):
+    def __init__(self, dom, tol, restart, max_iter, bc="dirichlet"):
+        if bc not in ("dirichlet", "neumann"):
+            raise ValueError("bc must be 'dirichlet' or 'neumann'")
         self.dom = dom
         self.tol, self.restart, self.max_iter = tol, restart, max_iter
+        self.bc = bc
         self.phi = None
         self.n = 0
         self.last_stats = None
 
     def _solve(self, f_grid, f_gamma, g, fixed_iters=None):
-        U, phi, st = helmholtz_solve(self.dom, self.kappa, f_grid, f_gamma, g,
-                                     phi0=self.phi, tol=self.tol,
-                                     restart=self.restart,
-                                     max_iter=self.max_iter,
-                                     fixed_iters=fixed_iters)
-        self.phi = phi
+        """One implicit solve.  Returns (U, trace of u on Gamma): the trace is
+        g for the Dirichlet problem and the extracted U+ for the Neumann one
+        (g is then du/dn)."""
+        if self.bc == "neumann":
+            U, psi, trace, st = neumann_solve(self.dom, self.kappa, f_grid, f_gamma, g, psi0=self.phi,
+                                              tol=self.tol, restart=self.restart, max_iter=self.max_iter,
+                                              fixed_iters=fixed_iters)
+            self.phi = psi
+        else:
+            U, phi, st = helmholtz_solve(self.dom, self.kappa, f_grid, f_gamma, g,
+                                         phi0=self.phi, tol=self.tol,
+                                         restart=self.restart,
+                                         max_iter=self.max_iter,
+                                         fixed_iters=fixed_iters)
+            self.phi = phi
+            trace = np.asarray(g)
         self.last_stats = st
         self.n += 1
-        return U
+        return U, trace
 
 
 class HeatStepper(_Base):
     def __init__(self, dom, tau, u0, lap_u0, u0_gamma, lap_u0_gamma, c=1.0,
-                 tol=1e-10, restart=50, max_iter=500):
-        super().__init__(dom, tol, restart, max_iter)
+                 tol=1e-10, restart=50, max_iter=500, bc="dirichlet"):
+        super().__init__(dom, tol, restart, max_iter, bc)
         self.tau = tau
         self.kappa = 2.0 * c / tau
         self.G = self.kappa * np.asarray(u0) + lap_u0
@@ -65,17 +80,17 @@ class HeatStepper(_Base):
     def step(self, g_next, src_grid=None, src_gamma=None, fixed_iters=None):
         F = self.G + (0.0 if src_grid is None else src_grid)
         Fg = self.G_gamma + (0.0 if src_gamma is None else src_gamma)
-        U = self._solve(-F, -Fg, g_next, fixed_iters)
+        U, tr = self._solve(-F, -Fg, g_next, fixed_iters)
         self.G = 2.0 * self.kappa * U - F
-        self.G_gamma = 2.0 * self.kappa * np.asarray(g_next) - Fg
+        self.G_gamma = 2.0 * self.kappa * tr - Fg
         return U
 
 
 class WaveStepper(_Base):
     def __init__(self, dom, tau, u0, lap_u0, u0_gamma, lap_u0_gamma,
                  um1, lap_um1, um1_gamma, lap_um1_gamma, theta=0.25,
-                 tol=1e-10, restart=50, max_iter=500):
-        super().__init__(dom, tol, restart, max_iter)
+                 tol=1e-10, restart=50, max_iter=500, bc="dirichlet"):
+        super().__init__(dom, tol, restart, max_iter, bc)
         self.tau, self.theta = tau, theta
         k = 1.0 / (theta * tau * tau)
         self.kappa = k
@@ -88,9 +103,9 @@ class WaveStepper(_Base):
     def step(self, g_next, fixed_iters=None):
         th, k = self.theta, self.kappa
         c1 = (1.0 - 2.0 * th) / th
-        U = self._solve(-self.F1, -self.F1_gamma, g_next, fixed_iters)
+        U, tr = self._solve(-self.F1, -self.F1_gamma, g_next, fixed_iters)
         F2 = (k / th) * U - c1 * self.F1 - self.F0
-        F2g = (k / th) * np.asarray(g_next) - c1 * self.F1_gamma - self.F0_gamma
+        F2g = (k / th) * tr - c1 * self.F1_gamma - self.F0_gamma
         self.F0, self.F1 = self.F1, F2
         self.F0_gamma, self.F1_gamma = self.F1_gamma, F2g
         return U
@@ -98,8 +113,8 @@ class WaveStepper(_Base):
 
 class SchrodingerStepper(_Base):
     def __init__(self, dom, tau, u0, lap_u0, u0_gamma, lap_u0_gamma,
-                 v_grid, v_gamma, w=0.0, tol=1e-10, restart=50, max_iter=500):
-        super().__init__(dom, tol, restart, max_iter)
+                 v_grid, v_gamma, w=0.0, tol=1e-10, restart=50, max_iter=500, bc="dirichlet"):
+        super().__init__(dom, tol, restart, max_iter, bc)
         self.tau, self.w = tau, w
         self.kappa = 2j / tau
         self.v, self.v_gamma = v_grid, v_gamma
@@ -115,8 +130,8 @@ class SchrodingerStepper(_Base):
         uss = self._b_step(self.ustar, self.v)
         uss_g = self._b_step(self.ustar_gamma, self.v_gamma)
         g_next = np.asarray(g_next, dtype=np.complex128)
-        U = self._solve(-self.kappa * uss, -self.kappa * uss_g, g_next,
-                        fixed_iters)
+        U, tr = self._solve(-self.kappa * uss, -self.kappa * uss_g, g_next,
+                            fixed_iters)
         self.ustar = 2.0 * U - uss
-        self.ustar_gamma = 2.0 * g_next - uss_g
+        self.ustar_gamma = 2.0 * tr - uss_g
         return U

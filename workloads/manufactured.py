@@ -1,7 +1,9 @@
 """Manufactured exact solutions and initial data (problem data only).
 
 Every function takes coordinate arrays x, y (any broadcastable shape) and
-returns float64 / complex128 arrays.  Laplacians are the analytic ones.
+returns float64 / complex128 arrays.  Laplacians and gradients (the
+`*_grad` functions, pairs (u_x, u_y) for Neumann data) are the analytic
+ones.
 """
 
 import numpy as np
@@ -19,6 +21,12 @@ def heat_lap(x, y, t):
     return -2.0 * PI * PI * heat_u(x, y, t)
 
 
+def heat_grad(x, y, t):
+    """(u_x, u_y), for Neumann data n . grad u."""
+    e = np.exp(-t)
+    return (PI * e * np.cos(PI * x) * np.cos(PI * y), -PI * e * np.sin(PI * x) * np.sin(PI * y))
+
+
 def heat_src(x, y, t):
     """s = u_t - lap u = (2 pi^2 - 1) u."""
     return (2.0 * PI * PI - 1.0) * heat_u(x, y, t)
@@ -33,6 +41,11 @@ def wave_lap(x, y, t):
     return -2.0 * PI * PI * wave_u(x, y, t)
 
 
+def wave_grad(x, y, t):
+    c = np.cos(SQRT2 * PI * t)
+    return (PI * c * np.cos(PI * x) * np.sin(PI * y), PI * c * np.sin(PI * x) * np.cos(PI * y))
+
+
 # ---- Schroedinger, i u_t = lap u + V u (w = 0) ------------------------------
 def schr_free_u(x, y, t):
     """V = 0: u = exp(i 2 pi^2 t) sin(pi x) sin(pi y) solves i u_t = lap u."""
@@ -41,6 +54,11 @@ def schr_free_u(x, y, t):
 
 def schr_free_lap(x, y, t):
     return -2.0 * PI * PI * schr_free_u(x, y, t)
+
+
+def schr_free_grad(x, y, t):
+    e = np.exp(1j * 2.0 * PI * PI * t)
+    return (PI * e * np.cos(PI * x) * np.sin(PI * y), PI * e * np.sin(PI * x) * np.cos(PI * y))
 
 
 def packet_u0(x, y, width=0.1, k=(20.0, 0.0)):
@@ -66,8 +84,17 @@ def helm_exp_u(x, y, a, b):
     return np.exp(a * x + b * y)
 
 
+def helm_exp_grad(x, y, a, b):
+    u = np.exp(a * x + b * y)
+    return (a * u, b * u)
+
+
 def helm_trig_u(x, y):
     return np.sin(PI * x) * np.cos(PI * y)
+
+
+def helm_trig_grad(x, y):
+    return (PI * np.cos(PI * x) * np.cos(PI * y), -PI * np.sin(PI * x) * np.sin(PI * y))
 
 
 def helm_trig_f(x, y, kappa):
