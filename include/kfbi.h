@@ -59,6 +59,7 @@ typedef enum { KFBI_CURVE_DISK = 0, KFBI_CURVE_ELLIPSE = 1, KFBI_CURVE_STAR = 2 
 typedef enum { KFBI_REAL = 0, KFBI_COMPLEX = 1 } kfbi_scalar;
 typedef enum { KFBI_PREC_FP64 = 0, KFBI_PREC_MIXED = 1 } kfbi_precision;
 typedef enum { KFBI_HEAT = 0, KFBI_WAVE = 1, KFBI_SCHRODINGER = 2 } kfbi_equation;
+typedef enum { KFBI_BC_DIRICHLET = 0, KFBI_BC_NEUMANN = 1 } kfbi_boundary_condition;
 
 /* Domain description (section 3.2.4 grid, Procedure 1 of section 3.3).
  * Curves, counter-clockwise in theta in [0, 2 pi):
@@ -168,6 +169,11 @@ int kfbi_domain_copy_classification(const kfbi_domain *dom, uint8_t *host_out);
 /* Collocation points z_k, host array of 2*Nb doubles (x0, y0, x1, y1, ...). */
 int kfbi_domain_copy_boundary(const kfbi_domain *dom, double *host_out);
 
+/* Outward unit normals n = (t_y, -t_x) at the collocation points (section
+ * 3.2.5; the direction of du/dn in kfbi_neumann_solve), host array of 2*Nb
+ * doubles (nx0, ny0, nx1, ny1, ...). */
+int kfbi_domain_copy_normals(const kfbi_domain *dom, double *host_out);
+
 /* Crossed edges: host arrays of n_edges entries each.  pq[2e], pq[2e+1] are
  * the linear indices of the edge's inside and outside node; xyt[3e..3e+2]
  * are the intersection (x, y) and its curve parameter theta. */
@@ -207,6 +213,26 @@ int kfbi_helmholtz_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
                          const void *g_gamma, void *u_grid_out, void *phi_inout,
                          const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
+/* Solve lap u - kappa u = f in Omega, du/dn = g_N on Gamma (n the outward
+ * normal) through the second-kind equation (3.19) for the density psi of
+ * u = Yf - V psi (eq. 3.20).  Each application of its operator is one
+ * interface problem (3.29) ([u] = 0, [u_n] = psi, the table after eq. 3.30)
+ * read out as the interior normal derivative at the collocation points: the
+ * first-order coefficients of the six-point fit of section 3.2.6.
+ * gn_gamma: du/dn at the collocation points; f_grid / f_gamma as for
+ * kfbi_helmholtz_solve; u_grid_out the grid solution (inside nodes);
+ * psi_inout (nullable) warm start on entry and density on exit; trace_out
+ * (nullable) receives U+, the solution's interior limit at the collocation
+ * points.  opts and stats as for kfbi_helmholtz_solve (GMRES or the
+ * Richardson form of eq. 3.22; FP64 or mixed precision).  kappa = 0 is
+ * refused (KFBI_EINVAL: the solution is then not unique); KFBI_ENOTSUP when
+ * Nb exceeds 8192 (real) or 4096 (complex) or the domain's correction
+ * windows cannot be merged.  Returns ENOCONV as kfbi_helmholtz_solve. */
+int kfbi_neumann_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
+                       const void *f_grid, const void *f_gamma,
+                       const void *gn_gamma, void *u_grid_out, void *psi_inout,
+                       void *trace_out, const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+
 /* Time-step parameters (section 3.1).
  *   HEAT: c u_t = lap u + s; Crank-Nicolson, kappa = 2c/tau (c = diffusivity,
  *         0 means 1).
@@ -215,7 +241,10 @@ int kfbi_helmholtz_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
  *   SCHRODINGER: i u_t = lap u + v u + w |u|^2 u (eq. 2.2); Strang splitting,
  *         kappa = 2i/tau; v_grid / v_gamma are device arrays (float64) of the
  *         potential on the grid and at the collocation points (nullable: 0).
- * The domain must be REAL for HEAT and WAVE, COMPLEX for SCHRODINGER. */
+ * The domain must be REAL for HEAT and WAVE, COMPLEX for SCHRODINGER.
+ * bc: KFBI_BC_DIRICHLET (g of each step is u on Gamma) or KFBI_BC_NEUMANN
+ * (g is du/dn; each step solves eq. 3.19 and carries the recurrence on
+ * Gamma with the extracted trace U+ of the new solution). */
 typedef struct {
     double tau;
     double theta;
@@ -223,6 +252,8 @@ typedef struct {
     double w;
     const void *v_grid;
     const void *v_gamma;
+    int32_t bc;
+    int32_t pad;
 } kfbi_step_params;
 
 int kfbi_stepper_create(kfbi_domain *dom, int32_t equation,
@@ -242,19 +273,20 @@ int kfbi_stepper_init(kfbi_stepper *st, const void *u0_grid, const void *lap_u0_
  * (heat: G, eq. 3.4; wave: F^{n+1} and F^n, the recurrence after eq. 3.7;
  * Schroedinger: u*, the algorithm after eq. 3.12) plus the density of the
  * last solve, which warm-starts the next one.  The blob is opaque: a 64-byte
- * header (equation, M, Nb, scalar type, tau, kappa) followed by those arrays
+ * header (equation, M, Nb, scalar type, boundary condition, tau, kappa)
+ * followed by those arrays
  * in the domain's element type.  dst / src are caller-owned device buffers
  * of at least kfbi_stepper_state_bytes() bytes.  get_state and set_state
  * synchronise the domain stream.  set_state accepts only a blob written by
- * a stepper with the same equation, grid, collocation count, scalar type and
- * kappa (else KFBI_EINVAL). */
+ * a stepper with the same equation, grid, collocation count, scalar type,
+ * boundary condition and kappa (else KFBI_EINVAL). */
 int kfbi_stepper_state_bytes(const kfbi_stepper *st, uint64_t *bytes);
 int kfbi_stepper_get_state(kfbi_stepper *st, void *dst, uint64_t bytes);
 int kfbi_stepper_set_state(kfbi_stepper *st, const void *src, uint64_t bytes);
 
 /* One Crank-Nicolson step t^n -> t^{n+1} (eqs. 3.2-3.4): g_next is u on
- * Gamma at t^{n+1}; src_grid / src_gamma (nullable) hold s^n + s^{n+1}.
- * u_grid_out receives u^{n+1}. */
+ * Gamma at t^{n+1} (du/dn for a Neumann stepper); src_grid / src_gamma
+ * (nullable) hold s^n + s^{n+1}.  u_grid_out receives u^{n+1}. */
 int kfbi_step_heat(kfbi_stepper *st, const void *g_next_gamma, const void *src_grid,
                    const void *src_gamma, void *u_grid_out,
                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
@@ -307,7 +339,8 @@ int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *
  * g_next, ... are host arrays of n entries; the results are on the batch
  * stream in stream order.  stats (n entries, zero for members not active)
  * as kfbi_batch_helmholtz.  Errors: KFBI_EINVAL (null, stepper not on the
- * member's domain, not initialised, Schroedinger stepper), KFBI_ENOCONV
+ * member's domain, not initialised, Schroedinger stepper), KFBI_ENOTSUP
+ * (a Neumann stepper: batched steps are Dirichlet only), KFBI_ENOCONV
  * (some member reached max_iter; its step still completes). */
 int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *active,
                     const void *const *g_next, const void *const *src_grid, const void *const *src_gamma,

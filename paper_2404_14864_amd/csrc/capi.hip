@@ -146,6 +146,7 @@ struct kfbi_stepper {
     void *B = nullptr, *Bg = nullptr;   // wave: F^n
     void *f = nullptr, *fg = nullptr;   // right-hand side of the current solve
     void *phi = nullptr;                // warm start / density
+    void *tr = nullptr;                 // Neumann: U+ on Gamma of the last step
 };
 
 extern "C" {
@@ -249,6 +250,10 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
         if ((s->eq != KFBI_HEAT && s->eq != KFBI_WAVE) || !s->initialized) {
             set_error("batched steps take initialised heat or wave steppers");
             return KFBI_EINVAL;
+        }
+        if (s->p.bc != KFBI_BC_DIRICHLET) {
+            set_error("batched steps take Dirichlet steppers only");
+            return KFBI_ENOTSUP;
         }
     }
     // right-hand sides of the members' solves (as kfbi_step_heat / kfbi_step_wave)
@@ -421,6 +426,18 @@ int kfbi_domain_copy_boundary(const kfbi_domain *d, double *host_out) {
     return KFBI_OK;
 }
 
+int kfbi_domain_copy_normals(const kfbi_domain *d, double *host_out) {
+    if (!d || !host_out) { set_error("null argument"); return KFBI_EINVAL; }
+    std::vector<Colloc> c(d->Nb);
+    KFBI_HIP(hipMemcpyAsync(c.data(), d->col, d->Nb * sizeof(Colloc), hipMemcpyDeviceToHost, d->stream));
+    KFBI_HIP(hipStreamSynchronize(d->stream));
+    for (int k = 0; k < d->Nb; ++k) {
+        host_out[2 * k] = c[k].fr.ty;
+        host_out[2 * k + 1] = -c[k].fr.tx;
+    }
+    return KFBI_OK;
+}
+
 int kfbi_domain_copy_edges(const kfbi_domain *d, int32_t *pq, double *xyt) {
     if (!d || !pq || !xyt) { set_error("null argument"); return KFBI_EINVAL; }
     std::vector<Edge> e(d->n_edges);
@@ -471,6 +488,19 @@ int kfbi_helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_g
     return helmholtz_solve(d, kre, kim, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
 }
 
+int kfbi_neumann_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
+                       const void *gn_gamma, void *u_grid_out, void *psi_inout, void *trace_out,
+                       const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+    if (!d || !gn_gamma) { set_error("null argument"); return KFBI_EINVAL; }
+    KFBI_TRY(check_kappa(d, kim));
+    if (kre == 0.0 && kim == 0.0) {
+        set_error("the Neumann problem needs kappa != 0 (for kappa = 0 its solution is not unique)");
+        return KFBI_EINVAL;
+    }
+    return helmholtz_solve(d, kre, kim, f_grid, f_gamma, gn_gamma, u_grid_out, psi_inout, opts, stats, 1,
+                           trace_out);
+}
+
 // ---------------------------------------------------------------------------
 // steppers
 // ---------------------------------------------------------------------------
@@ -488,6 +518,10 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
     if (!(p->tau > 0)) { set_error("tau must be positive"); return KFBI_EINVAL; }
     if ((eq == KFBI_SCHRODINGER) != d->cplx) {
         set_error("Schroedinger needs a complex domain; heat and wave a real one");
+        return KFBI_EINVAL;
+    }
+    if (p->bc != KFBI_BC_DIRICHLET && p->bc != KFBI_BC_NEUMANN) {
+        set_error("unknown boundary condition");
         return KFBI_EINVAL;
     }
     kfbi_stepper *s = new kfbi_stepper();
@@ -513,6 +547,7 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
     if (st == KFBI_OK) st = st_alloc(s, &s->f, nodes * es);
     if (st == KFBI_OK) st = st_alloc(s, &s->fg, Nb * es);
     if (st == KFBI_OK) st = st_alloc(s, &s->phi, Nb * es);
+    if (st == KFBI_OK && p->bc == KFBI_BC_NEUMANN) st = st_alloc(s, &s->tr, Nb * es);
     // every state buffer starts at zero (the checkpoint of a stepper is then
     // a function of its steps alone, also for buffers its equation leaves unused)
     void *zero_bufs[5] = {s->A, s->Ag, s->B, s->Bg, s->phi};
@@ -527,7 +562,7 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
 namespace {
 struct StateHeader {
     uint32_t magic, version;
-    int32_t eq, M, Nb, cplx, initialized, pad;
+    int32_t eq, M, Nb, cplx, initialized, bc;
     double tau, kre, kim, pad2;
 };
 static_assert(sizeof(StateHeader) == 64, "state header is 64 bytes");
@@ -559,6 +594,7 @@ int kfbi_stepper_get_state(kfbi_stepper *s, void *dst, uint64_t bytes) {
     h.Nb = d->Nb;
     h.cplx = d->cplx ? 1 : 0;
     h.initialized = s->initialized ? 1 : 0;
+    h.bc = s->p.bc;
     h.tau = s->p.tau;
     h.kre = s->kre;
     h.kim = s->kim;
@@ -585,7 +621,7 @@ int kfbi_stepper_set_state(kfbi_stepper *s, const void *src, uint64_t bytes) {
     KFBI_HIP(hipStreamSynchronize(d->stream));
     if (h.magic != kStateMagic || h.version != 1) { set_error("not a stepper state blob"); return KFBI_EINVAL; }
     if (h.eq != s->eq || h.M != d->M || h.Nb != d->Nb || h.cplx != (d->cplx ? 1 : 0) || h.kre != s->kre ||
-        h.kim != s->kim) {
+        h.kim != s->kim || h.bc != s->p.bc) {
         set_error("state blob belongs to a different stepper configuration");
         return KFBI_EINVAL;
     }
@@ -638,9 +674,15 @@ int kfbi_stepper_init(kfbi_stepper *s, const void *u0, const void *lap0, const v
     return KFBI_OK;
 }
 
+// One implicit solve of a step.  Returns the trace of u^{n+1} on Gamma that
+// the recurrence carries there: g itself for the Dirichlet problem, the
+// extracted U+ for the Neumann problem (g is then du/dn).
 static int step_solve(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_solve_opts *opts,
-                      kfbi_solve_stats *stats) {
-    return helmholtz_solve(s->dom, s->kre, s->kim, s->f, s->fg, g_next, u_out, s->phi, opts, stats);
+                      kfbi_solve_stats *stats, const void **trace) {
+    const bool neu = s->p.bc == KFBI_BC_NEUMANN;
+    *trace = neu ? s->tr : g_next;
+    return helmholtz_solve(s->dom, s->kre, s->kim, s->f, s->fg, g_next, u_out, s->phi, opts, stats, neu ? 1 : 0,
+                           neu ? s->tr : nullptr);
 }
 
 int kfbi_step_heat(kfbi_stepper *s, const void *g_next, const void *src, const void *srcg, void *u_out,
@@ -651,10 +693,11 @@ int kfbi_step_heat(kfbi_stepper *s, const void *g_next, const void *src, const v
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
     KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A, -1.0, src));
     KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag, -1.0, srcg));
-    int st = step_solve(s, g_next, u_out, opts, stats);
+    const void *tr = nullptr;
+    int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
     KFBI_TRY(lin4<double>(d, ng, s->A, 2.0 * s->kre, u_out, 1.0, s->f));
-    KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * s->kre, g_next, 1.0, s->fg));
+    KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * s->kre, tr, 1.0, s->fg));
     return st;
 }
 
@@ -666,12 +709,13 @@ int kfbi_step_wave(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
     KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A));
     KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag));
-    int st = step_solve(s, g_next, u_out, opts, stats);
+    const void *tr = nullptr;
+    int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
     const double th = s->p.theta, c1 = (1.0 - 2.0 * th) / th, a = s->kre / th;
     // F^{n+2} into the F^n buffer, then swap
     KFBI_TRY(lin4<double>(d, ng, s->B, a, u_out, -c1, s->A, -1.0, s->B));
-    KFBI_TRY(lin4<double>(d, Nb, s->Bg, a, g_next, -c1, s->Ag, -1.0, s->Bg));
+    KFBI_TRY(lin4<double>(d, Nb, s->Bg, a, tr, -c1, s->Ag, -1.0, s->Bg));
     std::swap(s->A, s->B);
     std::swap(s->Ag, s->Bg);
     return st;
@@ -689,11 +733,12 @@ int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, cons
     k_schr_b<<<(Nb + 255) / 256, 256, 0, d->stream>>>(Nb, (cd *)s->Ag, (const double *)s->p.v_gamma, s->p.w,
                                                      s->p.tau, (cd *)s->fg);
     KFBI_CHECK_LAUNCH();
-    int st = step_solve(s, g_next, u_out, opts, stats);
+    const void *tr = nullptr;
+    int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
     const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
     KFBI_TRY(lin4<cd>(d, ng, s->A, two, u_out, m1, s->A));
-    KFBI_TRY(lin4<cd>(d, Nb, s->Ag, two, g_next, m1, s->Ag));
+    KFBI_TRY(lin4<cd>(d, Nb, s->Ag, two, tr, m1, s->Ag));
     return st;
 }
 

@@ -1567,7 +1567,7 @@ int replay_slot(kfbi_domain *d, int reps, double *avg_ms, double *bytes) {
 
 int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
                     const void *g_gamma, void *u_grid_out, void *phi_inout, const kfbi_solve_opts *opts,
-                    kfbi_solve_stats *stats) {
+                    kfbi_solve_stats *stats, int bc, void *trace_out) {
     kfbi_solve_opts o;
     o.tol = 1e-10;
     o.max_iter = 500;
@@ -1620,15 +1620,25 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     const size_t vb = (size_t)d->Nb * elem_size(d);
     KFBI_TRY(ensure_coefficients(d, kre, kim));
     KFBI_TRY(tune_tridiag(d));
-    KFBI_TRY(ensure_operators(d, kre, kim));
+    KFBI_TRY(ensure_operators(d, kre, kim, bc));
+    if (bc && (size_t)d->Nb * elem_size(d) > 65536) {
+        set_error("the Neumann solve needs Nb <= 8192 (real) or 4096 (complex)");
+        return KFBI_ENOTSUP;
+    }
+    if (bc && !d->op_merged) {
+        set_error("the Neumann solve needs the merged operators (a node's edge windows are too far apart)");
+        return KFBI_ENOTSUP;
+    }
     if (mixed) KFBI_TRY(ensure_coefficients_low(d, kre, kim));
-    // b = g - IS(f, 0).U+
+    // b = g - IS(f, 0).U+ (Dirichlet), b = g - IS(f, 0, 0).dU+/dn (Neumann)
     if (f_grid) {
         KFBI_TRY(dst_rows_dense(d, f_grid, true, d->rhat));
         KFBI_TRY(compute_corrections(d, kre, kim, nullptr, f_gamma, d->corr));
         KFBI_TRY(tridiag_solve(d, d->rhat, d->corr, d->uhat));
         KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
-        KFBI_TRY(extract_boundary(d, kre, kim, d->ust, nullptr, f_gamma, g_gamma, -1.0, P.b));
+        if (bc) KFBI_TRY(extract_boundary_psi_ctl(d, kre, kim, d->ust, f_gamma, nullptr, true, g_gamma, -1.0, P.b,
+                                                  nullptr));
+        else KFBI_TRY(extract_boundary(d, kre, kim, d->ust, nullptr, f_gamma, g_gamma, -1.0, P.b));
     } else {
         KFBI_HIP(hipMemcpyAsync(P.b, g_gamma, vb, hipMemcpyDeviceToDevice, s));
     }
@@ -1640,9 +1650,16 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     // U = IS(f, phi).U on the grid (gate: null, or the finish flag of the
     // device-driven schedule)
     auto final_solve = [&](const int *gate) -> int {
-        KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
+        if (bc) KFBI_TRY(compute_corrections_psi_ctl(d, kre, kim, f_gamma, P.x, d->corr, gate));
+        else KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
         KFBI_TRY(tridiag_solve_ctl(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat, gate));
         if (u_grid_out) KFBI_TRY(idst_rows_dense_ctl(d, d->uhat, u_grid_out, gate));
+        if (bc && trace_out) {
+            // U+ of the solution at the collocation points (the trace of u)
+            KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, gate));
+            KFBI_TRY(extract_boundary_psi_ctl(d, kre, kim, d->ust, f_gamma, P.x, false, nullptr, 1.0, trace_out,
+                                              gate));
+        }
         if (phi_inout) {
             if (gate) {
                 const int n = (int)(vb / sizeof(double));

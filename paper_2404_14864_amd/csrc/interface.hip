@@ -47,6 +47,38 @@ __device__ inline Jumps<T> jumps_dirichlet(const Frame &f, T phi, T pt, T ptt, T
     return J;
 }
 
+// The jumps of a density psi = [u_n] alone ([u] = 0, f = 0): the tangential
+// derivative of [u] vanishes, so [grad u] = psi n with n = (t_y, -t_x); the
+// tangential-normal second derivative picks up psi_s and the curvature terms
+// of the same rows as above, and [lap u] = kappa [u] + [f] = 0 gives the
+// normal-normal one.
+template <class T>
+__device__ inline Jumps<T> jumps_psi(const Frame &f, T psi, T pst) {
+    Jumps<T> J;
+    const T pss = pst * (1.0 / f.sigma);
+    J.u = zero<T>();
+    J.ux = psi * f.ty;
+    J.uy = psi * (-f.tx);
+    const T rtt = zero<T>() - (J.ux * f.dtx + J.uy * f.dty);
+    const T rtn = pss + J.uy * f.dtx - J.ux * f.dty;
+    const T rnn = zero<T>() - rtt;
+    const double c = f.tx, s = f.ty;
+    J.uxx = rtt * (c * c) + rtn * (2.0 * c * s) + rnn * (s * s);
+    J.uxy = rtt * (c * s) + rtn * (s * s - c * c) - rnn * (s * c);
+    J.uyy = rtt * (s * s) - rtn * (2.0 * s * c) + rnn * (c * c);
+    return J;
+}
+
+template <class T>
+__device__ inline void add_jumps(Jumps<T> &J, const Jumps<T> &P) {
+    J.u += P.u;
+    J.ux += P.ux;
+    J.uy += P.uy;
+    J.uxx += P.uxx;
+    J.uxy += P.uxy;
+    J.uyy += P.uyy;
+}
+
 __device__ inline int wrapk(int k, int Nb) {
     k %= Nb;
     return k < 0 ? k + Nb : k;
@@ -79,6 +111,7 @@ __device__ void corrections_body(const CorrArgs<T> &A, int blk) {
     const T *phi_base = A.phi_base;
     const int *jptr = A.jptr;
     const T *__restrict__ fg = A.fg;
+    const T *__restrict__ psi = A.psi;
     T *__restrict__ corr = A.corr;
     if (A.done && *A.done) return;
     int q = blk * blockDim.x + threadIdx.x;
@@ -103,6 +136,16 @@ __device__ void corrections_body(const CorrArgs<T> &A, int blk) {
             if (fg) fv += fg[kk] * w;
         }
         Jumps<T> J = jumps_dirichlet(E.fr, p, pt, ptt, fv, kappa);
+        if (psi) {
+            T s = zero<T>(), st = zero<T>();
+            for (int o = 0; o < 4; ++o) {
+                T a, b, c;
+                bdata(psi, Nb, wrapk(E.k0 - 1 + o, Nb), i12d, i12d2, a, b, c);
+                s += a * E.w[o];
+                st += b * E.w[o];
+            }
+            add_jumps(J, jumps_psi(E.fr, s, st));
+        }
         const T ua = E.axis == 0 ? J.ux : J.uy;
         const T uaa = E.axis == 0 ? J.uxx : J.uyy;
         const double dd = R.d[s];
@@ -129,6 +172,8 @@ __device__ void extract_body(const ExtArgs<T> &A, int blk) {
     const T *phi_base = A.phi_base;
     const int *jptr = A.jptr;
     const T *__restrict__ fg = A.fg;
+    const T *__restrict__ psi = A.psi;
+    const double *__restrict__ wn = A.wn;
     const T *__restrict__ g = A.g;
     T *out_base = A.out_base;
     if (A.done && *A.done) return;
@@ -141,6 +186,11 @@ __device__ void extract_body(const ExtArgs<T> &A, int blk) {
     if (phi) bdata(phi, Nb, k, i12d, i12d2, p, pt, ptt);
     T fv = fg ? fg[k] : zero<T>();
     Jumps<T> J = jumps_dirichlet(col[k].fr, p, pt, ptt, fv, kappa);
+    if (psi) {
+        T a, b, c;
+        bdata(psi, Nb, k, i12d, i12d2, a, b, c);
+        add_jumps(J, jumps_psi(col[k].fr, a, b));
+    }
     const Stencil &S = st[k];
     T up = zero<T>();
     for (int q = 0; q < 6; ++q) {
@@ -150,7 +200,7 @@ __device__ void extract_body(const ExtArgs<T> &A, int blk) {
             val += J.u + J.ux * xi + J.uy * eta + J.uxx * (0.5 * xi * xi) + J.uxy * (xi * eta) +
                    J.uyy * (0.5 * eta * eta);
         }
-        up += val * S.w[q];
+        up += val * (wn ? wn[6 * k + q] : S.w[q]);
     }
     T res = up * scale;
     if (g) res += g[k];
@@ -179,7 +229,9 @@ __device__ inline void window_derivs(const T *win, int L, double i12d, double i1
     ptt = ((p1 + m1) * 16.0 - (p2 + m2) - c0 * 30.0) * i12d2;
 }
 
-template <class T>
+// PSI: the operator of the Neumann density ([u] = 0, [u_n] = window),
+// else of the Dirichlet density ([u] = window, [u_n] = 0)
+template <class T, bool PSI>
 __global__ void k_build_corr_op(int n_irr, const IrrNode *__restrict__ irr, const Edge *__restrict__ edges, int Nb,
                                 double dth, double h, T kappa, T *__restrict__ coef, int32_t *__restrict__ base) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -210,7 +262,7 @@ __global__ void k_build_corr_op(int n_irr, const IrrNode *__restrict__ irr, cons
                 pt += b * E.w[l];
                 ptt += c * E.w[l];
             }
-            Jumps<T> J = jumps_dirichlet(E.fr, p, pt, ptt, zero<T>(), kappa);
+            Jumps<T> J = PSI ? jumps_psi(E.fr, p, pt) : jumps_dirichlet(E.fr, p, pt, ptt, zero<T>(), kappa);
             const T ua = E.axis == 0 ? J.ux : J.uy;
             const T uaa = E.axis == 0 ? J.uxx : J.uyy;
             coef[(size_t)(s * 8 + o) * n_irr + q] = (J.u + ua * dd + uaa * (0.5 * dd * dd)) * scale;
@@ -255,32 +307,83 @@ __global__ void k_merge_corr_op(int n_irr, int Nb, const T *__restrict__ coef, c
         }
 }
 
-template <class T>
-__global__ void k_build_ext_op(int Nb, double dth, const Colloc *__restrict__ col, const Stencil *__restrict__ st,
-                               T kappa, T *__restrict__ bop, double *__restrict__ w6) {
+// Weights of the interior normal derivative at collocation point k: the
+// first-order coefficients of the same six-point Taylor fit as the value
+// weights, n . (U_x, U_y) with n = (t_y, -t_x).  In the 1/h-scaled system of
+// the stencil set-up they solve A^T w = (0, n_x/h, n_y/h, 0, 0, 0).
+__device__ inline void normal_weights(const Stencil &S, const Frame &fr, double h, double *w) {
+    double A[6][7];
+    for (int p = 0; p < 6; ++p) {
+        const double u = S.xi[p] / h, v = S.eta[p] / h;
+        const double row[6] = {1.0, u, v, 0.5 * u * u, u * v, 0.5 * v * v};
+        for (int q = 0; q < 6; ++q) A[q][p] = row[q];
+    }
+    for (int q = 0; q < 6; ++q) A[q][6] = 0.0;
+    A[1][6] = fr.ty / h;
+    A[2][6] = -fr.tx / h;
+    for (int c = 0; c < 6; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 6; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (piv != c)
+            for (int q = 0; q < 7; ++q) {
+                const double t = A[c][q];
+                A[c][q] = A[piv][q];
+                A[piv][q] = t;
+            }
+        const double inv = 1.0 / A[c][c];
+        for (int r = c + 1; r < 6; ++r) {
+            const double f = A[r][c] * inv;
+            for (int q = c; q < 7; ++q) A[r][q] -= f * A[c][q];
+        }
+    }
+    for (int r = 5; r >= 0; --r) {
+        double s = A[r][6];
+        for (int q = r + 1; q < 6; ++q) s -= A[r][q] * w[q];
+        w[r] = s / A[r][r];
+    }
+}
+
+template <class T, bool PSI>
+__global__ void k_build_ext_op(int Nb, double dth, double h, const Colloc *__restrict__ col,
+                               const Stencil *__restrict__ st, T kappa, T *__restrict__ bop, double *__restrict__ w6) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= Nb) return;
     const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
     const Stencil &S = st[k];
-    for (int p = 0; p < 6; ++p) w6[k * 6 + p] = S.w[p];
+    double w[6];
+    if (PSI) normal_weights(S, col[k].fr, h, w);
+    else
+        for (int p = 0; p < 6; ++p) w[p] = S.w[p];
+    for (int p = 0; p < 6; ++p) w6[k * 6 + p] = w[p];
     for (int o = 0; o < 5; ++o) {
         T win[5];
         for (int u = 0; u < 5; ++u) win[u] = zero<T>();
         win[o] = from_re_im<T>(1.0, 0.0);
         T p, pt, ptt;
         window_derivs(win, 2, i12d, i12d2, p, pt, ptt);
-        Jumps<T> J = jumps_dirichlet(col[k].fr, p, pt, ptt, zero<T>(), kappa);
+        Jumps<T> J = PSI ? jumps_psi(col[k].fr, p, pt) : jumps_dirichlet(col[k].fr, p, pt, ptt, zero<T>(), kappa);
         T acc = zero<T>();
         for (int q = 0; q < 6; ++q) {
             if ((S.out_mask >> q) & 1) {
                 const double xi = S.xi[q], eta = S.eta[q];
                 T jq = J.u + J.ux * xi + J.uy * eta + J.uxx * (0.5 * xi * xi) + J.uxy * (xi * eta) +
                        J.uyy * (0.5 * eta * eta);
-                acc += jq * S.w[q];
+                acc += jq * w[q];
             }
         }
         bop[k * 5 + o] = acc;
     }
+}
+
+// normal-derivative weights alone (the Neumann right-hand side and checks)
+__global__ void k_normal_weights(int Nb, double h, const Colloc *__restrict__ col, const Stencil *__restrict__ st,
+                                 double *__restrict__ wn) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Nb) return;
+    double w[6];
+    normal_weights(st[k], col[k].fr, h, w);
+    for (int p = 0; p < 6; ++p) wn[k * 6 + p] = w[p];
 }
 
 template <class T> T kappa_of(double kre, double kim);
@@ -289,7 +392,7 @@ template <> cd kappa_of<cd>(double kre, double kim) { return make_cd(kre, kim); 
 
 template <class T>
 CorrArgs<T> corr_args(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
-                      const void *fg, void *corr, const int *done) {
+                      const void *fg, void *corr, const int *done, const void *psi = nullptr) {
     CorrArgs<T> A;
     A.n_irr = d->n_irr;
     A.Nb = d->Nb;
@@ -301,6 +404,7 @@ CorrArgs<T> corr_args(kfbi_domain *d, double kre, double kim, const void *phi_ba
     A.phi_base = (const T *)phi_base;
     A.jptr = jptr;
     A.fg = (const T *)fg;
+    A.psi = (const T *)psi;
     A.corr = (T *)corr;
     A.done = done;
     return A;
@@ -308,7 +412,8 @@ CorrArgs<T> corr_args(kfbi_domain *d, double kre, double kim, const void *phi_ba
 
 template <class T>
 ExtArgs<T> ext_args(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi_base, const int *jptr,
-                    const void *fg, const void *g, double scale, void *out_base, int out_add, const int *done) {
+                    const void *fg, const void *g, double scale, void *out_base, int out_add, const int *done,
+                    const void *psi = nullptr, const double *wn = nullptr) {
     ExtArgs<T> A;
     A.Nb = d->Nb;
     A.out_add = out_add;
@@ -322,6 +427,8 @@ ExtArgs<T> ext_args(kfbi_domain *d, double kre, double kim, const void *ust, con
     A.phi_base = (const T *)phi_base;
     A.jptr = jptr;
     A.fg = (const T *)fg;
+    A.psi = (const T *)psi;
+    A.wn = wn;
     A.g = (const T *)g;
     A.out_base = (T *)out_base;
     A.done = done;
@@ -330,10 +437,10 @@ ExtArgs<T> ext_args(kfbi_domain *d, double kre, double kim, const void *ust, con
 
 template <class T>
 int launch_corr(kfbi_domain *d, double kre, double kim, const void *phi_base, const int *jptr,
-                const void *fg, void *corr, const int *done) {
+                const void *fg, void *corr, const int *done, const void *psi = nullptr) {
     const int ps = prof_begin(d);
     k_corrections<T><<<(d->n_irr + 127) / 128, 128, 0, d->stream>>>(
-        corr_args<T>(d, kre, kim, phi_base, jptr, fg, corr, done));
+        corr_args<T>(d, kre, kim, phi_base, jptr, fg, corr, done, psi));
     KFBI_CHECK_LAUNCH();
     prof_end(d, ps, KFBI_K_CORRECTIONS, (double)d->n_irr * (sizeof(IrrNode) + sizeof(T)));
     return KFBI_OK;
@@ -342,10 +449,10 @@ int launch_corr(kfbi_domain *d, double kre, double kim, const void *phi_base, co
 template <class T>
 int launch_extract(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi_base,
                    const int *jptr, const void *fg, const void *g, double scale, void *out_base,
-                   int out_add, const int *done) {
+                   int out_add, const int *done, const void *psi = nullptr, const double *wn = nullptr) {
     const int ps = prof_begin(d);
     k_extract<T><<<(d->Nb + 127) / 128, 128, 0, d->stream>>>(
-        ext_args<T>(d, kre, kim, ust, phi_base, jptr, fg, g, scale, out_base, out_add, done));
+        ext_args<T>(d, kre, kim, ust, phi_base, jptr, fg, g, scale, out_base, out_add, done, psi, wn));
     KFBI_CHECK_LAUNCH();
     prof_end(d, ps, KFBI_K_EXTRACT, (double)d->Nb * (sizeof(Colloc) + sizeof(Stencil) + 8.0 * sizeof(T)));
     return KFBI_OK;
@@ -377,6 +484,30 @@ int extract_boundary(kfbi_domain *d, double kre, double kim, const void *ust, co
     return extract_boundary_ctl(d, kre, kim, ust, phi, nullptr, f_gamma, g_minus, scale, out, 0, nullptr);
 }
 
+int compute_corrections_psi_ctl(kfbi_domain *d, double kre, double kim, const void *f_gamma, const void *psi,
+                                void *corr_out, const int *done) {
+    if (d->cplx) return launch_corr<cd>(d, kre, kim, nullptr, nullptr, f_gamma, corr_out, done, psi);
+    return launch_corr<double>(d, kre, kim, nullptr, nullptr, f_gamma, corr_out, done, psi);
+}
+
+int ensure_normal_weights(kfbi_domain *d) {
+    if (d->wn) return KFBI_OK;
+    KFBI_TRY(dalloc(d, (void **)&d->wn, (size_t)d->Nb * 6 * sizeof(double)));
+    k_normal_weights<<<(d->Nb + 127) / 128, 128, 0, d->stream>>>(d->Nb, d->h, d->col, d->st, d->wn);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+int extract_boundary_psi_ctl(kfbi_domain *d, double kre, double kim, const void *ust, const void *f_gamma,
+                             const void *psi, bool normal, const void *g, double scale, void *out,
+                             const int *done) {
+    if (normal) KFBI_TRY(ensure_normal_weights(d));
+    const double *wn = normal ? d->wn : nullptr;
+    if (d->cplx)
+        return launch_extract<cd>(d, kre, kim, ust, nullptr, nullptr, f_gamma, g, scale, out, 0, done, psi, wn);
+    return launch_extract<double>(d, kre, kim, ust, nullptr, nullptr, f_gamma, g, scale, out, 0, done, psi, wn);
+}
+
 size_t operators_bytes_pending(const kfbi_domain *d) {
     if (d->cop_coef) return 0;
     const size_t es = elem_size(d), ni = (size_t)d->n_irr, Nb = (size_t)d->Nb;
@@ -384,8 +515,8 @@ size_t operators_bytes_pending(const kfbi_domain *d) {
            Nb * 6 * sizeof(double);
 }
 
-int ensure_operators(kfbi_domain *d, double kre, double kim) {
-    if (d->op_valid && d->op_kre == kre && d->op_kim == kim) return KFBI_OK;
+int ensure_operators(kfbi_domain *d, double kre, double kim, int bc) {
+    if (d->op_valid && d->op_kre == kre && d->op_kim == kim && d->op_bc == bc) return KFBI_OK;
     const size_t es = elem_size(d);
     if (!d->cop_coef) {
         KFBI_TRY(dalloc(d, &d->cop_coef, (size_t)d->n_irr * 32 * es));
@@ -402,16 +533,34 @@ int ensure_operators(kfbi_domain *d, double kre, double kim) {
     const double dth = 6.283185307179586476925286766559 / d->Nb;
     const int gi = (d->n_irr + 127) / 128, gk = (d->Nb + 127) / 128;
     if (d->cplx) {
-        k_build_corr_op<cd><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h,
-                                                       make_cd(kre, kim), (cd *)d->cop_coef, d->cop_base);
-        KFBI_CHECK_LAUNCH();
-        k_build_ext_op<cd><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->col, d->st, make_cd(kre, kim), (cd *)d->bop,
-                                                      d->w6);
+        const cd kc = make_cd(kre, kim);
+        if (bc) {
+            k_build_corr_op<cd, true><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kc,
+                                                                 (cd *)d->cop_coef, d->cop_base);
+            KFBI_CHECK_LAUNCH();
+            k_build_ext_op<cd, true><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->h, d->col, d->st, kc, (cd *)d->bop,
+                                                                d->w6);
+        } else {
+            k_build_corr_op<cd, false><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kc,
+                                                                  (cd *)d->cop_coef, d->cop_base);
+            KFBI_CHECK_LAUNCH();
+            k_build_ext_op<cd, false><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->h, d->col, d->st, kc, (cd *)d->bop,
+                                                                 d->w6);
+        }
     } else {
-        k_build_corr_op<double><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h, kre,
-                                                           (double *)d->cop_coef, d->cop_base);
-        KFBI_CHECK_LAUNCH();
-        k_build_ext_op<double><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->col, d->st, kre, (double *)d->bop, d->w6);
+        if (bc) {
+            k_build_corr_op<double, true><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h,
+                                                                     kre, (double *)d->cop_coef, d->cop_base);
+            KFBI_CHECK_LAUNCH();
+            k_build_ext_op<double, true><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->h, d->col, d->st, kre,
+                                                                    (double *)d->bop, d->w6);
+        } else {
+            k_build_corr_op<double, false><<<gi, 128, 0, d->stream>>>(d->n_irr, d->irr, d->edges, d->Nb, dth, d->h,
+                                                                      kre, (double *)d->cop_coef, d->cop_base);
+            KFBI_CHECK_LAUNCH();
+            k_build_ext_op<double, false><<<gk, 128, 0, d->stream>>>(d->Nb, dth, d->h, d->col, d->st, kre,
+                                                                     (double *)d->bop, d->w6);
+        }
     }
     KFBI_CHECK_LAUNCH();
     if (d->cplx)
@@ -429,6 +578,7 @@ int ensure_operators(kfbi_domain *d, double kre, double kim) {
     d->op_valid = true;
     d->op_kre = kre;
     d->op_kim = kim;
+    d->op_bc = bc;
     return KFBI_OK;
 }
 

@@ -239,12 +239,17 @@ struct kfbi_domain {
     bool coef32_valid = false;
     double coef32_kre = 0, coef32_kim = 0;
 
-    // matrix-vector operators (per kappa): corrections = sum over the <= 4
-    // crossed edges of each irregular node of an 8-point window of phi
-    // starting at cop_base; extraction = sum_p w6[k][p] U(stencil p) + a
-    // 5-point window of phi around k with coefficients bop
+    // matrix-vector operators (per kappa and boundary condition):
+    // corrections = sum over the <= 4 crossed edges of each irregular node of
+    // an 8-point window of the density starting at cop_base; extraction =
+    // sum_p w6[k][p] U(stencil p) + a 5-point window of the density around k
+    // with coefficients bop.  op_bc 0: the Dirichlet operator (density [u],
+    // value weights); 1: the Neumann operator (density [u_n], normal-
+    // derivative weights)
     bool op_valid = false;
     double op_kre = 0, op_kim = 0;
+    int op_bc = 0;
+    double *wn = nullptr;               // Nb * 6 normal-derivative weights
     void *cop_coef = nullptr;           // n_irr * 4 * 8
     int32_t *cop_base = nullptr;        // n_irr * 4 (-1: unused slot)
     void *bop = nullptr;                // Nb * 5
@@ -339,7 +344,17 @@ int extract_boundary_ctl(kfbi_domain *d, double kre, double kim, const void *ust
                          const int *done);
 
 // build the matrix-vector operators for this kappa (no-op when current)
-int ensure_operators(kfbi_domain *d, double kre, double kim);
+int ensure_operators(kfbi_domain *d, double kre, double kim, int bc = 0);
+// Neumann pieces: corrections with [u] = 0, [u_n] = psi and f (f_gamma
+// nullable); extraction with [u_n] = psi (nullable) and f, of the value
+// (normal = false) or of the interior normal derivative (normal = true):
+// out = g + scale * (extracted), g nullable
+int compute_corrections_psi_ctl(kfbi_domain *d, double kre, double kim, const void *f_gamma, const void *psi,
+                                void *corr_out, const int *done);
+int extract_boundary_psi_ctl(kfbi_domain *d, double kre, double kim, const void *ust, const void *f_gamma,
+                             const void *psi, bool normal, const void *g, double scale, void *out,
+                             const int *done);
+int ensure_normal_weights(kfbi_domain *d);
 
 // one full interface solve IS(f, f_gamma, phi) -> (u grid, U+)
 int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
@@ -347,9 +362,13 @@ int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
                     void *uplus_out, bool reuse_rhat);
 
 // GMRES (gmres.hip)
+// bc 0: Dirichlet (g_gamma = u on Gamma, density [u]); bc 1: Neumann
+// (g_gamma = du/dn, density [u_n]); trace_out (nullable, Neumann) receives
+// the interior limit U+ at the collocation points
 int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
                     const void *f_gamma, const void *g_gamma, void *u_grid_out,
-                    void *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
+                    void *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats,
+                    int bc = 0, void *trace_out = nullptr);
 
 inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : sizeof(double); }
 
@@ -479,6 +498,7 @@ struct CorrArgs {
     const T *phi_base;
     const int *jptr;
     const T *fg;
+    const T *psi;         // nullable: [u_n] = psi (the Neumann density), else 0
     T *corr;
     const int *done;
 };
@@ -496,6 +516,9 @@ struct ExtArgs {
     const T *phi_base;
     const int *jptr;
     const T *fg;
+    const T *psi;         // nullable: [u_n] = psi, else 0
+    const double *wn;     // nullable: six weights per point replacing the
+                          // stencil's own (the normal-derivative weights)
     const T *g;
     T *out_base;
     const int *done;

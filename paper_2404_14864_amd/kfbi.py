@@ -23,6 +23,7 @@ KFBI_SOLVE_ASYNC = 1
 KFBI_BATCH_NO_TUNE = 2
 KFBI_SOLVE_RICHARDSON = 4
 KFBI_HEAT, KFBI_WAVE, KFBI_SCHRODINGER = 0, 1, 2
+KFBI_BC_DIRICHLET, KFBI_BC_NEUMANN = 0, 1
 
 
 class KfbiError(RuntimeError):
@@ -70,7 +71,8 @@ class SolveStats(ctypes.Structure):
 class StepParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("theta", ctypes.c_double),
                 ("diffusivity", ctypes.c_double), ("w", ctypes.c_double),
-                ("v_grid", ctypes.c_void_p), ("v_gamma", ctypes.c_void_p)]
+                ("v_grid", ctypes.c_void_p), ("v_gamma", ctypes.c_void_p),
+                ("bc", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class KernelProf(ctypes.Structure):
@@ -99,11 +101,14 @@ def lib():
         "kfbi_domain_get_info": ([_P, ctypes.POINTER(DomainInfo)], ctypes.c_int),
         "kfbi_domain_copy_classification": ([_P, _P], ctypes.c_int),
         "kfbi_domain_copy_boundary": ([_P, _P], ctypes.c_int),
+        "kfbi_domain_copy_normals": ([_P, _P], ctypes.c_int),
         "kfbi_domain_copy_edges": ([_P, _P, _P], ctypes.c_int),
         "kfbi_grid_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
         "kfbi_interface_apply": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P], ctypes.c_int),
         "kfbi_helmholtz_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_neumann_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P, _P,
+                                ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
         "kfbi_stepper_create": ([_P, ctypes.c_int32, ctypes.POINTER(StepParams), ctypes.POINTER(_P)], ctypes.c_int),
         "kfbi_stepper_destroy": ([_P], ctypes.c_int),
         "kfbi_stepper_init": ([_P] + [_P] * 8, ctypes.c_int),
@@ -143,7 +148,7 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read", "kfbi_profile_replay",
             "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state",
             "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz", "kfbi_batch_tuning",
-            "kfbi_batch_step")
+            "kfbi_batch_step", "kfbi_neumann_solve", "kfbi_domain_copy_normals")
 
 
 def kfbi_profile_enable(h, on=True):
@@ -323,6 +328,14 @@ def kfbi_domain_copy_boundary(h):
     return out[0::2].copy(), out[1::2].copy()
 
 
+def kfbi_domain_copy_normals(h):
+    import numpy as np
+    info = kfbi_domain_get_info(h)
+    out = np.zeros(2 * info["Nb"], dtype=np.float64)
+    _check(lib().kfbi_domain_copy_normals(h, out.ctypes.data_as(ctypes.c_void_p)))
+    return out[0::2].copy(), out[1::2].copy()
+
+
 def kfbi_domain_copy_edges(h):
     import numpy as np
     info = kfbi_domain_get_info(h)
@@ -355,11 +368,25 @@ def kfbi_helmholtz_solve(h, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_ino
     return st.as_dict()
 
 
+def kfbi_neumann_solve(h, kappa, f_grid, f_gamma, gn_gamma, u_grid_out, psi_inout=None, trace_out=None,
+                       opts=None):
+    """lap u - kappa u = f in Omega with du/dn = gn_gamma on Gamma; trace_out
+    (optional) receives u's interior limit at the collocation points."""
+    k = complex(kappa)
+    st = SolveStats()
+    code = lib().kfbi_neumann_solve(h, k.real, k.imag, _ptr(f_grid), _ptr(f_gamma), _ptr(gn_gamma),
+                                    _ptr(u_grid_out), _ptr(psi_inout), _ptr(trace_out), _opts(opts),
+                                    ctypes.byref(st))
+    _check(code, allow=(KFBI_ENOCONV,))
+    return st.as_dict()
+
+
 # ---- steppers --------------------------------------------------------------
-def kfbi_stepper_create(h, equation, tau, theta=0.25, diffusivity=1.0, w=0.0, v_grid=None, v_gamma=None):
+def kfbi_stepper_create(h, equation, tau, theta=0.25, diffusivity=1.0, w=0.0, v_grid=None, v_gamma=None,
+                        bc=KFBI_BC_DIRICHLET):
     p = StepParams(tau=tau, theta=theta, diffusivity=diffusivity, w=w,
                    v_grid=_ptr(v_grid, torch.float64, name="v_grid"),
-                   v_gamma=_ptr(v_gamma, torch.float64, name="v_gamma"))
+                   v_gamma=_ptr(v_gamma, torch.float64, name="v_gamma"), bc=bc)
     s = _P()
     _check(lib().kfbi_stepper_create(h, equation, ctypes.byref(p), ctypes.byref(s)))
     return s

@@ -41,3 +41,4 @@ def test_binding_struct_sizes_match_header_layout():
     assert ctypes.sizeof(kfbi.SolveOpts) == 8 + 4 * 6 + 8
     assert ctypes.sizeof(kfbi.SolveStats) == 4 * 2 + 8 + 4 * 2 + 8
     assert ctypes.sizeof(kfbi.DomainInfo) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8
+    assert ctypes.sizeof(kfbi.StepParams) == 8 * 4 + 8 * 2 + 4 * 2
