@@ -328,6 +328,53 @@ def main():
     log("solvers: " + ", ".join("%s %.1f products %.3f ms" % (k, v["products_per_step"], v["ms_per_step"])
                                 for k, v in rich.items() if isinstance(v, dict)))
 
+    # the Neumann problem (eqs. 3.19-3.20): the paper's Neumann wave example
+    # (eight-lobed star, u_n = 0, a logistic bump at rest), theta = 1/4,
+    # tau = 4h (at tau = h the Neumann recurrence on Gamma grows), at the same
+    # grid size
+    neu = None
+    nsteps = min(args.steps, 50)
+    if nsteps > 0:
+        ndesc = W.domain_neumann_wave(M)
+        ndom = kfbi.kfbi_domain_create(ndesc)
+        try:
+            nzx, nzy = kfbi.kfbi_domain_copy_boundary(ndom)
+            xn = W.grid_coords(ndesc["L"], M)
+            Xn, Yn = np.meshgrid(xn, xn)
+            ntau = 4.0 * 2.0 * ndesc["L"] / M
+            u0g, l0g = mf.logistic_u0(Xn, Yn), mf.logistic_lap(Xn, Yn)
+            u0b, l0b = mf.logistic_u0(nzx, nzy), mf.logistic_lap(nzx, nzy)
+            # at rest: u^{-1} = u^0 + tau^2/2 lap u^0, lap u^{-1} taken as lap u^0
+            ninit = [d(u0g.ravel()), d(l0g.ravel()), d(u0b), d(l0b), d((u0g + 0.5 * ntau ** 2 * l0g).ravel()),
+                     d(l0g.ravel()), d(u0b + 0.5 * ntau ** 2 * l0b), d(l0b)]
+            nst = kfbi.kfbi_stepper_create(ndom, kfbi.KFBI_WAVE, ntau, theta=theta, bc=kfbi.KFBI_BC_NEUMANN)
+            try:
+                gz = d(np.zeros(ndesc["Nb"]))
+                nu = torch.zeros_like(u)
+                kfbi.kfbi_stepper_init(nst, *ninit)
+                for k in range(args.warmup):
+                    kfbi.kfbi_step_wave(nst, gz, nu)
+                kfbi.kfbi_stepper_init(nst, *ninit)
+                its = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for k in range(nsteps):
+                    its.append(kfbi.kfbi_step_wave(nst, gz, nu, opts=aopts)["iters"])
+                torch.cuda.synchronize()
+                Tn = time.perf_counter() - t0
+                Un = nu.cpu().numpy()
+            finally:
+                kfbi.kfbi_stepper_destroy(nst)
+        finally:
+            kfbi.kfbi_domain_destroy(ndom)
+        neu = {"workload": "Neumann wave, star r=0.8+0.2 sin 8t in [-1.5,1.5]^2, M=%d, Nb=%d, u_n=0, logistic "
+                           "bump at rest, theta=1/4, dt=4h" % (M, ndesc["Nb"]),
+               "steps": nsteps, "ms_per_step": 1e3 * Tn / nsteps, "iters_per_step": float(np.mean(its)),
+               "value": pts * sum(its) / Tn, "unit": "grid-pts*GMRES-iters/s",
+               "finite": bool(np.all(np.isfinite(Un)))}
+        log("neumann: %d steps %.3f ms/step, %.1f iterations/step, %.3g grid-pts*iters/s" %
+            (nsteps, neu["ms_per_step"], neu["iters_per_step"], neu["value"]))
+
     # profiled pass: HIP events around every kernel launch of the same steps
     kfbi.kfbi_stepper_init(st, *init)
     kfbi.kfbi_profile_enable(dom, True)
@@ -431,6 +478,7 @@ def main():
                             "grid_solve": "fp32", "refinement": "fp64",
                             "rel_diff_vs_fp64_after_steps": mixed_err},
         "solvers": rich,
+        "neumann": neu,
         "batched": batched,
         "serving": served,
         "cpu_baseline": cpu,

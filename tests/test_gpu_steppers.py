@@ -245,3 +245,33 @@ def test_replay_timing_leaves_steps_unchanged():
             kfbi.kfbi_domain_destroy(h)
     for a, b in zip(*runs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("w", [10.0, -10.0])
+def test_schrodinger_nonlinear_matches_oracle(w):
+    """The cubic term w |u|^2 u of eq. 2.2 in the B-step of the splitting
+    (both signs), harmonic potential, packet on the ellipse."""
+    M = 128
+    desc = W.domain_c3_schrodinger(M)
+    od = Domain(desc)
+    tau = od.h / 2
+    X, Y = od.X, od.Y
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    V, Vg = mf.harmonic_potential(X, Y), mf.harmonic_potential(zx, zy)
+    ref = SchrodingerStepper(od, tau, mf.packet_u0(X, Y), mf.packet_lap(X, Y), mf.packet_u0(zx, zy),
+                             mf.packet_lap(zx, zy), V, Vg, w=w, tol=1e-12)
+    with GpuDomain(desc, cplx=True) as g:
+        gx, gy = g.zx, g.zy
+        vg = dev(mf.harmonic_potential(X, Y).ravel())
+        vgam = dev(mf.harmonic_potential(gx, gy))
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, w=w, v_grid=vg, v_gamma=vgam)
+        kfbi.kfbi_stepper_init(s, dev(mf.packet_u0(X, Y).ravel()), dev(mf.packet_lap(X, Y).ravel()),
+                               dev(mf.packet_u0(gx, gy)), dev(mf.packet_lap(gx, gy)))
+        u = empty_grid(g.M, cplx=True)
+        zero = dev(np.zeros(g.Nb, dtype=np.complex128))
+        for n in range(6):
+            Ur = ref.step(np.zeros(od.Nb, dtype=np.complex128))
+            st = kfbi.kfbi_step_schrodinger(s, zero, u, opts={"tol": 1e-12})
+            assert st["converged"]
+            assert rel_err(host(u).reshape(g.M + 1, g.M + 1), Ur, od.inside) < TOL, n
+        kfbi.kfbi_stepper_destroy(s)

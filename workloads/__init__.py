@@ -14,6 +14,7 @@ from .domains import (  # noqa: F401
     domain_c2_wave,
     domain_c3_schrodinger,
     domain_c4_instance,
+    domain_neumann_wave,
     grid_coords,
 )
 from . import manufactured  # noqa: F401

@@ -72,6 +72,13 @@ def domain_c3_schrodinger(M=1024, Nb=None):
     return ellipse(0.6, 0.4, 1.0, M, M if Nb is None else Nb)
 
 
+def domain_neumann_wave(M=512, Nb=None):
+    """The eight-lobed star of the paper's Neumann wave example, r = 0.8 +
+    0.2 sin(8 theta) (the example's (1-c) + c cos(8 theta), c = 0.2, turned
+    by pi/16), in [-1.5, 1.5]^2; M collocation points unless Nb is given."""
+    return star(0.8, 0.2, 8, 1.5, M, M if Nb is None else Nb)
+
+
 def domain_c4_instance(index, grids=(128, 256, 512, 1024)):
     """One seeded batched-Helmholtz instance.
 

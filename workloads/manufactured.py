@@ -78,6 +78,22 @@ def harmonic_potential(x, y, strength=50.0):
     return strength * (x * x + y * y)
 
 
+# ---- the Neumann wave example: a radial logistic bump at rest ----------------
+def logistic_u0(x, y, r1=0.5, k=20.0):
+    """1 / (1 + exp(k (r - r1))), r = |(x, y)|."""
+    return 1.0 / (1.0 + np.exp(k * (np.hypot(x, y) - r1)))
+
+
+def logistic_lap(x, y, r1=0.5, k=20.0, r_min=1e-3):
+    """u'' + u'/r of the bump, with r >= r_min in the 1/r term (the bump has
+    slope -k u (1 - u) ~ 1e-3 at r = 0, a kink whose Laplacian is
+    unbounded there)."""
+    u = logistic_u0(x, y, r1, k)
+    d1 = -k * u * (1.0 - u)
+    d2 = k * k * u * (1.0 - u) * (1.0 - 2.0 * u)
+    return d2 + d1 / np.maximum(np.hypot(x, y), r_min)
+
+
 # ---- modified Helmholtz BVP solutions (lap u - kappa u = f) -----------------
 def helm_exp_u(x, y, a, b):
     """exp(a x + b y): lap u - kappa u = 0 when a^2 + b^2 = kappa."""
