@@ -165,6 +165,8 @@ __device__ T block_sum(T v, T *red) {
 
 __device__ inline double absv(double a) { return fabs(a); }
 __device__ inline double absv(cd a) { return hypot(a.x, a.y); }
+__device__ inline double re_part(double a) { return a; }
+__device__ inline double re_part(cd a) { return a.x; }
 
 template <class T> __device__ inline T scale_of(double s);
 template <> __device__ inline double scale_of<double>(double s) { return s; }
@@ -772,6 +774,7 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     __shared__ double scs[72];
     __shared__ double redd[16];
     __shared__ int sflag, sconv, sit;
+    __shared__ double snrm;
     // one read of the control block (uniform); thread 0 writes back what
     // changes, so no control field is re-read from memory on the critical path
     const GmCtl c = *ctl;
@@ -851,7 +854,11 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     // flight before the first use.
     const bool staged = j + 1 <= nst;
     for (int pass = 0; pass < 2; ++pass) {
-        for (int i0 = 0; i0 <= j && staged; i0 += 16) {
+        // the second pass also forms ||w'||^2 (slot j + 1 of its reduction),
+        // from which the norm of the result follows without a reduction of
+        // its own
+        const int jn = pass == 1 ? j + 1 : j;
+        for (int i0 = 0; i0 <= jn && staged; i0 += 16) {
             T part[16];
 #pragma unroll
             for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
@@ -867,14 +874,15 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
                     }
 #pragma unroll
                     for (int ii = 0; ii < 16; ++ii)
-                        part[ii] += (i0 + ii <= j ? conjv(vv[ii]) : zero<T>()) * wl[e];
+                        part[ii] += (i0 + ii <= j ? conjv(vv[ii]) : (i0 + ii == jn ? conjv(wl[e]) : zero<T>())) *
+                                    wl[e];
                 }
             }
             const T sum = wave_sum16(part, lane);
             const int ii = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && i0 + ii <= j) red[wid][i0 + ii] = sum;
+            if ((lane & 3) == 0 && i0 + ii <= jn) red[wid][i0 + ii] = sum;
         }
-        for (int i0 = 0; i0 <= j && !staged; i0 += 16) {
+        for (int i0 = 0; i0 <= jn && !staged; i0 += 16) {
             T part[16];
 #pragma unroll
             for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
@@ -889,11 +897,14 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
                     for (int ii = 0; ii < 16; ++ii)
                         if (i0 + ii >= nst && i0 + ii <= j)
                             part[ii] += conjv(V[(size_t)(i0 + ii) * Nb + idx]) * wl[e];
+#pragma unroll
+                    for (int ii = 0; ii < 16; ++ii)
+                        if (i0 + ii > j && i0 + ii == jn) part[ii] += conjv(wl[e]) * wl[e];
                 }
             }
             const T sum = wave_sum16(part, lane);
             const int ii = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && i0 + ii <= j) red[wid][i0 + ii] = sum;
+            if ((lane & 3) == 0 && i0 + ii <= jn) red[wid][i0 + ii] = sum;
         }
         __syncthreads();
         if (tid <= j) {
@@ -901,6 +912,10 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
             for (int q = 0; q < (kGmThreads >> 6); ++q) sum += red[q][tid];
             hs[tid] = sum;
             hcol[tid] = pass == 0 ? sum : hcol[tid] + sum;
+        } else if (tid == jn) {
+            T sum = zero<T>();
+            for (int q = 0; q < (kGmThreads >> 6); ++q) sum += red[q][tid];
+            snrm = re_part(sum);
         }
         __syncthreads();
 #pragma unroll
@@ -926,10 +941,22 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
             }
         }
     }
-    double s2 = 0.0;
+    // ||w''||^2 = ||w'||^2 - sum |h2_i|^2 (w'' = w' - sum h2_i v_i, the v_i
+    // orthonormal).  The second pass removes only a rounding-size part of w'
+    // unless w' lay almost in the span; then (half of ||w'||^2 or more
+    // removed) the norm is summed directly.  Every thread forms the same
+    // value from LDS, so the branch is uniform.
+    double hn2 = snrm;
+    for (int i = 0; i <= j; ++i) hn2 -= abs2(hs[i]);
+    double hn;
+    if (hn2 > 0.5 * snrm) {
+        hn = sqrt(hn2);
+    } else {
+        double s2 = 0.0;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) s2 += abs2(wl[e]);
-    const double hn = sqrt(block_sum(s2, redd));
+        for (int e = 0; e < EPT; ++e) s2 += abs2(wl[e]);
+        hn = sqrt(block_sum(s2, redd));
+    }
     const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
