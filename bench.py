@@ -330,8 +330,8 @@ def main():
 
     # the Neumann problem (eqs. 3.19-3.20): the paper's Neumann wave example
     # (eight-lobed star, u_n = 0, a logistic bump at rest), theta = 1/4,
-    # tau = 4h (at tau = h the Neumann recurrence on Gamma grows), at the same
-    # grid size
+    # tau = 4h (at tau = h the theta = 1/4 steps of the Neumann problem grow
+    # faster than the Dirichlet ones), at the same grid size
     neu = None
     nsteps = min(args.steps, 50)
     if nsteps > 0:
