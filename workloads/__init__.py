@@ -15,6 +15,7 @@ from .domains import (  # noqa: F401
     domain_c3_schrodinger,
     domain_c4_instance,
     domain_neumann_wave,
+    domain_nls_example,
     grid_coords,
 )
 from . import manufactured  # noqa: F401

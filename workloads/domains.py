@@ -79,6 +79,14 @@ def domain_neumann_wave(M=512, Nb=None):
     return star(0.8, 0.2, 8, 1.5, M, M if Nb is None else Nb)
 
 
+def domain_nls_example(M=256, Nb=None):
+    """The three-lobed star of the paper's nonlinear Schroedinger example,
+    r = 1.2 + 0.3 sin(3 theta) (its 1.5[(1-c) + c cos(3 theta)] with c = 0.2,
+    which the example leaves unstated, turned by pi/6), in [-pi, pi]^2; M
+    collocation points unless Nb is given."""
+    return star(1.2, 0.3, 3, np.pi, M, M if Nb is None else Nb)
+
+
 def domain_c4_instance(index, grids=(128, 256, 512, 1024)):
     """One seeded batched-Helmholtz instance.
 

@@ -61,6 +61,23 @@ def schr_free_grad(x, y, t):
     return (PI * e * np.cos(PI * x) * np.sin(PI * y), PI * e * np.sin(PI * x) * np.cos(PI * y))
 
 
+# ---- nonlinear Schroedinger, w = 1 (the paper's Example 5) ----------------
+def nls_potential(x, y):
+    """v = 1 - cos^2 x cos^2 y (eq. 4.3)."""
+    c = np.cos(x) * np.cos(y)
+    return 1.0 - c * c
+
+
+def nls_u(x, y, t):
+    """exp(i t) cos x cos y (eq. 4.4): with v of eq. 4.3 and w = 1 it solves
+    i u_t = lap u + v u + w |u|^2 u."""
+    return np.exp(1j * t) * np.cos(x) * np.cos(y)
+
+
+def nls_lap(x, y, t):
+    return -2.0 * nls_u(x, y, t)
+
+
 def packet_u0(x, y, width=0.1, k=(20.0, 0.0)):
     """Gaussian wave packet exp(-|x|^2/(2 w^2)) exp(i k.x), centred at 0."""
     s2 = width * width
