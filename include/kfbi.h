@@ -240,7 +240,9 @@ int kfbi_neumann_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
  *         tau^2); theta in (0, 1/2].
  *   SCHRODINGER: i u_t = lap u + v u + w |u|^2 u (eq. 2.2); Strang splitting,
  *         kappa = 2i/tau; v_grid / v_gamma are device arrays (float64) of the
- *         potential on the grid and at the collocation points (nullable: 0).
+ *         potential on the grid and at the collocation points (nullable: 0),
+ *         copied by kfbi_stepper_create (which waits for the copy), so they
+ *         need not outlive the call.
  * The domain must be REAL for HEAT and WAVE, COMPLEX for SCHRODINGER.
  * bc: KFBI_BC_DIRICHLET (g of each step is u on Gamma) or KFBI_BC_NEUMANN
  * (g is du/dn; each step solves eq. 3.19 and carries the recurrence on

@@ -147,6 +147,7 @@ struct kfbi_stepper {
     void *f = nullptr, *fg = nullptr;   // right-hand side of the current solve
     void *phi = nullptr;                // warm start / density
     void *tr = nullptr;                 // Neumann: U+ on Gamma of the last step
+    void *v = nullptr, *vg = nullptr;   // Schroedinger: copies of the potential
 };
 
 extern "C" {
@@ -548,6 +549,22 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
     if (st == KFBI_OK) st = st_alloc(s, &s->fg, Nb * es);
     if (st == KFBI_OK) st = st_alloc(s, &s->phi, Nb * es);
     if (st == KFBI_OK && p->bc == KFBI_BC_NEUMANN) st = st_alloc(s, &s->tr, Nb * es);
+    // the potential is copied: the caller's arrays need not outlive the call
+    if (st == KFBI_OK && eq == KFBI_SCHRODINGER && p->v_grid) {
+        st = st_alloc(s, &s->v, nodes * sizeof(double));
+        if (st == KFBI_OK &&
+            hipMemcpyAsync(s->v, p->v_grid, nodes * sizeof(double), hipMemcpyDeviceToDevice, d->stream) != hipSuccess)
+            st = KFBI_EDEVICE;
+    }
+    if (st == KFBI_OK && eq == KFBI_SCHRODINGER && p->v_gamma) {
+        st = st_alloc(s, &s->vg, Nb * sizeof(double));
+        if (st == KFBI_OK &&
+            hipMemcpyAsync(s->vg, p->v_gamma, Nb * sizeof(double), hipMemcpyDeviceToDevice, d->stream) != hipSuccess)
+            st = KFBI_EDEVICE;
+    }
+    if (st == KFBI_OK && (s->v || s->vg) && hipStreamSynchronize(d->stream) != hipSuccess) st = KFBI_EDEVICE;
+    s->p.v_grid = s->v;
+    s->p.v_gamma = s->vg;
     // every state buffer starts at zero (the checkpoint of a stepper is then
     // a function of its steps alone, also for buffers its equation leaves unused)
     void *zero_bufs[5] = {s->A, s->Ag, s->B, s->Bg, s->phi};
@@ -727,11 +744,11 @@ int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, cons
     if (s->eq != KFBI_SCHRODINGER || !s->initialized) { set_error("not an initialised Schroedinger stepper"); return KFBI_EINVAL; }
     kfbi_domain *d = s->dom;
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
-    k_schr_b<<<(ng + 255) / 256, 256, 0, d->stream>>>(ng, (cd *)s->A, (const double *)s->p.v_grid, s->p.w,
-                                                     s->p.tau, (cd *)s->f);
+    k_schr_b<<<(ng + 255) / 256, 256, 0, d->stream>>>(ng, (cd *)s->A, (const double *)s->v, s->p.w, s->p.tau,
+                                                     (cd *)s->f);
     KFBI_CHECK_LAUNCH();
-    k_schr_b<<<(Nb + 255) / 256, 256, 0, d->stream>>>(Nb, (cd *)s->Ag, (const double *)s->p.v_gamma, s->p.w,
-                                                     s->p.tau, (cd *)s->fg);
+    k_schr_b<<<(Nb + 255) / 256, 256, 0, d->stream>>>(Nb, (cd *)s->Ag, (const double *)s->vg, s->p.w, s->p.tau,
+                                                     (cd *)s->fg);
     KFBI_CHECK_LAUNCH();
     const void *tr = nullptr;
     int st = step_solve(s, g_next, u_out, opts, stats, &tr);

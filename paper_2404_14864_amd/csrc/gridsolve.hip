@@ -125,17 +125,55 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
         a[bitrev(m, logN2)] = make_double2(re, im);
     }
     __syncthreads();
-    // in-place radix-2 decimation-in-time, twiddle exp(-2 pi i m / N2)
-    for (int len = 2, tstep = M; len <= N2; len <<= 1, tstep >>= 1) {
-        int half = len >> 1;
+    // in-place radix-2 decimation-in-time, twiddle exp(-2 pi i m / N2).
+    // Consecutive stages are taken in pairs: each thread carries a group of
+    // four points through both stages in registers (the same butterflies in
+    // the same order), so there is one barrier per pair of stages.  An odd
+    // number of stages starts with a single one.
+    int len = 2, tstep = M;
+    if (logN2 & 1) {
         for (int b = threadIdx.x; b < M; b += blockDim.x) {
-            int grp = b / half, pos = b - grp * half;
-            int i0 = grp * len + pos, i1 = i0 + half;
-            const double wr = twiddle[2 * pos * tstep], wi = twiddle[2 * pos * tstep + 1];
+            const int i0 = 2 * b, i1 = i0 + 1;
+            const double wr = twiddle[0], wi = twiddle[1];
             double2 u = a[i0], v = a[i1];
             double vr = v.x * wr - v.y * wi, vi = v.x * wi + v.y * wr;
             a[i0] = make_double2(u.x + vr, u.y + vi);
             a[i1] = make_double2(u.x - vr, u.y - vi);
+        }
+        __syncthreads();
+        len = 4;
+        tstep = M >> 1;
+    }
+    for (; len <= M; len <<= 2, tstep >>= 2) {
+        const int half = len >> 1, tstep2 = tstep >> 1;
+        for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
+            const int grp = b / half, pos = b - grp * half;
+            const int i0 = grp * 2 * len + pos, i1 = i0 + half, i2 = i0 + len, i3 = i2 + half;
+            double2 x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
+            // stage of length len: (i0, i1) and (i2, i3), twiddle of pos
+            {
+                const double wr = twiddle[2 * pos * tstep], wi = twiddle[2 * pos * tstep + 1];
+                double vr = x1.x * wr - x1.y * wi, vi = x1.x * wi + x1.y * wr;
+                x1 = make_double2(x0.x - vr, x0.y - vi);
+                x0 = make_double2(x0.x + vr, x0.y + vi);
+                vr = x3.x * wr - x3.y * wi;
+                vi = x3.x * wi + x3.y * wr;
+                x3 = make_double2(x2.x - vr, x2.y - vi);
+                x2 = make_double2(x2.x + vr, x2.y + vi);
+            }
+            // stage of length 2 len: (i0, i2) at pos and (i1, i3) at pos + half
+            {
+                double wr = twiddle[2 * pos * tstep2], wi = twiddle[2 * pos * tstep2 + 1];
+                double vr = x2.x * wr - x2.y * wi, vi = x2.x * wi + x2.y * wr;
+                a[i0] = make_double2(x0.x + vr, x0.y + vi);
+                a[i2] = make_double2(x0.x - vr, x0.y - vi);
+                wr = twiddle[2 * (pos + half) * tstep2];
+                wi = twiddle[2 * (pos + half) * tstep2 + 1];
+                vr = x3.x * wr - x3.y * wi;
+                vi = x3.x * wi + x3.y * wr;
+                a[i1] = make_double2(x1.x + vr, x1.y + vi);
+                a[i3] = make_double2(x1.x - vr, x1.y - vi);
+            }
         }
         __syncthreads();
     }
