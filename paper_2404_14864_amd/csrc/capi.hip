@@ -107,9 +107,16 @@ __global__ void k_lin4(int n, T *out, T c0, const T *x0, T c1, const T *x1, T c2
 
 // Schroedinger B-step in closed form, in place on u (u* -> u**), and
 // f = -kappa u** with kappa = 2i/tau
-__global__ void k_schr_b(int n, cd *u, const double *v, double w, double tau, cd *f) {
+// on the grid (indices below ng) and on Gamma (the next nb) in one launch
+__global__ void k_schr_b(int ng, int nb, cd *ugr, const double *vgr, cd *fgr, cd *uga, const double *vga, cd *fga,
+                         double w, double tau) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const bool grid = i < ng;
+    if (!grid) i -= ng;
+    if (i >= (grid ? ng : nb)) return;
+    cd *u = grid ? ugr : uga;
+    const double *v = grid ? vgr : vga;
+    cd *f = grid ? fgr : fga;
     cd us = u[i];
     double beta = 0.5 * tau * ((v ? v[i] : 0.0) + w * abs2(us));
     cd uss = us * make_cd(1.0, -beta) / make_cd(1.0, beta);
@@ -125,6 +132,43 @@ int lin4(kfbi_domain *d, int n, void *out, T c0, const void *x0, T c1 = zero<T>(
                                                        (const T *)x2, c3, (const T *)x3);
     KFBI_CHECK_LAUNCH();
     return KFBI_OK;
+}
+
+// the same combination on the grid and on Gamma in one launch: indices
+// below ng address the grid arrays, the next nb the Gamma arrays
+template <class T>
+struct Lin4Set {
+    T *out;
+    const T *x0, *x1, *x2, *x3;
+};
+
+template <class T>
+__global__ void k_lin4_pair(int ng, int nb, Lin4Set<T> g, Lin4Set<T> b, T c0, T c1, T c2, T c3) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool grid = i < ng;
+    if (!grid) i -= ng;
+    if (i >= (grid ? ng : nb)) return;
+    const Lin4Set<T> &P = grid ? g : b;
+    T acc = zero<T>();
+    if (P.x0) acc += c0 * P.x0[i];
+    if (P.x1) acc += c1 * P.x1[i];
+    if (P.x2) acc += c2 * P.x2[i];
+    if (P.x3) acc += c3 * P.x3[i];
+    P.out[i] = acc;
+}
+
+template <class T>
+int lin4_pair(kfbi_domain *d, int ng, int nb, Lin4Set<T> g, Lin4Set<T> b, T c0, T c1 = zero<T>(),
+              T c2 = zero<T>(), T c3 = zero<T>()) {
+    k_lin4_pair<T><<<(ng + nb + 255) / 256, 256, 0, d->stream>>>(ng, nb, g, b, c0, c1, c2, c3);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+template <class T>
+Lin4Set<T> lset(void *out, const void *x0, const void *x1 = nullptr, const void *x2 = nullptr,
+                const void *x3 = nullptr) {
+    return Lin4Set<T>{(T *)out, (const T *)x0, (const T *)x1, (const T *)x2, (const T *)x3};
 }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -265,11 +309,10 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
         const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
         if (s->eq == KFBI_HEAT) {
             const void *sg = src_grid ? src_grid[q] : nullptr, *sgg = src_gamma ? src_gamma[q] : nullptr;
-            KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A, -1.0, sg));
-            KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag, -1.0, sgg));
+            KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->f, s->A, sg), lset<double>(s->fg, s->Ag, sgg), -1.0,
+                                       -1.0));
         } else {
-            KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A));
-            KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag));
+            KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->f, s->A), lset<double>(s->fg, s->Ag), -1.0));
         }
         kap[q] = s->kre;
         f[q] = s->f;
@@ -288,12 +331,12 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
         kfbi_domain *d = s->dom;
         const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
         if (s->eq == KFBI_HEAT) {
-            KFBI_TRY(lin4<double>(d, ng, s->A, 2.0 * s->kre, u_out[q], 1.0, s->f));
-            KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * s->kre, g_next[q], 1.0, s->fg));
+            KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->A, u_out[q], s->f),
+                                       lset<double>(s->Ag, g_next[q], s->fg), 2.0 * s->kre, 1.0));
         } else {
             const double th = s->p.theta, c1 = (1.0 - 2.0 * th) / th, a = s->kre / th;
-            KFBI_TRY(lin4<double>(d, ng, s->B, a, u_out[q], -c1, s->A, -1.0, s->B));
-            KFBI_TRY(lin4<double>(d, Nb, s->Bg, a, g_next[q], -c1, s->Ag, -1.0, s->Bg));
+            KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->B, u_out[q], s->A, s->B),
+                                       lset<double>(s->Bg, g_next[q], s->Ag, s->Bg), a, -c1, -1.0));
             std::swap(s->A, s->B);
             std::swap(s->Ag, s->Bg);
         }
@@ -708,13 +751,13 @@ int kfbi_step_heat(kfbi_stepper *s, const void *g_next, const void *src, const v
     if (s->eq != KFBI_HEAT || !s->initialized) { set_error("not an initialised heat stepper"); return KFBI_EINVAL; }
     kfbi_domain *d = s->dom;
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
-    KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A, -1.0, src));
-    KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag, -1.0, srcg));
+    KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->f, s->A, src), lset<double>(s->fg, s->Ag, srcg), -1.0,
+                               -1.0));
     const void *tr = nullptr;
     int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
-    KFBI_TRY(lin4<double>(d, ng, s->A, 2.0 * s->kre, u_out, 1.0, s->f));
-    KFBI_TRY(lin4<double>(d, Nb, s->Ag, 2.0 * s->kre, tr, 1.0, s->fg));
+    KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->A, u_out, s->f), lset<double>(s->Ag, tr, s->fg),
+                               2.0 * s->kre, 1.0));
     return st;
 }
 
@@ -724,15 +767,14 @@ int kfbi_step_wave(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_
     if (s->eq != KFBI_WAVE || !s->initialized) { set_error("not an initialised wave stepper"); return KFBI_EINVAL; }
     kfbi_domain *d = s->dom;
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
-    KFBI_TRY(lin4<double>(d, ng, s->f, -1.0, s->A));
-    KFBI_TRY(lin4<double>(d, Nb, s->fg, -1.0, s->Ag));
+    KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->f, s->A), lset<double>(s->fg, s->Ag), -1.0));
     const void *tr = nullptr;
     int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
     const double th = s->p.theta, c1 = (1.0 - 2.0 * th) / th, a = s->kre / th;
     // F^{n+2} into the F^n buffer, then swap
-    KFBI_TRY(lin4<double>(d, ng, s->B, a, u_out, -c1, s->A, -1.0, s->B));
-    KFBI_TRY(lin4<double>(d, Nb, s->Bg, a, tr, -c1, s->Ag, -1.0, s->Bg));
+    KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->B, u_out, s->A, s->B), lset<double>(s->Bg, tr, s->Ag, s->Bg),
+                               a, -c1, -1.0));
     std::swap(s->A, s->B);
     std::swap(s->Ag, s->Bg);
     return st;
@@ -744,18 +786,15 @@ int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, cons
     if (s->eq != KFBI_SCHRODINGER || !s->initialized) { set_error("not an initialised Schroedinger stepper"); return KFBI_EINVAL; }
     kfbi_domain *d = s->dom;
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
-    k_schr_b<<<(ng + 255) / 256, 256, 0, d->stream>>>(ng, (cd *)s->A, (const double *)s->v, s->p.w, s->p.tau,
-                                                     (cd *)s->f);
-    KFBI_CHECK_LAUNCH();
-    k_schr_b<<<(Nb + 255) / 256, 256, 0, d->stream>>>(Nb, (cd *)s->Ag, (const double *)s->vg, s->p.w, s->p.tau,
-                                                     (cd *)s->fg);
+    k_schr_b<<<(ng + Nb + 255) / 256, 256, 0, d->stream>>>(ng, Nb, (cd *)s->A, (const double *)s->v, (cd *)s->f,
+                                                          (cd *)s->Ag, (const double *)s->vg, (cd *)s->fg, s->p.w,
+                                                          s->p.tau);
     KFBI_CHECK_LAUNCH();
     const void *tr = nullptr;
     int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
     const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
-    KFBI_TRY(lin4<cd>(d, ng, s->A, two, u_out, m1, s->A));
-    KFBI_TRY(lin4<cd>(d, Nb, s->Ag, two, tr, m1, s->Ag));
+    KFBI_TRY(lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u_out, s->A), lset<cd>(s->Ag, tr, s->Ag), two, m1));
     return st;
 }
 
