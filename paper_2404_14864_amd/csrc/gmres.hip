@@ -680,7 +680,10 @@ template <class T>
 struct GmInitArgs {
     const int *off;  // nonzero: member not solved in this call (batched solves)
     GmCtl *ctl;
-    const T *b, *x;
+    const T *b;
+    T *x;
+    const T *x0;  // the start: == x (already in place), another array (copied
+                  // into x), or null (zero)
     T *vcur;
     int Nb, max_iter, m, fixed;
     double tol, eta;
@@ -692,7 +695,8 @@ __device__ void gm_init_body(const GmInitArgs<T> &A, int) {
     if (A.off && *A.off) return;
     GmCtl *ctl = A.ctl;
     const T *__restrict__ b = A.b;
-    const T *__restrict__ x = A.x;
+    T *x = A.x;
+    const T *x0 = A.x0;
     T *__restrict__ vcur = A.vcur;
     const int Nb = A.Nb, max_iter = A.max_iter, m = A.m, fixed = A.fixed, mixed = A.mixed;
     const double tol = A.tol, eta = A.eta;
@@ -700,7 +704,14 @@ __device__ void gm_init_body(const GmInitArgs<T> &A, int) {
     double s = 0.0;
     for (int k = threadIdx.x; k < Nb; k += blockDim.x) {
         s += abs2(b[k]);
-        vcur[k] = x[k];
+        T v;
+        if (x0 == x) {
+            v = x[k];
+        } else {
+            v = x0 ? x0[k] : zero<T>();
+            x[k] = v;
+        }
+        vcur[k] = v;
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
@@ -1351,12 +1362,13 @@ static size_t slot_lds(int Nb, int m, int *nvl_out) {
 }
 
 template <class T>
-GmInitArgs<T> gm_init_args(GmPtrs &P, int Nb, const kfbi_solve_opts &o, bool mixed) {
+GmInitArgs<T> gm_init_args(GmPtrs &P, int Nb, const kfbi_solve_opts &o, bool mixed, const void *x0) {
     GmInitArgs<T> A;
     A.off = nullptr;
     A.ctl = P.ctl;
     A.b = (const T *)P.b;
-    A.x = (const T *)P.x;
+    A.x = (T *)P.x;
+    A.x0 = (const T *)x0;
     A.vcur = (T *)P.vcur;
     A.Nb = Nb;
     A.max_iter = o.max_iter;
@@ -1431,8 +1443,8 @@ static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index,
 // on the pinned mirror of the control block, not on the stream, so it
 // returns while the final solve is still running.
 template <class T, class Tail>
-static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, bool mixed, Tail &&tail,
-                           int *iters_out, double *rel_out, int *conv_out, int *cycles_out) {
+static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi_solve_opts &o, bool mixed,
+                           Tail &&tail, int *iters_out, double *rel_out, int *conv_out, int *cycles_out) {
     const bool rich = (o.flags & KFBI_SOLVE_RICHARDSON) != 0;
     hipStream_t s = d->stream;
     const int Nb = d->Nb, m = o.restart;
@@ -1444,7 +1456,7 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const kfbi_solve_opts &o, 
     GmMirror *mh = (GmMirror *)d->mirror_host;
     __atomic_store_n(&mh->seq, 0, __ATOMIC_RELEASE);
     const int fixed = o.fixed_iters > 0 ? o.fixed_iters : 0;
-    k_gm_init<T><<<1, kGmThreads, 0, s>>>(gm_init_args<T>(P, Nb, o, mixed));
+    k_gm_init<T><<<1, kGmThreads, 0, s>>>(gm_init_args<T>(P, Nb, o, mixed, x0));
     KFBI_CHECK_LAUNCH();
     const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
     // first batch: the previous solve's slot count on this domain plus one
@@ -1669,8 +1681,6 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     } else {
         KFBI_HIP(hipMemcpyAsync(P.b, g_gamma, vb, hipMemcpyDeviceToDevice, s));
     }
-    if (phi_inout) KFBI_HIP(hipMemcpyAsync(P.x, phi_inout, vb, hipMemcpyDeviceToDevice, s));
-    else KFBI_HIP(hipMemsetAsync(P.x, 0, vb, s));
     int iters = 0, conv = 0, cycles = 0;
     double rel = 0.0;
     int st;
@@ -1705,10 +1715,13 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
         return KFBI_ENOTSUP;
     }
     if (slots) {
-        if (d->cplx) st = gmres_run_slots<cd>(d, P, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
-        else st = gmres_run_slots<double>(d, P, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
+        // the start vector is placed by the schedule's first kernel
+        if (d->cplx) st = gmres_run_slots<cd>(d, P, phi_inout, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
+        else st = gmres_run_slots<double>(d, P, phi_inout, o, mixed, final_solve, &iters, &rel, &conv, &cycles);
         if (st != KFBI_OK) return st;
     } else {
+        if (phi_inout) KFBI_HIP(hipMemcpyAsync(P.x, phi_inout, vb, hipMemcpyDeviceToDevice, s));
+        else KFBI_HIP(hipMemsetAsync(P.x, 0, vb, s));
         if (d->cplx) st = gmres_run<cd>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
         else st = gmres_run<double>(d, kre, kim, P, o, mixed, &iters, &rel, &conv, &cycles);
         if (st != KFBI_OK) return st;
@@ -2163,7 +2176,7 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         batch_fill_ext(d, kappa[q], d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, one, at(kUExtB));
         *(CopyArgs *)at(kUCopyX) = CopyArgs{(double *)P.x, phi_inout ? (const double *)phi_inout[q] : nullptr,
                                             d->Nb, one};
-        GmInitArgs<double> ia = gm_init_args<double>(P, d->Nb, o, mixed);
+        GmInitArgs<double> ia = gm_init_args<double>(P, d->Nb, o, mixed, P.x);
         ia.off = one;
         *(GmInitArgs<double> *)at(kUInit) = ia;
         batch_fill_corr_phi(d, P.vcur, d->corr, skip64, at(kUCorrPhi64));
