@@ -3,7 +3,7 @@ same seeded synthetic inputs.
 
 Bars: node classification and irregular-node lists bit-exact; crossings and
 collocation geometry to 1e-13; every floating-point result of the FP64 path
-within 1e-10 relative (the spec bar; most land near 1e-13), with GMRES
+within 1e-10 relative (the FP64 tolerance of the path; most land near 1e-13), with GMRES
 run for the same fixed number of iterations on both sides where the
 iteration itself is compared (reading R20).
 """
