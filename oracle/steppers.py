@@ -28,6 +28,15 @@ after them; i u_t = lap u + v u + w|u|^2 u as in eq. 2.2; reading R16):
            (the Crank-Nicolson step of (3.10) solved in closed form; it
            keeps |u**| = |u*|, so the same beta holds on both sides),
     lap u^{n+1} - (2i/tau) u^{n+1} = -(2i/tau) u**.
+
+Schroedinger, Godunov (Lie) splitting u^{n+1} = S^A(tau) S^B(tau) u^n (the
+first-order splitting of section 1 and Example 7; reading R28): the B-step
+is the same closed-form Crank-Nicolson step of (3.10) over tau, applied to
+u^n itself; the A-step is the backward Euler step of (3.11) over the whole
+step tau, u^{n+1} + i tau lap u^{n+1} = u**, i.e.
+    lap u^{n+1} - (i/tau) u^{n+1} = -(i/tau) u**,
+so no Laplacian of a numerical solution is needed and the carried state is
+u^n (on Gamma its trace, g for the Dirichlet problem).
 """
 
 import numpy as np
@@ -113,14 +122,24 @@ class WaveStepper(_Base):
 
 class SchrodingerStepper(_Base):
     def __init__(self, dom, tau, u0, lap_u0, u0_gamma, lap_u0_gamma,
-                 v_grid, v_gamma, w=0.0, tol=1e-10, restart=50, max_iter=500, bc="dirichlet"):
+                 v_grid, v_gamma, w=0.0, tol=1e-10, restart=50, max_iter=500, bc="dirichlet",
+                 split="strang"):
         super().__init__(dom, tol, restart, max_iter, bc)
-        self.tau, self.w = tau, w
-        self.kappa = 2j / tau
+        if split not in ("strang", "godunov"):
+            raise ValueError("split must be 'strang' or 'godunov'")
+        self.tau, self.w, self.split = tau, w, split
         self.v, self.v_gamma = v_grid, v_gamma
-        self.ustar = np.asarray(u0, dtype=np.complex128) - 0.5j * tau * lap_u0
-        self.ustar_gamma = (np.asarray(u0_gamma, dtype=np.complex128)
-                            - 0.5j * tau * lap_u0_gamma)
+        if split == "strang":
+            # u* of the first step: the forward half step of the A part
+            self.kappa = 2j / tau
+            self.ustar = np.asarray(u0, dtype=np.complex128) - 0.5j * tau * lap_u0
+            self.ustar_gamma = (np.asarray(u0_gamma, dtype=np.complex128)
+                                - 0.5j * tau * lap_u0_gamma)
+        else:
+            # Godunov: the B-step acts on u^n itself
+            self.kappa = 1j / tau
+            self.ustar = np.array(u0, dtype=np.complex128)
+            self.ustar_gamma = np.array(u0_gamma, dtype=np.complex128)
 
     def _b_step(self, us, v):
         beta = 0.5 * self.tau * (v + self.w * np.abs(us) ** 2)
@@ -132,6 +151,12 @@ class SchrodingerStepper(_Base):
         g_next = np.asarray(g_next, dtype=np.complex128)
         U, tr = self._solve(-self.kappa * uss, -self.kappa * uss_g, g_next,
                             fixed_iters)
-        self.ustar = 2.0 * U - uss
-        self.ustar_gamma = 2.0 * tr - uss_g
+        if self.split == "strang":
+            # u* of the next step, u^{n+1} - i tau/2 lap u^{n+1}, from (3.12):
+            # i tau/2 lap u^{n+1} = u** - u^{n+1}
+            self.ustar = 2.0 * U - uss
+            self.ustar_gamma = 2.0 * tr - uss_g
+        else:
+            self.ustar = U
+            self.ustar_gamma = np.array(tr, dtype=np.complex128)
         return U

@@ -164,3 +164,57 @@ def test_nonlinear_schrodinger_example_second_order():
     assert abs(_order(errs) - 2.0) < 0.4, errs
     for e, p in zip(errs, t4[:3]):
         assert abs(e / p - 1.0) < 0.05, (errs, t4)
+
+
+def test_godunov_split_is_backward_euler_for_the_free_equation():
+    """Godunov splitting with v = 0, w = 0 is the backward Euler step of
+    (3.11) over tau: for the eigenfunction phi = sin(pi x) sin(pi y)
+    (lap phi = -2 pi^2 phi) its discrete solution is rho^n phi with
+    rho = 1 / (1 - 2 pi^2 i tau).  Fed that Dirichlet data, the stepper
+    reproduces rho^n phi up to the O(h^2) space error; fed the exact data
+    exp(i 2 pi^2 t) phi, its error halves with tau (first order in time)."""
+    e_be, e_ex = [], []
+    for M in (64, 128):
+        d = Domain(W.domain_c3_schrodinger(M))
+        tau = d.h / 2
+        zx, zy = d.colloc["x"], d.colloc["y"]
+        phi_g = np.sin(np.pi * d.X) * np.sin(np.pi * d.Y)
+        phi_b = np.sin(np.pi * zx) * np.sin(np.pi * zy)
+        rho = 1.0 / (1.0 - 2j * np.pi ** 2 * tau)
+        n = int(round(0.125 / tau))
+        for data, out in ((lambda k: rho ** k * phi_b, e_be), (lambda k: mf.schr_free_u(zx, zy, k * tau), e_ex)):
+            st = SchrodingerStepper(d, tau, phi_g + 0j, -2 * np.pi ** 2 * phi_g, phi_b + 0j,
+                                    -2 * np.pi ** 2 * phi_b, np.zeros_like(d.X), np.zeros_like(zx),
+                                    split="godunov", tol=1e-12)
+            for k in range(n):
+                U = st.step(data(k + 1))
+            exact = rho ** n * phi_g if out is e_be else mf.schr_free_u(d.X, d.Y, n * tau)
+            out.append(max_norm(U - exact, d.inside))
+    assert e_be[-1] < 5e-5 and e_be[0] / e_be[1] > 2.8, e_be
+    assert 1.8 < e_ex[0] / e_ex[1] < 2.2, e_ex
+    assert e_ex[-1] > 100 * e_be[-1]
+
+
+def test_godunov_split_nonlinear_example_first_order():
+    """The paper's nonlinear example (w = 1, v of eq. 4.3, exact solution
+    eq. 4.4, tau = 8/M, T = 1) with Godunov splitting: the error falls at
+    about first order (ratios 1.54 and 1.60 from M = 32 to 128, rising toward
+    2), and it stays well above the Strang splitting's -- the ordering the
+    paper's comparison example reports (Table 5)."""
+    errs, strang = [], []
+    for M in (32, 64, 128):
+        d = Domain(W.domain_nls_example(M))
+        X, Y, zx, zy = d.X, d.Y, d.colloc["x"], d.colloc["y"]
+        tau = 8.0 / M
+        n = int(round(1.0 / tau))
+        for split, out in (("godunov", errs), ("strang", strang)):
+            st = SchrodingerStepper(d, tau, mf.nls_u(X, Y, 0), mf.nls_lap(X, Y, 0), mf.nls_u(zx, zy, 0),
+                                    mf.nls_lap(zx, zy, 0), mf.nls_potential(X, Y), mf.nls_potential(zx, zy),
+                                    w=1.0, tol=1e-12, split=split)
+            for k in range(n):
+                U = st.step(mf.nls_u(zx, zy, (k + 1) * tau))
+            out.append(max_norm(U - mf.nls_u(X, Y, n * tau), d.inside))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert all(1.4 < r < 2.2 for r in ratios), errs
+    assert ratios[1] > ratios[0]
+    assert all(g > 3.0 * s for g, s in zip(errs[1:], strang[1:])), (errs, strang)
