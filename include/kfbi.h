@@ -60,6 +60,14 @@ typedef enum { KFBI_REAL = 0, KFBI_COMPLEX = 1 } kfbi_scalar;
 typedef enum { KFBI_PREC_FP64 = 0, KFBI_PREC_MIXED = 1 } kfbi_precision;
 typedef enum { KFBI_HEAT = 0, KFBI_WAVE = 1, KFBI_SCHRODINGER = 2 } kfbi_equation;
 typedef enum { KFBI_BC_DIRICHLET = 0, KFBI_BC_NEUMANN = 1 } kfbi_boundary_condition;
+/* Operator splitting of the Schroedinger step (section 3.1; the comparison
+ * of section 4.1, Example 7).  STRANG: S^A(tau/2) S^B(tau) S^A(tau/2), the
+ * three-step algorithm after eq. 3.12, second order, kappa = 2i/tau.
+ * GODUNOV: S^A(tau) S^B(tau), first order: the closed-form Crank-Nicolson
+ * B-step of eq. 3.10 over tau applied to u^n, then the backward-Euler A-step
+ * of eq. 3.11 over tau, lap u^{n+1} - (i/tau) u^{n+1} = -(i/tau) u**,
+ * kappa = i/tau. */
+typedef enum { KFBI_SPLIT_STRANG = 0, KFBI_SPLIT_GODUNOV = 1 } kfbi_split;
 
 /* Domain description (section 3.2.4 grid, Procedure 1 of section 3.3).
  * Curves, counter-clockwise in theta in [0, 2 pi):
@@ -90,7 +98,8 @@ typedef struct {
     int32_t n_irregular;  /* interior nodes with a 4-neighbour on the other
                              side of Gamma (section 3.2.4)                  */
     int32_t n_edges;      /* grid edges crossed by Gamma                    */
-    int32_t pad;
+    int32_t scalar;       /* kfbi_scalar of the domain: element type of its
+                             arrays (float64 or interleaved complex128)    */
     uint64_t device_bytes;/* device memory held by the domain               */
     uint64_t device_bytes_max; /* what it holds once every solve has run:
                              the per-kappa operator tables and the FP32 tables
@@ -239,7 +248,9 @@ int kfbi_neumann_solve(kfbi_domain *dom, double kappa_re, double kappa_im,
  *   WAVE: u_tt = lap u; implicit theta-scheme (eq. 3.5), kappa = 1/(theta
  *         tau^2); theta in (0, 1/2].
  *   SCHRODINGER: i u_t = lap u + v u + w |u|^2 u (eq. 2.2); Strang splitting,
- *         kappa = 2i/tau; v_grid / v_gamma are device arrays (float64) of the
+ *         kappa = 2i/tau, or Godunov splitting, kappa = i/tau (split, see
+ *         kfbi_split; any other value is KFBI_EINVAL); the carried state is
+ *         u* for Strang and u^n for Godunov; v_grid / v_gamma are device arrays (float64) of the
  *         potential on the grid and at the collocation points (nullable: 0),
  *         copied by kfbi_stepper_create (which waits for the copy), so they
  *         need not outlive the call.
@@ -255,7 +266,7 @@ typedef struct {
     const void *v_grid;
     const void *v_gamma;
     int32_t bc;
-    int32_t pad;
+    int32_t split;       /* SCHRODINGER only: kfbi_split (0, Strang, by default) */
 } kfbi_step_params;
 
 int kfbi_stepper_create(kfbi_domain *dom, int32_t equation,
@@ -297,7 +308,9 @@ int kfbi_step_heat(kfbi_stepper *st, const void *g_next_gamma, const void *src_g
 int kfbi_step_wave(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
-/* One Strang-splitting step (the three-step algorithm after eq. 3.12). */
+/* One Schroedinger step: the Strang three-step algorithm after eq. 3.12, or
+ * the Godunov step S^A(tau) S^B(tau) of a stepper created with
+ * KFBI_SPLIT_GODUNOV (see kfbi_split). */
 int kfbi_step_schrodinger(kfbi_stepper *st, const void *g_next_gamma, void *u_grid_out,
                           const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 

@@ -105,11 +105,12 @@ __global__ void k_lin4(int n, T *out, T c0, const T *x0, T c1, const T *x1, T c2
     out[i] = acc;
 }
 
-// Schroedinger B-step in closed form, in place on u (u* -> u**), and
-// f = -kappa u** with kappa = 2i/tau
-// on the grid (indices below ng) and on Gamma (the next nb) in one launch
+// Schroedinger B-step in closed form (the Crank-Nicolson step of eq. 3.10
+// over tau), in place on u (u* -> u**), and f = -kappa u** with
+// kappa = i kim (2i/tau for Strang, i/tau for Godunov), on the grid (indices
+// below ng) and on Gamma (the next nb) in one launch
 __global__ void k_schr_b(int ng, int nb, cd *ugr, const double *vgr, cd *fgr, cd *uga, const double *vga, cd *fga,
-                         double w, double tau) {
+                         double w, double tau, double kim) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool grid = i < ng;
     if (!grid) i -= ng;
@@ -121,8 +122,8 @@ __global__ void k_schr_b(int ng, int nb, cd *ugr, const double *vgr, cd *fgr, cd
     double beta = 0.5 * tau * ((v ? v[i] : 0.0) + w * abs2(us));
     cd uss = us * make_cd(1.0, -beta) / make_cd(1.0, beta);
     u[i] = uss;
-    // -(2i/tau) uss
-    f[i] = make_cd(2.0 / tau * uss.y, -2.0 / tau * uss.x);
+    // -(i kim) uss
+    f[i] = make_cd(kim * uss.y, -kim * uss.x);
 }
 
 template <class T>
@@ -445,6 +446,7 @@ int kfbi_domain_get_info(const kfbi_domain *d, kfbi_domain_info *out) {
     out->n_inside = d->n_inside;
     out->n_irregular = d->n_irr;
     out->n_edges = d->n_edges;
+    out->scalar = d->cplx ? KFBI_COMPLEX : KFBI_REAL;
     out->device_bytes = d->bytes;
     out->device_bytes_max = d->bytes + operators_bytes_pending(d) + low_tables_bytes_pending(d);
     return KFBI_OK;
@@ -579,8 +581,13 @@ int kfbi_stepper_create(kfbi_domain *d, int32_t eq, const kfbi_step_params *p, k
         if (!(p->theta > 0 && p->theta <= 0.5)) { delete s; set_error("theta must be in (0, 1/2]"); return KFBI_EINVAL; }
         s->kre = 1.0 / (p->theta * p->tau * p->tau);
     } else {
+        if (p->split != KFBI_SPLIT_STRANG && p->split != KFBI_SPLIT_GODUNOV) {
+            delete s;
+            set_error("unknown splitting");
+            return KFBI_EINVAL;
+        }
         s->kre = 0.0;
-        s->kim = 2.0 / p->tau;
+        s->kim = (p->split == KFBI_SPLIT_GODUNOV ? 1.0 : 2.0) / p->tau;
     }
     const size_t es = elem_size(d), nodes = (size_t)(d->M + 1) * (d->M + 1), Nb = d->Nb;
     int st = KFBI_OK;
@@ -724,8 +731,8 @@ int kfbi_stepper_init(kfbi_stepper *s, const void *u0, const void *lap0, const v
         KFBI_TRY(lin4<double>(d, ng, s->B, k, u0, -1.0, lap0));
         KFBI_TRY(lin4<double>(d, Nb, s->Bg, k, u0g, -1.0, lap0g));
     } else {
-        // u*^0 = u^0 - i tau/2 lap u^0
-        const cd c = make_cd(0.0, -0.5 * s->p.tau);
+        // Strang: u*^0 = u^0 - i tau/2 lap u^0;  Godunov: the state is u^0
+        const cd c = make_cd(0.0, s->p.split == KFBI_SPLIT_GODUNOV ? 0.0 : -0.5 * s->p.tau);
         KFBI_TRY(lin4<cd>(d, ng, s->A, make_cd(1.0, 0.0), u0, c, lap0));
         KFBI_TRY(lin4<cd>(d, Nb, s->Ag, make_cd(1.0, 0.0), u0g, c, lap0g));
     }
@@ -788,13 +795,19 @@ int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, cons
     const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
     k_schr_b<<<(ng + Nb + 255) / 256, 256, 0, d->stream>>>(ng, Nb, (cd *)s->A, (const double *)s->v, (cd *)s->f,
                                                           (cd *)s->Ag, (const double *)s->vg, (cd *)s->fg, s->p.w,
-                                                          s->p.tau);
+                                                          s->p.tau, s->kim);
     KFBI_CHECK_LAUNCH();
     const void *tr = nullptr;
     int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
-    const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
-    KFBI_TRY(lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u_out, s->A), lset<cd>(s->Ag, tr, s->Ag), two, m1));
+    if (s->p.split == KFBI_SPLIT_GODUNOV) {
+        // the next B-step acts on u^{n+1} itself
+        KFBI_TRY(lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u_out), lset<cd>(s->Ag, tr), make_cd(1.0, 0.0)));
+    } else {
+        // u* of the next step, u^{n+1} - i tau/2 lap u^{n+1} = 2 u^{n+1} - u** (eq. 3.12)
+        const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
+        KFBI_TRY(lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u_out, s->A), lset<cd>(s->Ag, tr, s->Ag), two, m1));
+    }
     return st;
 }
 

@@ -24,6 +24,7 @@ KFBI_BATCH_NO_TUNE = 2
 KFBI_SOLVE_RICHARDSON = 4
 KFBI_HEAT, KFBI_WAVE, KFBI_SCHRODINGER = 0, 1, 2
 KFBI_BC_DIRICHLET, KFBI_BC_NEUMANN = 0, 1
+KFBI_SPLIT_STRANG, KFBI_SPLIT_GODUNOV = 0, 1
 
 
 class KfbiError(RuntimeError):
@@ -46,7 +47,7 @@ class DomainInfo(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("Nb", ctypes.c_int32), ("L", ctypes.c_double),
                 ("h", ctypes.c_double), ("n_inside", ctypes.c_int32),
                 ("n_irregular", ctypes.c_int32), ("n_edges", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("scalar", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
                 ("device_bytes_max", ctypes.c_uint64)]
 
 
@@ -72,7 +73,7 @@ class StepParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("theta", ctypes.c_double),
                 ("diffusivity", ctypes.c_double), ("w", ctypes.c_double),
                 ("v_grid", ctypes.c_void_p), ("v_gamma", ctypes.c_void_p),
-                ("bc", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("bc", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 class KernelProf(ctypes.Structure):
@@ -169,11 +170,32 @@ def kfbi_batch_create(domains):
     arr = (_P * n)(*[d.value if isinstance(d, ctypes.c_void_p) else d for d in domains])
     out = _P()
     _check(lib().kfbi_batch_create(arr, n, ctypes.byref(out)))
+    _BATCHES[out.value] = [_hv(d) for d in domains]
     return out
 
 
 def kfbi_batch_destroy(b):
     _check(lib().kfbi_batch_destroy(b))
+    _BATCHES.pop(_hv(b), None)
+
+
+def _batch_doms(b, n):
+    doms = _BATCHES.get(_hv(b))
+    if doms is None:
+        raise ValueError("unknown batch handle (not created by kfbi_batch_create, or destroyed)")
+    if n != len(doms):
+        raise ValueError("the batch has %d members; got %d entries" % (len(doms), n))
+    return doms
+
+
+def _member_ptrs(doms, lst, name, grid):
+    if lst is None:
+        return None
+    if len(lst) != len(doms):
+        raise ValueError("%s needs one entry per member (%d), got %d" % (name, len(doms), len(lst)))
+    chk = _grid if grid else _gam
+    return (_P * len(doms))(*[(chk(h, t, "%s[%d]" % (name, q)).value if t is not None else None)
+                              for q, (h, t) in enumerate(zip(doms, lst))])
 
 
 def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, phi_inout=None, opts=None):
@@ -181,19 +203,14 @@ def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, p
     Gamma; all arguments are lists of float64 CUDA tensors (u_grid_out and
     phi_inout may be None or contain None).  Returns the per-member stats."""
     n = len(kappas)
-    if not (len(f_grid) == len(f_gamma) == len(g_gamma) == n):
-        raise ValueError("one entry per member is required")
+    doms = _batch_doms(b, n)
     kap = (ctypes.c_double * n)(*[float(k) for k in kappas])
-
-    def ptrs(lst, name):
-        if lst is None:
-            return None
-        return (_P * n)(*[(_ptr(t, torch.float64, None, name).value if t is not None else None) for t in lst])
-
     stats = (SolveStats * n)()
-    code = lib().kfbi_batch_helmholtz(b, kap, ptrs(f_grid, "f_grid"), ptrs(f_gamma, "f_gamma"),
-                                      ptrs(g_gamma, "g_gamma"), ptrs(u_grid_out, "u_grid_out"),
-                                      ptrs(phi_inout, "phi_inout"), _opts(opts), stats)
+    code = lib().kfbi_batch_helmholtz(b, kap, _member_ptrs(doms, f_grid, "f_grid", True),
+                                      _member_ptrs(doms, f_gamma, "f_gamma", False),
+                                      _member_ptrs(doms, g_gamma, "g_gamma", False),
+                                      _member_ptrs(doms, u_grid_out, "u_grid_out", True),
+                                      _member_ptrs(doms, phi_inout, "phi_inout", False), _opts(opts), stats)
     _check(code, allow=(KFBI_ENOCONV,))
     return [stats[q].as_dict() for q in range(n)]
 
@@ -205,19 +222,19 @@ def kfbi_batch_step(b, steppers, g_next, u_out, active=None, src_grid=None, src_
     members not active or without sources); active: booleans (None: all).
     Returns the per-member stats."""
     n = len(steppers)
-    if len(g_next) != n or len(u_out) != n:
-        raise ValueError("one entry per member is required")
-    st = (_P * n)(*[(x.value if isinstance(x, ctypes.c_void_p) else x) for x in steppers])
+    doms = _batch_doms(b, n)
+    for q, x in enumerate(steppers):
+        if _stepper_dom(x) != doms[q]:
+            raise ValueError("steppers[%d] is not on the batch's member domain %d" % (q, q))
+    if active is not None and len(active) != n:
+        raise ValueError("active needs one entry per member (%d), got %d" % (n, len(active)))
+    st = (_P * n)(*[_hv(x) for x in steppers])
     act = None if active is None else (ctypes.c_uint8 * n)(*[1 if a else 0 for a in active])
-
-    def ptrs(lst, name):
-        if lst is None:
-            return None
-        return (_P * n)(*[(_ptr(t, torch.float64, None, name).value if t is not None else None) for t in lst])
-
     stats = (SolveStats * n)()
-    code = lib().kfbi_batch_step(b, st, act, ptrs(g_next, "g_next"), ptrs(src_grid, "src_grid"),
-                                 ptrs(src_gamma, "src_gamma"), ptrs(u_out, "u_out"), _opts(opts), stats)
+    code = lib().kfbi_batch_step(b, st, act, _member_ptrs(doms, g_next, "g_next", False),
+                                 _member_ptrs(doms, src_grid, "src_grid", True),
+                                 _member_ptrs(doms, src_gamma, "src_gamma", False),
+                                 _member_ptrs(doms, u_out, "u_out", True), _opts(opts), stats)
     _check(code, allow=(KFBI_ENOCONV,))
     return [stats[q].as_dict() for q in range(n)]
 
@@ -271,6 +288,49 @@ def _ptr(t, dtype=None, numel=None, name="array"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# What the wrappers know of the handles they created: every array argument is
+# checked against its domain (element type and length) before the call, so a
+# wrong dtype or a short tensor is refused on the host instead of being read
+# or written past its end on the device.
+_DOMAINS = {}    # domain handle value -> (M, Nb, complex?)
+_STEPPERS = {}   # stepper handle value -> domain handle value
+_BATCHES = {}    # batch handle value -> [domain handle values]
+
+
+def _hv(h):
+    return h.value if isinstance(h, ctypes.c_void_p) else h
+
+
+def _meta(h):
+    v = _hv(h)
+    m = _DOMAINS.get(v)
+    if m is None:
+        info = DomainInfo()
+        _check(lib().kfbi_domain_get_info(h, ctypes.byref(info)))
+        m = (info.M, info.Nb, info.scalar == KFBI_COMPLEX)
+        _DOMAINS[v] = m
+    return m
+
+
+def _stepper_dom(s):
+    v = _hv(s)
+    if v not in _STEPPERS:
+        raise ValueError("unknown stepper handle (not created by kfbi_stepper_create, or destroyed)")
+    return _STEPPERS[v]
+
+
+def _grid(h, t, name):
+    """A grid array ((M+1)^2 elements of the domain's type) or None."""
+    M, _, c = _meta(h)
+    return _ptr(t, torch.complex128 if c else torch.float64, (M + 1) * (M + 1), name)
+
+
+def _gam(h, t, name):
+    """A Gamma array (Nb elements of the domain's type) or None."""
+    _, Nb, c = _meta(h)
+    return _ptr(t, torch.complex128 if c else torch.float64, Nb, name)
+
+
 def _opts(opts):
     if opts is None:
         return None
@@ -297,11 +357,13 @@ def kfbi_domain_create(desc, scalar=KFBI_REAL, precision=KFBI_PREC_FP64, stream=
                    precision=precision, stream=ctypes.c_void_p(stream))
     h = _P()
     _check(lib().kfbi_domain_create(ctypes.byref(d), ctypes.byref(h)))
+    _DOMAINS[h.value] = (desc["M"], desc["Nb"], scalar == KFBI_COMPLEX)
     return h
 
 
 def kfbi_domain_destroy(h):
     _check(lib().kfbi_domain_destroy(h))
+    _DOMAINS.pop(_hv(h), None)
 
 
 def kfbi_domain_get_info(h):
@@ -309,7 +371,8 @@ def kfbi_domain_get_info(h):
     _check(lib().kfbi_domain_get_info(h, ctypes.byref(info)))
     return {"M": info.M, "Nb": info.Nb, "L": info.L, "h": info.h, "n_inside": info.n_inside,
             "n_irregular": info.n_irregular, "n_edges": info.n_edges,
-            "device_bytes": int(info.device_bytes), "device_bytes_max": int(info.device_bytes_max)}
+            "scalar": info.scalar, "device_bytes": int(info.device_bytes),
+            "device_bytes_max": int(info.device_bytes_max)}
 
 
 def kfbi_domain_copy_classification(h):
@@ -350,20 +413,24 @@ def kfbi_domain_copy_edges(h):
 # ---- solves ----------------------------------------------------------------
 def kfbi_grid_solve(h, kappa, rhs, u_out):
     k = complex(kappa)
-    _check(lib().kfbi_grid_solve(h, k.real, k.imag, _ptr(rhs, name="rhs"), _ptr(u_out, name="u_out")))
+    if rhs is None or u_out is None:
+        raise ValueError("rhs and u_out are required")
+    _check(lib().kfbi_grid_solve(h, k.real, k.imag, _grid(h, rhs, "rhs"), _grid(h, u_out, "u_out")))
 
 
 def kfbi_interface_apply(h, kappa, f_grid, f_gamma, phi, u_grid_out, uplus_out):
     k = complex(kappa)
-    _check(lib().kfbi_interface_apply(h, k.real, k.imag, _ptr(f_grid), _ptr(f_gamma), _ptr(phi),
-                                      _ptr(u_grid_out), _ptr(uplus_out)))
+    _check(lib().kfbi_interface_apply(h, k.real, k.imag, _grid(h, f_grid, "f_grid"), _gam(h, f_gamma, "f_gamma"),
+                                      _gam(h, phi, "phi"), _grid(h, u_grid_out, "u_grid_out"),
+                                      _gam(h, uplus_out, "uplus_out")))
 
 
 def kfbi_helmholtz_solve(h, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout=None, opts=None):
     k = complex(kappa)
     st = SolveStats()
-    code = lib().kfbi_helmholtz_solve(h, k.real, k.imag, _ptr(f_grid), _ptr(f_gamma), _ptr(g_gamma),
-                                      _ptr(u_grid_out), _ptr(phi_inout), _opts(opts), ctypes.byref(st))
+    code = lib().kfbi_helmholtz_solve(h, k.real, k.imag, _grid(h, f_grid, "f_grid"), _gam(h, f_gamma, "f_gamma"),
+                                      _gam(h, g_gamma, "g_gamma"), _grid(h, u_grid_out, "u_grid_out"),
+                                      _gam(h, phi_inout, "phi_inout"), _opts(opts), ctypes.byref(st))
     _check(code, allow=(KFBI_ENOCONV,))
     return st.as_dict()
 
@@ -374,26 +441,30 @@ def kfbi_neumann_solve(h, kappa, f_grid, f_gamma, gn_gamma, u_grid_out, psi_inou
     (optional) receives u's interior limit at the collocation points."""
     k = complex(kappa)
     st = SolveStats()
-    code = lib().kfbi_neumann_solve(h, k.real, k.imag, _ptr(f_grid), _ptr(f_gamma), _ptr(gn_gamma),
-                                    _ptr(u_grid_out), _ptr(psi_inout), _ptr(trace_out), _opts(opts),
-                                    ctypes.byref(st))
+    code = lib().kfbi_neumann_solve(h, k.real, k.imag, _grid(h, f_grid, "f_grid"), _gam(h, f_gamma, "f_gamma"),
+                                    _gam(h, gn_gamma, "gn_gamma"), _grid(h, u_grid_out, "u_grid_out"),
+                                    _gam(h, psi_inout, "psi_inout"), _gam(h, trace_out, "trace_out"),
+                                    _opts(opts), ctypes.byref(st))
     _check(code, allow=(KFBI_ENOCONV,))
     return st.as_dict()
 
 
 # ---- steppers --------------------------------------------------------------
 def kfbi_stepper_create(h, equation, tau, theta=0.25, diffusivity=1.0, w=0.0, v_grid=None, v_gamma=None,
-                        bc=KFBI_BC_DIRICHLET):
+                        bc=KFBI_BC_DIRICHLET, split=KFBI_SPLIT_STRANG):
+    M, Nb, _ = _meta(h)
     p = StepParams(tau=tau, theta=theta, diffusivity=diffusivity, w=w,
-                   v_grid=_ptr(v_grid, torch.float64, name="v_grid"),
-                   v_gamma=_ptr(v_gamma, torch.float64, name="v_gamma"), bc=bc)
+                   v_grid=_ptr(v_grid, torch.float64, (M + 1) * (M + 1), "v_grid"),
+                   v_gamma=_ptr(v_gamma, torch.float64, Nb, "v_gamma"), bc=bc, split=split)
     s = _P()
     _check(lib().kfbi_stepper_create(h, equation, ctypes.byref(p), ctypes.byref(s)))
+    _STEPPERS[s.value] = _hv(h)
     return s
 
 
 def kfbi_stepper_destroy(s):
     _check(lib().kfbi_stepper_destroy(s))
+    _STEPPERS.pop(_hv(s), None)
 
 
 def kfbi_stepper_state_bytes(s):
@@ -418,27 +489,33 @@ def kfbi_stepper_set_state(s, blob):
 
 def kfbi_stepper_init(s, u0, lap_u0, u0_gamma, lap_u0_gamma, uprev=None, lap_uprev=None,
                       uprev_gamma=None, lap_uprev_gamma=None):
-    _check(lib().kfbi_stepper_init(s, _ptr(u0), _ptr(lap_u0), _ptr(u0_gamma), _ptr(lap_u0_gamma),
-                                   _ptr(uprev), _ptr(lap_uprev), _ptr(uprev_gamma),
-                                   _ptr(lap_uprev_gamma)))
+    h = _stepper_dom(s)
+    _check(lib().kfbi_stepper_init(s, _grid(h, u0, "u0"), _grid(h, lap_u0, "lap_u0"), _gam(h, u0_gamma, "u0_gamma"),
+                                   _gam(h, lap_u0_gamma, "lap_u0_gamma"), _grid(h, uprev, "uprev"),
+                                   _grid(h, lap_uprev, "lap_uprev"), _gam(h, uprev_gamma, "uprev_gamma"),
+                                   _gam(h, lap_uprev_gamma, "lap_uprev_gamma")))
 
 
 def kfbi_step_heat(s, g_next, src_grid, src_gamma, u_out, opts=None):
     st = SolveStats()
-    _check(lib().kfbi_step_heat(s, _ptr(g_next), _ptr(src_grid), _ptr(src_gamma), _ptr(u_out),
+    h = _stepper_dom(s)
+    _check(lib().kfbi_step_heat(s, _gam(h, g_next, "g_next"), _grid(h, src_grid, "src_grid"),
+                                _gam(h, src_gamma, "src_gamma"), _grid(h, u_out, "u_out"),
                                 _opts(opts), ctypes.byref(st)), allow=(KFBI_ENOCONV,))
     return st.as_dict()
 
 
 def kfbi_step_wave(s, g_next, u_out, opts=None):
     st = SolveStats()
-    _check(lib().kfbi_step_wave(s, _ptr(g_next), _ptr(u_out), _opts(opts), ctypes.byref(st)),
-           allow=(KFBI_ENOCONV,))
+    h = _stepper_dom(s)
+    _check(lib().kfbi_step_wave(s, _gam(h, g_next, "g_next"), _grid(h, u_out, "u_out"), _opts(opts),
+                                ctypes.byref(st)), allow=(KFBI_ENOCONV,))
     return st.as_dict()
 
 
 def kfbi_step_schrodinger(s, g_next, u_out, opts=None):
     st = SolveStats()
-    _check(lib().kfbi_step_schrodinger(s, _ptr(g_next), _ptr(u_out), _opts(opts), ctypes.byref(st)),
-           allow=(KFBI_ENOCONV,))
+    h = _stepper_dom(s)
+    _check(lib().kfbi_step_schrodinger(s, _gam(h, g_next, "g_next"), _grid(h, u_out, "u_out"), _opts(opts),
+                                       ctypes.byref(st)), allow=(KFBI_ENOCONV,))
     return st.as_dict()

@@ -1,0 +1,108 @@
+"""GPU parity of the Godunov (Lie) splitting of the Schroedinger step,
+S^A(tau) S^B(tau) (section 3.1; the comparison of section 4.1, Example 7 and
+Table 5), against the oracle stepper, and its first order in time on the
+paper's nonlinear example at grids the oracle is not run at.
+
+Bar: 1e-10 relative over inside nodes in FP64 (complex128), step by step.
+Inputs: the Gaussian packet with the harmonic potential on the 0.6/0.4
+ellipse (the Schroedinger workload at a reduced grid), and the nonlinear
+example of eqs. 4.3-4.4 (w = 1, exact solution e^{it} cos x cos y).
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads import manufactured as mf
+from oracle.geometry import Domain
+from oracle.steppers import SchrodingerStepper
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2404_14864_amd import kfbi  # noqa: E402
+from tests.gpu_util import GpuDomain, dev, empty_grid, host, rel_err  # noqa: E402
+
+TOL = 1e-10
+
+
+@pytest.mark.parametrize("w", [0.0, 10.0])
+def test_godunov_packet_matches_oracle(w):
+    M = 128
+    desc = W.domain_c3_schrodinger(M)
+    od = Domain(desc)
+    tau = od.h / 2
+    X, Y = od.X, od.Y
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    V, Vg = mf.harmonic_potential(X, Y), mf.harmonic_potential(zx, zy)
+    ref = SchrodingerStepper(od, tau, mf.packet_u0(X, Y), mf.packet_lap(X, Y), mf.packet_u0(zx, zy),
+                             mf.packet_lap(zx, zy), V, Vg, w=w, tol=1e-12, split="godunov")
+    with GpuDomain(desc, cplx=True) as g:
+        gx, gy = g.zx, g.zy
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, w=w,
+                                     v_grid=dev(mf.harmonic_potential(X, Y).ravel()),
+                                     v_gamma=dev(mf.harmonic_potential(gx, gy)), split=kfbi.KFBI_SPLIT_GODUNOV)
+        kfbi.kfbi_stepper_init(s, dev(mf.packet_u0(X, Y).ravel()), dev(mf.packet_lap(X, Y).ravel()),
+                               dev(mf.packet_u0(gx, gy)), dev(mf.packet_lap(gx, gy)))
+        u = empty_grid(g.M, cplx=True)
+        zero = dev(np.zeros(g.Nb, dtype=np.complex128))
+        for n in range(6):
+            Ur = ref.step(np.zeros(od.Nb, dtype=np.complex128))
+            st = kfbi.kfbi_step_schrodinger(s, zero, u, opts={"tol": 1e-12})
+            assert st["converged"]
+            assert rel_err(host(u).reshape(g.M + 1, g.M + 1), Ur, od.inside) < TOL, n
+        kfbi.kfbi_stepper_destroy(s)
+
+
+def _nls_error(M, split):
+    desc = W.domain_nls_example(M)
+    x = W.grid_coords(desc["L"], M)
+    X, Y = np.meshgrid(x, x)
+    tau = 8.0 / M
+    with GpuDomain(desc, cplx=True) as g:
+        gx, gy = g.zx, g.zy
+        s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, w=1.0,
+                                     v_grid=dev(mf.nls_potential(X, Y).ravel()),
+                                     v_gamma=dev(mf.nls_potential(gx, gy)), split=split)
+        kfbi.kfbi_stepper_init(s, dev(mf.nls_u(X, Y, 0).ravel()), dev(mf.nls_lap(X, Y, 0).ravel()),
+                               dev(mf.nls_u(gx, gy, 0)), dev(mf.nls_lap(gx, gy, 0)))
+        u = empty_grid(M, cplx=True)
+        n = int(round(1.0 / tau))
+        for k in range(n):
+            st = kfbi.kfbi_step_schrodinger(s, dev(mf.nls_u(gx, gy, (k + 1) * tau)), u, opts={"tol": 1e-11})
+            assert st["converged"]
+        inside = (kfbi.kfbi_domain_copy_classification(g.h) & 1).astype(bool)
+        err = np.max(np.abs(host(u).reshape(M + 1, M + 1) - mf.nls_u(X, Y, n * tau))[inside])
+        kfbi.kfbi_stepper_destroy(s)
+    return err
+
+
+def test_godunov_nonlinear_example_first_order_on_large_grids():
+    """tau = 8/M, T = 1: from 128 to 512 the Godunov error falls by about 2
+    per halving (first order), the Strang error by about 4, and Godunov stays
+    well above Strang (the ordering of the paper's Table 5)."""
+    god = [_nls_error(M, kfbi.KFBI_SPLIT_GODUNOV) for M in (128, 256, 512)]
+    strang = _nls_error(512, kfbi.KFBI_SPLIT_STRANG)
+    ratios = [god[i] / god[i + 1] for i in range(2)]
+    assert all(1.6 < r < 2.4 for r in ratios), god
+    assert god[-1] > 5.0 * strang, (god, strang)
+
+
+def test_split_mismatch_is_refused():
+    """A checkpoint of a Strang stepper is not accepted by a Godunov stepper
+    (their kappa differs), and an unknown splitting is refused."""
+    desc = W.domain_c3_schrodinger(64)
+    with GpuDomain(desc, cplx=True) as g:
+        tau = 1.0 / 64
+        a = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau)
+        b = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, split=kfbi.KFBI_SPLIT_GODUNOV)
+        blob = kfbi.kfbi_stepper_get_state(a)
+        with pytest.raises(kfbi.KfbiError):
+            kfbi.kfbi_stepper_set_state(b, blob)
+        with pytest.raises(kfbi.KfbiError):
+            kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, split=7)
+        kfbi.kfbi_stepper_destroy(a)
+        kfbi.kfbi_stepper_destroy(b)
