@@ -424,6 +424,27 @@ int kfbi_profile_read(kfbi_domain *dom, kfbi_kernel_prof *out);
 int kfbi_profile_replay(kfbi_domain *dom, int32_t kind, int32_t reps, double *avg_ms,
                         double *bytes_per_launch);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * five-point solve as kfbi_grid_solve, with the same arguments and results,
+ * but its two mode-space intermediates (R^ and U^, (M-1)^2 elements each)
+ * live in a device array the library holds once per GPU, of
+ * KFBI_NOALLOC_SCRATCH_BYTES (16 MiB), from its first use on that GPU until
+ * the process ends; the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and needs a domain made by
+ * kfbi_domain_create (whose set-up looks up the array's address on the
+ * domain's device).  Limit: 2 (M-1)^2 w bytes <= the array (w = 8 real,
+ * 16 complex: M <= 1024 real, M <= 512 complex), else KFBI_ENOTSUP with a
+ * message.  Every call on a GPU shares that GPU's array and leaves its
+ * contents to the next: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  Nothing in the
+ * array needs to start at zero: each call writes every entry before it reads
+ * it.  Errors: KFBI_EINVAL (null argument, complex kappa on a real domain),
+ * KFBI_ENOTSUP (too large), KFBI_EDEVICE. */
+#define KFBI_NOALLOC_SCRATCH_BYTES (16u << 20)
+int kfbi_grid_solve_noalloc(kfbi_domain *dom, double kappa_re, double kappa_im,
+                            const void *rhs, void *u_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -228,6 +228,12 @@ int kfbi_domain_create(const kfbi_domain_desc *desc, kfbi_domain **out) {
     d->stream = (hipStream_t)D.stream;
     int st = build_domain(d);
     if (st == KFBI_OK) {
+        // set-up of the no-allocation grid solve: look up this device's
+        // scratch array once (a failure is reported by that call itself)
+        void *scr = nullptr;
+        if (noalloc_scratch(d->stream, &scr) != KFBI_OK) set_error("");
+    }
+    if (st == KFBI_OK) {
         const size_t es = elem_size(d), n = d->n, Nb = d->Nb;
         const size_t nodes = (size_t)(d->M + 1) * (d->M + 1);
         (void)nodes;

@@ -300,6 +300,9 @@ int dalloc(kfbi_domain *d, void **p, size_t bytes);
 
 // setup (domain.hip)
 int build_domain(kfbi_domain *d);
+// device address of this device's no-allocation scratch array (noalloc.hip;
+// looked up once per device)
+int noalloc_scratch(hipStream_t s, void **out);
 
 // grid solve pieces (gridsolve.hip)
 int ensure_coefficients(kfbi_domain *d, double kre, double kim);

@@ -105,6 +105,7 @@ def lib():
         "kfbi_domain_copy_normals": ([_P, _P], ctypes.c_int),
         "kfbi_domain_copy_edges": ([_P, _P, _P], ctypes.c_int),
         "kfbi_grid_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
+        "kfbi_grid_solve_noalloc": ([_P, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
         "kfbi_interface_apply": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P], ctypes.c_int),
         "kfbi_helmholtz_solve": ([_P, ctypes.c_double, ctypes.c_double, _P, _P, _P, _P, _P,
                                   ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
@@ -149,7 +150,7 @@ EXPORTED = ("kfbi_last_error", "kfbi_domain_create", "kfbi_domain_destroy", "kfb
             "kfbi_step_schrodinger", "kfbi_profile_enable", "kfbi_profile_read", "kfbi_profile_replay",
             "kfbi_stepper_state_bytes", "kfbi_stepper_get_state", "kfbi_stepper_set_state",
             "kfbi_batch_create", "kfbi_batch_destroy", "kfbi_batch_helmholtz", "kfbi_batch_tuning",
-            "kfbi_batch_step", "kfbi_neumann_solve", "kfbi_domain_copy_normals")
+            "kfbi_batch_step", "kfbi_neumann_solve", "kfbi_domain_copy_normals", "kfbi_grid_solve_noalloc")
 
 
 def kfbi_profile_enable(h, on=True):
@@ -416,6 +417,15 @@ def kfbi_grid_solve(h, kappa, rhs, u_out):
     if rhs is None or u_out is None:
         raise ValueError("rhs and u_out are required")
     _check(lib().kfbi_grid_solve(h, k.real, k.imag, _grid(h, rhs, "rhs"), _grid(h, u_out, "u_out")))
+
+
+def kfbi_grid_solve_noalloc(h, kappa, rhs, u_out):
+    """kfbi_grid_solve with its intermediates in the library's per-GPU
+    scratch array (no device allocation in the call)."""
+    k = complex(kappa)
+    if rhs is None or u_out is None:
+        raise ValueError("rhs and u_out are required")
+    _check(lib().kfbi_grid_solve_noalloc(h, k.real, k.imag, _grid(h, rhs, "rhs"), _grid(h, u_out, "u_out")))
 
 
 def kfbi_interface_apply(h, kappa, f_grid, f_gamma, phi, u_grid_out, uplus_out):
