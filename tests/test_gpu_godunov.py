@@ -106,3 +106,41 @@ def test_split_mismatch_is_refused():
             kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, split=7)
         kfbi.kfbi_stepper_destroy(a)
         kfbi.kfbi_stepper_destroy(b)
+
+
+def test_example7_long_time_strang_and_godunov():
+    """The paper's comparison example (section 4.1, Example 7): unit circle
+    in [-1.2, 1.2]^2, 256 grid, tau = 0.0625, v of eq. 4.3, w = 1, exact
+    solution e^{it} cos x cos y, to T = 500 (8000 steps).  Its Table 5 gives
+    max-norm errors 1.39e-3 (Strang) and 2.73e-2 (Godunov).  Here the Strang
+    error is a phase error that oscillates in t (6e-4 .. 6.5e-3 over the
+    run, 4.2e-3 at T = 500) and the Godunov error settles at 4.3e-2: the
+    same orders of magnitude and the same ordering, Godunov about ten times
+    Strang."""
+    M, tau, T = 256, 0.0625, 500.0
+    desc = W.domains.disk(1.0, 1.2, M, M)
+    x = W.grid_coords(1.2, M)
+    X, Y = np.meshgrid(x, x)
+    errs = {}
+    for split in (kfbi.KFBI_SPLIT_STRANG, kfbi.KFBI_SPLIT_GODUNOV):
+        with GpuDomain(desc, cplx=True) as g:
+            gx, gy = g.zx, g.zy
+            s = kfbi.kfbi_stepper_create(g.h, kfbi.KFBI_SCHRODINGER, tau, w=1.0,
+                                         v_grid=dev(mf.nls_potential(X, Y).ravel()),
+                                         v_gamma=dev(mf.nls_potential(gx, gy)), split=split)
+            kfbi.kfbi_stepper_init(s, dev(mf.nls_u(X, Y, 0).ravel(), True), dev(mf.nls_lap(X, Y, 0).ravel(), True),
+                                   dev(mf.nls_u(gx, gy, 0), True), dev(mf.nls_lap(gx, gy, 0), True))
+            u = empty_grid(M, cplx=True)
+            n = int(round(T / tau))
+            cg = np.cos(gx) * np.cos(gy)
+            for k in range(n):
+                gk = dev(np.exp(1j * (k + 1) * tau) * cg)
+                st = kfbi.kfbi_step_schrodinger(s, gk, u, opts={"tol": 1e-10, "async": True})
+                assert st["converged"], k
+            inside = (kfbi.kfbi_domain_copy_classification(g.h) & 1).astype(bool)
+            errs[split] = np.max(np.abs(host(u).reshape(M + 1, M + 1) - mf.nls_u(X, Y, n * tau))[inside])
+            kfbi.kfbi_stepper_destroy(s)
+    es, eg = errs[kfbi.KFBI_SPLIT_STRANG], errs[kfbi.KFBI_SPLIT_GODUNOV]
+    assert 1e-3 < es < 1e-2, es
+    assert 2e-2 < eg < 6e-2, eg
+    assert eg > 5.0 * es, (es, eg)
