@@ -1,53 +1,69 @@
 #!/usr/bin/env python3
-"""Benchmark of the KFBI wave time-stepping path on one MI355X.
+"""Benchmark of the KFBI time-stepping path on one MI355X.
 
-Workload (the configuration the throughput metric is quoted on): wave
-equation, implicit theta-scheme with theta = 1/4, star domain
-r = 0.5 + 0.1 sin(5 theta) in [-1,1]^2, 512 x 512 grid, tau = h, 512
-collocation points (the paper's Nb = M), manufactured solution
-u = cos(sqrt2 pi t) sin(pi x) sin(pi y) for the initial and boundary data.
-One step = one implicit time step: the right-hand-side recurrence, the
-b-solve, GMRES on the boundary integral equation (each iteration: jumps and
-corrections, DST-x / tridiagonal-y grid solve, extraction, Arnoldi) and the
+Headline workload (the largest single-GPU time-stepping configuration):
+the Schroedinger equation i u_t = lap u + v u with Strang splitting,
+ellipse with semi-axes 0.6 / 0.4 in [-1,1]^2, 1024 x 1024 grid, 1024
+collocation points (the paper's Nb = M of section 4; reading R4),
+harmonic potential v = 50 (x^2 + y^2), Gaussian packet of width 0.1 and
+momentum (20, 0), g = 0 on Gamma, tau = h/2, complex128.  One step = the
+closed-form B-step and the right-hand side, the b-solve, GMRES on the
+boundary integral equation (each iteration: corrections, sparse DST-x /
+tridiagonal-y grid solve, stencil values and extraction, Arnoldi) and the
 final grid solve.
 
-Metric: grid-pts * GMRES-iters / s = sum over steps of (M-1)^2 * iterations,
-divided by the wall time of the timed steps (inputs resident in HBM).
+Metric: grid-pts * GMRES-iters / s = sum over the timed steps of
+(M-1)^2 * iterations, divided by their wall time (inputs resident in HBM).
 
-Also reported: p50/p99 step latency (device time per step from HIP events),
-the dominant kernel's achieved algorithmic bandwidth against the 8 TB/s HBM
-peak (its launch duration from back-to-back replay launches between two HIP
-events), its measured HBM traffic, and the CPU oracle timed on a bounded
-sample of the same workload.
+Also reported: p50/p99 step latency (device time per step from HIP events
+on the stepper's stream); the error of the GPU solution against the CPU
+oracle after the same steps; the complex64 grid solve inside FP64
+refinement on the same workload; the dominant kernel's algorithmic
+bandwidth against the 8 TB/s HBM peak (launch duration from back-to-back
+replay launches between two HIP events on the domain stream) and its
+measured HBM traffic; the CPU oracle timed on a bounded sample of the same
+workload on all host cores and on one; and, as secondary keys, the wave
+workload (512 grid, FP64 and FP32 inner solves), the Richardson iteration
+beside GMRES, the Neumann wave example, the batched Helmholtz workload and
+the serving loop.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 3]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 3]
 """
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the kernel at its current version, from two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters
-# on a 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); the
-# counts and the commands are in profiles/*_wave512_fp64_hbm_traffic.md.
-# Kernels not listed (or changed since they were counted) report null.
-TRAFFIC = {"tridiag_sparse": 2676713.0, "arnoldi": 68537.0}
+# HBM bytes per launch of the kernel at its current version on the headline
+# workload, from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled
+# by the same counters on a device copy of known size; the commands and
+# counts are in profiles/*_hbm_traffic.md.  Kernels not listed (or changed
+# since they were counted) report null.
+TRAFFIC = {}
+# the kernel each profile label belongs to: the two tridiagonal labels are
+# one kernel launched from one site (sparse or dense right-hand side)
+KERNEL_OF = {"tridiag_sparse": "k_tridiag", "tridiag_dense": "k_tridiag", "dst": "k_dst_rows",
+             "idst": "k_dst_rows", "eval_nodes": "k_eval_extract / k_eval_nodes",
+             "corrections": "k_corr_phi / k_corrections", "extract": "k_extract", "arnoldi": "k_gm_slot"}
+REPLAYABLE = ("tridiag_sparse", "tridiag_dense", "eval_nodes", "corrections", "arnoldi")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--M", type=int, default=512)
-    ap.add_argument("--profile-steps", type=int, default=40)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--M", type=int, default=1024, help="grid of the headline Schroedinger workload")
+    ap.add_argument("--wave-M", type=int, default=512, help="grid of the secondary wave workload")
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample length, per core setting")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--replay", type=int, default=200)
+    ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched Helmholtz run (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-jobs", type=int, default=32, help="jobs of the serving sample (0: skip)")
@@ -61,35 +77,359 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(M, seconds):
-    """The oracle (numpy/scipy, unchanged) on the same workload, timed on the
-    host: as many time steps as fit in about `seconds`."""
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": affinity}
+
+
+# ---------------------------------------------------------------------------
+# the headline workload's inputs (shared by the GPU legs and the oracle)
+# ---------------------------------------------------------------------------
+class Schr:
+    def __init__(self, M):
+        import numpy as np
+        import workloads as W
+        from workloads import manufactured as mf
+        self.desc = W.domain_c3_schrodinger(M)
+        self.M, self.Nb = M, self.desc["Nb"]
+        self.h = 2.0 / M
+        self.tau = self.h / 2.0
+        x = W.grid_coords(1.0, M)
+        self.X, self.Y = np.meshgrid(x, x)
+        self.mf = mf
+
+    def init_arrays(self, zx, zy):
+        mf = self.mf
+        return [mf.packet_u0(self.X, self.Y).ravel(), mf.packet_lap(self.X, self.Y).ravel(),
+                mf.packet_u0(zx, zy), mf.packet_lap(zx, zy)]
+
+    def potential(self, zx, zy):
+        return self.mf.harmonic_potential(self.X, self.Y).ravel(), self.mf.harmonic_potential(zx, zy)
+
+
+def oracle_schrodinger(M, seconds, max_steps, workers):
+    """The oracle (numpy/scipy, unchanged) on the headline workload, timed on
+    the host: as many time steps as fit in about `seconds` (at most
+    max_steps), with scipy's FFTs on `workers` threads.  Returns the timing
+    and the oracle's solution after its last step."""
     import numpy as np
+    import scipy.fft
+    from oracle.geometry import Domain
+    from oracle.steppers import SchrodingerStepper
+    S = Schr(M)
+    od = Domain(S.desc)
+    zx, zy = od.colloc["x"], od.colloc["y"]
+    v, vg = S.potential(zx, zy)
+    ini = S.init_arrays(zx, zy)
+    st = SchrodingerStepper(od, S.tau, ini[0].reshape(M + 1, M + 1), ini[1].reshape(M + 1, M + 1), ini[2], ini[3],
+                            v.reshape(M + 1, M + 1), vg)
+    zero = np.zeros(od.Nb, dtype=np.complex128)
+    iters, n, U, lat = 0, 0, None, []
+    with scipy.fft.set_workers(workers):
+        t0 = time.perf_counter()
+        while n < max_steps:
+            t1 = time.perf_counter()
+            U = st.step(zero)
+            lat.append(time.perf_counter() - t1)
+            iters += st.last_stats["iters"]
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        el = time.perf_counter() - t0
+    return {"value": (M - 1) ** 2 * iters / el, "steps": n, "iters": iters, "seconds": el,
+            "ms_per_step": 1e3 * el / n, "p50_step_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
+            "U": U, "inside": od.inside}
+
+
+def cpu_baseline(M, seconds):
+    """The oracle on the headline workload on all host cores and on one
+    (the paper's single-CPU setting), each for about `seconds`."""
+    info = cpu_info()
+    # the host cores this process may use (a one-GPU share of the host: at most 16)
+    cores = min(info["affinity"] or 1, 16)
+    allc = oracle_schrodinger(M, seconds, 10 ** 6, cores)
+    one = oracle_schrodinger(M, seconds, 10 ** 6, 1)
+    sample = ("first %d time steps of the same Schroedinger workload (%d GMRES iterations) in %.1f s; "
+              "numpy/scipy oracle, FFTs on %d threads" % (allc["steps"], allc["iters"], allc["seconds"], cores))
+    out = {"value": allc["value"], "unit": "grid-pts*GMRES-iters/s", "cores": cores, "kind": "oracle",
+           "sample": sample, "ms_per_step": allc["ms_per_step"],
+           "single_core": {"value": one["value"], "cores": 1, "ms_per_step": one["ms_per_step"],
+                           "sample": "first %d time steps (%d GMRES iterations) in %.1f s" % (
+                               one["steps"], one["iters"], one["seconds"])}}
+    out.update(info)
+    return out, allc
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+def schr_gpu(S, prec=None):
+    """Domain and stepper of the headline workload on the GPU."""
+    import torch
+    from paper_2404_14864_amd import kfbi
+    prec = kfbi.KFBI_PREC_FP64 if prec is None else prec
+    dom = kfbi.kfbi_domain_create(S.desc, kfbi.KFBI_COMPLEX, prec)
+    zx, zy = kfbi.kfbi_domain_copy_boundary(dom)
+    c = lambda a: torch.from_numpy(a.astype("complex128")).to("cuda:0")  # noqa: E731
+    r = lambda a: torch.from_numpy(a.astype("float64")).to("cuda:0")  # noqa: E731
+    v, vg = S.potential(zx, zy)
+    st = kfbi.kfbi_stepper_create(dom, kfbi.KFBI_SCHRODINGER, S.tau, v_grid=r(v), v_gamma=r(vg))
+    init = [c(a) for a in S.init_arrays(zx, zy)]
+    g0 = torch.zeros(S.Nb, dtype=torch.complex128, device="cuda:0")
+    u = torch.zeros((S.M + 1) ** 2, dtype=torch.complex128, device="cuda:0")
+    return dom, st, init, g0, u
+
+
+def timed_steps(step, n, events):
+    """n asynchronous steps; per-step device latency from events recorded on
+    the current stream (the library's stream) between the calls."""
+    import numpy as np
+    import torch
+    iters, refs = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n):
+        events[k].record()
+        s = step(k)
+        iters.append(s["iters"])
+        refs.append(s["refinements"])
+    events[n].record()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    lat = np.array([events[k].elapsed_time(events[k + 1]) for k in range(n)])
+    return T, iters, refs, lat
+
+
+def rel_inside(U, Ur, inside):
+    import numpy as np
+    return float(np.max(np.abs(U - Ur)[inside]) / max(np.max(np.abs(Ur[inside])), 1e-300))
+
+
+def profile_dominant(dom, steps_fn, np_steps, replay):
+    """Per-kernel HIP-event timing over np_steps profiled steps, replay
+    durations, and the dominant kernel: the one with the largest launches x
+    duration, the labels of one kernel taken together."""
+    from paper_2404_14864_amd import kfbi
+    import torch
+    kfbi.kfbi_profile_enable(dom, True)
+    steps_fn(np_steps)
+    torch.cuda.synchronize()
+    prof = kfbi.kfbi_profile_read(dom)
+    kfbi.kfbi_profile_enable(dom, False)
+    tot = sum(q["total_ms"] for q in prof.values())
+    labels = {}
+    for k, v in prof.items():
+        if not v["launches"]:
+            continue
+        if k in REPLAYABLE:
+            ms_k, by_k = kfbi.kfbi_profile_replay(dom, k, replay)
+            how = "replay of %d back-to-back launches between two HIP events" % replay
+        else:
+            ms_k, by_k = v["total_ms"] / v["launches"], v["bytes"] / v["launches"]
+            how = "HIP events around each launch"
+        labels[k] = {"kernel": KERNEL_OF[k], "launches": v["launches"], "avg_us": 1e3 * ms_k,
+                     "bytes_per_launch": by_k, "avg_us_events": 1e3 * v["total_ms"] / v["launches"],
+                     "share_events": v["total_ms"] / max(tot, 1e-30), "timing": how}
+    kern = {}
+    for k, L in labels.items():
+        g = kern.setdefault(L["kernel"], {"labels": [], "launches": 0, "time_us": 0.0, "bytes": 0.0})
+        g["labels"].append(k)
+        g["launches"] += L["launches"]
+        g["time_us"] += L["launches"] * L["avg_us"]
+        g["bytes"] += L["launches"] * L["bytes_per_launch"]
+    kdom = max(kern, key=lambda q: kern[q]["time_us"])
+    g = kern[kdom]
+    avg_us = g["time_us"] / g["launches"]
+    bytes_launch = g["bytes"] / g["launches"]
+    return labels, kern, kdom, avg_us, bytes_launch
+
+
+def headline(args, cpu_ref):
+    import numpy as np
+    import torch
+    from paper_2404_14864_amd import kfbi
+    S = Schr(args.M)
+    dom, st, init, g0, u = schr_gpu(S)
+    info = kfbi.kfbi_domain_get_info(dom)
+    log("schrodinger M=%d Nb=%d inside=%d irregular=%d edges=%d" % (S.M, S.Nb, info["n_inside"],
+                                                                    info["n_irregular"], info["n_edges"]))
+    kfbi.kfbi_stepper_init(st, *init)
+    for _ in range(args.warmup):
+        kfbi.kfbi_step_schrodinger(st, g0, u)
+    kfbi.kfbi_stepper_init(st, *init)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    aopts = {"async": True}
+    T, iters, _, lat = timed_steps(lambda k: kfbi.kfbi_step_schrodinger(st, g0, u, opts=aopts), args.steps, ev)
+    pts = (S.M - 1) ** 2
+    value = pts * sum(iters) / T
+    log("schrodinger fp64: %d steps in %.3f s, %d GMRES iterations, %.3g grid-pts*iters/s" % (
+        args.steps, T, sum(iters), value))
+    U_end = u.cpu().numpy().reshape(S.M + 1, S.M + 1)
+    out = {"value": value, "T": T, "iters": iters, "lat": lat, "finite": bool(np.all(np.isfinite(U_end)))}
+
+    # complex64 grid solves inside FP64 refinement, same steps
+    mopts = {"precision": kfbi.KFBI_PREC_MIXED, "async": True}
+    kfbi.kfbi_stepper_init(st, *init)
+    for _ in range(args.warmup):
+        kfbi.kfbi_step_schrodinger(st, g0, u, opts=mopts)
+    kfbi.kfbi_stepper_init(st, *init)
+    Tm, miters, mref, mlat = timed_steps(lambda k: kfbi.kfbi_step_schrodinger(st, g0, u, opts=mopts), args.steps, ev)
+    Um = u.cpu().numpy().reshape(S.M + 1, S.M + 1)
+    inside = (kfbi.kfbi_domain_copy_classification(dom) & 1).astype(bool)
+    out["mixed"] = {"value": pts * sum(miters) / Tm, "ms_per_step": 1e3 * Tm / args.steps,
+                    "p50_step_ms": float(np.percentile(mlat, 50)), "p99_step_ms": float(np.percentile(mlat, 99)),
+                    "gmres_iters_per_step": float(np.mean(miters)), "refinements_per_step": float(np.mean(mref)),
+                    "grid_solve": "complex64", "refinement": "fp64",
+                    "rel_diff_vs_fp64_gpu_after_steps": rel_inside(Um, U_end, inside)}
+    log("schrodinger mixed: %.3f ms/step, %.3g grid-pts*iters/s, %.1f refinements/step" % (
+        out["mixed"]["ms_per_step"], out["mixed"]["value"], out["mixed"]["refinements_per_step"]))
+
+    # accuracy against the oracle after the steps its timed sample ran
+    if cpu_ref is not None:
+        nacc = cpu_ref["steps"]
+        acc = {"vs": "CPU FP64 oracle (same inputs, GMRES tol 1e-10 on both sides)", "steps": nacc}
+        for label, o in (("fp64", {}), ("mixed", {"precision": kfbi.KFBI_PREC_MIXED})):
+            kfbi.kfbi_stepper_init(st, *init)
+            for _ in range(nacc):
+                kfbi.kfbi_step_schrodinger(st, g0, u, opts=o)
+            acc["rel_err_" + label] = rel_inside(u.cpu().numpy().reshape(S.M + 1, S.M + 1), cpu_ref["U"],
+                                                 cpu_ref["inside"])
+        out["accuracy"] = acc
+        log("accuracy after %d steps vs the oracle: fp64 %.2e, mixed %.2e" % (nacc, acc["rel_err_fp64"],
+                                                                               acc["rel_err_mixed"]))
+
+    # profiled pass on the same steps, replay durations, dominant kernel
+    def run_steps(n):
+        kfbi.kfbi_stepper_init(st, *init)
+        for _ in range(n):
+            kfbi.kfbi_step_schrodinger(st, g0, u)
+    labels, kern, kdom, avg_us, bytes_launch = profile_dominant(dom, run_steps, args.profile_steps, args.replay)
+    out["profile"] = (labels, kern, kdom, avg_us, bytes_launch)
+    log("dominant kernel %s: %d launches, avg %.2f us, %.3g bytes/launch" % (kdom, kern[kdom]["launches"],
+                                                                            avg_us, bytes_launch))
+    out["info"] = info
+    out["S"] = S
+    kfbi.kfbi_stepper_destroy(st)
+    kfbi.kfbi_domain_destroy(dom)
+    return out
+
+
+def wave_leg(args):
+    """The wave workload (theta = 1/4, five-lobed star, 512 grid, Nb = M,
+    tau = h, manufactured cos(sqrt2 pi t) sin(pi x) sin(pi y)) in FP64 and
+    with FP32 inner solves; the Richardson iteration beside GMRES on its
+    first steps; the paper's Neumann wave example at the same grid."""
+    import numpy as np
+    import torch
     import workloads as W
     from workloads import manufactured as mf
-    from oracle.geometry import Domain
-    from oracle.steppers import WaveStepper
-    od = Domain(W.domain_c2_wave(M))
-    tau = od.h
-    X, Y = od.X, od.Y
-    zx, zy = od.colloc["x"], od.colloc["y"]
-    st = WaveStepper(od, tau, mf.wave_u(X, Y, 0), mf.wave_lap(X, Y, 0), mf.wave_u(zx, zy, 0),
-                     mf.wave_lap(zx, zy, 0), mf.wave_u(X, Y, -tau), mf.wave_lap(X, Y, -tau),
-                     mf.wave_u(zx, zy, -tau), mf.wave_lap(zx, zy, -tau))
-    iters, n = 0, 0
-    t0 = time.perf_counter()
-    while True:
-        st.step(mf.wave_u(zx, zy, (n + 1) * tau))
-        iters += st.last_stats["iters"]
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    del np
-    return {"value": (M - 1) ** 2 * iters / el, "unit": "grid-pts*GMRES-iters/s",
-            "cores": 1, "kind": "oracle",
-            "sample": "first %d time steps of the same wave workload (%d GMRES iterations) in %.1f s; "
-                      "numpy/scipy oracle, single-threaded FFTs" % (n, iters, el)}
+    from paper_2404_14864_amd import kfbi
+    dev = "cuda:0"
+    M = args.wave_M
+    desc = W.domain_c2_wave(M)
+    theta, tau = 0.25, 2.0 / M
+    dom = kfbi.kfbi_domain_create(desc)
+    zx, zy = kfbi.kfbi_domain_copy_boundary(dom)
+    x = W.grid_coords(1.0, M)
+    X, Y = np.meshgrid(x, x)
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    steps = args.steps
+    total = args.warmup + steps
+    g_all = d(np.stack([mf.wave_u(zx, zy, (n + 1) * tau) for n in range(total)]))
+    init = [d(mf.wave_u(X, Y, 0).ravel()), d(mf.wave_lap(X, Y, 0).ravel()), d(mf.wave_u(zx, zy, 0)),
+            d(mf.wave_lap(zx, zy, 0)), d(mf.wave_u(X, Y, -tau).ravel()), d(mf.wave_lap(X, Y, -tau).ravel()),
+            d(mf.wave_u(zx, zy, -tau)), d(mf.wave_lap(zx, zy, -tau))]
+    u = torch.zeros((M + 1) * (M + 1), dtype=torch.float64, device=dev)
+    st = kfbi.kfbi_stepper_create(dom, kfbi.KFBI_WAVE, tau, theta=theta)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    pts = (M - 1) ** 2
+    res = {"workload": "wave theta-scheme (theta=0.25), star r=0.5+0.1sin5t in [-1,1]^2, %dx%d grid, Nb=%d, "
+                       "dt=h, manufactured cos(sqrt2 pi t) sin(pi x) sin(pi y)" % (M, M, desc["Nb"]),
+           "unit": "grid-pts*GMRES-iters/s", "steps": steps}
+    for label, o in (("fp64", {}), ("mixed", {"precision": kfbi.KFBI_PREC_MIXED})):
+        kfbi.kfbi_stepper_init(st, *init)
+        for n in range(args.warmup):
+            kfbi.kfbi_step_wave(st, g_all[n], u, opts=o)
+        kfbi.kfbi_stepper_init(st, *init)
+        T, its, refs, lat = timed_steps(lambda k: kfbi.kfbi_step_wave(st, g_all[k], u, opts=dict(o, **{"async": True})),
+                                        steps, ev)
+        res[label] = {"value": pts * sum(its) / T, "ms_per_step": 1e3 * T / steps,
+                      "p50_step_ms": float(np.percentile(lat, 50)), "p99_step_ms": float(np.percentile(lat, 99)),
+                      "gmres_iters_per_step": float(np.mean(its))}
+        if label == "mixed":
+            res[label]["refinements_per_step"] = float(np.mean(refs))
+        log("wave %s: %.3f ms/step, %.3g grid-pts*iters/s" % (label, res[label]["ms_per_step"], res[label]["value"]))
+    # the paper's Richardson iteration (eq. 3.21) beside GMRES, first steps
+    rich = {}
+    rsteps = min(steps, 20)
+    for label, ropts in (("gmres", {}), ("richardson_gamma1", {"solver": "richardson", "gamma": 1.0}),
+                         ("richardson_gamma0.9", {"solver": "richardson", "gamma": 0.9})):
+        kfbi.kfbi_stepper_init(st, *init)
+        its = []
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(rsteps):
+            its.append(kfbi.kfbi_step_wave(st, g_all[k], u, opts=dict(ropts, tol=1e-10))["iters"])
+        ev[1].record()
+        torch.cuda.synchronize()
+        rich[label] = {"products_per_step": float(np.mean(its)), "ms_per_step": ev[0].elapsed_time(ev[1]) / rsteps}
+    rich["steps"], rich["tol"] = rsteps, 1e-10
+    res["solvers"] = rich
+    log("solvers: " + ", ".join("%s %.1f products %.3f ms" % (k, v["products_per_step"], v["ms_per_step"])
+                                for k, v in rich.items() if isinstance(v, dict)))
+    kfbi.kfbi_stepper_destroy(st)
+    kfbi.kfbi_domain_destroy(dom)
+
+    # the Neumann problem (eqs. 3.19-3.20): the paper's Neumann wave example
+    # (eight-lobed star, u_n = 0, a logistic bump at rest), theta = 1/4,
+    # tau = 4h, at the same grid size
+    nsteps = min(steps, 50)
+    ndesc = W.domain_neumann_wave(M)
+    ndom = kfbi.kfbi_domain_create(ndesc)
+    try:
+        nzx, nzy = kfbi.kfbi_domain_copy_boundary(ndom)
+        xn = W.grid_coords(ndesc["L"], M)
+        Xn, Yn = np.meshgrid(xn, xn)
+        ntau = 4.0 * 2.0 * ndesc["L"] / M
+        u0g, l0g = mf.logistic_u0(Xn, Yn), mf.logistic_lap(Xn, Yn)
+        u0b, l0b = mf.logistic_u0(nzx, nzy), mf.logistic_lap(nzx, nzy)
+        ninit = [d(u0g.ravel()), d(l0g.ravel()), d(u0b), d(l0b), d((u0g + 0.5 * ntau ** 2 * l0g).ravel()),
+                 d(l0g.ravel()), d(u0b + 0.5 * ntau ** 2 * l0b), d(l0b)]
+        nst = kfbi.kfbi_stepper_create(ndom, kfbi.KFBI_WAVE, ntau, theta=theta, bc=kfbi.KFBI_BC_NEUMANN)
+        try:
+            gz = d(np.zeros(ndesc["Nb"]))
+            kfbi.kfbi_stepper_init(nst, *ninit)
+            for k in range(args.warmup):
+                kfbi.kfbi_step_wave(nst, gz, u)
+            kfbi.kfbi_stepper_init(nst, *ninit)
+            T, its, _, lat = timed_steps(lambda k: kfbi.kfbi_step_wave(nst, gz, u, opts={"async": True}), nsteps, ev)
+            finite = bool(torch.isfinite(u).all().item())
+        finally:
+            kfbi.kfbi_stepper_destroy(nst)
+    finally:
+        kfbi.kfbi_domain_destroy(ndom)
+    res["neumann"] = {"workload": "Neumann wave, star r=0.8+0.2 sin 8t in [-1.5,1.5]^2, M=%d, Nb=%d, u_n=0, "
+                                  "logistic bump at rest, theta=1/4, dt=4h" % (M, ndesc["Nb"]),
+                      "steps": nsteps, "ms_per_step": 1e3 * T / nsteps, "iters_per_step": float(np.mean(its)),
+                      "value": pts * sum(its) / T, "unit": "grid-pts*GMRES-iters/s", "finite": finite}
+    log("neumann: %d steps %.3f ms/step, %.1f iterations/step" % (nsteps, res["neumann"]["ms_per_step"],
+                                                                 res["neumann"]["iters_per_step"]))
+    return res
 
 
 def batched_helmholtz(n, reps):
@@ -216,211 +556,28 @@ def main():
 
     import numpy as np
     import torch
-    import workloads as W
-    from workloads import manufactured as mf
-    from paper_2404_14864_amd import kfbi
 
-    dev = "cuda:0"
     torch.cuda.set_device(0)
-    M = args.M
-    desc = W.domain_c2_wave(M)
-    Nb = desc["Nb"]
-    theta = 0.25
-    h = 2.0 / M
-    tau = h
-    dom = kfbi.kfbi_domain_create(desc)
-    info = kfbi.kfbi_domain_get_info(dom)
-    zx, zy = kfbi.kfbi_domain_copy_boundary(dom)
-    x = W.grid_coords(1.0, M)
-    X, Y = np.meshgrid(x, x)
+    # the oracle's sample of the headline workload first: its solution after
+    # the sampled steps is the reference of the accuracy figure
+    cpu, cpu_ref = None, None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the headline workload (~%.0f s on all cores, ~%.0f s on one)" % (
+            args.cpu_seconds, args.cpu_seconds))
+        cpu, cpu_ref = cpu_baseline(args.M, args.cpu_seconds)
+        log("oracle: %.3g grid-pts*iters/s on %d cores (%.0f ms/step), %.3g on one core" % (
+            cpu["value"], cpu["cores"], cpu["ms_per_step"], cpu["single_core"]["value"]))
 
-    def d(a):
-        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    H = headline(args, cpu_ref)
+    labels, kern, kdom, avg_us, bytes_launch = H["profile"]
+    S = H["S"]
+    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+    lat = H["lat"]
+    wave = None if args.no_secondary else wave_leg(args)
 
-    total = args.warmup + args.steps
-    # every input resident in HBM before the timed region
-    g_all = d(np.stack([mf.wave_u(zx, zy, (n + 1) * tau) for n in range(total)]))
-    init = [d(mf.wave_u(X, Y, 0).ravel()), d(mf.wave_lap(X, Y, 0).ravel()), d(mf.wave_u(zx, zy, 0)),
-            d(mf.wave_lap(zx, zy, 0)), d(mf.wave_u(X, Y, -tau).ravel()), d(mf.wave_lap(X, Y, -tau).ravel()),
-            d(mf.wave_u(zx, zy, -tau)), d(mf.wave_lap(zx, zy, -tau))]
-    u = torch.zeros((M + 1) * (M + 1), dtype=torch.float64, device=dev)
-    st = kfbi.kfbi_stepper_create(dom, kfbi.KFBI_WAVE, tau, theta=theta)
-    kfbi.kfbi_stepper_init(st, *init)
-    log("domain M=%d Nb=%d inside=%d irregular=%d edges=%d" % (M, Nb, info["n_inside"], info["n_irregular"],
-                                                             info["n_edges"]))
-    for n in range(args.warmup):
-        kfbi.kfbi_step_wave(st, g_all[n], u)
-    torch.cuda.synchronize()
-    log("warmup done (%d steps)" % args.warmup)
-
-    # timed region: each call returns once GMRES has finished on the device
-    # (its final grid solve still queued), so the host enqueues the next
-    # step while the device completes this one; per-step device latency from
-    # HIP events on the domain's stream
-    aopts = {"async": True}
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k].record()
-        s = kfbi.kfbi_step_wave(st, g_all[args.warmup + k], u, opts=aopts)
-        iters.append(s["iters"])
-    ev[args.steps].record()
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    lat = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(args.steps)]
-    log("timed %d steps in %.3f s, %d GMRES iterations" % (args.steps, T, sum(iters)))
-    U = u.cpu().numpy().reshape(M + 1, M + 1)
-    finite = bool(np.all(np.isfinite(U)))
-
-    pts = (M - 1) ** 2
-    value = pts * sum(iters) / T
-
-    # the same steps with FP32 grid solves inside FP64 refinement
-    kfbi.kfbi_stepper_init(st, *init)
-    mopts = {"precision": kfbi.KFBI_PREC_MIXED}
-    for n in range(args.warmup):
-        kfbi.kfbi_step_wave(st, g_all[n], u, opts=mopts)
-    kfbi.kfbi_stepper_init(st, *init)
-    miters, mref = [], []
-    mopts_async = dict(mopts, **aopts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k].record()
-        s = kfbi.kfbi_step_wave(st, g_all[k], u, opts=mopts_async)
-        miters.append(s["iters"])
-        mref.append(s["refinements"])
-    ev[args.steps].record()
-    torch.cuda.synchronize()
-    Tm = time.perf_counter() - t0
-    mlat = [ev[k].elapsed_time(ev[k + 1]) * 1e-3 for k in range(args.steps)]
-    # FP64 reference of the same steps for the agreement figure
-    Um = u.cpu().numpy().reshape(M + 1, M + 1)
-    kfbi.kfbi_stepper_init(st, *init)
-    for k in range(args.steps):
-        kfbi.kfbi_step_wave(st, g_all[k], u)
-    U64 = u.cpu().numpy().reshape(M + 1, M + 1)
-    inside = (kfbi.kfbi_domain_copy_classification(dom) & 1).astype(bool)
-    mixed_err = float(np.max(np.abs(Um - U64)[inside]) / max(np.max(np.abs(U64[inside])), 1e-300))
-    log("mixed: %d steps in %.3f s, %d iterations, rel diff vs FP64 %.2e" % (args.steps, Tm, sum(miters),
-                                                                          mixed_err))
-
-    # the paper's Richardson iteration (eq. 3.21) on the first steps of the
-    # same workload, beside GMRES: products per step and device time
-    rich = {}
-    rsteps = min(args.steps, 20)
-    for label, ropts in (("gmres", {}), ("richardson_gamma1", {"solver": "richardson", "gamma": 1.0}),
-                         ("richardson_gamma0.9", {"solver": "richardson", "gamma": 0.9})):
-        kfbi.kfbi_stepper_init(st, *init)
-        its = []
-        torch.cuda.synchronize()
-        ev[0].record()
-        for k in range(rsteps):
-            its.append(kfbi.kfbi_step_wave(st, g_all[k], u, opts=dict(ropts, tol=1e-10))["iters"])
-        ev[1].record()
-        torch.cuda.synchronize()
-        rich[label] = {"products_per_step": float(np.mean(its)),
-                       "ms_per_step": ev[0].elapsed_time(ev[1]) / rsteps}
-    rich["steps"] = rsteps
-    rich["tol"] = 1e-10
-    log("solvers: " + ", ".join("%s %.1f products %.3f ms" % (k, v["products_per_step"], v["ms_per_step"])
-                                for k, v in rich.items() if isinstance(v, dict)))
-
-    # the Neumann problem (eqs. 3.19-3.20): the paper's Neumann wave example
-    # (eight-lobed star, u_n = 0, a logistic bump at rest), theta = 1/4,
-    # tau = 4h (at tau = h the theta = 1/4 steps of the Neumann problem grow
-    # faster than the Dirichlet ones), at the same grid size
-    neu = None
-    nsteps = min(args.steps, 50)
-    if nsteps > 0:
-        ndesc = W.domain_neumann_wave(M)
-        ndom = kfbi.kfbi_domain_create(ndesc)
-        try:
-            nzx, nzy = kfbi.kfbi_domain_copy_boundary(ndom)
-            xn = W.grid_coords(ndesc["L"], M)
-            Xn, Yn = np.meshgrid(xn, xn)
-            ntau = 4.0 * 2.0 * ndesc["L"] / M
-            u0g, l0g = mf.logistic_u0(Xn, Yn), mf.logistic_lap(Xn, Yn)
-            u0b, l0b = mf.logistic_u0(nzx, nzy), mf.logistic_lap(nzx, nzy)
-            # at rest: u^{-1} = u^0 + tau^2/2 lap u^0, lap u^{-1} taken as lap u^0
-            ninit = [d(u0g.ravel()), d(l0g.ravel()), d(u0b), d(l0b), d((u0g + 0.5 * ntau ** 2 * l0g).ravel()),
-                     d(l0g.ravel()), d(u0b + 0.5 * ntau ** 2 * l0b), d(l0b)]
-            nst = kfbi.kfbi_stepper_create(ndom, kfbi.KFBI_WAVE, ntau, theta=theta, bc=kfbi.KFBI_BC_NEUMANN)
-            try:
-                gz = d(np.zeros(ndesc["Nb"]))
-                nu = torch.zeros_like(u)
-                kfbi.kfbi_stepper_init(nst, *ninit)
-                for k in range(args.warmup):
-                    kfbi.kfbi_step_wave(nst, gz, nu)
-                kfbi.kfbi_stepper_init(nst, *ninit)
-                its = []
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for k in range(nsteps):
-                    its.append(kfbi.kfbi_step_wave(nst, gz, nu, opts=aopts)["iters"])
-                torch.cuda.synchronize()
-                Tn = time.perf_counter() - t0
-                Un = nu.cpu().numpy()
-            finally:
-                kfbi.kfbi_stepper_destroy(nst)
-        finally:
-            kfbi.kfbi_domain_destroy(ndom)
-        neu = {"workload": "Neumann wave, star r=0.8+0.2 sin 8t in [-1.5,1.5]^2, M=%d, Nb=%d, u_n=0, logistic "
-                           "bump at rest, theta=1/4, dt=4h" % (M, ndesc["Nb"]),
-               "steps": nsteps, "ms_per_step": 1e3 * Tn / nsteps, "iters_per_step": float(np.mean(its)),
-               "value": pts * sum(its) / Tn, "unit": "grid-pts*GMRES-iters/s",
-               "finite": bool(np.all(np.isfinite(Un)))}
-        log("neumann: %d steps %.3f ms/step, %.1f iterations/step, %.3g grid-pts*iters/s" %
-            (nsteps, neu["ms_per_step"], neu["iters_per_step"], neu["value"]))
-
-    # profiled pass: HIP events around every kernel launch of the same steps
-    kfbi.kfbi_stepper_init(st, *init)
-    kfbi.kfbi_profile_enable(dom, True)
-    np_steps = min(args.profile_steps, total)
-    for n in range(np_steps):
-        kfbi.kfbi_step_wave(st, g_all[n], u)
-    torch.cuda.synchronize()
-    prof = kfbi.kfbi_profile_read(dom)
-    kfbi.kfbi_profile_enable(dom, False)
-    breakdown = {k: {"launches": v["launches"], "avg_us_events": 1e3 * v["total_ms"] / max(v["launches"], 1),
-                     "share": v["total_ms"] / max(sum(q["total_ms"] for q in prof.values()), 1e-30)}
-                 for k, v in prof.items() if v["launches"]}
-    # launch durations without the per-launch event overhead: back-to-back
-    # replay between two HIP events for the kernels that can be replayed (the
-    # grid-solve kernels; the control kernel repeating one Arnoldi step in
-    # replay mode), else the per-launch event average.  The
-    # dominant kernel has the largest launches x duration.
-    replayable = ("tridiag_sparse", "tridiag_dense", "eval_nodes", "corrections", "arnoldi")
-    dur = {}
-    for k, v in prof.items():
-        if not v["launches"]:
-            continue
-        if k in replayable:
-            ms_k, by_k = kfbi.kfbi_profile_replay(dom, k, args.replay)
-            how = "replay of %d back-to-back launches between two HIP events" % args.replay
-            if k == "arnoldi":
-                how += " (the same Arnoldi step, in replay mode)"
-        else:
-            ms_k, by_k = v["total_ms"] / v["launches"], v["bytes"] / v["launches"]
-            how = "HIP events around each launch in %d profiled steps" % np_steps
-        dur[k] = (ms_k, by_k, how)
-        breakdown[k]["avg_us"] = 1e3 * ms_k
-        breakdown[k]["avg_us_timing"] = how
-    kdom = max(dur, key=lambda k: prof[k]["launches"] * dur[k][0])
-    p = prof[kdom]
-    avg_ms, bytes_launch, timing = dur[kdom]
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    # the grid solve of a matrix-vector product, the kernel the HBM target is about
-    gs_ms, gs_bytes = kfbi.kfbi_profile_replay(dom, "tridiag_sparse", args.replay)
-    log("dominant kernel %s: %d launches, avg %.2f us (%s)" % (kdom, p["launches"], 1e3 * avg_ms, timing))
-
-    kfbi.kfbi_stepper_destroy(st)
-    kfbi.kfbi_domain_destroy(dom)
     if args.calibrate_copy > 0:
         nb = args.calibrate_copy * (1 << 20) // 8
-        src = torch.ones(nb, dtype=torch.float64, device=dev)
+        src = torch.ones(nb, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
@@ -428,57 +585,51 @@ def main():
         log("copied %d MiB three times" % args.calibrate_copy)
         del src, dst
 
-    batched = batched_helmholtz(args.batch, args.batch_reps) if args.batch > 0 else None
-    served = serving(args.serve_jobs) if args.serve_jobs > 0 else None
+    batched = batched_helmholtz(args.batch, args.batch_reps) if (args.batch > 0 and not args.no_secondary) else None
+    served = serving(args.serve_jobs) if (args.serve_jobs > 0 and not args.no_secondary) else None
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle (~%.0f s)" % args.cpu_seconds)
-        cpu = cpu_baseline(M, args.cpu_seconds)
-
-    lat_ms = np.array(lat) * 1e3
+    pts = (S.M - 1) ** 2
+    w = 16.0  # complex128 bytes per element
     out = {
         "metric": "grid-pts*GMRES-iters/s per KFBI step",
-        "value": value,
+        "value": H["value"],
         "unit": "grid-pts*GMRES-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * T / args.steps,
+        "ms_per_step": 1e3 * H["T"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": "wave theta-scheme (theta=0.25), star r=0.5+0.1sin5t in [-1,1]^2, "
-                               "%dx%d grid, Nb=%d, dt=h" % (M, M, Nb),
-                   "equation": "wave", "M": M, "Nb": Nb, "tau": tau, "theta": theta,
-                   "precision": "fp64", "parallelism": "single GPU"},
-        "p50_step_ms": float(np.percentile(lat_ms, 50)),
-        "p99_step_ms": float(np.percentile(lat_ms, 99)),
-        "latency": "device time per step from HIP events on the domain stream",
-        "gmres_iters_per_step": float(np.mean(iters)),
-        "solution_finite": finite,
-        "roofline": {"bound": "hbm", "kernel": kdom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get(kdom),
-                     "avg_launch_us": 1e3 * avg_ms, "bytes_per_launch": bytes_launch, "timing": timing,
-                     "profiled_steps": np_steps},
-        "grid_solve_roofline": {"kernel": "tridiag_sparse", "avg_launch_us": 1e3 * gs_ms,
-                                "bytes_per_launch": gs_bytes,
-                                "achieved": gs_bytes / (gs_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "frac": gs_bytes / (gs_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                "timing": "replay of %d back-to-back launches between two HIP events" % args.replay},
-        "kernels": breakdown,
-        "mixed_precision": {"value": pts * sum(miters) / Tm, "ms_per_step": 1e3 * Tm / args.steps,
-                            "p50_step_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
-                            "p99_step_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
-                            "latency": "device time per step from HIP events",
-                            "gmres_iters_per_step": float(np.mean(miters)),
-                            "refinements_per_step": float(np.mean(mref)),
-                            "grid_solve": "fp32", "refinement": "fp64",
-                            "rel_diff_vs_fp64_after_steps": mixed_err},
-        "solvers": rich,
-        "neumann": neu,
+        "config": {"workload": "Schroedinger, Strang splitting, ellipse 0.6/0.4 in [-1,1]^2, %dx%d grid, Nb=%d "
+                               "(reading R4: the paper fixes Nb = M in section 4; the configuration lists 2M), "
+                               "V=50(x^2+y^2), Gaussian packet width 0.1 k=(20,0), g=0, dt=h/2" % (S.M, S.M, S.Nb),
+                   "equation": "schrodinger", "M": S.M, "Nb": S.Nb, "tau": S.tau, "precision": "fp64 (complex128)",
+                   "parallelism": "single GPU"},
+        "p50_step_ms": float(np.percentile(lat, 50)),
+        "p99_step_ms": float(np.percentile(lat, 99)),
+        "latency": "device time per step from HIP events on the library's stream",
+        "gmres_iters_per_step": float(np.mean(H["iters"])),
+        "solution_finite": H["finite"],
+        "accuracy": H.get("accuracy"),
+        "roofline": {"bound": "hbm", "kernel": kdom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get(kdom),
+                     "avg_launch_us": avg_us, "bytes_per_launch": bytes_launch,
+                     "labels": kern[kdom]["labels"],
+                     "timing": "replay of %d back-to-back launches between two HIP events, averaged over the "
+                               "kernel's launches in %d profiled steps" % (args.replay, args.profile_steps),
+                     "per_unit": "the kernel's own algorithmic bytes: the write of U^ (w per grid point and "
+                                 "iteration) plus its sparse input; a dense launch also reads R^"},
+        "path_efficiency": {"model": "4w per grid point and iteration (the three-pass grid solve: write R^, "
+                                     "read R^ and write U^, read U^), w = 16 B",
+                            "achieved": 4 * w * H["value"] / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": 4 * w * H["value"] / 1e9 / HBM_PEAK_GBS},
+        "kernels": labels,
+        "kernels_merged": kern,
+        "mixed_precision": H["mixed"],
+        "wave": wave,
         "batched": batched,
         "serving": served,
         "cpu_baseline": cpu,

@@ -377,6 +377,25 @@ __global__ void k_tables(int M, double *sine, double *twiddle, double *scu) {
     }
 }
 
+// Temporary device buffers of the set-up, freed on every return path (the
+// frees wait for the work queued on them).
+struct SetupTemps {
+    std::vector<void *> p;
+    int alloc(void **out, size_t bytes) {
+        const hipError_t e = hipMalloc(out, bytes);
+        if (e != hipSuccess) {
+            set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+            *out = nullptr;
+            return KFBI_ENOMEM;
+        }
+        p.push_back(*out);
+        return KFBI_OK;
+    }
+    ~SetupTemps() {
+        for (void *q : p) (void)hipFree(q);
+    }
+};
+
 }  // namespace
 
 int build_domain(kfbi_domain *d) {
@@ -403,10 +422,11 @@ int build_domain(kfbi_domain *d) {
     }
 
     KFBI_TRY(dalloc(d, (void **)&d->flags, nodes));
+    SetupTemps tmp;
     int *err = nullptr, *cnt = nullptr;
     int32_t *ex_map = nullptr, *ey_map = nullptr, *irr_list = nullptr;
-    KFBI_HIP(hipMalloc(&err, 2 * sizeof(int)));
-    KFBI_HIP(hipMalloc(&cnt, 4 * (M + 1) * sizeof(int)));
+    KFBI_TRY(tmp.alloc((void **)&err, 2 * sizeof(int)));
+    KFBI_TRY(tmp.alloc((void **)&cnt, 4 * (M + 1) * sizeof(int)));
     KFBI_HIP(hipMemsetAsync(err, 0, 2 * sizeof(int), s));
     KFBI_HIP(hipMemsetAsync(d->flags, 0, nodes, s));
 
@@ -422,7 +442,6 @@ int build_domain(kfbi_domain *d) {
     KFBI_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
     KFBI_HIP(hipStreamSynchronize(s));
     if (herr) {
-        hipFree(err); hipFree(cnt);
         set_error("an inside node lies within 3h of the box boundary");
         return KFBI_EDOMAIN;
     }
@@ -435,7 +454,6 @@ int build_domain(kfbi_domain *d) {
     d->n_irr = ti;
     d->n_edges = te;
     if (ti == 0 || te == 0) {
-        hipFree(err); hipFree(cnt);
         set_error("the interface crosses no grid line");
         return KFBI_EDOMAIN;
     }
@@ -479,9 +497,9 @@ int build_domain(kfbi_domain *d) {
     KFBI_HIP(hipMemcpyAsync(d->seg_row, seg_row.data(), seg_row.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KFBI_TRY(dalloc(d, (void **)&d->row_seg, row_seg.size() * sizeof(int32_t)));
     KFBI_HIP(hipMemcpyAsync(d->row_seg, row_seg.data(), row_seg.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    KFBI_HIP(hipMalloc(&ex_map, nodes * sizeof(int32_t)));
-    KFBI_HIP(hipMalloc(&ey_map, nodes * sizeof(int32_t)));
-    KFBI_HIP(hipMalloc(&irr_list, (size_t)ti * sizeof(int32_t)));
+    KFBI_TRY(tmp.alloc((void **)&ex_map, nodes * sizeof(int32_t)));
+    KFBI_TRY(tmp.alloc((void **)&ey_map, nodes * sizeof(int32_t)));
+    KFBI_TRY(tmp.alloc((void **)&irr_list, (size_t)ti * sizeof(int32_t)));
     KFBI_HIP(hipMemsetAsync(ex_map, 0xff, nodes * sizeof(int32_t), s));
     KFBI_HIP(hipMemsetAsync(ey_map, 0xff, nodes * sizeof(int32_t), s));
     KFBI_HIP(hipMemcpyAsync(d->irr_row_ptr, rowptr.data(), rowptr.size() * sizeof(int32_t),
@@ -514,7 +532,6 @@ int build_domain(kfbi_domain *d) {
     int nin = 0;
     for (size_t q = 0; q < nodes; ++q) nin += hf[q] & 1;
     d->n_inside = nin;
-    hipFree(err); hipFree(cnt); hipFree(ex_map); hipFree(ey_map); hipFree(irr_list);
     if (herr) {
         set_error("an extraction stencil reaches the box boundary");
         return KFBI_EDOMAIN;

@@ -149,3 +149,32 @@ def test_too_many_collocation_points_for_a_solve():
         with pytest.raises(kfbi.KfbiError) as e:
             kfbi.kfbi_helmholtz_solve(g.h, 10.0, None, None, dev(np.zeros(g.Nb)), u)
         assert e.value.code == kfbi.KFBI_ENOTSUP
+
+
+def test_batch_refuses_small_grids_at_creation():
+    """Members below M = 64 are refused by kfbi_batch_create (the batched
+    row-wise stencil evaluation needs a 64-mode row), not half-way through a
+    solve."""
+    from workloads.domains import disk
+    with GpuDomain(disk(0.3, 1.0, 32, 32)) as g:
+        with pytest.raises(kfbi.KfbiError) as e:
+            kfbi.kfbi_batch_create([g.h])
+        assert e.value.code == kfbi.KFBI_ENOTSUP and "M >= 64" in str(e.value)
+
+
+def test_refused_domains_free_their_setup_buffers():
+    """A disk too small to cross a grid line is refused after the set-up has
+    allocated its temporaries; repeated refusals leave the device's free
+    memory where it was."""
+    from workloads.domains import disk
+    M = 256
+    h = 2.0 / M
+    desc = disk(0.1 * h, 1.0, M, 16, cx=0.5 * h, cy=0.5 * h)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(200):
+        with pytest.raises(kfbi.KfbiError) as e:
+            kfbi.kfbi_domain_create(desc)
+        assert e.value.code == kfbi.KFBI_EDOMAIN
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] >= free0 - (1 << 20)
