@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="headline workload only")
     ap.add_argument("--batch", type=int, default=256, help="instances of the batched Helmholtz run (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=3)
-    ap.add_argument("--serve-jobs", type=int, default=32, help="jobs of the serving sample (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=16, help="jobs of the serving sample (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device to device three times (the reference transfer "
                          "for HBM byte counters)")
@@ -523,28 +523,71 @@ def batched_helmholtz(n, reps):
     return out
 
 
-def serving(n_jobs):
+def serving(n_jobs, seed=20240423):
     """The serving workload on a bounded sample: n_jobs seeded jobs (heat,
     wave, Schroedinger 40/40/20; star or ellipse domains; grids uniform over
-    {256, 512, 1024}; 20..60 steps each), Poisson arrivals at 0.5 job per
-    tick, admitted within 0.8 of the free device memory.  Step latency is
-    the device time of the tick that advanced the job."""
+    {256, 512, 1024, 2048}; 50..500 steps each).  First the capacity: the
+    jobs served with every arrival at t = 0 (jobs per second at
+    saturation); then Poisson arrivals at 0.8 of that rate, in FP64 and with
+    the FP32 / complex64 inner solves; then the plain per-solve path (each
+    job alone, FP64, synchronous steps).  The budget is half of what the
+    sample's jobs hold together, so admission waits for memory.  Every
+    served job's final grid is compared with the plain path's."""
+    import numpy as np
     import torch
     from workloads.serving import job_fields, job_stream
-    from paper_2404_14864_amd.serving import Server
-    free, _ = torch.cuda.mem_get_info()
-    specs = job_stream(20240423, n_jobs, rate=0.5, grids=(256, 512, 1024), steps=(20, 60))
-    srv = Server(int(0.8 * free), job_fields, {"tol": 1e-10})
-    rep = srv.run(specs, tick=1.0)
-    rep["workload"] = ("%d jobs, heat/wave/Schroedinger 40/40/20, star (heat, wave) and ellipse (Schroedinger) "
-                       "domains, grids U{256,512,1024}, Nb=M, 20-60 steps, Poisson arrivals 0.5/tick, "
-                       "tol 1e-10" % n_jobs)
-    rep["n_finished"] = len(rep.pop("finished"))
-    rep["n_rejected"] = len(rep.pop("rejected"))
-    log("serving: %d jobs in %d ticks, p50 %.2f ms, p99 %.2f ms per step, %.3g %s, up to %d jobs at once" % (
-        rep["n_finished"], rep["ticks"], rep["p50_step_ms"], rep["p99_step_ms"], rep["throughput"], rep["unit"],
-        rep["max_concurrent_jobs"]))
-    return rep
+    from paper_2404_14864_amd import kfbi
+    from paper_2404_14864_amd.serving import Job, Server, serve_plain
+    specs = job_stream(seed, n_jobs, rate=1.0, grids=(256, 512, 1024, 2048), steps=(50, 500))
+    # footprint of each job shape, for the budget
+    fp = {}
+    for s in specs:
+        key = (s["kind"], s["desc"]["M"])
+        if key not in fp:
+            j = Job(s, job_fields)
+            fp[key] = j.footprint
+            j.close()
+    total = sum(fp[(s["kind"], s["desc"]["M"])] for s in specs)
+    budget = total // 2
+    outs = {}
+
+    def keeper(tag):
+        d = outs.setdefault(tag, {})
+        return lambda j: d.__setitem__(j.spec["id"], j.u.cpu().numpy())
+
+    base = {"tol": 1e-10}
+    sat = [dict(s, arrival=0.0) for s in specs]
+    rep_sat = Server(budget, job_fields, base).run(sat, tick=1.0)
+    capacity = len(specs) / rep_sat["wall_s"]
+    rate = 0.8 * capacity
+    # arrival times of the stream rescaled to the measured rate
+    t = np.array([s["arrival"] for s in specs])
+    poisson = [dict(s, arrival=float(a)) for s, a in zip(specs, t / rate)]
+    rep = Server(budget, job_fields, base, keep_output=keeper("fp64")).run(poisson, tick=1.0)
+    repm = Server(budget, job_fields, dict(base, precision=kfbi.KFBI_PREC_MIXED),
+                  keep_output=keeper("mixed")).run(poisson, tick=1.0)
+    plain = serve_plain(specs, job_fields, base, keep_output=keeper("plain"))
+    diff = {}
+    for tag in ("fp64", "mixed"):
+        diff[tag] = max(float(np.max(np.abs(outs[tag][i] - outs["plain"][i])) /
+                              max(float(np.max(np.abs(outs["plain"][i]))), 1e-300)) for i in outs["plain"])
+    for r in (rep_sat, rep, repm):
+        r["n_finished"] = len(r.pop("finished"))
+        r["n_rejected"] = len(r.pop("rejected"))
+    out = {"workload": "%d jobs, heat/wave/Schroedinger 40/40/20, star (heat, wave) and ellipse (Schroedinger) "
+                       "domains, grids U{256,512,1024,2048}, Nb=M, 50-500 steps, tol 1e-10; Poisson arrivals at 0.8 "
+                       "of the measured capacity; budget half of the jobs' summed footprint" % len(specs),
+           "capacity_jobs_per_s": capacity, "arrival_rate_jobs_per_s": rate, "budget_bytes": budget,
+           "sum_of_footprints_bytes": total, "saturated": rep_sat, "served_fp64": rep, "served_mixed": repm,
+           "plain_fp64": plain, "max_rel_diff_vs_plain": diff,
+           "speedup_fp64_vs_plain": rep["throughput"] / plain["throughput"],
+           "speedup_mixed_vs_plain": repm["throughput"] / plain["throughput"]}
+    log("serving: capacity %.2f jobs/s; served fp64 %.3g (p50 %.2f p99 %.2f ms), mixed %.3g (p99 %.2f ms), plain %.3g "
+        "(p50 %.2f p99 %.2f ms) grid-pts*iters/s; %d admitted while busy; diff vs plain fp64 %.1e mixed %.1e" % (
+            capacity, rep["throughput"], rep["p50_step_ms"], rep["p99_step_ms"], repm["throughput"],
+            repm["p99_step_ms"], plain["throughput"], plain["p50_step_ms"], plain["p99_step_ms"],
+            rep["admitted_while_device_busy"], diff["fp64"], diff["mixed"]))
+    return out
 
 
 def main():

@@ -315,38 +315,42 @@ int kfbi_step_schrodinger(kfbi_stepper *st, const void *g_next_gamma, void *u_gr
                           const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
 /* Batched modified-Helmholtz solves (eq. 3.13 through eqs. 3.17-3.18, one
- * problem per member domain).  A batch holds n REAL domains that share one
- * stream; every kernel launch of a batched solve runs the blocks of all
- * members, each member with its own GMRES state, so members of different
- * grid sizes, curves and kappa advance together and finished members drop
- * out on the device.  Members must have Nb <= 8192; a domain may belong to
+ * problem per member domain).  A batch holds n domains of one scalar type
+ * (all REAL or all COMPLEX) that share one stream; every kernel launch of a
+ * batched solve runs the blocks of all members, each member with its own
+ * GMRES state, so members of different grid sizes, curves and kappa advance
+ * together and finished members drop out on the device.  Members must have
+ * M >= 64 and Nb <= 8192 (real) or 4096 (complex); a domain may belong to
  * several batches but must not be used by two calls at once.
  * kfbi_batch_create copies the launch tables to the device (it
  * synchronises the stream); kfbi_batch_destroy frees only the batch's own
- * memory.  Errors: KFBI_EINVAL (null or empty, mixed streams),
- * KFBI_ENOTSUP (complex member, too large), KFBI_ENOMEM. */
+ * memory.  Errors: KFBI_EINVAL (null or empty, mixed streams, mixed scalar
+ * types), KFBI_ENOTSUP (M < 64, too large), KFBI_ENOMEM. */
 int kfbi_batch_create(kfbi_domain *const *doms, int32_t n, kfbi_batch **out);
 int kfbi_batch_destroy(kfbi_batch *b);
 
-/* n solves, member q with kappa[q] and the device arrays f_grid[q] (grid,
- * f at inside nodes), f_gamma[q] and g_gamma[q] (Nb values on Gamma);
- * u_grid_out[q] (grid) and phi_inout[q] (density: warm start in, result
- * out) may be NULL as arrays or entries.  kappa, f_grid, ... are host
- * arrays of n entries.  opts as for kfbi_helmholtz_solve (the precision
- * field selects FP64 or the FP32 inner solves for all members); stats, if
- * not NULL, receives n entries, device_ms the time of the whole batch.
- * Returns KFBI_ENOCONV when some member reached max_iter (all outputs are
- * still written). */
-int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid,
-                         const void *const *f_gamma, const void *const *g_gamma,
-                         void *const *u_grid_out, void *const *phi_inout,
+/* n solves, member q with kappa = kappa_re[q] + i kappa_im[q] (kappa_im
+ * NULL: real kappa; nonzero entries need a complex batch) and the device
+ * arrays f_grid[q] (grid, f at inside nodes), f_gamma[q] and g_gamma[q] (Nb
+ * values on Gamma), of the batch's element type; u_grid_out[q] (grid) and
+ * phi_inout[q] (density: warm start in, result out) may be NULL as arrays
+ * or entries.  kappa_re, f_grid, ... are host arrays of n entries.  opts as
+ * for kfbi_helmholtz_solve (the precision field selects FP64 or the FP32 /
+ * complex64 inner solves for all members); stats, if not NULL, receives n
+ * entries, device_ms the time of the whole batch.  Returns KFBI_ENOCONV when
+ * some member reached max_iter (all outputs are still written). */
+int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa_re, const double *kappa_im,
+                         const void *const *f_grid, const void *const *f_gamma,
+                         const void *const *g_gamma, void *const *u_grid_out, void *const *phi_inout,
                          const kfbi_solve_opts *opts, kfbi_solve_stats *stats);
 
 /* One time step of every active member stepper: the Crank-Nicolson step of
  * kfbi_step_heat (eq. 3.4) or the theta-scheme step of kfbi_step_wave
- * (eqs. 3.5-3.7), with the members' modified-Helmholtz solves batched as in
- * kfbi_batch_helmholtz.  st[q] is an initialised REAL heat or wave stepper
- * on member q's domain.  active (host, n bytes; NULL: all) selects the
+ * (eqs. 3.5-3.7) in a real batch, the splitting step of
+ * kfbi_step_schrodinger in a complex batch, with the members'
+ * modified-Helmholtz solves batched as in kfbi_batch_helmholtz.  st[q] is
+ * an initialised stepper on member q's domain (heat or wave: real batch;
+ * Schroedinger: complex batch).  active (host, n bytes; NULL: all) selects the
  * members that step; for each, g_next[q] is g on Gamma at the new time and
  * u_grid_out[q] (grid) receives u; a heat member may pass its sources as
  * kfbi_step_heat does (src_grid[q], src_gamma[q]; the arrays or entries may
@@ -354,7 +358,8 @@ int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *
  * g_next, ... are host arrays of n entries; the results are on the batch
  * stream in stream order.  stats (n entries, zero for members not active)
  * as kfbi_batch_helmholtz.  Errors: KFBI_EINVAL (null, stepper not on the
- * member's domain, not initialised, Schroedinger stepper), KFBI_ENOTSUP
+ * member's domain, not initialised, equation not of the batch's scalar
+ * type), KFBI_ENOTSUP
  * (a Neumann stepper: batched steps are Dirichlet only), KFBI_ENOCONV
  * (some member reached max_iter; its step still completes). */
 int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *active,

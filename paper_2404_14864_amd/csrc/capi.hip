@@ -195,6 +195,32 @@ struct kfbi_stepper {
     void *v = nullptr, *vg = nullptr;   // Schroedinger: copies of the potential
 };
 
+// The B-step of a Schroedinger step in place on the carried state (u* for
+// Strang, u^n for Godunov), with the right-hand side f = -kappa u** of the
+// A-step's solve, on the grid and on Gamma.
+static int schr_b_step(kfbi_stepper *s) {
+    kfbi_domain *d = s->dom;
+    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+    k_schr_b<<<(ng + Nb + 255) / 256, 256, 0, d->stream>>>(ng, Nb, (cd *)s->A, (const double *)s->v, (cd *)s->f,
+                                                          (cd *)s->Ag, (const double *)s->vg, (cd *)s->fg, s->p.w,
+                                                          s->p.tau, s->kim);
+    KFBI_CHECK_LAUNCH();
+    return KFBI_OK;
+}
+
+// The carried state after the A-step's solve u^{n+1} (trace tr on Gamma).
+static int schr_state_update(kfbi_stepper *s, const void *u, const void *tr) {
+    kfbi_domain *d = s->dom;
+    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
+    if (s->p.split == KFBI_SPLIT_GODUNOV) {
+        // the next B-step acts on u^{n+1} itself
+        return lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u), lset<cd>(s->Ag, tr), make_cd(1.0, 0.0));
+    }
+    // u* of the next step, u^{n+1} - i tau/2 lap u^{n+1} = 2 u^{n+1} - u** (eq. 3.12)
+    const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
+    return lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u, s->A), lset<cd>(s->Ag, tr, s->Ag), two, m1);
+}
+
 extern "C" {
 
 const char *kfbi_last_error(void) { return g_err.c_str(); }
@@ -279,10 +305,10 @@ int kfbi_batch_destroy(kfbi_batch *b) {
     return KFBI_OK;
 }
 
-int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
-                         const void *const *g_gamma, void *const *u_grid_out, void *const *phi_inout,
-                         const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
-    return batch_helmholtz(b, kappa, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
+int kfbi_batch_helmholtz(kfbi_batch *b, const double *kappa_re, const double *kappa_im, const void *const *f_grid,
+                         const void *const *f_gamma, const void *const *g_gamma, void *const *u_grid_out,
+                         void *const *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
+    return batch_helmholtz(b, kappa_re, kappa_im, f_grid, f_gamma, g_gamma, u_grid_out, phi_inout, opts, stats);
 }
 
 int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *active, const void *const *g_next,
@@ -290,8 +316,9 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
                     const kfbi_solve_opts *opts, kfbi_solve_stats *stats) {
     if (!b || !st || !g_next || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
     const int n = batch_size(b);
+    const bool cplx = batch_complex(b);
     auto on = [&](int q) { return !active || active[q] != 0; };
-    std::vector<double> kap(n, 0.0);
+    std::vector<double> kap(n, 0.0), kapi(n, 0.0);
     std::vector<const void *> f(n, nullptr), fg(n, nullptr), g(n, nullptr);
     std::vector<void *> u(n, nullptr), phi(n, nullptr);
     for (int q = 0; q < n; ++q) {
@@ -299,8 +326,10 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
         kfbi_stepper *s = st[q];
         if (!s || !g_next[q] || !u_out[q]) { set_error("null stepper or array of an active member"); return KFBI_EINVAL; }
         if (s->dom != batch_domain(b, q)) { set_error("stepper is not on the batch member's domain"); return KFBI_EINVAL; }
-        if ((s->eq != KFBI_HEAT && s->eq != KFBI_WAVE) || !s->initialized) {
-            set_error("batched steps take initialised heat or wave steppers");
+        if (!s->initialized) { set_error("batched steps take initialised steppers"); return KFBI_EINVAL; }
+        if (cplx ? s->eq != KFBI_SCHRODINGER : (s->eq != KFBI_HEAT && s->eq != KFBI_WAVE)) {
+            set_error("batched steps take heat or wave steppers (real batch) or Schroedinger steppers "
+                      "(complex batch)");
             return KFBI_EINVAL;
         }
         if (s->p.bc != KFBI_BC_DIRICHLET) {
@@ -318,18 +347,21 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
             const void *sg = src_grid ? src_grid[q] : nullptr, *sgg = src_gamma ? src_gamma[q] : nullptr;
             KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->f, s->A, sg), lset<double>(s->fg, s->Ag, sgg), -1.0,
                                        -1.0));
-        } else {
+        } else if (s->eq == KFBI_WAVE) {
             KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->f, s->A), lset<double>(s->fg, s->Ag), -1.0));
+        } else {
+            KFBI_TRY(schr_b_step(s));
         }
         kap[q] = s->kre;
+        kapi[q] = s->kim;
         f[q] = s->f;
         fg[q] = s->fg;
         g[q] = g_next[q];
         u[q] = u_out[q];
         phi[q] = s->phi;
     }
-    const int rc = batch_helmholtz(b, kap.data(), f.data(), fg.data(), g.data(), u.data(), phi.data(), opts, stats,
-                                   active);
+    const int rc = batch_helmholtz(b, kap.data(), cplx ? kapi.data() : nullptr, f.data(), fg.data(), g.data(),
+                                   u.data(), phi.data(), opts, stats, active);
     if (rc != KFBI_OK && rc != KFBI_ENOCONV) return rc;
     // state updates (as the single steps)
     for (int q = 0; q < n; ++q) {
@@ -340,6 +372,8 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
         if (s->eq == KFBI_HEAT) {
             KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->A, u_out[q], s->f),
                                        lset<double>(s->Ag, g_next[q], s->fg), 2.0 * s->kre, 1.0));
+        } else if (s->eq == KFBI_SCHRODINGER) {
+            KFBI_TRY(schr_state_update(s, u_out[q], g_next[q]));
         } else {
             const double th = s->p.theta, c1 = (1.0 - 2.0 * th) / th, a = s->kre / th;
             KFBI_TRY(lin4_pair<double>(d, ng, Nb, lset<double>(s->B, u_out[q], s->A, s->B),
@@ -797,23 +831,11 @@ int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, cons
                           kfbi_solve_stats *stats) {
     if (!s || !g_next || !u_out) { set_error("null argument"); return KFBI_EINVAL; }
     if (s->eq != KFBI_SCHRODINGER || !s->initialized) { set_error("not an initialised Schroedinger stepper"); return KFBI_EINVAL; }
-    kfbi_domain *d = s->dom;
-    const int ng = (d->M + 1) * (d->M + 1), Nb = d->Nb;
-    k_schr_b<<<(ng + Nb + 255) / 256, 256, 0, d->stream>>>(ng, Nb, (cd *)s->A, (const double *)s->v, (cd *)s->f,
-                                                          (cd *)s->Ag, (const double *)s->vg, (cd *)s->fg, s->p.w,
-                                                          s->p.tau, s->kim);
-    KFBI_CHECK_LAUNCH();
+    KFBI_TRY(schr_b_step(s));
     const void *tr = nullptr;
     int st = step_solve(s, g_next, u_out, opts, stats, &tr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
-    if (s->p.split == KFBI_SPLIT_GODUNOV) {
-        // the next B-step acts on u^{n+1} itself
-        KFBI_TRY(lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u_out), lset<cd>(s->Ag, tr), make_cd(1.0, 0.0)));
-    } else {
-        // u* of the next step, u^{n+1} - i tau/2 lap u^{n+1} = 2 u^{n+1} - u** (eq. 3.12)
-        const cd two = make_cd(2.0, 0.0), m1 = make_cd(-1.0, 0.0);
-        KFBI_TRY(lin4_pair<cd>(d, ng, Nb, lset<cd>(s->A, u_out, s->A), lset<cd>(s->Ag, tr, s->Ag), two, m1));
-    }
+    KFBI_TRY(schr_state_update(s, u_out, tr));
     return st;
 }
 

@@ -51,17 +51,31 @@ struct GmCtl {
 };
 
 // host-visible copy of the control block's outcome, in pinned host memory;
-// written by every control kernel, seq last
+// written by every control kernel, seq last.  seq carries the publishing
+// slot and its state, 4 slot + state, so that the host reads both in one
+// load; the other fields were complete before that store, and after a
+// publish with state Done nothing is published until the next solve resets
+// seq, so a host that has read Done from seq reads final fields.
 struct GmMirror {
     int seq, state, iters, converged, cycles, pad;
     double resid, bnorm;
 };
+
+// the slot count and state a mirror's seq word holds (host side)
+inline void mirror_seq(const GmMirror *mh, int *slot, int *state) {
+    const int w = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
+    *slot = w >> 2;
+    *state = w & 3;
+}
 
 namespace {
 
 constexpr int kGmThreads = 512;
 // dynamic LDS of the iteration kernel: the new vector and staged basis vectors
 constexpr size_t kGmIterLds = 131072;
+// dynamic LDS of the slot control kernel: the working vector and the staged
+// basis (its static LDS, under 16 KB, fills the CU's 160 KB)
+constexpr size_t kGmSlotLds = 147456;
 
 
 // Cross-lane exchanges of the wavefront reductions on the VALU (gfx950),
@@ -147,6 +161,43 @@ __device__ inline T wave_sum16(T (&v)[16], int lane) {
     v[0] += xl<1>(v[0]);
     v[0] += xl<0>(v[0]);
     return v[0];
+}
+
+// K wavefront sums at once (K = 4, 8): the butterfly of wave_sum16 with
+// log2 K halving exchanges, then full exchanges over the remaining lane bits;
+// lane l returns the total of v[(l >> (6 - log2 K)) & (K - 1)]
+template <int B, int H, class T, int K>
+__device__ __forceinline__ void halve_at(T (&v)[K], int lane) {
+    const bool hi = (lane >> B) & 1;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const T send = hi ? v[i] : v[i + H];
+        const T keep = hi ? v[i + H] : v[i];
+        v[i] = keep + xl<B>(send);
+    }
+}
+template <int K, class T>
+__device__ inline T wave_sum_k(T (&v)[K], int lane) {
+    if constexpr (K == 16) {
+        return wave_sum16(v, lane);
+    } else if constexpr (K == 8) {
+        halve_at<5, 4>(v, lane);
+        halve_at<4, 2>(v, lane);
+        halve_at<3, 1>(v, lane);
+        v[0] += xl<2>(v[0]);
+        v[0] += xl<1>(v[0]);
+        v[0] += xl<0>(v[0]);
+        return v[0];
+    } else {
+        static_assert(K == 4, "K = 4, 8 or 16");
+        halve_at<5, 2>(v, lane);
+        halve_at<4, 1>(v, lane);
+        v[0] += xl<3>(v[0]);
+        v[0] += xl<2>(v[0]);
+        v[0] += xl<1>(v[0]);
+        v[0] += xl<0>(v[0]);
+        return v[0];
+    }
 }
 
 // block-wide sum; every thread gets the result
@@ -672,7 +723,7 @@ __device__ inline void gm_publish(GmCtl *ctl, GmMirror *mir) {
     mir->resid = ctl->resid;
     mir->bnorm = ctl->bnorm;
     __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __hip_atomic_store(&mir->seq, ctl->slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&mir->seq, 4 * ctl->slot + ctl->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // control block, ||b||, and x_0 as the first slot's density
@@ -775,7 +826,9 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     extern __shared__ double dyn[];
     T *sw = reinterpret_cast<T *>(dyn);
     T *sV = sw + Nb;
-    T *sH = sV + (size_t)nvl * Nb;
+    // the triangular factor of a cycle end takes the place of the staged
+    // basis, which is no longer read by then
+    T *sH = sV;
     __shared__ T red[kGmThreads / 64][65];
     __shared__ T hcol[72];
     __shared__ T hs[72];
@@ -869,29 +922,46 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
         // from which the norm of the result follows without a reduction of
         // its own
         const int jn = pass == 1 ? j + 1 : j;
-        for (int i0 = 0; i0 <= jn && staged; i0 += 16) {
-            T part[16];
+        // the products in chunks of 4, 8 or 16 (the fewest that cover the
+        // jn + 1 terms, so that few lanes of the reduction carry zeros)
+        auto chunk = [&](auto kk, int i0) {
+            constexpr int K = decltype(kk)::value;
+            T part[K];
 #pragma unroll
-            for (int ii = 0; ii < 16; ++ii) part[ii] = zero<T>();
+            for (int ii = 0; ii < K; ++ii) part[ii] = zero<T>();
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int idx = tid + e * kGmThreads;
                 if (idx < Nb) {
-                    T vv[16];
+                    T vv[K];
 #pragma unroll
-                    for (int ii = 0; ii < 16; ++ii) {
+                    for (int ii = 0; ii < K; ++ii) {
                         const int i = i0 + ii <= j ? i0 + ii : j;
                         vv[ii] = sV[(size_t)i * Nb + idx];
                     }
 #pragma unroll
-                    for (int ii = 0; ii < 16; ++ii)
+                    for (int ii = 0; ii < K; ++ii)
                         part[ii] += (i0 + ii <= j ? conjv(vv[ii]) : (i0 + ii == jn ? conjv(wl[e]) : zero<T>())) *
                                     wl[e];
                 }
             }
-            const T sum = wave_sum16(part, lane);
-            const int ii = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && i0 + ii <= jn) red[wid][i0 + ii] = sum;
+            const T sum = wave_sum_k<K>(part, lane);
+            constexpr int S = K == 16 ? 2 : (K == 8 ? 3 : 4);
+            const int ii = (lane >> S) & (K - 1);
+            if ((lane & ((1 << S) - 1)) == 0 && i0 + ii <= jn) red[wid][i0 + ii] = sum;
+        };
+        for (int i0 = 0; i0 <= jn && staged;) {
+            const int rem = jn + 1 - i0;
+            if (rem <= 4) {
+                chunk(std::integral_constant<int, 4>(), i0);
+                i0 += 4;
+            } else if (rem <= 8) {
+                chunk(std::integral_constant<int, 8>(), i0);
+                i0 += 8;
+            } else {
+                chunk(std::integral_constant<int, 16>(), i0);
+                i0 += 16;
+            }
         }
         for (int i0 = 0; i0 <= jn && !staged; i0 += 16) {
             T part[16];
@@ -934,16 +1004,16 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
             const int idx = tid + e * kGmThreads;
             if (idx < Nb) {
                 if (staged) {
-                    for (int i0 = 0; i0 <= j; i0 += 8) {
-                        T vv[8], hh[8];
+                    for (int i0 = 0; i0 <= j; i0 += 4) {
+                        T vv[4], hh[4];
 #pragma unroll
-                        for (int ii = 0; ii < 8; ++ii) {
+                        for (int ii = 0; ii < 4; ++ii) {
                             const int i = i0 + ii <= j ? i0 + ii : j;
                             vv[ii] = sV[(size_t)i * Nb + idx];
                             hh[ii] = i0 + ii <= j ? hs[i] : zero<T>();
                         }
 #pragma unroll
-                        for (int ii = 0; ii < 8; ++ii) wl[e] -= hh[ii] * vv[ii];
+                        for (int ii = 0; ii < 4; ++ii) wl[e] -= hh[ii] * vv[ii];
                     }
                 } else {
                     for (int i = 0; i < nst; ++i) wl[e] -= hs[i] * sV[(size_t)i * Nb + idx];
@@ -1052,8 +1122,7 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
         const int idx = tid + e * kGmThreads;
         if (idx < Nb) {
             T acc = x[idx];
-            for (int i = 0; i < nst; ++i) acc += sV[(size_t)i * Nb + idx] * ys[i];
-            for (int i = nst; i <= j; ++i) acc += V[(size_t)i * Nb + idx] * ys[i];
+            for (int i = 0; i <= j; ++i) acc += V[(size_t)i * Nb + idx] * ys[i];
             x[idx] = acc;
             vcur[idx] = acc;
         }
@@ -1350,15 +1419,16 @@ __global__ void k_copy_gated(int n, T *__restrict__ dst, const T *__restrict__ s
     if (i < n) dst[i] = src[i];
 }
 
-// dynamic LDS of the control kernel; nvl basis vectors staged
+// dynamic LDS of the control kernel: the working vector, then nvl staged
+// basis vectors, which the m x m triangular factor of a cycle end reuses
 template <class T>
 static size_t slot_lds(int Nb, int m, int *nvl_out) {
     const size_t es = sizeof(T), hb = (size_t)m * m * es, vb = (size_t)Nb * es;
     int nvl = 0;
-    if (kGmIterLds >= hb + vb) nvl = (int)((kGmIterLds - hb - vb) / vb);
+    if (kGmSlotLds >= vb) nvl = (int)((kGmSlotLds - vb) / vb);
     if (nvl > m + 1) nvl = m + 1;
     *nvl_out = nvl;
-    return vb * (1 + nvl) + hb;
+    return vb + std::max(vb * nvl, hb);
 }
 
 template <class T>
@@ -1405,7 +1475,7 @@ SlotArgs<T> slot_args(GmPtrs &P, GmMirror *mir, int Nb, int m, int nvl) {
 template <class T>
 static bool slots_supported(kfbi_domain *d, int m) {
     int nvl;
-    return d->op_merged && (size_t)d->Nb * sizeof(T) <= 65536 && slot_lds<T>(d->Nb, m, &nvl) <= kGmIterLds;
+    return d->op_merged && (size_t)d->Nb * sizeof(T) <= 65536 && slot_lds<T>(d->Nb, m, &nvl) <= kGmSlotLds;
 }
 
 template <class T>
@@ -1461,7 +1531,7 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
     const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
     // first batch: the previous solve's slot count on this domain plus one
     int want = d->last_slots > 0 ? d->last_slots + 1 : (fixed > 0 ? fixed + 2 : 12);
-    int n_enq = 0, last_batch = 0;
+    int n_enq = 0, last_batch = 0, seq_last = 0;
     for (int batch = 0;; ++batch) {
         last_batch = batch;
         for (int c = 0; c < want; ++c) {
@@ -1492,8 +1562,7 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
         const auto t0 = std::chrono::steady_clock::now();
         int seq = 0, st = kStIter;
         for (long spin = 1;; ++spin) {
-            seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
-            st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+            mirror_seq(mh, &seq, &st);
             if (seq > 0 && (st == kStDone || seq >= n_enq)) break;
             if ((spin & 255) == 0) {
                 const hipError_t q = hipStreamQuery(s);
@@ -1502,8 +1571,7 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
                     return KFBI_EDEVICE;
                 }
                 if (q == hipSuccess) {  // stream drained: the mirror must be final
-                    seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
-                    st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+                    mirror_seq(mh, &seq, &st);
                     if (seq > 0 && (st == kStDone || seq >= n_enq)) break;
                     set_error("GMRES control block not published by the device");
                     return KFBI_EDEVICE;
@@ -1514,13 +1582,14 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
                 }
             }
         }
+        seq_last = seq;
         if (st == kStDone) {
             d->last_slots = seq;
             break;
         }
         want = 4;
     }
-    if (d->prof_on) KFBI_TRY(prof_flush(d, mh->seq, kTailTag + last_batch));
+    if (d->prof_on) KFBI_TRY(prof_flush(d, seq_last, kTailTag + last_batch));
     *iters_out = mh->iters;
     *rel_out = mh->bnorm > 0 ? mh->resid / mh->bnorm : mh->resid;
     *conv_out = mh->converged;
@@ -1787,13 +1856,14 @@ __global__ void kb_final(const FinalArgs *__restrict__ A, int n) {
     if (q < n && *A[q].skip_tail == 0) *A[q].skip_tail = 2;
 }
 
-__global__ __launch_bounds__(kGmThreads) void kb_gm_init(const GmInitArgs<double> *__restrict__ A) {
+template <class T>
+__global__ __launch_bounds__(kGmThreads) void kb_gm_init(const GmInitArgs<T> *__restrict__ A) {
     gm_init_body(A[blockIdx.x], 0);
 }
 
-template <int EPT>
-__global__ __launch_bounds__(kGmThreads) void kb_gm_slot(const SlotArgs<double> *__restrict__ A) {
-    gm_slot_body<double, EPT>(A[blockIdx.x], 0);
+template <class T, int EPT>
+__global__ __launch_bounds__(kGmThreads) void kb_gm_slot(const SlotArgs<T> *__restrict__ A) {
+    gm_slot_body<T, EPT>(A[blockIdx.x], 0);
 }
 
 // argument arrays of one batched solve, one entry per member each
@@ -1825,6 +1895,7 @@ inline int mb_log2(int mb) { return mb >= 8 ? 3 : mb >= 4 ? 2 : mb >= 2 ? 1 : 0;
 struct kfbi_batch {
     std::vector<kfbi_domain *> doms;
     hipStream_t stream = nullptr;
+    bool cplx = false;  // every member complex (else every member real)
     // workgroup maps, one array for all kinds and classes
     kfbi::BlkMap *d_map = nullptr;
     int map_off[kfbi::kBaKinds] = {}, map_blocks[kfbi::kBaKinds] = {};
@@ -1855,20 +1926,33 @@ void batch_destroy(kfbi_batch *b) {
 int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
     if (!doms || n < 1 || !out) { set_error("null argument or empty batch"); return KFBI_EINVAL; }
     *out = nullptr;
+    if (!doms[0]) { set_error("null domain in batch"); return KFBI_EINVAL; }
     kfbi_batch *b = new kfbi_batch();
     b->stream = doms[0]->stream;
+    b->cplx = doms[0]->cplx;
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = doms[q];
         if (!d) { batch_destroy(b); set_error("null domain in batch"); return KFBI_EINVAL; }
-        if (d->cplx) { batch_destroy(b); set_error("batched solves support real domains only"); return KFBI_ENOTSUP; }
+        if (d->cplx != b->cplx) {
+            batch_destroy(b);
+            set_error("batch members must share one scalar type (all real or all complex)");
+            return KFBI_EINVAL;
+        }
         if (d->stream != b->stream) {
             batch_destroy(b);
             set_error("batch members must share one stream");
             return KFBI_EINVAL;
         }
-        if ((size_t)d->Nb * sizeof(double) > 65536) {
+        if ((size_t)d->Nb * elem_size(d) > 65536) {
             batch_destroy(b);
-            set_error("batch members need Nb <= 8192");
+            set_error("batch members need Nb <= 8192 (real) or 4096 (complex)");
+            return KFBI_ENOTSUP;
+        }
+        if (d->M < 64) {
+            // the row-wise stencil evaluation holds a row of 64 KR modes in
+            // registers, KR >= 1
+            batch_destroy(b);
+            set_error("batch members need M >= 64");
             return KFBI_ENOTSUP;
         }
         if (d->erow_blk_max > kErowCols) {
@@ -1888,7 +1972,7 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
         for (int q = 0; q < n; ++q) {
             int nbk;
             if (kind == kBaCorr || kind == kBaExt) nbk = batch_blocks_iface(doms[q], kind);
-            else if (kind == kBaCopy) nbk = (doms[q]->Nb + 255) / 256;
+            else if (kind == kBaCopy) nbk = ((doms[q]->cplx ? 2 : 1) * doms[q]->Nb + 255) / 256;  // doubles
             else nbk = batch_blocks(doms[q], kind);
             for (int l = 0; l < nbk; ++l) map.push_back(BlkMap{q, l});
         }
@@ -1926,19 +2010,19 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
     // argument arrays
     auto use_size = [&](int u) -> size_t {
         switch (u) {
-            case kUDstF: case kUIdst: return batch_args_size(kBaDst);
-            case kUZero: return batch_args_size(kBaZero);
-            case kUCorrB: case kUCorrF: return batch_args_size_iface(kBaCorr);
-            case kUExtB: return batch_args_size_iface(kBaExt);
-            case kUTriB: case kUTriF: case kUTri64: return batch_args_size(kBaTri64);
-            case kUTri32: return batch_args_size(kBaTri32);
-            case kUErowB: case kUErow64: return batch_args_size(kBaErow64);
-            case kUErow32: return batch_args_size(kBaErow32);
-            case kUExm64: case kUExm32: return batch_args_size(kBaExm);
-            case kUCorrPhi64: case kUCorrPhi32: return batch_args_size(kBaCorrPhi);
+            case kUDstF: case kUIdst: return batch_args_size(kBaDst, b->cplx);
+            case kUZero: return batch_args_size(kBaZero, b->cplx);
+            case kUCorrB: case kUCorrF: return batch_args_size_iface(kBaCorr, b->cplx);
+            case kUExtB: return batch_args_size_iface(kBaExt, b->cplx);
+            case kUTriB: case kUTriF: case kUTri64: return batch_args_size(kBaTri64, b->cplx);
+            case kUTri32: return batch_args_size(kBaTri32, b->cplx);
+            case kUErowB: case kUErow64: return batch_args_size(kBaErow64, b->cplx);
+            case kUErow32: return batch_args_size(kBaErow32, b->cplx);
+            case kUExm64: case kUExm32: return batch_args_size(kBaExm, b->cplx);
+            case kUCorrPhi64: case kUCorrPhi32: return batch_args_size(kBaCorrPhi, b->cplx);
             case kUCopyX: case kUCopyF: return sizeof(CopyArgs);
-            case kUInit: return sizeof(GmInitArgs<double>);
-            case kUSlot: return sizeof(SlotArgs<double>);
+            case kUInit: return b->cplx ? sizeof(GmInitArgs<cd>) : sizeof(GmInitArgs<double>);
+            case kUSlot: return b->cplx ? sizeof(SlotArgs<cd>) : sizeof(SlotArgs<double>);
             case kUFinal: return sizeof(FinalArgs);
             default: return 0;
         }
@@ -1981,7 +2065,9 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
 int tune_time(kfbi_batch *b, int kind, const void *args, const BatchClass &C, const BatchTriShape &S, double *us) {
     hipStream_t s = b->stream;
     const int lm = mb_log2(S.mb);
-    auto go = [&]() { return batch_launch(kind, args, b->d_map + C.map_mb[lm], C.blocks_mb[lm], C.M, &S, s); };
+    auto go = [&]() {
+        return batch_launch(kind, args, b->d_map + C.map_mb[lm], C.blocks_mb[lm], C.M, &S, s, b->cplx);
+    };
     KFBI_TRY(go());
     float ms = 0.f;
     KFBI_HIP(hipEventRecord(b->ev0, s));
@@ -2007,7 +2093,7 @@ int tune_time(kfbi_batch *b, int kind, const void *args, const BatchClass &C, co
 // cleared; the launches write only the scratch transforms.
 int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) {
     const int n = (int)b->doms.size();
-    const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64);
+    const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64, b->cplx);
     for (auto &C : b->classes) {
         std::vector<kfbi_domain *> cd;
         bool any = false;
@@ -2053,7 +2139,7 @@ int batch_tune(kfbi_batch *b, bool low, const uint8_t *active) {
     if (!need) return KFBI_OK;
     const int n = (int)b->doms.size();
     hipStream_t s = b->stream;
-    const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64);
+    const size_t as = batch_args_size(low ? kBaTri32 : kBaTri64, b->cplx);
     std::vector<char> h(2 * as * n);
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = b->doms[q];
@@ -2061,8 +2147,8 @@ int batch_tune(kfbi_batch *b, bool low, const uint8_t *active) {
         // members not solved in this call may lack their coefficients: gated off
         const int *one = (!active || active[q]) ? nullptr : b->d_one;
         if (!one) {
-            KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * sizeof(double), s));
-            KFBI_HIP(hipMemsetAsync(d->rhat, 0, (size_t)nn * nn * sizeof(double), s));
+            KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * elem_size(d), s));
+            KFBI_HIP(hipMemsetAsync(d->rhat, 0, (size_t)nn * nn * elem_size(d), s));
         }
         batch_fill_tri(d, nullptr, d->corr, low ? d->uhat32 : d->uhat, one, low, h.data() + (size_t)q * as);
         if (!low) batch_fill_tri(d, d->rhat, d->corr, d->uhat, one, false, h.data() + (size_t)(n + q) * as);
@@ -2103,10 +2189,16 @@ int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_
     return KFBI_OK;
 }
 
-int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
-                    const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
-                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats, const uint8_t *active) {
-    if (!b || !kappa || !f_grid || !f_gamma || !g_gamma) { set_error("null argument"); return KFBI_EINVAL; }
+namespace {
+template <class T>
+int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im, const void *const *f_grid,
+                      const void *const *f_gamma, const void *const *g_gamma, void *const *u_out,
+                      void *const *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats,
+                      const uint8_t *active) {
+    auto kim = [&](int q) { return kappa_im ? kappa_im[q] : 0.0; };
+    const bool cplx = b->cplx;
+    // a complex element moves as two doubles in the density copies
+    const int cw = cplx ? 2 : 1;
     const int n = (int)b->doms.size();
     auto on = [&](int q) { return !active || active[q] != 0; };
     int n_on = 0;
@@ -2141,10 +2233,10 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         kfbi_domain *d = b->doms[q];
         if (!on(q)) continue;
         if (!f_grid[q] || !f_gamma[q] || !g_gamma[q]) { set_error("null member array"); return KFBI_EINVAL; }
-        KFBI_TRY(ensure_coefficients(d, kappa[q], 0.0));
-        KFBI_TRY(ensure_operators(d, kappa[q], 0.0));
-        if (mixed) KFBI_TRY(ensure_coefficients_low(d, kappa[q], 0.0));
-        if (!slots_supported<double>(d, o.restart)) {
+        KFBI_TRY(ensure_coefficients(d, kappa[q], kim(q)));
+        KFBI_TRY(ensure_operators(d, kappa[q], kim(q)));
+        if (mixed) KFBI_TRY(ensure_coefficients_low(d, kappa[q], kim(q)));
+        if (!slots_supported<T>(d, o.restart)) {
             set_error("batch member without the merged operators or too large for the control kernel");
             return KFBI_ENOTSUP;
         }
@@ -2159,7 +2251,6 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         if (mixed) KFBI_TRY(batch_tune(b, true, active));
     }
     // argument blocks
-    int nvl_min = 1 << 30;
     size_t slot_lds_max = 0;
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = b->doms[q];
@@ -2170,15 +2261,15 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
                   *skip_tail = one ? one : &P.ctl->skip_tail;
         auto at = [&](int u) { return b->h_args + b->use_off[u] + (size_t)q * b->use_size[u]; };
         batch_fill_dst(d, f_grid[q], true, true, d->rhat, false, 1.0, one, at(kUDstF));
-        batch_fill_corr(d, kappa[q], nullptr, f_gamma[q], d->corr, one, at(kUCorrB));
+        batch_fill_corr(d, kappa[q], kim(q), nullptr, f_gamma[q], d->corr, one, at(kUCorrB));
         batch_fill_tri(d, d->rhat, d->corr, d->uhat, one, false, at(kUTriB));
         batch_fill_erow(d, d->uhat, d->ust, one, false, at(kUErowB));
-        batch_fill_ext(d, kappa[q], d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, one, at(kUExtB));
+        batch_fill_ext(d, kappa[q], kim(q), d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, one, at(kUExtB));
         *(CopyArgs *)at(kUCopyX) = CopyArgs{(double *)P.x, phi_inout ? (const double *)phi_inout[q] : nullptr,
-                                            d->Nb, one};
-        GmInitArgs<double> ia = gm_init_args<double>(P, d->Nb, o, mixed, P.x);
+                                            cw * d->Nb, one};
+        GmInitArgs<T> ia = gm_init_args<T>(P, d->Nb, o, mixed, P.x);
         ia.off = one;
-        *(GmInitArgs<double> *)at(kUInit) = ia;
+        *(GmInitArgs<T> *)at(kUInit) = ia;
         batch_fill_corr_phi(d, P.vcur, d->corr, skip64, at(kUCorrPhi64));
         batch_fill_tri(d, nullptr, d->corr, d->uhat, skip64, false, at(kUTri64));
         batch_fill_erow(d, d->uhat, d->ust, skip64, false, at(kUErow64));
@@ -2188,47 +2279,42 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
         batch_fill_erow(d, d->uhat32, d->ust, skip32, true, at(kUErow32));
         batch_fill_exm(d, d->ust, P.vcur, P.r, skip32, at(kUExm32));
         int nvl;
-        const size_t lds = slot_lds<double>(d->Nb, o.restart, &nvl);
+        const size_t lds = slot_lds<T>(d->Nb, o.restart, &nvl);
         slot_lds_max = std::max(slot_lds_max, lds);
-        nvl_min = std::min(nvl_min, nvl);
-        SlotArgs<double> sa = slot_args<double>(P, (GmMirror *)d->mirror_dev, d->Nb, o.restart, nvl);
+        SlotArgs<T> sa = slot_args<T>(P, (GmMirror *)d->mirror_dev, d->Nb, o.restart, nvl);
         sa.off = one;
-        *(SlotArgs<double> *)at(kUSlot) = sa;
-        batch_fill_corr(d, kappa[q], P.x, f_gamma[q], d->corr, skip_tail, at(kUCorrF));
+        *(SlotArgs<T> *)at(kUSlot) = sa;
+        batch_fill_corr(d, kappa[q], kim(q), P.x, f_gamma[q], d->corr, skip_tail, at(kUCorrF));
         batch_fill_tri(d, d->rhat, d->corr, d->uhat, skip_tail, false, at(kUTriF));
         void *uo = u_out ? u_out[q] : nullptr;
         batch_fill_dst(d, d->uhat, false, false, uo, true, 2.0 / d->M, skip_tail, at(kUIdst));
         batch_fill_zero(d, uo, skip_tail, at(kUZero));
         *(CopyArgs *)at(kUCopyF) = CopyArgs{phi_inout ? (double *)phi_inout[q] : nullptr, (const double *)P.x,
-                                            d->Nb, skip_tail};
+                                            cw * d->Nb, skip_tail};
         *(FinalArgs *)at(kUFinal) = FinalArgs{one ? b->d_one : &P.ctl->skip_tail};
         if (on(q)) __atomic_store_n(&((GmMirror *)d->mirror_host)->seq, 0, __ATOMIC_RELEASE);
     }
-    // the dynamic LDS of a batched control launch must hold every member's
-    // layout, with nvl staged vectors of the largest Nb
-    for (int q = 0; q < n; ++q) {
-        SlotArgs<double> *A = (SlotArgs<double> *)(b->h_args + b->use_off[kUSlot] + (size_t)q * b->use_size[kUSlot]);
-        A->nvl = nvl_min;
-    }
-    slot_lds_max = (size_t)b->nb_max * sizeof(double) * (1 + nvl_min) + (size_t)o.restart * o.restart * sizeof(double);
+    // every member keeps the layout of its own single solve (its own number
+    // of staged basis vectors, so the same Gram-Schmidt code path and the
+    // same rounding); the launch's dynamic LDS holds the largest layout
     KFBI_HIP(hipEventRecord(b->ev0, s));
     KFBI_HIP(hipMemcpyAsync(b->d_args, b->h_args, b->args_bytes, hipMemcpyHostToDevice, s));
     auto dargs = [&](int u) { return (const void *)(b->d_args + b->use_off[u]); };
     auto mapk = [&](int kind) { return b->d_map + b->map_off[kind]; };
     auto launch = [&](int kind, int use) -> int {
-        return batch_launch(kind, dargs(use), mapk(kind), b->map_blocks[kind], 0, nullptr, s);
+        return batch_launch(kind, dargs(use), mapk(kind), b->map_blocks[kind], 0, nullptr, s, cplx);
     };
     // DST launches: LDS for the largest grid (each block uses its own M)
     int m_max = 0;
     for (auto *d : b->doms) m_max = std::max(m_max, d->M);
     auto launch_dst = [&](int use) -> int {
-        return batch_launch(kBaDst, dargs(use), mapk(kBaDst), b->map_blocks[kBaDst], m_max, nullptr, s);
+        return batch_launch(kBaDst, dargs(use), mapk(kBaDst), b->map_blocks[kBaDst], m_max, nullptr, s, cplx);
     };
     // stencil evaluation per class of equal M (register rows sized to M)
     auto launch_erow = [&](int use, bool low) -> int {
         for (auto &C : b->classes)
             KFBI_TRY(batch_launch(low ? kBaErow32 : kBaErow64, dargs(use), b->d_map + C.map_erow, C.blocks_erow, C.M,
-                                  nullptr, s));
+                                  nullptr, s, cplx));
         return KFBI_OK;
     };
     auto launch_tri = [&](int use, bool low, bool dense) -> int {
@@ -2236,19 +2322,19 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
             const BatchTriShape &S = C.shape[low ? 2 : (dense ? 1 : 0)];
             const int lm = mb_log2(S.mb);
             KFBI_TRY(batch_launch(low ? kBaTri32 : kBaTri64, dargs(use), b->d_map + C.map_mb[lm], C.blocks_mb[lm],
-                                  C.M, &S, s));
+                                  C.M, &S, s, cplx));
         }
         return KFBI_OK;
     };
     // b-solve for every member
     KFBI_TRY(launch_dst(kUDstF));
-    KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrB), mapk(kBaCorr), b->map_blocks[kBaCorr], s));
+    KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrB), mapk(kBaCorr), b->map_blocks[kBaCorr], s, cplx));
     KFBI_TRY(launch_tri(kUTriB, false, true));
     KFBI_TRY(launch_erow(kUErowB, false));
-    KFBI_TRY(batch_launch_iface(kBaExt, dargs(kUExtB), mapk(kBaExt), b->map_blocks[kBaExt], s));
+    KFBI_TRY(batch_launch_iface(kBaExt, dargs(kUExtB), mapk(kBaExt), b->map_blocks[kBaExt], s, cplx));
     kb_copy<<<b->map_blocks[kBaCopy], 256, 0, s>>>((const CopyArgs *)dargs(kUCopyX), mapk(kBaCopy));
     KFBI_CHECK_LAUNCH();
-    kb_gm_init<<<n, kGmThreads, 0, s>>>((const GmInitArgs<double> *)dargs(kUInit));
+    kb_gm_init<T><<<n, kGmThreads, 0, s>>>((const GmInitArgs<T> *)dargs(kUInit));
     KFBI_CHECK_LAUNCH();
     // slots until every member has finished
     const int ept = (b->nb_max + kGmThreads - 1) / kGmThreads;
@@ -2266,17 +2352,17 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
                 KFBI_TRY(launch_erow(kUErow32, true));
                 KFBI_TRY(launch(kBaExm, kUExm32));
             }
-            const SlotArgs<double> *SA = (const SlotArgs<double> *)dargs(kUSlot);
-            if (ept <= 1) kb_gm_slot<1><<<n, kGmThreads, slot_lds_max, s>>>(SA);
-            else if (ept <= 2) kb_gm_slot<2><<<n, kGmThreads, slot_lds_max, s>>>(SA);
-            else if (ept <= 4) kb_gm_slot<4><<<n, kGmThreads, slot_lds_max, s>>>(SA);
-            else if (ept <= 8) kb_gm_slot<8><<<n, kGmThreads, slot_lds_max, s>>>(SA);
-            else kb_gm_slot<16><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            const SlotArgs<T> *SA = (const SlotArgs<T> *)dargs(kUSlot);
+            if (ept <= 1) kb_gm_slot<T, 1><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else if (ept <= 2) kb_gm_slot<T, 2><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else if (ept <= 4) kb_gm_slot<T, 4><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else if (ept <= 8) kb_gm_slot<T, 8><<<n, kGmThreads, slot_lds_max, s>>>(SA);
+            else kb_gm_slot<T, 16><<<n, kGmThreads, slot_lds_max, s>>>(SA);
             KFBI_CHECK_LAUNCH();
         }
         n_enq += want;
         // final solve of the members that have finished (gated per member)
-        KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrF), mapk(kBaCorr), b->map_blocks[kBaCorr], s));
+        KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrF), mapk(kBaCorr), b->map_blocks[kBaCorr], s, cplx));
         KFBI_TRY(launch_tri(kUTriF, false, true));
         if (u_out) {
             KFBI_TRY(launch_dst(kUIdst));
@@ -2297,8 +2383,8 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
             for (int q = 0; q < n; ++q) {
                 if (!on(q)) continue;
                 GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
-                const int seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
-                const int st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+                int seq, st;
+                mirror_seq(mh, &seq, &st);
                 const bool done = seq > 0 && st == kStDone;
                 if (!done) all_done = false;
                 if (!(done || seq >= n_enq)) settled = false;
@@ -2316,8 +2402,8 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
                     for (int q = 0; q < n; ++q) {
                         if (!on(q)) continue;
                         GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
-                        const int seq = __atomic_load_n(&mh->seq, __ATOMIC_ACQUIRE);
-                        const int st = __atomic_load_n(&mh->state, __ATOMIC_RELAXED);
+                        int seq, st;
+                        mirror_seq(mh, &seq, &st);
                         if (!((seq > 0 && st == kStDone) || seq >= n_enq)) ok = false;
                     }
                     if (ok) continue;
@@ -2337,7 +2423,9 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     for (int q = 0; q < n; ++q) {
         if (!on(q)) continue;
         GmMirror *mh = (GmMirror *)b->doms[q]->mirror_host;
-        max_seq = std::max(max_seq, mh->seq);
+        int seq_q, st_q;
+        mirror_seq(mh, &seq_q, &st_q);
+        max_seq = std::max(max_seq, seq_q);
         if (stats) {
             stats[q].iters = mh->iters;
             stats[q].converged = mh->converged;
@@ -2361,5 +2449,26 @@ int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_gri
     if (st == KFBI_ENOCONV) set_error("GMRES reached max_iter before the tolerance for a batch member");
     return st;
 }
+}  // namespace
+
+int batch_helmholtz(kfbi_batch *b, const double *kappa, const double *kappa_im, const void *const *f_grid,
+                    const void *const *f_gamma, const void *const *g_gamma, void *const *u_out,
+                    void *const *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats,
+                    const uint8_t *active) {
+    if (!b || !kappa || !f_grid || !f_gamma || !g_gamma) { set_error("null argument"); return KFBI_EINVAL; }
+    if (kappa_im && !b->cplx)
+        for (int q = 0; q < (int)b->doms.size(); ++q)
+            if (kappa_im[q] != 0.0 && (!active || active[q])) {
+                set_error("complex kappa needs a batch of complex domains");
+                return KFBI_EINVAL;
+            }
+    if (b->cplx)
+        return batch_helmholtz_t<cd>(b, kappa, kappa_im, f_grid, f_gamma, g_gamma, u_out, phi_inout, opts, stats,
+                                     active);
+    return batch_helmholtz_t<double>(b, kappa, kappa_im, f_grid, f_gamma, g_gamma, u_out, phi_inout, opts, stats,
+                                     active);
+}
+
+bool batch_complex(const kfbi_batch *b) { return b->cplx; }
 
 }  // namespace kfbi

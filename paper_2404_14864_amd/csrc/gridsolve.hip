@@ -1330,7 +1330,8 @@ int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, cons
 // ---------------------------------------------------------------------------
 // Batched launches: one grid runs the blocks of many instances; workgroup b
 // looks up (instance, local block) in a map and reads that instance's
-// argument block.  Only real instances (FP64 with FP32 inner solves).
+// argument block.  The instances of a launch share one scalar type: real
+// (FP64, FP32 inner solves) or complex (complex128, complex64 inner solves).
 // ---------------------------------------------------------------------------
 namespace {
 template <class T>
@@ -1383,69 +1384,99 @@ template <int KR>
 void ErowLaunchBatch<T, TO>::go() const {
     kb_eval_rows<T, TO, KR><<<blocks, 256, lds, s>>>(A, map);
 }
-__global__ __launch_bounds__(256) void kb_extract_merged(const ExmArgs<double> *__restrict__ A,
+template <class T>
+__global__ __launch_bounds__(256) void kb_extract_merged(const ExmArgs<T> *__restrict__ A,
                                                          const BlkMap *__restrict__ map) {
     const BlkMap e = map[blockIdx.x];
     extract_merged_body(A[e.inst], e.local);
 }
 }  // namespace
 
-// argument blocks of one member, written to host memory
-size_t batch_args_size(int kind) {
+// argument blocks of one member, written to host memory: a batched kernel
+// indexes its blocks with the size of its own instantiation, so the stride is
+// the exact size for the batch's scalar type
+namespace {
+template <class R, class C>
+size_t args_size(bool cplx) {
+    return cplx ? sizeof(C) : sizeof(R);
+}
+}  // namespace
+
+size_t batch_args_size(int kind, bool cplx) {
     switch (kind) {
-        case kBaDst: return sizeof(DstArgs<double>);
-        case kBaZero: return sizeof(ZeroArgs<double>);
-        case kBaTri64: return sizeof(TriArgs<double, double>);
-        case kBaTri32: return sizeof(TriArgs<float, double>);
-        case kBaEval: return sizeof(EvalArgs<double, double>);
-        case kBaEvx64: return sizeof(EvxArgs<double, double>);
-        case kBaEvx32: return sizeof(EvxArgs<float, double>);
-        case kBaCorrPhi: return sizeof(CorrPhiArgs<double>);
-        case kBaErow64: return sizeof(ErowArgs<double, double>);
-        case kBaErow32: return sizeof(ErowArgs<float, double>);
-        case kBaExm: return sizeof(ExmArgs<double>);
+        case kBaDst: return args_size<DstArgs<double>, DstArgs<cd>>(cplx);
+        case kBaZero: return args_size<ZeroArgs<double>, ZeroArgs<cd>>(cplx);
+        case kBaTri64: return args_size<TriArgs<double, double>, TriArgs<cd, cd>>(cplx);
+        case kBaTri32: return args_size<TriArgs<float, double>, TriArgs<cf, cd>>(cplx);
+        case kBaEval: return args_size<EvalArgs<double, double>, EvalArgs<cd, cd>>(cplx);
+        case kBaEvx64: return args_size<EvxArgs<double, double>, EvxArgs<cd, cd>>(cplx);
+        case kBaEvx32: return args_size<EvxArgs<float, double>, EvxArgs<cf, cd>>(cplx);
+        case kBaCorrPhi: return args_size<CorrPhiArgs<double>, CorrPhiArgs<cd>>(cplx);
+        case kBaErow64: return args_size<ErowArgs<double, double>, ErowArgs<cd, cd>>(cplx);
+        case kBaErow32: return args_size<ErowArgs<float, double>, ErowArgs<cf, cd>>(cplx);
+        case kBaExm: return args_size<ExmArgs<double>, ExmArgs<cd>>(cplx);
         default: return 0;
     }
 }
 
 void batch_fill_dst(kfbi_domain *d, const void *in, bool in_grid, bool mask_inside, void *out, bool out_grid,
                     double scale, const int *done, void *dst) {
-    *(DstArgs<double> *)dst = dst_args<double>(d, in, in_grid, mask_inside ? d->flags : nullptr, out, out_grid,
-                                               scale, done);
+    const uint8_t *mask = mask_inside ? d->flags : nullptr;
+    if (d->cplx) *(DstArgs<cd> *)dst = dst_args<cd>(d, in, in_grid, mask, out, out_grid, scale, done);
+    else *(DstArgs<double> *)dst = dst_args<double>(d, in, in_grid, mask, out, out_grid, scale, done);
 }
 void batch_fill_zero(kfbi_domain *d, void *grid, const int *done, void *dst) {
-    *(ZeroArgs<double> *)dst = ZeroArgs<double>{d->M, (double *)grid, done};
+    if (d->cplx) *(ZeroArgs<cd> *)dst = ZeroArgs<cd>{d->M, (cd *)grid, done};
+    else *(ZeroArgs<double> *)dst = ZeroArgs<double>{d->M, (double *)grid, done};
 }
 void batch_fill_tri(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done, bool low,
                     void *dst) {
-    if (low) *(TriArgs<float, double> *)dst = tri_args<float>(d, rhat, corr, uhat, done);
-    else *(TriArgs<double, double> *)dst = tri_args<double>(d, rhat, corr, uhat, done);
+    if (d->cplx) {
+        if (low) *(TriArgs<cf, cd> *)dst = tri_args<cf>(d, rhat, corr, uhat, done);
+        else *(TriArgs<cd, cd> *)dst = tri_args<cd>(d, rhat, corr, uhat, done);
+    } else {
+        if (low) *(TriArgs<float, double> *)dst = tri_args<float>(d, rhat, corr, uhat, done);
+        else *(TriArgs<double, double> *)dst = tri_args<double>(d, rhat, corr, uhat, done);
+    }
 }
 void batch_fill_eval(kfbi_domain *d, const void *uhat, void *out, const int *done, void *dst) {
-    *(EvalArgs<double, double> *)dst = eval_args<double, double>(d, uhat, out, done);
+    if (d->cplx) *(EvalArgs<cd, cd> *)dst = eval_args<cd, cd>(d, uhat, out, done);
+    else *(EvalArgs<double, double> *)dst = eval_args<double, double>(d, uhat, out, done);
 }
 void batch_fill_evx(kfbi_domain *d, const void *uhat, const void *phi, void *kv, const int *done, bool low,
                     void *dst) {
-    if (low) *(EvxArgs<float, double> *)dst = evx_args<float, double>(d, uhat, phi, kv, done);
-    else *(EvxArgs<double, double> *)dst = evx_args<double, double>(d, uhat, phi, kv, done);
+    if (d->cplx) {
+        if (low) *(EvxArgs<cf, cd> *)dst = evx_args<cf, cd>(d, uhat, phi, kv, done);
+        else *(EvxArgs<cd, cd> *)dst = evx_args<cd, cd>(d, uhat, phi, kv, done);
+    } else {
+        if (low) *(EvxArgs<float, double> *)dst = evx_args<float, double>(d, uhat, phi, kv, done);
+        else *(EvxArgs<double, double> *)dst = evx_args<double, double>(d, uhat, phi, kv, done);
+    }
 }
 void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst) {
-    *(CorrPhiArgs<double> *)dst = corr_phi_args<double>(d, phi, corr, done);
+    if (d->cplx) *(CorrPhiArgs<cd> *)dst = corr_phi_args<cd>(d, phi, corr, done);
+    else *(CorrPhiArgs<double> *)dst = corr_phi_args<double>(d, phi, corr, done);
 }
 void batch_fill_erow(kfbi_domain *d, const void *uhat, void *ust, const int *done, bool low, void *dst) {
-    if (low) *(ErowArgs<float, double> *)dst = erow_args<float, double>(d, uhat, ust, done);
-    else *(ErowArgs<double, double> *)dst = erow_args<double, double>(d, uhat, ust, done);
+    if (d->cplx) {
+        if (low) *(ErowArgs<cf, cd> *)dst = erow_args<cf, cd>(d, uhat, ust, done);
+        else *(ErowArgs<cd, cd> *)dst = erow_args<cd, cd>(d, uhat, ust, done);
+    } else {
+        if (low) *(ErowArgs<float, double> *)dst = erow_args<float, double>(d, uhat, ust, done);
+        else *(ErowArgs<double, double> *)dst = erow_args<double, double>(d, uhat, ust, done);
+    }
 }
 void batch_fill_exm(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done, void *dst) {
-    *(ExmArgs<double> *)dst = exm_args<double>(d, ust, phi, kv, done);
+    if (d->cplx) *(ExmArgs<cd> *)dst = exm_args<cd>(d, ust, phi, kv, done);
+    else *(ExmArgs<double> *)dst = exm_args<double>(d, ust, phi, kv, done);
 }
 
 int batch_blocks(const kfbi_domain *d, int kind) {
     switch (kind) {
-        case kBaDst: return dst_blocks<double>(d->M);
+        case kBaDst: return d->cplx ? dst_blocks<cd>(d->M) : dst_blocks<double>(d->M);
         case kBaZero: return (d->M + 1 + 255) / 256;
-        case kBaTri64: return tri_shape<double>(d, true).blocks;
-        case kBaTri32: return tri_shape<float>(d, true).blocks;
+        case kBaTri64: return d->cplx ? tri_shape<cd>(d, true).blocks : tri_shape<double>(d, true).blocks;
+        case kBaTri32: return d->cplx ? tri_shape<cf>(d, true).blocks : tri_shape<float>(d, true).blocks;
         case kBaEval: return (6 * d->Nb + 3) / 4;
         case kBaEvx64:
         case kBaEvx32: return d->Nb;
@@ -1460,10 +1491,16 @@ int batch_blocks(const kfbi_domain *d, int kind) {
 // launch shape of the tridiagonal kernel shared by a batch class (equal M,
 // mb and c; LDS the largest over the members; staged when all fit)
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb, int stage_pref) {
+    const bool cplx = doms[0]->cplx;
     // the static default, not a member's own timed choice, when none is given
-    if (mb <= 0) mb = low ? tri_default_mb<float>(doms[0]->M - 1) : tri_default_mb<double>(doms[0]->M - 1);
+    if (mb <= 0) {
+        const int n0 = doms[0]->M - 1;
+        mb = cplx ? (low ? tri_default_mb<cf>(n0) : tri_default_mb<cd>(n0))
+                  : (low ? tri_default_mb<float>(n0) : tri_default_mb<double>(n0));
+    }
     for (int q = 0; q < n; ++q) {
-        const TriShape S = low ? tri_shape<float>(doms[q], sparse, mb) : tri_shape<double>(doms[q], sparse, mb);
+        const TriShape S = cplx ? (low ? tri_shape<cf>(doms[q], sparse, mb) : tri_shape<cd>(doms[q], sparse, mb))
+                                : (low ? tri_shape<float>(doms[q], sparse, mb) : tri_shape<double>(doms[q], sparse, mb));
         if (q == 0) {
             out->mb = S.mb;
             out->c = S.c;
@@ -1496,52 +1533,53 @@ int batch_tri_blocks(const kfbi_domain *d, int mb) {
     return (d->M - 1 + mb - 1) / mb;
 }
 
-int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
-                 hipStream_t s) {
-    if (blocks <= 0) return KFBI_OK;
+namespace {
+// one batched launch of kind `kind` with element type T (double or cd) and
+// inner-solve type TL (float or cf)
+template <class T, class TL>
+int batch_launch_t(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
+                   hipStream_t s) {
     switch (kind) {
         case kBaDst:
-            kb_dst_rows<double><<<blocks, 256, dst_lds(M), s>>>((const DstArgs<double> *)args, map);
+            kb_dst_rows<T><<<blocks, 256, dst_lds(M), s>>>((const DstArgs<T> *)args, map);
             break;
         case kBaZero:
-            kb_zero_edge_rows<double><<<blocks, 256, 0, s>>>((const ZeroArgs<double> *)args, map);
+            kb_zero_edge_rows<T><<<blocks, 256, 0, s>>>((const ZeroArgs<T> *)args, map);
             break;
         case kBaTri64: {
-            TriLaunchBatch<double, double> L{(const TriArgs<double, double> *)args, map, blocks, shape->lds, s};
+            TriLaunchBatch<T, T> L{(const TriArgs<T, T> *)args, map, blocks, shape->lds, s};
             tri_dispatch(shape->mb, shape->c, shape->stage, L);
             break;
         }
         case kBaTri32: {
-            TriLaunchBatch<float, double> L{(const TriArgs<float, double> *)args, map, blocks, shape->lds, s};
+            TriLaunchBatch<TL, T> L{(const TriArgs<TL, T> *)args, map, blocks, shape->lds, s};
             tri_dispatch(shape->mb, shape->c, shape->stage, L);
             break;
         }
         case kBaEval:
-            kb_eval_nodes<double, double><<<blocks, 256, 0, s>>>((const EvalArgs<double, double> *)args, map);
+            kb_eval_nodes<T, T><<<blocks, 256, 0, s>>>((const EvalArgs<T, T> *)args, map);
             break;
         case kBaEvx64:
-            kb_eval_extract<double, double><<<blocks, 384, 0, s>>>((const EvxArgs<double, double> *)args, map);
+            kb_eval_extract<T, T><<<blocks, 384, 0, s>>>((const EvxArgs<T, T> *)args, map);
             break;
         case kBaEvx32:
-            kb_eval_extract<float, double><<<blocks, 384, 0, s>>>((const EvxArgs<float, double> *)args, map);
+            kb_eval_extract<TL, T><<<blocks, 384, 0, s>>>((const EvxArgs<TL, T> *)args, map);
             break;
         case kBaCorrPhi:
-            kb_corr_phi<double><<<blocks, 64, 0, s>>>((const CorrPhiArgs<double> *)args, map);
+            kb_corr_phi<T><<<blocks, 64, 0, s>>>((const CorrPhiArgs<T> *)args, map);
             break;
         case kBaErow64: {
-            ErowLaunchBatch<double, double> L{(const ErowArgs<double, double> *)args, map, blocks,
-                                              erow_lds<double, double>(M), s};
+            ErowLaunchBatch<T, T> L{(const ErowArgs<T, T> *)args, map, blocks, erow_lds<T, T>(M), s};
             KFBI_TRY(erow_dispatch(M, L));
             break;
         }
         case kBaErow32: {
-            ErowLaunchBatch<float, double> L{(const ErowArgs<float, double> *)args, map, blocks,
-                                             erow_lds<float, double>(M), s};
+            ErowLaunchBatch<TL, T> L{(const ErowArgs<TL, T> *)args, map, blocks, erow_lds<TL, T>(M), s};
             KFBI_TRY(erow_dispatch(M, L));
             break;
         }
         case kBaExm:
-            kb_extract_merged<<<blocks, 256, 0, s>>>((const ExmArgs<double> *)args, map);
+            kb_extract_merged<T><<<blocks, 256, 0, s>>>((const ExmArgs<T> *)args, map);
             break;
         default:
             set_error("unknown batched kernel");
@@ -1549,6 +1587,14 @@ int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int 
     }
     KFBI_CHECK_LAUNCH();
     return KFBI_OK;
+}
+}  // namespace
+
+int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
+                 hipStream_t s, bool cplx) {
+    if (blocks <= 0) return KFBI_OK;
+    if (cplx) return batch_launch_t<cd, cf>(kind, args, map, blocks, M, shape, s);
+    return batch_launch_t<double, float>(kind, args, map, blocks, M, shape, s);
 }
 
 }  // namespace kfbi

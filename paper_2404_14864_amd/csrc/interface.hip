@@ -18,6 +18,8 @@
 // Q = (t | n), n = (t_y, -t_x).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kfbi_internal.h"
 
 namespace kfbi {
@@ -596,23 +598,27 @@ int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     return KFBI_OK;
 }
 
-// batched launches (real members)
+// batched launches (members of one scalar type: real, or complex with
+// complex kappa)
 namespace {
-__global__ __launch_bounds__(128) void kb_corrections(const CorrArgs<double> *__restrict__ A,
+template <class T>
+__global__ __launch_bounds__(128) void kb_corrections(const CorrArgs<T> *__restrict__ A,
                                                       const BlkMap *__restrict__ map) {
     const BlkMap e = map[blockIdx.x];
     corrections_body(A[e.inst], e.local);
 }
-__global__ __launch_bounds__(128) void kb_extract(const ExtArgs<double> *__restrict__ A,
+template <class T>
+__global__ __launch_bounds__(128) void kb_extract(const ExtArgs<T> *__restrict__ A,
                                                   const BlkMap *__restrict__ map) {
     const BlkMap e = map[blockIdx.x];
     extract_body(A[e.inst], e.local);
 }
 }  // namespace
 
-size_t batch_args_size_iface(int kind) {
-    if (kind == kBaCorr) return sizeof(CorrArgs<double>);
-    if (kind == kBaExt) return sizeof(ExtArgs<double>);
+// the exact size for the batch's scalar type (the stride the kernels index with)
+size_t batch_args_size_iface(int kind, bool cplx) {
+    if (kind == kBaCorr) return cplx ? sizeof(CorrArgs<cd>) : sizeof(CorrArgs<double>);
+    if (kind == kBaExt) return cplx ? sizeof(ExtArgs<cd>) : sizeof(ExtArgs<double>);
     return 0;
 }
 
@@ -622,22 +628,32 @@ int batch_blocks_iface(const kfbi_domain *d, int kind) {
     return 0;
 }
 
-void batch_fill_corr(kfbi_domain *d, double kre, const void *phi, const void *fg, void *corr, const int *done,
-                     void *dst) {
-    *(CorrArgs<double> *)dst = corr_args<double>(d, kre, 0.0, phi, nullptr, fg, corr, done);
+void batch_fill_corr(kfbi_domain *d, double kre, double kim, const void *phi, const void *fg, void *corr,
+                     const int *done, void *dst) {
+    if (d->cplx) *(CorrArgs<cd> *)dst = corr_args<cd>(d, kre, kim, phi, nullptr, fg, corr, done);
+    else *(CorrArgs<double> *)dst = corr_args<double>(d, kre, 0.0, phi, nullptr, fg, corr, done);
 }
 
-void batch_fill_ext(kfbi_domain *d, double kre, const void *ust, const void *phi, const void *fg, const void *g,
-                    double scale, void *out, const int *done, void *dst) {
-    ExtArgs<double> A = ext_args<double>(d, kre, 0.0, ust, phi, nullptr, fg, g, scale, out, 0, done);
-    A.nid = d->erow_nid;  // batched stencil values come one per distinct node
-    *(ExtArgs<double> *)dst = A;
+void batch_fill_ext(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi, const void *fg,
+                    const void *g, double scale, void *out, const int *done, void *dst) {
+    // batched stencil values come one per distinct node
+    if (d->cplx) {
+        ExtArgs<cd> A = ext_args<cd>(d, kre, kim, ust, phi, nullptr, fg, g, scale, out, 0, done);
+        A.nid = d->erow_nid;
+        *(ExtArgs<cd> *)dst = A;
+    } else {
+        ExtArgs<double> A = ext_args<double>(d, kre, 0.0, ust, phi, nullptr, fg, g, scale, out, 0, done);
+        A.nid = d->erow_nid;
+        *(ExtArgs<double> *)dst = A;
+    }
 }
 
-int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s) {
+int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s, bool cplx) {
     if (blocks <= 0) return KFBI_OK;
-    if (kind == kBaCorr) kb_corrections<<<blocks, 128, 0, s>>>((const CorrArgs<double> *)args, map);
-    else if (kind == kBaExt) kb_extract<<<blocks, 128, 0, s>>>((const ExtArgs<double> *)args, map);
+    if (kind == kBaCorr && cplx) kb_corrections<cd><<<blocks, 128, 0, s>>>((const CorrArgs<cd> *)args, map);
+    else if (kind == kBaCorr) kb_corrections<double><<<blocks, 128, 0, s>>>((const CorrArgs<double> *)args, map);
+    else if (kind == kBaExt && cplx) kb_extract<cd><<<blocks, 128, 0, s>>>((const ExtArgs<cd> *)args, map);
+    else if (kind == kBaExt) kb_extract<double><<<blocks, 128, 0, s>>>((const ExtArgs<double> *)args, map);
     else {
         set_error("unknown batched kernel");
         return KFBI_EINVAL;

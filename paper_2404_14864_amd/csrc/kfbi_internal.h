@@ -561,9 +561,12 @@ struct BlkMap {
 };
 
 // ---------------------------------------------------------------------------
-// Batched solves (many real domains per launch).  Each kernel kind has an
-// argument block per member and a block count per member; the batch driver
-// lays the members' blocks out in a BlkMap and launches one grid.
+// Batched solves (many domains of one scalar type per launch).  Each kernel
+// kind has an argument block per member and a block count per member; the
+// batch driver lays the members' blocks out in a BlkMap and launches one
+// grid.  A kernel indexes the argument blocks with the size of its own
+// instantiation, so they are laid out with the exact size for the batch's
+// scalar type.
 // ---------------------------------------------------------------------------
 enum {
     kBaDst = 0,       // DST rows (dense forward or inverse)
@@ -593,15 +596,16 @@ struct BatchTriShape {
     int blocks_per;
 };
 
-size_t batch_args_size(int kind);
+size_t batch_args_size(int kind, bool cplx);
 int batch_blocks(const kfbi_domain *d, int kind);
 // mb: modes per workgroup (0: each domain's default); stage_pref: -1 stage
 // the sparse input when it fits, 0 never, 1 always (error if it does not fit)
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb = 0,
                     int stage_pref = -1);
 int batch_tri_blocks(const kfbi_domain *d, int mb);
+// cplx: the members are complex (complex128, complex64 inner solves)
 int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,
-                 hipStream_t s);
+                 hipStream_t s, bool cplx);
 void batch_fill_dst(kfbi_domain *d, const void *in, bool in_grid, bool mask_inside, void *out, bool out_grid,
                     double scale, const int *done, void *dst);
 void batch_fill_zero(kfbi_domain *d, void *grid, const int *done, void *dst);
@@ -614,13 +618,13 @@ void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int 
 void batch_fill_erow(kfbi_domain *d, const void *uhat, void *ust, const int *done, bool low, void *dst);
 void batch_fill_exm(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done, void *dst);
 // interface.hip
-size_t batch_args_size_iface(int kind);
+size_t batch_args_size_iface(int kind, bool cplx);
 int batch_blocks_iface(const kfbi_domain *d, int kind);
-void batch_fill_corr(kfbi_domain *d, double kre, const void *phi, const void *fg, void *corr, const int *done,
-                     void *dst);
-void batch_fill_ext(kfbi_domain *d, double kre, const void *ust, const void *phi, const void *fg, const void *g,
-                    double scale, void *out, const int *done, void *dst);
-int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s);
+void batch_fill_corr(kfbi_domain *d, double kre, double kim, const void *phi, const void *fg, void *corr,
+                     const int *done, void *dst);
+void batch_fill_ext(kfbi_domain *d, double kre, double kim, const void *ust, const void *phi, const void *fg,
+                    const void *g, double scale, void *out, const int *done, void *dst);
+int batch_launch_iface(int kind, const void *args, const BlkMap *map, int blocks, hipStream_t s, bool cplx);
 
 // batched Helmholtz solves (gmres.hip)
 int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out);
@@ -633,9 +637,12 @@ int replay_slot(kfbi_domain *d, int reps, double *avg_ms, double *bytes);
 int batch_size(const kfbi_batch *b);
 kfbi_domain *batch_domain(const kfbi_batch *b, int q);
 int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_t *n_rows);
-int batch_helmholtz(kfbi_batch *b, const double *kappa, const void *const *f_grid, const void *const *f_gamma,
-                    const void *const *g_gamma, void *const *u_out, void *const *phi_inout,
-                    const kfbi_solve_opts *opts, kfbi_solve_stats *stats, const uint8_t *active = nullptr);
+// kappa_im (nullable: 0) only for a batch of complex domains
+int batch_helmholtz(kfbi_batch *b, const double *kappa, const double *kappa_im, const void *const *f_grid,
+                    const void *const *f_gamma, const void *const *g_gamma, void *const *u_out,
+                    void *const *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats,
+                    const uint8_t *active = nullptr);
+bool batch_complex(const kfbi_batch *b);
 
 // kernel timing: prof_begin returns a slot (or -1 when profiling is off);
 // prof_end closes it with the launch's algorithmic bytes; prof_flush waits

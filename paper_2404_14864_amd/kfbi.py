@@ -124,9 +124,10 @@ def lib():
         "kfbi_stepper_set_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
         "kfbi_batch_create": ([ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int),
         "kfbi_batch_destroy": ([_P], ctypes.c_int),
-        "kfbi_batch_helmholtz": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_P), ctypes.POINTER(_P),
-                                  ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
-                                  ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)], ctypes.c_int),
+        "kfbi_batch_helmholtz": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                  ctypes.POINTER(_P), ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)],
+                                 ctypes.c_int),
         "kfbi_batch_step": ([_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(_P),
                              ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(SolveOpts),
                              ctypes.POINTER(SolveStats)], ctypes.c_int),
@@ -166,7 +167,8 @@ def kfbi_profile_read(h):
 
 # ---- batches ---------------------------------------------------------------
 def kfbi_batch_create(domains):
-    """A batch of real domain handles (same stream) solved together."""
+    """A batch of domain handles of one scalar type (all real or all
+    complex) on one stream, solved together."""
     n = len(domains)
     arr = (_P * n)(*[d.value if isinstance(d, ctypes.c_void_p) else d for d in domains])
     out = _P()
@@ -201,13 +203,17 @@ def _member_ptrs(doms, lst, name, grid):
 
 def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, phi_inout=None, opts=None):
     """Member q solves lap u - kappas[q] u = f_grid[q] with u = g_gamma[q] on
-    Gamma; all arguments are lists of float64 CUDA tensors (u_grid_out and
-    phi_inout may be None or contain None).  Returns the per-member stats."""
+    Gamma; the arrays are lists of CUDA tensors of the batch's element type
+    (float64, or complex128 for a batch of complex domains, whose kappas may
+    be complex); u_grid_out and phi_inout may be None or contain None.
+    Returns the per-member stats."""
     n = len(kappas)
     doms = _batch_doms(b, n)
-    kap = (ctypes.c_double * n)(*[float(k) for k in kappas])
+    ks = [complex(k) for k in kappas]
+    kap = (ctypes.c_double * n)(*[k.real for k in ks])
+    kim = (ctypes.c_double * n)(*[k.imag for k in ks]) if any(k.imag != 0.0 for k in ks) else None
     stats = (SolveStats * n)()
-    code = lib().kfbi_batch_helmholtz(b, kap, _member_ptrs(doms, f_grid, "f_grid", True),
+    code = lib().kfbi_batch_helmholtz(b, kap, kim, _member_ptrs(doms, f_grid, "f_grid", True),
                                       _member_ptrs(doms, f_gamma, "f_gamma", False),
                                       _member_ptrs(doms, g_gamma, "g_gamma", False),
                                       _member_ptrs(doms, u_grid_out, "u_grid_out", True),
@@ -217,11 +223,12 @@ def kfbi_batch_helmholtz(b, kappas, f_grid, f_gamma, g_gamma, u_grid_out=None, p
 
 
 def kfbi_batch_step(b, steppers, g_next, u_out, active=None, src_grid=None, src_gamma=None, opts=None):
-    """One time step of the active member steppers (heat or wave, member q
-    on the batch's domain q) with their solves batched.  g_next, u_out,
-    src_grid, src_gamma: lists of float64 CUDA tensors (None entries for
-    members not active or without sources); active: booleans (None: all).
-    Returns the per-member stats."""
+    """One time step of the active member steppers (heat or wave in a real
+    batch, Schroedinger in a complex one; member q on the batch's domain q)
+    with their solves batched.  g_next, u_out, src_grid, src_gamma: lists of
+    CUDA tensors of the batch's element type (None entries for members not
+    active or without sources); active: booleans (None: all).  Returns the
+    per-member stats."""
     n = len(steppers)
     doms = _batch_doms(b, n)
     for q, x in enumerate(steppers):

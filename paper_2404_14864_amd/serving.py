@@ -1,26 +1,38 @@
-"""Serving loop: time-stepping jobs admitted by device footprint and advanced
-together.
+"""Serving loop: continuous batching of time-stepping jobs.
 
 Each job is one heat, wave or Schroedinger stepper on its own domain, with
-its state resident on the device from admission to completion.  Every tick
-  1. jobs that have arrived join a FIFO queue;
-  2. queued jobs are admitted in order while the sum of the admitted jobs'
-     device footprints (domain, stepper state and output grid, as the
-     library reports them) stays within the budget; a job that cannot fit
-     even alone is rejected;
-  3. every admitted job advances one step: the real (heat and wave) jobs in
-     one kfbi_batch_step call, whose launches run all of them together, and
-     the complex (Schroedinger) jobs one kfbi_step_schrodinger call each;
-  4. finished jobs free their memory.
-The device time of each tick's steps (HIP events on the stream) is the step
-latency of every job that stepped in it.  Only control scalars cross to the
-host inside a tick.
+its state resident on the device from admission to completion.  Jobs arrive
+over wall time (Poisson arrivals of `workloads.serving`) and are served by
 
-A job's data come from a fields provider (see workloads.serving.job_fields):
+  * the admission loop (the calling thread): arrivals join a FIFO queue;
+    the head of the queue is admitted as soon as the admitted jobs' device
+    footprints (domain with every table it allocates on first use, stepper
+    state, output grid, as the library reports them) leave room for it in
+    the budget; a job that cannot fit even alone is rejected;
+  * two lanes, threads that each own a HIP stream and step their jobs in
+    rounds: every round advances each of the lane's admitted jobs by one
+    step in one kfbi_batch_step call, whose launches run all of them
+    together; the real lane holds the heat and wave jobs, the complex lane
+    the Schroedinger jobs.  Between rounds a lane takes in the jobs
+    admitted meanwhile and retires the ones whose last step has completed
+    on the device, which frees their memory for the admission loop.
+
+The lanes never wait for each other or for admission: a job that arrives
+while both lanes have work on the device is admitted at once if memory
+allows and joins its lane's next round, and the two streams run
+concurrently on the device.  Every step is asynchronous (the host returns
+once GMRES has finished on the device, the final grid solve still queued),
+so a lane enqueues its next round while the previous one completes.  A
+round is timed by HIP events on the lane's stream; the step latency of a
+job is the device time of the round that advanced it, read once the run is
+over.  Only control scalars cross to the host inside a round.
+
+A job's data come from a fields provider (workloads.serving.job_fields):
 initial arrays and boundary data that are fixed arrays times scalar time
-factors, placed on the device once.
+factors, placed on the device once, on the job's lane stream.
 """
 
+import threading
 import time
 
 import numpy as np
@@ -39,9 +51,11 @@ def _dev(a):
 
 
 class Job:
-    """One admitted job: domain, stepper, device-resident data and output."""
+    """One admitted job: domain, stepper, device-resident data and output.
+    The domain and every upload use the current torch stream of the
+    creating thread (a lane's stream when the server creates it)."""
 
-    def __init__(self, spec, fields_fn):
+    def __init__(self, spec, fields_fn, precision=kfbi.KFBI_PREC_FP64):
         self.spec = spec
         self.kind = spec["kind"]
         self.cplx = self.kind == "schrodinger"
@@ -49,7 +63,7 @@ class Job:
         self.M, self.Nb, self.tau = desc["M"], desc["Nb"], spec["tau"]
         self.steps = spec["steps"]
         self.n = 0
-        self.h = kfbi.kfbi_domain_create(desc, kfbi.KFBI_COMPLEX if self.cplx else kfbi.KFBI_REAL)
+        self.h = kfbi.kfbi_domain_create(desc, kfbi.KFBI_COMPLEX if self.cplx else kfbi.KFBI_REAL, precision)
         self.s = None
         try:
             zx, zy = kfbi.kfbi_domain_copy_boundary(self.h)
@@ -69,8 +83,6 @@ class Job:
             kfbi.kfbi_stepper_init(self.s, *[_dev(a) for a in f["init"]])
             dt = torch.complex128 if self.cplx else torch.float64
             self.u = torch.zeros((self.M + 1) ** 2, dtype=dt, device=DEV)
-            # the domain's peak (tables allocated on first use included), the
-            # stepper's state and the output grid
             self.footprint = (kfbi.kfbi_domain_get_info(self.h)["device_bytes_max"]
                               + kfbi.kfbi_stepper_state_bytes(self.s) + self.u.numel() * self.u.element_size())
         except Exception:
@@ -110,13 +122,107 @@ class Job:
             self.h = None
 
 
+class _Lane(threading.Thread):
+    """Steps its jobs in rounds on its own stream (see the module text)."""
+
+    def __init__(self, server, cplx):
+        super().__init__(daemon=True)
+        self.srv = server
+        self.cplx = cplx
+        self.stream = torch.cuda.Stream(device=DEV)
+        self.incoming = []          # admitted, not yet stepped (guarded by srv.cond)
+        self.jobs = []              # stepping
+        self.retiring = []          # (job, event of its last round)
+        self.rounds = []            # (ev0, ev1, [(job kind, M, iters)])
+        self.busy = False           # a round is on the device (guarded by srv.cond)
+        self.batch, self.batch_ids = None, None
+        self.error = None
+
+    def _rebuild_batch(self):
+        ids = [id(j) for j in self.jobs]
+        if ids == self.batch_ids:
+            return
+        if self.batch is not None:
+            kfbi.kfbi_batch_destroy(self.batch)
+            self.batch = None
+        self.batch_ids = ids
+        if self.jobs:
+            self.batch = kfbi.kfbi_batch_create([j.h for j in self.jobs])
+
+    def _round(self):
+        srv = self.srv
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(self.stream)
+        opts = dict(srv.opts or {}, **{"async": True})
+        self._rebuild_batch()
+        ins = [j.inputs() for j in self.jobs]
+        st = kfbi.kfbi_batch_step(self.batch, [j.s for j in self.jobs], [x[0] for x in ins],
+                                  [j.u for j in self.jobs], src_grid=[x[1] for x in ins],
+                                  src_gamma=[x[2] for x in ins], opts=opts)
+        for j in self.jobs:
+            j.n += 1
+        ev1.record(self.stream)
+        self.rounds.append((ev0, ev1, [(j.kind, j.M, s["iters"]) for j, s in zip(self.jobs, st)]))
+        for j in [j for j in self.jobs if j.done]:
+            self.jobs.remove(j)
+            self.retiring.append((j, ev1))
+
+    def _retire(self, wait=False):
+        srv = self.srv
+        keep = []
+        for j, ev in self.retiring:
+            if wait:
+                ev.synchronize()
+            if not ev.query():
+                keep.append((j, ev))
+                continue
+            if srv.keep_output is not None:
+                srv.keep_output(j)
+            j.close()
+            with srv.cond:
+                srv.used -= j.footprint
+                srv.finished.append(j.spec["id"])
+                srv.cond.notify_all()
+        self.retiring = keep
+
+    def run(self):
+        srv = self.srv
+        try:
+            with torch.cuda.stream(self.stream):
+                while True:
+                    with srv.cond:
+                        while not self.incoming and not self.jobs and not self.retiring and not srv.closing:
+                            srv.cond.wait(0.05)
+                        self.jobs += self.incoming
+                        self.incoming = []
+                        if not self.jobs and not self.retiring and srv.closing:
+                            break
+                        self.busy = bool(self.jobs)
+                    if self.jobs:
+                        self._round()
+                    self._retire(wait=not self.jobs)
+                    with srv.cond:
+                        self.busy = False
+                if self.batch is not None:
+                    kfbi.kfbi_batch_destroy(self.batch)
+                    self.batch = None
+                self.stream.synchronize()
+        except BaseException as e:  # reported by Server.run
+            self.error = e
+            with srv.cond:
+                srv.closing = True
+                srv.cond.notify_all()
+
+
 class Server:
-    """Admission by footprint and batched stepping of the admitted jobs.
+    """Continuous batching of time-stepping jobs (see the module text).
 
     budget_bytes: device memory the admitted jobs may hold together.
-    fields_fn: the job data provider.  opts: solver options of every step.
-    keep_output: called as keep_output(job) when a job finishes (before its
-    memory is freed), e.g. to copy its final grid.
+    fields_fn: the job data provider.  opts: solver options of every step
+    (precision: the FP64 or mixed grid solve of every job).
+    keep_output: called as keep_output(job) when a job's last step has
+    completed, before its memory is freed (e.g. to copy its final grid; it
+    runs on the job's lane, whose stream is then current).
     """
 
     def __init__(self, budget_bytes, fields_fn, opts=None, keep_output=None):
@@ -124,120 +230,149 @@ class Server:
         self.fields_fn = fields_fn
         self.opts = opts
         self.keep_output = keep_output
+        self.cond = threading.Condition()
         self.used = 0
         self.max_used = 0
         self.max_jobs = 0
-        self.batch = None
-        self.batch_members = None
+        self.finished = []
+        self.closing = False
 
-    def _rebuild_batch(self, real):
-        ids = [id(j) for j in real]
-        if ids == self.batch_members:
-            return
-        if self.batch is not None:
-            kfbi.kfbi_batch_destroy(self.batch)
-            self.batch = None
-        self.batch_members = ids
-        if real:
-            self.batch = kfbi.kfbi_batch_create([j.h for j in real])
-
-    def run(self, specs, tick=1.0, max_ticks=100000):
-        """Serve the jobs of `specs` (arrival times in units of `tick`) to
-        completion.  Returns a report: step latencies (ms) overall and per
-        (kind, M), throughput in grid-pts*GMRES-iters/s over the steps'
-        device time, the peak footprint and job counts."""
+    def run(self, specs, tick=1.0):
+        """Serve the jobs of `specs`, whose arrival times are in units of
+        `tick` seconds of wall time, to completion.  Returns a report: step
+        latencies (ms, device time of the round that advanced the job)
+        overall and per (kind, M), throughput in grid-pts*GMRES-iters/s over
+        the wall time from the first arrival to the last completion, the
+        peak footprint, job counts, and how many admissions happened while a
+        lane had a round on the device."""
         pending = sorted(specs, key=lambda s: s["arrival"])
-        queue, active = [], []
-        lat, lat_by, rejected, finished = [], {}, [], []
-        work = 0.0
-        dev_ms = 0.0
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        queue, rejected = [], []
         cache = {}  # footprint of a job shape, once one has been created
-        t_wall = time.perf_counter()
-        k = 0
+        self.used, self.max_used, self.max_jobs = 0, 0, 0
+        self.finished, self.closing = [], False
+        lanes = {False: _Lane(self, False), True: _Lane(self, True)}
+        prec = (self.opts or {}).get("precision", kfbi.KFBI_PREC_FP64)
+        admitted_busy = 0
+        for ln in lanes.values():
+            ln.start()
+        t0 = time.perf_counter()
         try:
-            while (pending or queue or active) and k < max_ticks:
-                now = k * tick
+            while pending or queue:
+                now = (time.perf_counter() - t0) / tick
                 while pending and pending[0]["arrival"] <= now:
                     queue.append(pending.pop(0))
-                # admission, in arrival order
+                admitted = False
                 while queue:
                     spec = queue[0]
                     key = (spec["kind"], spec["desc"]["M"], spec["desc"]["Nb"])
-                    need = cache.get(key)  # footprint of an earlier job of this shape
-                    if need is not None and need <= self.budget and self.used + need > self.budget:
+                    need = cache.get(key)
+                    with self.cond:
+                        used = self.used
+                    if need is not None and need <= self.budget and used + need > self.budget:
                         break
-                    job = Job(spec, self.fields_fn)
+                    lane = lanes[spec["kind"] == "schrodinger"]
+                    with torch.cuda.stream(lane.stream):
+                        job = Job(spec, self.fields_fn, prec)
                     cache[key] = job.footprint
                     if job.footprint > self.budget:
                         job.close()
                         rejected.append(queue.pop(0)["id"])
                         continue
-                    if self.used + job.footprint > self.budget:
+                    with self.cond:
+                        if self.used + job.footprint > self.budget:
+                            fits = False
+                        else:
+                            fits = True
+                            busy = any(ln.busy for ln in lanes.values())
+                            admitted_busy += 1 if busy else 0
+                            lane.incoming.append(job)
+                            self.used += job.footprint
+                            self.max_used = max(self.max_used, self.used)
+                            n_act = sum(len(ln.jobs) + len(ln.incoming) + len(ln.retiring) for ln in lanes.values())
+                            self.max_jobs = max(self.max_jobs, n_act)
+                            self.cond.notify_all()
+                    if not fits:
                         job.close()
                         break
                     queue.pop(0)
-                    active.append(job)
-                    self.used += job.footprint
-                self.max_used = max(self.max_used, self.used)
-                self.max_jobs = max(self.max_jobs, len(active))
-                if not active:
-                    k += 1
-                    continue
-                # one step of every admitted job
-                real = [j for j in active if not j.cplx]
-                self._rebuild_batch(real)
-                ev0.record()
-                stats = []
-                if real:
-                    ins = [j.inputs() for j in real]
-                    st = kfbi.kfbi_batch_step(self.batch, [j.s for j in real], [x[0] for x in ins],
-                                              [j.u for j in real], src_grid=[x[1] for x in ins],
-                                              src_gamma=[x[2] for x in ins], opts=self.opts)
-                    for j in real:
-                        j.n += 1
-                    stats += list(zip(real, st))
-                for j in active:
-                    if j.cplx:
-                        stats.append((j, j.step_alone(self.opts)))
-                ev1.record()
-                ev1.synchronize()
+                    admitted = True
+                if any(ln.error is not None for ln in lanes.values()):
+                    break
+                if not admitted:
+                    # wait for the next arrival or for memory to free up
+                    wait = 0.05 if not pending else max(0.0, pending[0]["arrival"] * tick - (time.perf_counter() - t0))
+                    with self.cond:
+                        self.cond.wait(min(wait, 0.05) if queue else min(wait, 0.5))
+        finally:
+            with self.cond:
+                self.closing = True
+                self.cond.notify_all()
+            for ln in lanes.values():
+                ln.join()
+        wall = time.perf_counter() - t0
+        for ln in lanes.values():
+            if ln.error is not None:
+                raise ln.error
+        torch.cuda.synchronize()
+        lat, lat_by, work, dev_ms = [], {}, 0.0, 0.0
+        for ln in lanes.values():
+            for ev0, ev1, steps in ln.rounds:
                 ms = ev0.elapsed_time(ev1)
                 dev_ms += ms
-                for j, st in stats:
+                for kind, M, it in steps:
                     lat.append(ms)
-                    lat_by.setdefault("%s M=%d" % (j.kind, j.M), []).append(ms)
-                    work += float((j.M - 1) ** 2) * st["iters"]
-                # completions free their memory
-                for j in [j for j in active if j.done]:
-                    if self.keep_output is not None:
-                        self.keep_output(j)
-                    finished.append(j.spec["id"])
-                    active.remove(j)
-                    self.used -= j.footprint
-                    j.close()
-                k += 1
-        finally:
-            if self.batch is not None:
-                kfbi.kfbi_batch_destroy(self.batch)
-                self.batch = None
-                self.batch_members = None
-            for j in active:
-                j.close()
+                    lat_by.setdefault("%s M=%d" % (kind, M), []).append(ms)
+                    work += float((M - 1) ** 2) * it
         lat = np.asarray(lat)
+        first = min((s["arrival"] for s in specs), default=0.0) * tick
         return {
-            "ticks": k,
-            "finished": finished,
+            "finished": list(self.finished),
             "rejected": rejected,
             "steps": int(lat.size),
+            "rounds": sum(len(ln.rounds) for ln in lanes.values()),
             "p50_step_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_step_ms": float(np.percentile(lat, 99)) if lat.size else None,
-            "p50_by_type_ms": {key: float(np.percentile(v, 50)) for key, v in sorted(lat_by.items())},
-            "throughput": work / (dev_ms * 1e-3) if dev_ms > 0 else 0.0,
+            "p50_by_type_ms": {k: float(np.percentile(v, 50)) for k, v in sorted(lat_by.items())},
+            "p99_by_type_ms": {k: float(np.percentile(v, 99)) for k, v in sorted(lat_by.items())},
+            "throughput": work / max(wall - first, 1e-9),
             "unit": "grid-pts*GMRES-iters/s",
-            "device_s": dev_ms * 1e-3,
-            "wall_s": time.perf_counter() - t_wall,
+            "work": work,
+            "wall_s": wall,
+            "device_s_sum_of_lanes": dev_ms * 1e-3,
             "max_used_bytes": self.max_used,
             "budget_bytes": self.budget,
             "max_concurrent_jobs": self.max_jobs,
+            "admitted_while_device_busy": admitted_busy,
         }
+
+
+def serve_plain(specs, fields_fn, opts=None, keep_output=None):
+    """The plain per-solve path on the same jobs: each job alone, in arrival
+    order, one synchronous step after another.  Returns its per-step
+    latencies (device time of the step), throughput over the wall time and
+    the work done."""
+    lat, lat_by, work = [], {}, 0.0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    for spec in sorted(specs, key=lambda s: s["arrival"]):
+        j = Job(spec, fields_fn)
+        try:
+            for _ in range(j.steps):
+                ev0.record()
+                st = j.step_alone(opts)
+                ev1.record()
+                ev1.synchronize()
+                ms = ev0.elapsed_time(ev1)
+                lat.append(ms)
+                lat_by.setdefault("%s M=%d" % (j.kind, j.M), []).append(ms)
+                work += float((j.M - 1) ** 2) * st["iters"]
+            if keep_output is not None:
+                keep_output(j)
+        finally:
+            j.close()
+    wall = time.perf_counter() - t0
+    lat = np.asarray(lat)
+    return {"steps": int(lat.size), "p50_step_ms": float(np.percentile(lat, 50)),
+            "p99_step_ms": float(np.percentile(lat, 99)),
+            "p50_by_type_ms": {k: float(np.percentile(v, 50)) for k, v in sorted(lat_by.items())},
+            "throughput": work / wall, "unit": "grid-pts*GMRES-iters/s", "work": work, "wall_s": wall}

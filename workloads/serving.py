@@ -3,7 +3,8 @@
 Jobs arrive as a Poisson process; each is a heat, wave or Schroedinger
 time-stepping problem (40/40/20) on a seeded star (heat, wave) or ellipse
 (Schroedinger) domain, on a grid drawn uniformly from the given powers of
-two, for a number of steps drawn uniformly from a range.  The data of a job
+two, for a number of steps drawn uniformly from a range (heat: tau = h,
+wave: tau = 4h, Schroedinger: tau = h/2).  The data of a job
 are the manufactured solutions of `manufactured`: heat and wave use the exact
 solutions of the heat and wave workloads, Schroedinger the Gaussian packet in
 the harmonic potential with g = 0 on the boundary.  Every field here is a
@@ -38,7 +39,9 @@ def job_stream(seed, n_jobs, rate, grids=(256, 512, 1024, 2048), steps=(50, 500)
             r0 = rng.uniform(0.3, 0.6)
             lobes = int(rng.integers(3, 9))
             desc = star(r0, 0.2 * r0, lobes, 1.0, M, M)
-            tau = 2.0 / M
+            # heat: tau = h; wave: tau = 4h, where the theta = 1/4 steps stay
+            # accurate over hundreds of steps (at tau = h they grow)
+            tau = (2.0 / M) * (4.0 if kind == "wave" else 1.0)
         jobs.append({"id": i, "arrival": float(t), "kind": kind, "desc": desc, "steps": n_steps, "tau": tau})
     return jobs
 
