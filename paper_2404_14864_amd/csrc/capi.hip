@@ -267,6 +267,7 @@ int kfbi_domain_create(const kfbi_domain_desc *desc, kfbi_domain **out) {
         if (s2 == KFBI_OK) s2 = dalloc(d, &d->rhat, n * n * es);
         if (s2 == KFBI_OK) s2 = dalloc(d, &d->uhat, n * n * es);
         if (s2 == KFBI_OK) s2 = dalloc(d, &d->corr, (size_t)d->n_irr * es);
+        if (s2 == KFBI_OK) s2 = dalloc(d, &d->corr_f, (size_t)d->n_irr * es);
         if (s2 == KFBI_OK) s2 = dalloc(d, &d->ust, 6 * Nb * es);
         if (s2 == KFBI_OK) s2 = dalloc(d, &d->etab, n * n * es);
         if (s2 == KFBI_OK) s2 = dalloc(d, &d->elim, n * es);

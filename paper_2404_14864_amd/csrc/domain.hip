@@ -497,6 +497,27 @@ int build_domain(kfbi_domain *d) {
     KFBI_HIP(hipMemcpyAsync(d->seg_row, seg_row.data(), seg_row.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     KFBI_TRY(dalloc(d, (void **)&d->row_seg, row_seg.size() * sizeof(int32_t)));
     KFBI_HIP(hipMemcpyAsync(d->row_seg, row_seg.data(), row_seg.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    {
+        std::vector<int32_t> sd(4 * seg_q0.size()), rd(4 * order.size());
+        for (size_t g = 0; g < seg_q0.size(); ++g) {
+            const int32_t t = seg_row[g], q0 = seg_q0[g];
+            sd[4 * g] = q0;
+            sd[4 * g + 1] = std::min(q0 + kSegLen, rowptr[t + 1]);
+            sd[4 * g + 2] = t;
+            sd[4 * g + 3] = 0;
+        }
+        for (size_t a = 0; a < order.size(); ++a) {
+            rd[4 * a] = order[a];
+            rd[4 * a + 1] = row_seg[a];
+            rd[4 * a + 2] = row_seg[a + 1];
+            rd[4 * a + 3] = 0;
+        }
+        KFBI_TRY(dalloc(d, (void **)&d->seg_desc, sd.size() * sizeof(int32_t)));
+        KFBI_HIP(hipMemcpyAsync(d->seg_desc, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        KFBI_TRY(dalloc(d, (void **)&d->row_desc, rd.size() * sizeof(int32_t)));
+        KFBI_HIP(hipMemcpyAsync(d->row_desc, rd.data(), rd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        KFBI_HIP(hipStreamSynchronize(s));
+    }
     KFBI_TRY(tmp.alloc((void **)&ex_map, nodes * sizeof(int32_t)));
     KFBI_TRY(tmp.alloc((void **)&ey_map, nodes * sizeof(int32_t)));
     KFBI_TRY(tmp.alloc((void **)&irr_list, (size_t)ti * sizeof(int32_t)));

@@ -1741,8 +1741,10 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     // b = g - IS(f, 0).U+ (Dirichlet), b = g - IS(f, 0, 0).dU+/dn (Neumann)
     if (f_grid) {
         KFBI_TRY(dst_rows_dense(d, f_grid, true, d->rhat));
-        KFBI_TRY(compute_corrections(d, kre, kim, nullptr, f_gamma, d->corr));
-        KFBI_TRY(tridiag_solve(d, d->rhat, d->corr, d->uhat));
+        // the corrections of f alone are kept: the final solve adds those of
+        // the density to them (the interface problem is affine in phi)
+        KFBI_TRY(compute_corrections(d, kre, kim, nullptr, f_gamma, d->corr_f));
+        KFBI_TRY(tridiag_solve(d, d->rhat, d->corr_f, d->uhat));
         KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
         if (bc) KFBI_TRY(extract_boundary_psi_ctl(d, kre, kim, d->ust, f_gamma, nullptr, true, g_gamma, -1.0, P.b,
                                                   nullptr));
@@ -1757,6 +1759,10 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     // device-driven schedule)
     auto final_solve = [&](const int *gate) -> int {
         if (bc) KFBI_TRY(compute_corrections_psi_ctl(d, kre, kim, f_gamma, P.x, d->corr, gate));
+        else if (d->op_merged && (f_grid != nullptr) == (f_gamma != nullptr))
+            // corrections of f (from the b-solve) plus the density's, by the
+            // merged operator
+            KFBI_TRY(corrections_of_density(d, P.x, d->corr, gate, f_grid ? d->corr_f : nullptr));
         else KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
         KFBI_TRY(tridiag_solve_ctl(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat, gate));
         if (u_grid_out) KFBI_TRY(idst_rows_dense_ctl(d, d->uhat, u_grid_out, gate));
@@ -2012,7 +2018,8 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
         switch (u) {
             case kUDstF: case kUIdst: return batch_args_size(kBaDst, b->cplx);
             case kUZero: return batch_args_size(kBaZero, b->cplx);
-            case kUCorrB: case kUCorrF: return batch_args_size_iface(kBaCorr, b->cplx);
+            case kUCorrB: return batch_args_size_iface(kBaCorr, b->cplx);
+            case kUCorrF: return batch_args_size(kBaCorrPhi, b->cplx);
             case kUExtB: return batch_args_size_iface(kBaExt, b->cplx);
             case kUTriB: case kUTriF: case kUTri64: return batch_args_size(kBaTri64, b->cplx);
             case kUTri32: return batch_args_size(kBaTri32, b->cplx);
@@ -2261,8 +2268,8 @@ int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im
                   *skip_tail = one ? one : &P.ctl->skip_tail;
         auto at = [&](int u) { return b->h_args + b->use_off[u] + (size_t)q * b->use_size[u]; };
         batch_fill_dst(d, f_grid[q], true, true, d->rhat, false, 1.0, one, at(kUDstF));
-        batch_fill_corr(d, kappa[q], kim(q), nullptr, f_gamma[q], d->corr, one, at(kUCorrB));
-        batch_fill_tri(d, d->rhat, d->corr, d->uhat, one, false, at(kUTriB));
+        batch_fill_corr(d, kappa[q], kim(q), nullptr, f_gamma[q], d->corr_f, one, at(kUCorrB));
+        batch_fill_tri(d, d->rhat, d->corr_f, d->uhat, one, false, at(kUTriB));
         batch_fill_erow(d, d->uhat, d->ust, one, false, at(kUErowB));
         batch_fill_ext(d, kappa[q], kim(q), d->ust, nullptr, f_gamma[q], g_gamma[q], -1.0, P.b, one, at(kUExtB));
         *(CopyArgs *)at(kUCopyX) = CopyArgs{(double *)P.x, phi_inout ? (const double *)phi_inout[q] : nullptr,
@@ -2284,7 +2291,7 @@ int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im
         SlotArgs<T> sa = slot_args<T>(P, (GmMirror *)d->mirror_dev, d->Nb, o.restart, nvl);
         sa.off = one;
         *(SlotArgs<T> *)at(kUSlot) = sa;
-        batch_fill_corr(d, kappa[q], kim(q), P.x, f_gamma[q], d->corr, skip_tail, at(kUCorrF));
+        batch_fill_corr_phi(d, P.x, d->corr, skip_tail, at(kUCorrF), d->corr_f);
         batch_fill_tri(d, d->rhat, d->corr, d->uhat, skip_tail, false, at(kUTriF));
         void *uo = u_out ? u_out[q] : nullptr;
         batch_fill_dst(d, d->uhat, false, false, uo, true, 2.0 / d->M, skip_tail, at(kUIdst));
@@ -2362,7 +2369,7 @@ int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im
         }
         n_enq += want;
         // final solve of the members that have finished (gated per member)
-        KFBI_TRY(batch_launch_iface(kBaCorr, dargs(kUCorrF), mapk(kBaCorr), b->map_blocks[kBaCorr], s, cplx));
+        KFBI_TRY(launch(kBaCorrPhi, kUCorrF));
         KFBI_TRY(launch_tri(kUTriF, false, true));
         if (u_out) {
             KFBI_TRY(launch_dst(kUIdst));

@@ -296,6 +296,10 @@ __device__ inline int tidx(int t, int m) {
 // LDS first; otherwise they are read from global memory.
 
 constexpr int kCorrWin = 16;
+// segment and row descriptors each thread of the tridiagonal kernel loads
+// ahead (the rest, if any, are loaded where they are used)
+constexpr int kPf = 2;
+typedef int gi4 __attribute__((ext_vector_type(4)));
 
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
 __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
@@ -306,11 +310,8 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     const gmem<TC> *__restrict__ corr = gview(A.corr);
     const TriSparse &sp = A.sp;
     const gmem<int32_t> *__restrict__ irr_col = gview(sp.irr_col);
-    const gmem<int32_t> *__restrict__ row_ptr = gview(sp.row_ptr);
-    const gmem<int32_t> *__restrict__ row_order = gview(sp.row_order);
-    const gmem<int32_t> *__restrict__ seg_q0 = gview(sp.seg_q0);
-    const gmem<int32_t> *__restrict__ seg_row = gview(sp.seg_row);
-    const gmem<int32_t> *__restrict__ row_seg = gview(sp.row_seg);
+    const gmem<gi4> *__restrict__ seg_desc = (const gmem<gi4> *)gview(sp.seg_desc);
+    const gmem<gi4> *__restrict__ row_desc = (const gmem<gi4> *)gview(sp.row_desc);
     const gmem<R> *__restrict__ sine = gview(A.sine);
     const gmem<T> *__restrict__ etab = gview(A.etab);
     const gmem<T> *__restrict__ elim = gview(A.elim);
@@ -327,17 +328,23 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     T *tile = reinterpret_cast<T *>(lds + 2 * M);       // n*MB + n/C + 1
     const int tile_len = n * MB + n / C + 1;
     T *spart = tile + tile_len;                          // n_seg*MB partial sums
-    // staged sparse right-hand side: values, columns, row pointers, row
-    // order, segment tables
+    // staged sparse right-hand side: values and columns
     const bool sparse = corr != nullptr;
     T *sval = spart + (sparse ? n_seg * MB : 0);
     int32_t *scol = reinterpret_cast<int32_t *>(sval + (STAGE ? nnz : 0));
-    int32_t *srp = scol + (STAGE ? nnz : 0);
-    int32_t *srow = srp + (STAGE ? n + 1 : 0);
-    int32_t *ssq0 = srow + (STAGE ? n_act : 0);
-    int32_t *ssrow = ssq0 + (STAGE ? n_seg : 0);
-    int32_t *srseg = ssrow + (STAGE ? n_seg : 0);
     const int k0 = tile_idx * MB;
+    // the descriptors of the thread's first kPf segments and rows, loaded
+    // before anything else so that the sums and the merge below start
+    // without a dependent round trip to memory
+    gi4 sdesc[kPf], rdesc[kPf];
+    if (sparse) {
+#pragma unroll
+        for (int r = 0; r < kPf; ++r) {
+            const int g = threadIdx.x + r * NT, a = threadIdx.x + r * NT;
+            sdesc[r] = seg_desc[g < n_seg ? g : 0];
+            rdesc[r] = row_desc[a < n_act ? a : 0];
+        }
+    }
     const int lane = threadIdx.x % LANES;
     const int m = threadIdx.x / LANES;
     const int k = k0 + m;
@@ -380,18 +387,6 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
             }
         }
     }
-    if (STAGE && sparse) {
-        for (int q = threadIdx.x; q <= n; q += NT) srp[q] = row_ptr[q];
-        for (int q = threadIdx.x; q < n_seg; q += NT) {
-            ssq0[q] = seg_q0[q];
-            ssrow[q] = seg_row[q];
-        }
-        for (int q = threadIdx.x; q < n_act; q += NT) {
-            srow[q] = row_order[q];
-            srseg[q] = row_seg[q];
-        }
-        if (threadIdx.x == 0) srseg[n_act] = row_seg[n_act];
-    }
     // dense part (or zero) of the right-hand side
     for (int p = threadIdx.x; p < n * MB; p += NT) {
         const int t = p / MB, mm = p - t * MB;
@@ -411,11 +406,10 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     // segments' partial sums in order, so the result does not depend on
     // the schedule.
     if (sparse) {
-        for (int sg = threadIdx.x; sg < n_seg; sg += NT) {
-            const int t = STAGE ? ssrow[sg] : seg_row[sg];
-            int q = STAGE ? ssq0[sg] : seg_q0[sg];
-            const int rend = STAGE ? srp[t + 1] : row_ptr[t + 1];
-            const int q1 = q + kSegLen < rend ? q + kSegLen : rend;
+        // one segment's sums, descriptor d = {first node, end node, row}
+        auto seg_sum = [&](const gi4 d, int sg) {
+            int q = d.x;
+            const int q1 = d.y;
             T acc[MB];
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) acc[mm] = zero<T>();
@@ -449,12 +443,18 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
             }
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) spart[sg * MB + mm] = acc[mm];
+        };
+#pragma unroll
+        for (int r = 0; r < kPf; ++r) {
+            const int sg = threadIdx.x + r * NT;
+            if (sg < n_seg) seg_sum(sdesc[r], sg);
         }
+        for (int sg = threadIdx.x + kPf * NT; sg < n_seg; sg += NT) seg_sum(seg_desc[sg], sg);
         __syncthreads();
-        for (int a = threadIdx.x; a < n_act; a += NT) {
-            const int t = STAGE ? srow[a] : row_order[a];
-            const int s0 = STAGE ? srseg[a] : row_seg[a];
-            const int s1 = STAGE ? srseg[a + 1] : row_seg[a + 1];
+        // one row's segments added in order, descriptor d = {row, first
+        // segment, end segment}
+        auto row_merge = [&](const gi4 d) {
+            const int t = d.x, s0 = d.y, s1 = d.z;
             T acc[MB];
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) acc[mm] = spart[s0 * MB + mm];
@@ -463,7 +463,13 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
                 for (int mm = 0; mm < MB; ++mm) acc[mm] += spart[sg * MB + mm];
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) tile[tidx<MB, C>(t, mm)] += acc[mm];
+        };
+#pragma unroll
+        for (int r = 0; r < kPf; ++r) {
+            const int a = threadIdx.x + r * NT;
+            if (a < n_act) row_merge(rdesc[r]);
         }
+        for (int a = threadIdx.x + kPf * NT; a < n_act; a += NT) row_merge(row_desc[a]);
     }
     __syncthreads();
     // phase B
@@ -629,7 +635,7 @@ __device__ void corr_phi_body(const CorrPhiArgs<TC> &A, int blk) {
     const int q = blk * blockDim.x + threadIdx.x;
     if (q >= nnz) return;
     const int b = mbase[q];
-    TC acc = zero<TC>();
+    TC acc = A.base ? A.base[q] : zero<TC>();
 #pragma unroll
     for (int o = 0; o < kCorrWin; ++o) {
         int idx = b + o;
@@ -854,8 +860,10 @@ int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask
 }
 
 template <class TC>
-CorrPhiArgs<TC> corr_phi_args(kfbi_domain *d, const void *phi, void *corr, const int *done) {
-    return CorrPhiArgs<TC>{(const TC *)phi, d->Nb, d->n_irr, (const TC *)d->mcoef, d->mbase, (TC *)corr, done};
+CorrPhiArgs<TC> corr_phi_args(kfbi_domain *d, const void *phi, void *corr, const int *done,
+                              const void *base = nullptr) {
+    return CorrPhiArgs<TC>{(const TC *)phi, d->Nb,  d->n_irr, (const TC *)d->mcoef, d->mbase, (TC *)corr, done,
+                           (const TC *)base};
 }
 
 template <class T, class TO>
@@ -970,9 +978,7 @@ TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0) {
     S.blocks = (n + mb - 1) / mb;
     S.lds_base = (size_t)2 * d->M * sizeof(double) + ((size_t)n * mb + n / S.c + 1) * sizeof(T);
     if (sparse) S.lds_base += (size_t)d->n_seg * mb * sizeof(T);
-    S.stage_bytes = sparse ? (size_t)d->n_irr * (sizeof(T) + sizeof(int32_t)) +
-                                 (size_t)(n + 1 + 2 * d->n_act_rows + 1 + 2 * d->n_seg) * sizeof(int32_t)
-                           : 0;
+    S.stage_bytes = sparse ? (size_t)d->n_irr * (sizeof(T) + sizeof(int32_t)) : 0;
     S.lds = S.lds_base;
     return S;
 }
@@ -993,6 +999,8 @@ TriArgs<T, typename High<T>::type> tri_args(kfbi_domain *d, const void *rhat, co
     A.sp.seg_q0 = d->seg_q0;
     A.sp.seg_row = d->seg_row;
     A.sp.row_seg = d->row_seg;
+    A.sp.seg_desc = d->seg_desc;
+    A.sp.row_desc = d->row_desc;
     A.sp.nnz = d->n_irr;
     A.sp.n_act = d->n_act_rows;
     A.sp.n_seg = d->n_seg;
@@ -1272,13 +1280,14 @@ int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out) {
 
 
 
-int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done) {
+int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done, const void *base) {
     const int nnz = d->n_irr;
     const int ps = prof_begin(d);
     if (d->cplx)
-        k_corr_phi<cd><<<(nnz + 63) / 64, 64, 0, d->stream>>>(corr_phi_args<cd>(d, phi, corr_out, done));
+        k_corr_phi<cd><<<(nnz + 63) / 64, 64, 0, d->stream>>>(corr_phi_args<cd>(d, phi, corr_out, done, base));
     else
-        k_corr_phi<double><<<(nnz + 63) / 64, 64, 0, d->stream>>>(corr_phi_args<double>(d, phi, corr_out, done));
+        k_corr_phi<double><<<(nnz + 63) / 64, 64, 0, d->stream>>>(
+            corr_phi_args<double>(d, phi, corr_out, done, base));
     KFBI_CHECK_LAUNCH();
     const double es = elem_size(d);
     prof_end(d, ps, KFBI_K_CORRECTIONS, (double)nnz * (kCorrWin * es + 4.0 + es) + (double)d->Nb * es);
@@ -1453,9 +1462,10 @@ void batch_fill_evx(kfbi_domain *d, const void *uhat, const void *phi, void *kv,
         else *(EvxArgs<double, double> *)dst = evx_args<double, double>(d, uhat, phi, kv, done);
     }
 }
-void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst) {
-    if (d->cplx) *(CorrPhiArgs<cd> *)dst = corr_phi_args<cd>(d, phi, corr, done);
-    else *(CorrPhiArgs<double> *)dst = corr_phi_args<double>(d, phi, corr, done);
+void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst,
+                         const void *base) {
+    if (d->cplx) *(CorrPhiArgs<cd> *)dst = corr_phi_args<cd>(d, phi, corr, done, base);
+    else *(CorrPhiArgs<double> *)dst = corr_phi_args<double>(d, phi, corr, done, base);
 }
 void batch_fill_erow(kfbi_domain *d, const void *uhat, void *ust, const int *done, bool low, void *dst) {
     if (d->cplx) {

@@ -200,6 +200,11 @@ struct kfbi_domain {
     int32_t *seg_q0 = nullptr;
     int32_t *seg_row = nullptr;
     int32_t *row_seg = nullptr;
+    // the same tables as descriptors of four int32 each, one load apiece:
+    // per segment {first node, end node, row, 0}, per row of row_order
+    // {row, first segment, end segment, 0}
+    int32_t *seg_desc = nullptr;
+    int32_t *row_desc = nullptr;
     int n_seg = 0;
     // the distinct stencil nodes grouped by interior grid row: rows
     // erow_t[r] hold nodes erow_ptr[r] .. erow_ptr[r+1] (column erow_col[j]);
@@ -220,6 +225,7 @@ struct kfbi_domain {
     void *rhat = nullptr;               // n*n: DST of the dense right-hand side
     void *uhat = nullptr;               // n*n: mode-space solution
     void *corr = nullptr;               // n_irr: corrections
+    void *corr_f = nullptr;             // n_irr: corrections of the b-solve (f alone)
     void *ust = nullptr;                // 6*Nb: grid solution at stencil nodes
     void *tmp_grid = nullptr;           // (M+1)^2
     void *vec = nullptr;                // scratch boundary vectors (8*Nb)
@@ -328,8 +334,10 @@ int tridiag_solve_low(kfbi_domain *d, const void *corr, void *uhat32_out, const 
 int tridiag_solve_phi(kfbi_domain *d, const void *phi, void *uhat_out, const int *done, bool low);
 // the density of the last solve on the domain (null before the first)
 const void *gmres_last_density(kfbi_domain *d);
-// corrections of a density with the merged operator (many workgroups)
-int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done);
+// corrections of a density with the merged operator (many workgroups),
+// plus base (nullable) node by node
+int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done,
+                           const void *base = nullptr);
 
 // interface pieces (interface.hip)
 int compute_corrections(kfbi_domain *d, double kre, double kim, const void *phi,
@@ -441,6 +449,7 @@ struct ZeroArgs {
 
 struct TriSparse {
     const int32_t *irr_col, *row_ptr, *row_order, *seg_q0, *seg_row, *row_seg;
+    const int32_t *seg_desc, *row_desc;
     int nnz, n_act, n_seg;
 };
 
@@ -476,6 +485,7 @@ struct CorrPhiArgs {
     const int32_t *mbase;
     TC *corr;
     const int *done;
+    const TC *base;       // nullable: corrections added to the density's
 };
 
 template <class T, class TO>
@@ -614,7 +624,8 @@ void batch_fill_tri(kfbi_domain *d, const void *rhat, const void *corr, void *uh
 void batch_fill_eval(kfbi_domain *d, const void *uhat, void *out, const int *done, void *dst);
 void batch_fill_evx(kfbi_domain *d, const void *uhat, const void *phi, void *kv, const int *done, bool low,
                     void *dst);
-void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst);
+void batch_fill_corr_phi(kfbi_domain *d, const void *phi, void *corr, const int *done, void *dst,
+                         const void *base = nullptr);
 void batch_fill_erow(kfbi_domain *d, const void *uhat, void *ust, const int *done, bool low, void *dst);
 void batch_fill_exm(kfbi_domain *d, const void *ust, const void *phi, void *kv, const int *done, void *dst);
 // interface.hip
