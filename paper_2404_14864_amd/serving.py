@@ -9,18 +9,20 @@ over wall time (Poisson arrivals of `workloads.serving`) and are served by
     footprints (domain with every table it allocates on first use, stepper
     state, output grid, as the library reports them) leave room for it in
     the budget; a job that cannot fit even alone is rejected;
-  * two lanes, threads that each own a HIP stream and step their jobs in
+  * lanes, threads that each own a HIP stream and step their jobs in
     rounds: every round advances each of the lane's admitted jobs by one
     step in one kfbi_batch_step call, whose launches run all of them
-    together; the real lane holds the heat and wave jobs, the complex lane
-    the Schroedinger jobs.  Between rounds a lane takes in the jobs
+    together.  There is one lane per class of jobs with the same scalar
+    type (real: heat and wave; complex: Schroedinger) and grid size, made
+    when the first job of the class is admitted, so a round never waits for
+    a larger grid's solves.  Between rounds a lane takes in the jobs
     admitted meanwhile and retires the ones whose last step has completed
     on the device, which frees their memory for the admission loop.
 
 The lanes never wait for each other or for admission: a job that arrives
-while both lanes have work on the device is admitted at once if memory
-allows and joins its lane's next round, and the two streams run
-concurrently on the device.  Every step is asynchronous (the host returns
+while lanes have work on the device is admitted at once if memory allows
+and joins its lane's next round, and the lanes' streams run concurrently on
+the device.  Every step is asynchronous (the host returns
 once GMRES has finished on the device, the final grid solve still queued),
 so a lane enqueues its next round while the previous one completes.  A
 round is timed by HIP events on the lane's stream; the step latency of a
@@ -32,6 +34,7 @@ initial arrays and boundary data that are fixed arrays times scalar time
 factors, placed on the device once, on the job's lane stream.
 """
 
+import itertools
 import threading
 import time
 
@@ -55,7 +58,10 @@ class Job:
     The domain and every upload use the current torch stream of the
     creating thread (a lane's stream when the server creates it)."""
 
+    _serial = itertools.count()
+
     def __init__(self, spec, fields_fn, precision=kfbi.KFBI_PREC_FP64):
+        self.serial = next(Job._serial)  # unique for the process (id() is reused after a job is freed)
         self.spec = spec
         self.kind = spec["kind"]
         self.cplx = self.kind == "schrodinger"
@@ -125,10 +131,10 @@ class Job:
 class _Lane(threading.Thread):
     """Steps its jobs in rounds on its own stream (see the module text)."""
 
-    def __init__(self, server, cplx):
+    def __init__(self, server, key):
         super().__init__(daemon=True)
         self.srv = server
-        self.cplx = cplx
+        self.key = key
         self.stream = torch.cuda.Stream(device=DEV)
         self.incoming = []          # admitted, not yet stepped (guarded by srv.cond)
         self.jobs = []              # stepping
@@ -139,7 +145,7 @@ class _Lane(threading.Thread):
         self.error = None
 
     def _rebuild_batch(self):
-        ids = [id(j) for j in self.jobs]
+        ids = [j.serial for j in self.jobs]
         if ids == self.batch_ids:
             return
         if self.batch is not None:
@@ -162,7 +168,7 @@ class _Lane(threading.Thread):
         for j in self.jobs:
             j.n += 1
         ev1.record(self.stream)
-        self.rounds.append((ev0, ev1, [(j.kind, j.M, s["iters"]) for j, s in zip(self.jobs, st)]))
+        self.rounds.append((ev0, ev1, [(j.kind, j.M, s["iters"], s["converged"]) for j, s in zip(self.jobs, st)]))
         for j in [j for j in self.jobs if j.done]:
             self.jobs.remove(j)
             self.retiring.append((j, ev1))
@@ -250,11 +256,10 @@ class Server:
         cache = {}  # footprint of a job shape, once one has been created
         self.used, self.max_used, self.max_jobs = 0, 0, 0
         self.finished, self.closing = [], False
-        lanes = {False: _Lane(self, False), True: _Lane(self, True)}
+        lanes = {}  # (complex?, M) -> lane; read by the lanes under self.cond
         prec = (self.opts or {}).get("precision", kfbi.KFBI_PREC_FP64)
         admitted_busy = 0
-        for ln in lanes.values():
-            ln.start()
+        self.lanes = lanes
         t0 = time.perf_counter()
         try:
             while pending or queue:
@@ -270,7 +275,13 @@ class Server:
                         used = self.used
                     if need is not None and need <= self.budget and used + need > self.budget:
                         break
-                    lane = lanes[spec["kind"] == "schrodinger"]
+                    lkey = (spec["kind"] == "schrodinger", spec["desc"]["M"])
+                    lane = lanes.get(lkey)
+                    if lane is None:
+                        lane = _Lane(self, lkey)
+                        with self.cond:
+                            lanes[lkey] = lane
+                        lane.start()
                     with torch.cuda.stream(lane.stream):
                         job = Job(spec, self.fields_fn, prec)
                     cache[key] = job.footprint
@@ -283,7 +294,7 @@ class Server:
                             fits = False
                         else:
                             fits = True
-                            busy = any(ln.busy for ln in lanes.values())
+                            busy = any(ln.busy for ln in lanes.values() if ln is not lane) or lane.busy
                             admitted_busy += 1 if busy else 0
                             lane.incoming.append(job)
                             self.used += job.footprint
@@ -314,21 +325,24 @@ class Server:
             if ln.error is not None:
                 raise ln.error
         torch.cuda.synchronize()
-        lat, lat_by, work, dev_ms = [], {}, 0.0, 0.0
+        lat, lat_by, work, dev_ms, unconv = [], {}, 0.0, 0.0, 0
         for ln in lanes.values():
             for ev0, ev1, steps in ln.rounds:
                 ms = ev0.elapsed_time(ev1)
                 dev_ms += ms
-                for kind, M, it in steps:
+                for kind, M, it, conv in steps:
+                    unconv += 0 if conv else 1
                     lat.append(ms)
                     lat_by.setdefault("%s M=%d" % (kind, M), []).append(ms)
                     work += float((M - 1) ** 2) * it
         lat = np.asarray(lat)
         first = min((s["arrival"] for s in specs), default=0.0) * tick
         return {
+            "lanes": len(lanes),
             "finished": list(self.finished),
             "rejected": rejected,
             "steps": int(lat.size),
+            "unconverged_steps": unconv,
             "rounds": sum(len(ln.rounds) for ln in lanes.values()),
             "p50_step_ms": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_step_ms": float(np.percentile(lat, 99)) if lat.size else None,
