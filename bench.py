@@ -511,8 +511,9 @@ def batched_helmholtz(n, reps):
         out[label] = {"plain_value": plain, "plain_ms": 1e3 * Tp, "batched_value": batched, "batched_ms": 1e3 * Tb,
                       "batched_untuned_ms": 1e3 * Tu, "speedup": batched / plain, "gmres_iters_total": int(sum(bits)),
                       "max_rel_diff_batched_vs_plain": diff,
-                      "tridiag_shapes": ["M%d %s: %d modes/wg%s, %.1f us" % (
-                          r["M"], r["kind"], r["modes_per_wg"], " staged" if r["staged"] else "", r["us"])
+                      "tridiag_shapes": ["M%d %s: %s kernel, %d modes/wg%s, %.1f us" % (
+                          r["M"], r["kind"], "register-row" if r["register_rows"] else "LDS-tile", r["modes_per_wg"],
+                          " staged" if r["staged"] else "", r["us"])
                           for r in tuning]}
         log("batch %s: plain %.3g (%.1f ms), batched %.3g (%.1f ms; default shapes %.1f ms), x%.1f, %d iterations" % (
             label, plain, 1e3 * Tp, batched, 1e3 * Tb, 1e3 * Tu, batched / plain, sum(bits)))
@@ -567,10 +568,15 @@ def serving(n_jobs, seed=20240423):
     repm = Server(budget, job_fields, dict(base, precision=kfbi.KFBI_PREC_MIXED),
                   keep_output=keeper("mixed")).run(poisson, tick=1.0)
     plain = serve_plain(specs, job_fields, base, keep_output=keeper("plain"))
-    diff = {}
+    diff, diff_by = {}, {}
+    kind_of = {s["id"]: "%s M=%d" % (s["kind"], s["desc"]["M"]) for s in specs}
     for tag in ("fp64", "mixed"):
-        diff[tag] = max(float(np.max(np.abs(outs[tag][i] - outs["plain"][i])) /
-                              max(float(np.max(np.abs(outs["plain"][i]))), 1e-300)) for i in outs["plain"])
+        by = diff_by.setdefault(tag, {})
+        for i in outs["plain"]:
+            e = float(np.max(np.abs(outs[tag][i] - outs["plain"][i])) /
+                      max(float(np.max(np.abs(outs["plain"][i]))), 1e-300))
+            by[kind_of[i]] = max(by.get(kind_of[i], 0.0), e)
+        diff[tag] = max(by.values())
     for r in (rep_sat, rep, repm):
         r["n_finished"] = len(r.pop("finished"))
         r["n_rejected"] = len(r.pop("rejected"))
@@ -579,7 +585,7 @@ def serving(n_jobs, seed=20240423):
                        "of the measured capacity; budget half of the jobs' summed footprint" % len(specs),
            "capacity_jobs_per_s": capacity, "arrival_rate_jobs_per_s": rate, "budget_bytes": budget,
            "sum_of_footprints_bytes": total, "saturated": rep_sat, "served_fp64": rep, "served_mixed": repm,
-           "plain_fp64": plain, "max_rel_diff_vs_plain": diff,
+           "plain_fp64": plain, "max_rel_diff_vs_plain": diff, "max_rel_diff_vs_plain_by_type": diff_by,
            "speedup_fp64_vs_plain": rep["throughput"] / plain["throughput"],
            "speedup_mixed_vs_plain": repm["throughput"] / plain["throughput"]}
     log("serving: capacity %.2f jobs/s; served fp64 %.3g (p50 %.2f p99 %.2f ms), mixed %.3g (p99 %.2f ms), plain %.3g "

@@ -516,6 +516,16 @@ int build_domain(kfbi_domain *d) {
         KFBI_HIP(hipMemcpyAsync(d->seg_desc, sd.data(), sd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         KFBI_TRY(dalloc(d, (void **)&d->row_desc, rd.size() * sizeof(int32_t)));
         KFBI_HIP(hipMemcpyAsync(d->row_desc, rd.data(), rd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // segment span of every interior row, padded with empty spans to 64 c rows
+        int c64 = 1;
+        while (64 * c64 < d->n) c64 <<= 1;
+        std::vector<int32_t> rs(2 * (size_t)std::max(64 * c64, d->n), 0);
+        for (size_t a = 0; a < order.size(); ++a) {
+            rs[2 * (size_t)order[a]] = row_seg[a];
+            rs[2 * (size_t)order[a] + 1] = row_seg[a + 1];
+        }
+        KFBI_TRY(dalloc(d, (void **)&d->row_span, rs.size() * sizeof(int32_t)));
+        KFBI_HIP(hipMemcpyAsync(d->row_span, rs.data(), rs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         KFBI_HIP(hipStreamSynchronize(s));
     }
     KFBI_TRY(tmp.alloc((void **)&ex_map, nodes * sizeof(int32_t)));

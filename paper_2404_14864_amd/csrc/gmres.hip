@@ -2094,8 +2094,9 @@ int tune_time(kfbi_batch *b, int kind, const void *args, const BatchClass &C, co
 
 // Times the tridiagonal launch shapes of every class once per precision and
 // keeps the fastest.  Only shapes with 64-lane mode groups (1, 2 or 4 modes
-// per workgroup) are candidates: for a given mode they run the same
-// operations in the same order, so the choice never changes the values.
+// per workgroup; the tile kernel, and for sparse input also the register-row
+// kernel) are candidates: for a given mode they run the same operations in
+// the same order, so the choice never changes the values.
 // Inputs are the members' own tables with the scratch right-hand sides
 // cleared; the launches write only the scratch transforms.
 int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) {
@@ -2118,15 +2119,20 @@ int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) 
             const void *args = d_buf + (kind == 1 ? (size_t)n * as : 0);
             BatchTriShape best = C.shape[kind];
             double best_us = 1e300;
-            for (int mb : {1, 2, 4}) {
-                for (int stage : {0, 1}) {
-                    BatchTriShape S;
-                    if (batch_tri_shape(cd.data(), (int)cd.size(), true, low, &S, mb, stage) != KFBI_OK) continue;
-                    double us = 0.0;
-                    KFBI_TRY(tune_time(b, low ? kBaTri32 : kBaTri64, args, C, S, &us));
-                    if (us < best_us) {
-                        best_us = us;
-                        best = S;
+            const int pref = tri_kernel_pref();
+            for (int rows = 0; rows < (kind == 1 ? 1 : 2); ++rows) {
+                if (kind != 1 && pref >= 0 && rows != pref) continue;
+                for (int mb : {1, 2, 4}) {
+                    for (int stage : {0, 1}) {
+                        BatchTriShape S;
+                        if (batch_tri_shape(cd.data(), (int)cd.size(), true, low, &S, mb, stage, rows != 0) != KFBI_OK)
+                            continue;
+                        double us = 0.0;
+                        KFBI_TRY(tune_time(b, low ? kBaTri32 : kBaTri64, args, C, S, &us));
+                        if (us < best_us) {
+                            best_us = us;
+                            best = S;
+                        }
                     }
                 }
             }
@@ -2184,12 +2190,13 @@ int batch_tuning(const kfbi_batch *b, int cap, int32_t *rows, double *us, int32_
     for (const auto &C : b->classes)
         for (int kind = 0; kind < 3; ++kind, ++r) {
             if (r >= cap) continue;
-            int32_t *o = rows + 5 * r;
+            int32_t *o = rows + 6 * r;
             o[0] = C.M;
             o[1] = kind;
             o[2] = C.shape[kind].mb;
             o[3] = C.shape[kind].stage ? 1 : 0;
             o[4] = C.tuned[kind] ? 1 : 0;
+            o[5] = C.shape[kind].rows ? 1 : 0;
             if (us) us[r] = C.tuned[kind] ? C.us[kind] : -1.0;
         }
     *n_rows = r;

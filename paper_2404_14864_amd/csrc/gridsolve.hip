@@ -33,6 +33,9 @@
 #include <algorithm>
 #include <cstdint>
 
+#include <cstdlib>
+#include <cstring>
+
 #include "kfbi_internal.h"
 
 namespace kfbi {
@@ -301,6 +304,119 @@ constexpr int kCorrWin = 16;
 constexpr int kPf = 2;
 typedef int gi4 __attribute__((ext_vector_type(4)));
 
+// Phase A of the sparse solves: the sums over every segment (at most kSegLen
+// irregular nodes of one row) of corr[q] sin(pi i_q k / M) for the MB modes
+// k = k0+1 .. k0+MB, into spart[segment * MB + mode].  Thread i of NT takes
+// segments i, i + NT, ... (the first kPf from the descriptors it loaded
+// ahead); four nodes per step keep several LDS round trips in flight, and
+// each mode's terms are added in node order.
+template <class T, class TC, int MB, int NT, bool STAGE>
+__device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem<gi4> *__restrict__ seg_desc,
+                                             int n_seg, int k0, int mask2M, const typename Real<T>::type *S,
+                                             const T *sval, const int32_t *scol, const gmem<TC> *__restrict__ corr,
+                                             const gmem<int32_t> *__restrict__ irr_col, T *spart) {
+    // one segment's sums, descriptor d = {first node, end node, row}
+    auto seg_sum = [&](const gi4 d, int sg) {
+        int q = d.x;
+        const int q1 = d.y;
+        T acc[MB];
+#pragma unroll
+        for (int mm = 0; mm < MB; ++mm) acc[mm] = zero<T>();
+        for (; q + 4 <= q1; q += 4) {
+            T cv[4];
+            int col[4], idx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                cv[u] = STAGE ? sval[q + u] : Conv<T>::from(gld(corr + (q + u)));
+                col[u] = STAGE ? scol[q + u] : irr_col[q + u];
+                idx[u] = (col[u] * (k0 + 1)) & mask2M;
+            }
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    acc[mm] += cv[u] * S[idx[u]];
+                    idx[u] = (idx[u] + col[u]) & mask2M;
+                }
+            }
+        }
+        for (; q < q1; ++q) {
+            const T cv = STAGE ? sval[q] : Conv<T>::from(gld(corr + (q)));
+            const int col = STAGE ? scol[q] : irr_col[q];
+            int idx = (col * (k0 + 1)) & mask2M;
+#pragma unroll
+            for (int mm = 0; mm < MB; ++mm) {
+                acc[mm] += cv * S[idx];
+                idx = (idx + col) & mask2M;
+            }
+        }
+#pragma unroll
+        for (int mm = 0; mm < MB; ++mm) spart[sg * MB + mm] = acc[mm];
+    };
+#pragma unroll
+    for (int r = 0; r < kPf; ++r) {
+        const int sg = threadIdx.x + r * NT;
+        if (sg < n_seg) seg_sum(sdesc[r], sg);
+    }
+    for (int sg = threadIdx.x + kPf * NT; sg < n_seg; sg += NT) seg_sum(seg_desc[sg], sg);
+}
+
+// Phase B of the tridiagonal solves for one lane of a LANES-lane mode group:
+// v holds h^2 rho of the lane's C rows t0 .. t0+C-1 on entry and U^ on exit,
+// e their Thomas coefficients (rows past n: v = e = 0).  The forward sweep
+// x_t = e_t (x_{t-1} - rho_t) and the backward sweep U_t = e_t U_{t+1} + x_t
+// are affine maps composed per lane and then across the group by shuffle
+// scans (Hillis-Steele), each lane finishing its rows from the carried-in
+// value.
+template <class T, int LANES, int C>
+__device__ __forceinline__ void thomas_rows(T (&v)[C], const T (&e)[C], int lane, int t0, int n) {
+    T A = one<T>(), B = zero<T>();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if (t0 + c < n) {
+            B = e[c] * (B - v[c]);
+            A = e[c] * A;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < LANES; off <<= 1) {
+        T Ap = Shfl<T>::up(A, off, LANES), Bp = Shfl<T>::up(B, off, LANES);
+        if (lane >= off) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    T x = Shfl<T>::up(B, 1, LANES);
+    if (lane == 0) x = zero<T>();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        x = e[c] * (x - v[c]);
+        v[c] = x;
+    }
+    A = one<T>();
+    B = zero<T>();
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        B = e[c] * B + v[c];
+        A = e[c] * A;
+    }
+#pragma unroll
+    for (int off = 1; off < LANES; off <<= 1) {
+        T Ap = Shfl<T>::down(A, off, LANES), Bp = Shfl<T>::down(B, off, LANES);
+        if (lane + off < LANES) {
+            B = A * Bp + B;
+            A = A * Ap;
+        }
+    }
+    T y = Shfl<T>::down(B, 1, LANES);
+    if (lane == LANES - 1) y = zero<T>();
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        y = e[c] * y + v[c];
+        v[c] = y;
+    }
+}
+
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
 __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     typedef typename Real<T>::type R;
@@ -406,50 +522,7 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     // segments' partial sums in order, so the result does not depend on
     // the schedule.
     if (sparse) {
-        // one segment's sums, descriptor d = {first node, end node, row}
-        auto seg_sum = [&](const gi4 d, int sg) {
-            int q = d.x;
-            const int q1 = d.y;
-            T acc[MB];
-#pragma unroll
-            for (int mm = 0; mm < MB; ++mm) acc[mm] = zero<T>();
-            for (; q + 4 <= q1; q += 4) {
-                T cv[4];
-                int col[4], idx[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    cv[u] = STAGE ? sval[q + u] : Conv<T>::from(gld(corr + (q + u)));
-                    col[u] = STAGE ? scol[q + u] : irr_col[q + u];
-                    idx[u] = (col[u] * (k0 + 1)) & mask2M;
-                }
-#pragma unroll
-                for (int mm = 0; mm < MB; ++mm) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        acc[mm] += cv[u] * S[idx[u]];
-                        idx[u] = (idx[u] + col[u]) & mask2M;
-                    }
-                }
-            }
-            for (; q < q1; ++q) {
-                const T cv = STAGE ? sval[q] : Conv<T>::from(gld(corr + (q)));
-                const int col = STAGE ? scol[q] : irr_col[q];
-                int idx = (col * (k0 + 1)) & mask2M;
-#pragma unroll
-                for (int mm = 0; mm < MB; ++mm) {
-                    acc[mm] += cv * S[idx];
-                    idx = (idx + col) & mask2M;
-                }
-            }
-#pragma unroll
-            for (int mm = 0; mm < MB; ++mm) spart[sg * MB + mm] = acc[mm];
-        };
-#pragma unroll
-        for (int r = 0; r < kPf; ++r) {
-            const int sg = threadIdx.x + r * NT;
-            if (sg < n_seg) seg_sum(sdesc[r], sg);
-        }
-        for (int sg = threadIdx.x + kPf * NT; sg < n_seg; sg += NT) seg_sum(seg_desc[sg], sg);
+        segment_sums<T, TC, MB, NT, STAGE>(sdesc, seg_desc, n_seg, k0, mask2M, S, sval, scol, corr, irr_col, spart);
         __syncthreads();
         // one row's segments added in order, descriptor d = {row, first
         // segment, end segment}
@@ -483,51 +556,10 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
             v[c] = ok ? tile[tidx<MB, C>(t0 + c, m)] * (R)h2 : zero<T>();
             if (!ok) e[c] = zero<T>();
         }
-        T A = one<T>(), B = zero<T>();
+        thomas_rows<T, LANES, C>(v, e, lane, t0, n);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            if (t0 + c < n) {
-                B = e[c] * (B - v[c]);
-                A = e[c] * A;
-            }
-        }
-#pragma unroll
-        for (int off = 1; off < LANES; off <<= 1) {
-            T Ap = Shfl<T>::up(A, off, LANES), Bp = Shfl<T>::up(B, off, LANES);
-            if (lane >= off) {
-                B = A * Bp + B;
-                A = A * Ap;
-            }
-        }
-        T x = Shfl<T>::up(B, 1, LANES);
-        if (lane == 0) x = zero<T>();
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            x = e[c] * (x - v[c]);
-            v[c] = x;
-        }
-        A = one<T>();
-        B = zero<T>();
-#pragma unroll
-        for (int c = C - 1; c >= 0; --c) {
-            B = e[c] * B + v[c];
-            A = e[c] * A;
-        }
-#pragma unroll
-        for (int off = 1; off < LANES; off <<= 1) {
-            T Ap = Shfl<T>::down(A, off, LANES), Bp = Shfl<T>::down(B, off, LANES);
-            if (lane + off < LANES) {
-                B = A * Bp + B;
-                A = A * Ap;
-            }
-        }
-        T y = Shfl<T>::down(B, 1, LANES);
-        if (lane == LANES - 1) y = zero<T>();
-#pragma unroll
-        for (int c = C - 1; c >= 0; --c) {
-            y = e[c] * y + v[c];
-            if (t0 + c < n) tile[tidx<MB, C>(t0 + c, m)] = y;
-        }
+        for (int c = C - 1; c >= 0; --c)
+            if (t0 + c < n) tile[tidx<MB, C>(t0 + c, m)] = v[c];
     }
     __syncthreads();
     // phase C
@@ -540,6 +572,161 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
 __global__ __launch_bounds__(MB *LANES) void k_tridiag(TriArgs<T, TC> A) {
     tridiag_body<T, TC, MB, LANES, C, STAGE>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// The same solves for a sparse right-hand side without the LDS tile: after
+// phase A's segment sums each lane adds the partial sums of its own C rows
+// (row t's segments row_span[t], in the order of the row merge above)
+// straight into registers, runs the same scans, and the results leave
+// through a small LDS buffer, CH rows per lane at a time, as the same MB-mode
+// row segments.  Every value is formed by the same operations in the same
+// order as in tridiag_body; the LDS shrinks from the n*MB tile to the larger
+// of the partial sums and the buffer, so more workgroups share a CU.
+// 64-lane mode groups only.
+// ---------------------------------------------------------------------------
+template <int C>
+struct RowsOut {
+    static constexpr int CH = C < 4 ? C : 4;  // rows per lane per output chunk
+};
+
+template <class T, int MB, int C>
+constexpr size_t rows_obuf_bytes() {
+    return (size_t)RowsOut<C>::CH * 64 * (MB > 1 ? MB + 1 : 1) * sizeof(T);
+}
+
+typedef int gi2 __attribute__((ext_vector_type(2)));
+
+template <class T, class TC, int MB, int C, bool STAGE>
+__device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
+    typedef typename Real<T>::type R;
+    constexpr int LANES = 64, NT = MB * LANES;
+    constexpr int CH = RowsOut<C>::CH;
+    constexpr int OST = MB > 1 ? MB + 1 : 1;  // padded slot stride of the buffer
+    const int M = A.M;
+    const double h2 = A.h2;
+    const gmem<TC> *__restrict__ corr = gview(A.corr);
+    const TriSparse &sp = A.sp;
+    const gmem<int32_t> *__restrict__ irr_col = gview(sp.irr_col);
+    const gmem<gi4> *__restrict__ seg_desc = (const gmem<gi4> *)gview(sp.seg_desc);
+    const gmem<gi2> *__restrict__ row_span = (const gmem<gi2> *)gview(sp.row_span);
+    const gmem<R> *__restrict__ sine = gview(A.sine);
+    const gmem<T> *__restrict__ etab = gview(A.etab);
+    const gmem<T> *__restrict__ elim = gview(A.elim);
+    const gmem<int32_t> *__restrict__ tconv = gview(A.tconv);
+    gmem<T> *__restrict__ uhat = gview(A.uhat);
+    const gmem<int> *__restrict__ done = gview(A.done);
+    extern __shared__ double lds[];
+    const int n = M - 1;
+    const int mask2M = 2 * M - 1;
+    if (done && *done) return;
+    const int nnz = sp.nnz, n_seg = sp.n_seg;
+    R *S = reinterpret_cast<R *>(lds);                   // 2M sine values
+    T *spart = reinterpret_cast<T *>(lds + 2 * M);      // n_seg*MB partial sums
+    T *obuf = spart;                                     // later: the output chunks
+    T *sval = spart + n_seg * MB;
+    int32_t *scol = reinterpret_cast<int32_t *>(sval + (STAGE ? nnz : 0));
+    const int k0 = tile_idx * MB;
+    const int lane = threadIdx.x % LANES;
+    const int m = threadIdx.x / LANES;
+    const int k = k0 + m;
+    const int t0 = lane * C;
+    gi4 sdesc[kPf];
+#pragma unroll
+    for (int r = 0; r < kPf; ++r) {
+        const int g = threadIdx.x + r * NT;
+        sdesc[r] = seg_desc[g < n_seg ? g : 0];
+    }
+    // segment spans of the lane's rows (the table holds 64*C rows)
+    gi2 rsp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) rsp[c] = row_span[t0 + c];
+    int tc = 0;
+    T lim = zero<T>();
+    if (k < n) {
+        tc = tconv[k];
+        lim = gld(elim + k);
+    }
+    for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * NT) {
+        R v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u * NT < 2 * M) v[u] = sine[q0 + u * NT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u * NT < 2 * M) S[q0 + u * NT] = v[u];
+    }
+    if (STAGE) {
+        for (int q0 = threadIdx.x; q0 < nnz; q0 += 4 * NT) {
+            TC v[4];
+            int32_t c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * NT;
+                if (q < nnz) {
+                    v[u] = gld(corr + (q));
+                    c[u] = irr_col[q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * NT;
+                if (q < nnz) {
+                    sval[q] = Conv<T>::from(v[u]);
+                    scol[q] = c[u];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    T e[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int t = t0 + c;
+        e[c] = (t < tc && t < n) ? gld(etab + (size_t)t * n + k) : lim;
+    }
+    // phase A
+    segment_sums<T, TC, MB, NT, STAGE>(sdesc, seg_desc, n_seg, k0, mask2M, S, sval, scol, corr, irr_col, spart);
+    __syncthreads();
+    // phase B: the lane's rows from the partial sums (0 + the row's segments
+    // in order, as the tile kernel's zeroed tile plus its row merge), then
+    // the scans
+    T v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T acc = zero<T>();
+        const int s0 = rsp[c].x, s1 = rsp[c].y;
+        if (s0 < s1) {
+            T a = spart[s0 * MB + m];
+            for (int sg = s0 + 1; sg < s1; ++sg) a += spart[sg * MB + m];
+            acc += a;
+        }
+        const bool ok = t0 + c < n;
+        v[c] = ok ? acc * (R)h2 : zero<T>();
+        if (!ok) e[c] = zero<T>();
+    }
+    if (k < n) thomas_rows<T, LANES, C>(v, e, lane, t0, n);
+    // phase C: CH rows per lane at a time through the buffer (which
+    // overlays the partial sums: the first barrier also ends their reads)
+#pragma unroll
+    for (int cb = 0; cb < C; cb += CH) {
+        __syncthreads();
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) obuf[(cc * LANES + lane) * OST + m] = v[cb + cc];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < CH; ++r) {
+            const int p = threadIdx.x + r * NT;  // < CH * LANES * MB
+            const int slot = p / MB, mm = p - slot * MB;
+            const int t = (slot % LANES) * C + cb + slot / LANES;
+            if (t < n && k0 + mm < n) gst(uhat + (size_t)t * n + k0 + mm, obuf[slot * OST + mm]);
+        }
+    }
+}
+
+template <class T, class TC, int MB, int C, bool STAGE>
+__global__ __launch_bounds__(MB * 64) void k_tridiag_rows(TriArgs<T, TC> A) {
+    tridiag_rows_body<T, TC, MB, C, STAGE>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -954,7 +1141,8 @@ EvalArgs<T, TO> eval_args(kfbi_domain *d, const void *uhat, void *out, const int
 // use 64), rows per lane, LDS and whether the sparse input is staged
 struct TriShape {
     int mb, lanes, c, blocks;
-    size_t lds, lds_base, stage_bytes;
+    bool rows;                          // the register-row kernel
+    size_t lds, lds_base, lds_stage;    // LDS in use; unstaged; staged
 };
 
 // the largest power of two <= 4 modes whose LDS tile stays within 32 KB
@@ -965,8 +1153,10 @@ int tri_default_mb(int n) {
     return mb;
 }
 
+// rows: the register-row kernel, for sparse input with 1, 2 or 4 modes per
+// workgroup and at least 4 rows per lane (tri_rows_ok)
 template <class T>
-TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0) {
+TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0, bool rows = false) {
     TriShape S;
     const int n = d->M - 1;
     int mb = mb_force > 0 ? mb_force : d->tri_mb;
@@ -976,12 +1166,40 @@ TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0) {
     S.c = 1;
     while (S.lanes * S.c < n) S.c <<= 1;
     S.blocks = (n + mb - 1) / mb;
-    S.lds_base = (size_t)2 * d->M * sizeof(double) + ((size_t)n * mb + n / S.c + 1) * sizeof(T);
-    if (sparse) S.lds_base += (size_t)d->n_seg * mb * sizeof(T);
-    S.stage_bytes = sparse ? (size_t)d->n_irr * (sizeof(T) + sizeof(int32_t)) : 0;
+    S.rows = rows;
+    const size_t sine = (size_t)2 * d->M * sizeof(double);
+    const size_t spart = sparse ? (size_t)d->n_seg * mb * sizeof(T) : 0;
+    const size_t stage = sparse ? (size_t)d->n_irr * (sizeof(T) + sizeof(int32_t)) : 0;
+    if (rows) {
+        const size_t obuf = (size_t)std::min(S.c, 4) * 64 * (mb > 1 ? mb + 1 : 1) * sizeof(T);
+        S.lds_base = sine + std::max(spart, obuf);
+        S.lds_stage = sine + std::max(spart + stage, obuf);
+    } else {
+        S.lds_base = sine + ((size_t)n * mb + n / S.c + 1) * sizeof(T) + spart;
+        S.lds_stage = S.lds_base + stage;
+    }
     S.lds = S.lds_base;
     return S;
 }
+
+// whether the register-row kernel has an instantiation for this shape
+inline bool tri_rows_ok(const TriShape &S) { return S.mb <= 4 && S.lanes == 64 && S.c >= 4 && S.c <= 32; }
+
+}  // namespace
+
+// The tridiagonal kernels the launch-shape timing may choose from: the
+// environment variable KFBI_TRIDIAG_KERNEL = "tile" or "rows" restricts it to
+// one of them (both compute the same values; for tests and diagnosis), -1
+// when unset.
+int tri_kernel_pref() {
+    const char *v = std::getenv("KFBI_TRIDIAG_KERNEL");
+    if (!v) return -1;
+    if (std::strcmp(v, "tile") == 0) return 0;
+    if (std::strcmp(v, "rows") == 0) return 1;
+    return -1;
+}
+
+namespace {
 
 template <class T>
 TriArgs<T, typename High<T>::type> tri_args(kfbi_domain *d, const void *rhat, const void *corr, void *uhat,
@@ -1001,6 +1219,7 @@ TriArgs<T, typename High<T>::type> tri_args(kfbi_domain *d, const void *rhat, co
     A.sp.row_seg = d->row_seg;
     A.sp.seg_desc = d->seg_desc;
     A.sp.row_desc = d->row_desc;
+    A.sp.row_span = d->row_span;
     A.sp.nnz = d->n_irr;
     A.sp.n_act = d->n_act_rows;
     A.sp.n_seg = d->n_seg;
@@ -1025,6 +1244,10 @@ struct TriLaunchOne {
     void go() const {
         k_tridiag<T, TC, MB, L, C, ST><<<blocks, MB * L, lds, s>>>(A);
     }
+    template <int MB, int C, bool ST>
+    void go_rows() const {
+        k_tridiag_rows<T, TC, MB, C, ST><<<blocks, MB * 64, lds, s>>>(A);
+    }
 };
 
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
@@ -1032,6 +1255,13 @@ __global__ __launch_bounds__(MB *LANES) void kb_tridiag(const TriArgs<T, TC> *__
                                                         const BlkMap *__restrict__ map) {
     const BlkMap e = map[xcd_tile(blockIdx.x, gridDim.x)];
     tridiag_body<T, TC, MB, LANES, C, STAGE>(A[e.inst], e.local);
+}
+
+template <class T, class TC, int MB, int C, bool STAGE>
+__global__ __launch_bounds__(MB * 64) void kb_tridiag_rows(const TriArgs<T, TC> *__restrict__ A,
+                                                         const BlkMap *__restrict__ map) {
+    const BlkMap e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    tridiag_rows_body<T, TC, MB, C, STAGE>(A[e.inst], e.local);
 }
 
 template <class T, class TC>
@@ -1044,6 +1274,10 @@ struct TriLaunchBatch {
     template <int MB, int L, int C, bool ST>
     void go() const {
         kb_tridiag<T, TC, MB, L, C, ST><<<blocks, MB * L, lds, s>>>(A, map);
+    }
+    template <int MB, int C, bool ST>
+    void go_rows() const {
+        kb_tridiag_rows<T, TC, MB, C, ST><<<blocks, MB * 64, lds, s>>>(A, map);
     }
 };
 
@@ -1073,22 +1307,55 @@ void tri_dispatch(int mb, int c, bool stage, const F &f) {
 #undef KFBI_TRI
 }
 
+// the register-row kernel: mb in {1, 2, 4}, c in {4, ..., 32} (tri_rows_ok)
+template <class F>
+void tri_rows_dispatch(int mb, int c, bool stage, const F &f) {
+#define KFBI_TRR(MBv, CC)                                   \
+    do {                                                    \
+        if (stage) f.template go_rows<MBv, CC, true>();     \
+        else f.template go_rows<MBv, CC, false>();          \
+    } while (0)
+#define KFBI_TRR_C(MBv)                       \
+    switch (c) {                              \
+        case 4: KFBI_TRR(MBv, 4); break;      \
+        case 8: KFBI_TRR(MBv, 8); break;      \
+        case 16: KFBI_TRR(MBv, 16); break;    \
+        default: KFBI_TRR(MBv, 32); break;    \
+    }
+    switch (mb) {
+        case 4: KFBI_TRR_C(4); break;
+        case 2: KFBI_TRR_C(2); break;
+        default: KFBI_TRR_C(1); break;
+    }
+#undef KFBI_TRR_C
+#undef KFBI_TRR
+}
+
+// a tile- or row-kernel launch of shape S
+template <class F>
+void tri_launch(const TriShape &S, bool stage, const F &f) {
+    if (S.rows) tri_rows_dispatch(S.mb, S.c, stage, f);
+    else tri_dispatch(S.mb, S.c, stage, f);
+}
+
 template <class T>
 int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
     typedef typename High<T>::type TC;
     const int n = d->M - 1;
-    TriShape S = tri_shape<T>(d, corr != nullptr);
+    // sparse input: the row kernel when timing chose it
+    TriShape S = tri_shape<T>(d, corr != nullptr, 0, corr && !rhat && d->tri_rows);
+    if (S.rows && !tri_rows_ok(S)) S = tri_shape<T>(d, corr != nullptr);
     if (S.c > 32 || S.lds > kTriLdsMax) {
         set_error("grid too large for the tridiagonal kernel");
         return KFBI_ENOTSUP;
     }
     // stage the sparse right-hand side in LDS when it fits (unless timing
     // found the unstaged kernel faster)
-    const bool stage = corr && S.lds + S.stage_bytes <= kTriLdsMax && d->tri_stage != 0;
-    if (stage) S.lds += S.stage_bytes;
+    const bool stage = corr && S.lds_stage <= kTriLdsMax && d->tri_stage != 0;
+    if (stage) S.lds = S.lds_stage;
     TriLaunchOne<T, TC> L{tri_args<T>(d, rhat, corr, uhat, done), S.blocks, S.lds, d->stream};
     const int ps = prof_begin(d);
-    tri_dispatch(S.mb, S.c, stage, L);
+    tri_launch(S, stage, L);
     KFBI_CHECK_LAUNCH();
     {
         // algorithmic bytes: write U^ (and read R^ when dense) plus the sparse input
@@ -1104,8 +1371,9 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
 
 // Times the sparse-input tridiagonal launch of this domain for 1, 2 and 4
 // modes per workgroup (64-lane mode groups: the same operations in the same
-// order for every mode) with and without LDS staging, on the domain's own
-// tables, and keeps the fastest.  Writes only the scratch transforms.
+// order for every mode), with and without LDS staging, in the tile and the
+// register-row kernels, on the domain's own tables, and keeps the fastest.
+// Writes only the scratch transforms.
 template <class T>
 int tune_tridiag_t(kfbi_domain *d) {
     typedef typename High<T>::type TC;
@@ -1119,27 +1387,33 @@ int tune_tridiag_t(kfbi_domain *d) {
         set_error("hipEventCreate failed");
         return KFBI_EDEVICE;
     }
-    int best_mb = tri_default_mb<T>(n), best_stage = -1, st = KFBI_OK;
+    int best_mb = tri_default_mb<T>(n), best_stage = -1, best_rows = 0, st = KFBI_OK;
     float best = 1e30f;
-    for (int mb : {1, 2, 4}) {
-        const TriShape S = tri_shape<T>(d, true, mb);
-        if (S.c > 32 || S.lds > kTriLdsMax) continue;
-        for (int stage : {0, 1}) {
-            if (stage && S.lds + S.stage_bytes > kTriLdsMax) continue;
-            const size_t lds = S.lds + (stage ? S.stage_bytes : 0);
-            TriLaunchOne<T, TC> L{tri_args<T>(d, nullptr, d->corr, d->uhat, nullptr), S.blocks, lds, s};
-            tri_dispatch(S.mb, S.c, stage != 0, L);
-            if (hipEventRecord(e0, s) != hipSuccess) st = KFBI_EDEVICE;
-            for (int r = 0; r < 20; ++r) tri_dispatch(S.mb, S.c, stage != 0, L);
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = KFBI_EDEVICE;
-            float ms = 0.f;
-            if (st == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = KFBI_EDEVICE;
-            if (st != KFBI_OK) break;
-            if (ms < best) {
-                best = ms;
-                best_mb = mb;
-                best_stage = stage ? -1 : 0;
+    const int pref = tri_kernel_pref();
+    for (int rows : {0, 1}) {
+        if (pref >= 0 && rows != pref) continue;
+        for (int mb : {1, 2, 4}) {
+            const TriShape S = tri_shape<T>(d, true, mb, rows != 0);
+            if (S.c > 32 || S.lds > kTriLdsMax || (rows && !tri_rows_ok(S))) continue;
+            for (int stage : {0, 1}) {
+                if (stage && S.lds_stage > kTriLdsMax) continue;
+                const size_t lds = stage ? S.lds_stage : S.lds;
+                TriLaunchOne<T, TC> L{tri_args<T>(d, nullptr, d->corr, d->uhat, nullptr), S.blocks, lds, s};
+                tri_launch(S, stage != 0, L);
+                if (hipEventRecord(e0, s) != hipSuccess) st = KFBI_EDEVICE;
+                for (int r = 0; r < 20; ++r) tri_launch(S, stage != 0, L);
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = KFBI_EDEVICE;
+                float ms = 0.f;
+                if (st == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = KFBI_EDEVICE;
+                if (st != KFBI_OK) break;
+                if (ms < best) {
+                    best = ms;
+                    best_mb = mb;
+                    best_stage = stage ? -1 : 0;
+                    best_rows = rows;
+                }
             }
+            if (st != KFBI_OK) break;
         }
         if (st != KFBI_OK) break;
     }
@@ -1151,6 +1425,7 @@ int tune_tridiag_t(kfbi_domain *d) {
     }
     d->tri_mb = best_mb;
     d->tri_stage = best_stage;
+    d->tri_rows = best_rows;
     return KFBI_OK;
 }
 
@@ -1500,7 +1775,8 @@ int batch_blocks(const kfbi_domain *d, int kind) {
 
 // launch shape of the tridiagonal kernel shared by a batch class (equal M,
 // mb and c; LDS the largest over the members; staged when all fit)
-int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb, int stage_pref) {
+int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb, int stage_pref,
+                    bool rows) {
     const bool cplx = doms[0]->cplx;
     // the static default, not a member's own timed choice, when none is given
     if (mb <= 0) {
@@ -1508,21 +1784,31 @@ int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, Batc
         mb = cplx ? (low ? tri_default_mb<cf>(n0) : tri_default_mb<cd>(n0))
                   : (low ? tri_default_mb<float>(n0) : tri_default_mb<double>(n0));
     }
+    if (rows && !sparse) {
+        set_error("the register-row tridiagonal kernel takes sparse input only");
+        return KFBI_ENOTSUP;
+    }
     for (int q = 0; q < n; ++q) {
-        const TriShape S = cplx ? (low ? tri_shape<cf>(doms[q], sparse, mb) : tri_shape<cd>(doms[q], sparse, mb))
-                                : (low ? tri_shape<float>(doms[q], sparse, mb) : tri_shape<double>(doms[q], sparse, mb));
+        kfbi_domain *d = doms[q];
+        const TriShape S = cplx ? (low ? tri_shape<cf>(d, sparse, mb, rows) : tri_shape<cd>(d, sparse, mb, rows))
+                                : (low ? tri_shape<float>(d, sparse, mb, rows) : tri_shape<double>(d, sparse, mb, rows));
+        if (rows && !tri_rows_ok(S)) {
+            set_error("no register-row tridiagonal kernel for this shape");
+            return KFBI_ENOTSUP;
+        }
         if (q == 0) {
             out->mb = S.mb;
             out->c = S.c;
+            out->rows = rows;
             out->lds = S.lds_base;
-            out->stage_lds = S.lds_base + S.stage_bytes;
+            out->stage_lds = S.lds_stage;
         } else {
             if (S.mb != out->mb || S.c != out->c) {
                 set_error("batch class members differ in tridiagonal launch shape");
                 return KFBI_EINVAL;
             }
             out->lds = std::max(out->lds, S.lds_base);
-            out->stage_lds = std::max(out->stage_lds, S.lds_base + S.stage_bytes);
+            out->stage_lds = std::max(out->stage_lds, S.lds_stage);
         }
     }
     if (out->c > 32 || out->lds > kTriLdsMax) {
@@ -1558,12 +1844,14 @@ int batch_launch_t(int kind, const void *args, const BlkMap *map, int blocks, in
             break;
         case kBaTri64: {
             TriLaunchBatch<T, T> L{(const TriArgs<T, T> *)args, map, blocks, shape->lds, s};
-            tri_dispatch(shape->mb, shape->c, shape->stage, L);
+            if (shape->rows) tri_rows_dispatch(shape->mb, shape->c, shape->stage, L);
+            else tri_dispatch(shape->mb, shape->c, shape->stage, L);
             break;
         }
         case kBaTri32: {
             TriLaunchBatch<TL, T> L{(const TriArgs<TL, T> *)args, map, blocks, shape->lds, s};
-            tri_dispatch(shape->mb, shape->c, shape->stage, L);
+            if (shape->rows) tri_rows_dispatch(shape->mb, shape->c, shape->stage, L);
+            else tri_dispatch(shape->mb, shape->c, shape->stage, L);
             break;
         }
         case kBaEval:

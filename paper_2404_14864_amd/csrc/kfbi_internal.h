@@ -205,6 +205,11 @@ struct kfbi_domain {
     // {row, first segment, end segment, 0}
     int32_t *seg_desc = nullptr;
     int32_t *row_desc = nullptr;
+    // per interior row t, {first segment, end segment} of the row (equal
+    // for a row without irregular nodes); zero-padded to 64 * c rows, c the
+    // rows per lane of a 64-lane mode group, so a lane may read all of its
+    // rows
+    int32_t *row_span = nullptr;
     int n_seg = 0;
     // the distinct stencil nodes grouped by interior grid row: rows
     // erow_t[r] hold nodes erow_ptr[r] .. erow_ptr[r+1] (column erow_col[j]);
@@ -234,6 +239,7 @@ struct kfbi_domain {
     // and LDS staging of the sparse input (-1: when it fits, 0: never), set by
     // timing at the first solve (the candidates compute the same values)
     int tri_mb = 0, tri_stage = -1;
+    int tri_rows = 0;  // sparse launches: 1 the register-row kernel, 0 the LDS-tile kernel
     bool tri_tuned = false;
 
     // mixed precision (FP32 / complex64 grid solve), allocated on first use
@@ -450,6 +456,7 @@ struct ZeroArgs {
 struct TriSparse {
     const int32_t *irr_col, *row_ptr, *row_order, *seg_q0, *seg_row, *row_seg;
     const int32_t *seg_desc, *row_desc;
+    const int32_t *row_span;  // per interior row {first segment, end segment}
     int nnz, n_act, n_seg;
 };
 
@@ -602,6 +609,7 @@ enum {
 struct BatchTriShape {
     int mb, c;
     bool stage;
+    bool rows;  // the register-row kernel (sparse input only)
     size_t lds, stage_lds;
     int blocks_per;
 };
@@ -610,8 +618,12 @@ size_t batch_args_size(int kind, bool cplx);
 int batch_blocks(const kfbi_domain *d, int kind);
 // mb: modes per workgroup (0: each domain's default); stage_pref: -1 stage
 // the sparse input when it fits, 0 never, 1 always (error if it does not fit)
+// KFBI_TRIDIAG_KERNEL from the environment: 0 "tile", 1 "rows", -1 either
+int tri_kernel_pref();
+// rows: the register-row kernel (sparse input, 64-lane groups of at least 4
+// rows per lane; refused with KFBI_ENOTSUP otherwise)
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb = 0,
-                    int stage_pref = -1);
+                    int stage_pref = -1, bool rows = false);
 int batch_tri_blocks(const kfbi_domain *d, int mb);
 // cplx: the members are complex (complex128, complex64 inner solves)
 int batch_launch(int kind, const void *args, const BlkMap *map, int blocks, int M, const BatchTriShape *shape,

@@ -252,17 +252,17 @@ TUNING_KINDS = ("sparse64", "dense64", "sparse32")
 
 def kfbi_batch_tuning(b):
     """Tridiagonal launch shape per class of equal M and solve kind:
-    dicts {M, kind, modes_per_wg, staged, tuned, us}."""
+    dicts {M, kind, modes_per_wg, staged, tuned, register_rows, us}."""
     n = ctypes.c_int32(0)
     _check(lib().kfbi_batch_tuning(b, 0, None, None, ctypes.byref(n)))
-    rows = (ctypes.c_int32 * (5 * max(n.value, 1)))()
+    rows = (ctypes.c_int32 * (6 * max(n.value, 1)))()
     us = (ctypes.c_double * max(n.value, 1))()
     _check(lib().kfbi_batch_tuning(b, n.value, rows, us, ctypes.byref(n)))
     out = []
     for r in range(n.value):
-        M, kind, mb, st, tuned = rows[5 * r:5 * r + 5]
+        M, kind, mb, st, tuned, reg = rows[6 * r:6 * r + 6]
         out.append({"M": M, "kind": TUNING_KINDS[kind], "modes_per_wg": mb, "staged": bool(st),
-                    "tuned": bool(tuned), "us": us[r] if tuned else None})
+                    "tuned": bool(tuned), "register_rows": bool(reg), "us": us[r] if tuned else None})
     return out
 
 
