@@ -596,6 +596,62 @@ def serving(n_jobs, seed=20240423):
     return out
 
 
+def graph_leg(grids=(256, 1024), n=50):
+    """kfbi_grid_solve_noalloc (three dependent kernels, no allocation) n times
+    back to back on a stream, and the same n calls captured once in a HIP
+    graph and replayed: per-solve time of each, and whether every replay
+    gives the stream's bits."""
+    import torch
+    import workloads as W
+    from paper_2404_14864_amd import kfbi
+    out = {}
+    s = torch.cuda.Stream()
+    for M in grids:
+        h = kfbi.kfbi_domain_create(W.domain_c2_wave(M), kfbi.KFBI_REAL, stream=s.cuda_stream)
+        try:
+            g_rhs = torch.Generator(device="cuda:0")
+            g_rhs.manual_seed(M)
+            rhs = torch.randn((M + 1) ** 2, dtype=torch.float64, device="cuda:0", generator=g_rhs)
+            u = torch.zeros_like(rhs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    kfbi.kfbi_grid_solve_noalloc(h, 7.0, rhs, u)
+                e0.record(s)
+                for _ in range(n):
+                    kfbi.kfbi_grid_solve_noalloc(h, 7.0, rhs, u)
+                e1.record(s)
+            s.synchronize()
+            t_stream = e0.elapsed_time(e1) / n
+            ref = u.clone()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(n):
+                    kfbi.kfbi_grid_solve_noalloc(h, 7.0, rhs, u)
+            s.synchronize()
+            times, same = [], True
+            for _ in range(3):
+                u.zero_()
+                torch.cuda.synchronize()
+                with torch.cuda.stream(s):
+                    e0.record(s)
+                    g.replay()
+                    e1.record(s)
+                s.synchronize()
+                times.append(e0.elapsed_time(e1) / n)
+                same = same and bool(torch.equal(u, ref))
+            del g
+        finally:
+            kfbi.kfbi_domain_destroy(h)
+        out["M=%d" % M] = {"stream_us_per_solve": 1e3 * t_stream, "graph_us_per_solve": 1e3 * min(times),
+                           "graph_replays_bitwise_equal": same}
+        log("graph capture, grid solve M=%d: stream %.2f us, graph replay %.2f us per solve (3 kernels)%s" % (
+            M, 1e3 * t_stream, 1e3 * min(times), "" if same else "; REPLAY DIFFERS"))
+    out["what"] = ("kfbi_grid_solve_noalloc x%d (x-DST, tridiagonal, inverse x-DST) on a stream vs captured in one "
+                   "HIP graph and replayed (best of 3 replays)" % n)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -636,6 +692,7 @@ def main():
 
     batched = batched_helmholtz(args.batch, args.batch_reps) if (args.batch > 0 and not args.no_secondary) else None
     served = serving(args.serve_jobs) if (args.serve_jobs > 0 and not args.no_secondary) else None
+    graph = None if args.no_secondary else graph_leg()
 
     pts = (S.M - 1) ** 2
     w = 16.0  # complex128 bytes per element
@@ -681,6 +738,7 @@ def main():
         "wave": wave,
         "batched": batched,
         "serving": served,
+        "graph_capture": graph,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -304,6 +304,38 @@ constexpr int kCorrWin = 16;
 constexpr int kPf = 2;
 typedef int gi4 __attribute__((ext_vector_type(4)));
 
+// a * b + c and a * b with every fused step written out (nothing left for
+// the compiler to contract), so that each kernel inlining the sweeps below
+// rounds alike whatever surrounds it.  The complex forms take the real part
+// as fma(ar, br, fma(-ai, bi, cr)) and the imaginary part as
+// fma(ar, bi, fma(ai, br, ci)).
+__device__ __forceinline__ double mad_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float mad_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ cd mad_(cd a, cd b, cd c) {
+    return make_cd(__builtin_fma(a.x, b.x, __builtin_fma(-a.y, b.y, c.x)),
+                   __builtin_fma(a.x, b.y, __builtin_fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ cf mad_(cf a, cf b, cf c) {
+    return make_cf(__builtin_fmaf(a.x, b.x, __builtin_fmaf(-a.y, b.y, c.x)),
+                   __builtin_fmaf(a.x, b.y, __builtin_fmaf(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ cd mad_(cd a, double b, cd c) {
+    return make_cd(__builtin_fma(a.x, b, c.x), __builtin_fma(a.y, b, c.y));
+}
+__device__ __forceinline__ cf mad_(cf a, float b, cf c) {
+    return make_cf(__builtin_fmaf(a.x, b, c.x), __builtin_fmaf(a.y, b, c.y));
+}
+__device__ __forceinline__ double mul_(double a, double b) { return a * b; }
+__device__ __forceinline__ float mul_(float a, float b) { return a * b; }
+__device__ __forceinline__ cd mul_(cd a, cd b) {
+    const double p = a.y * b.y, q = a.y * b.x;
+    return make_cd(__builtin_fma(a.x, b.x, -p), __builtin_fma(a.x, b.y, q));
+}
+__device__ __forceinline__ cf mul_(cf a, cf b) {
+    const float p = a.y * b.y, q = a.y * b.x;
+    return make_cf(__builtin_fmaf(a.x, b.x, -p), __builtin_fmaf(a.x, b.y, q));
+}
+
 // Phase A of the sparse solves: the sums over every segment (at most kSegLen
 // irregular nodes of one row) of corr[q] sin(pi i_q k / M) for the MB modes
 // k = k0+1 .. k0+MB, into spart[segment * MB + mode].  Thread i of NT takes
@@ -315,6 +347,7 @@ __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem
                                              int n_seg, int k0, int mask2M, const typename Real<T>::type *S,
                                              const T *sval, const int32_t *scol, const gmem<TC> *__restrict__ corr,
                                              const gmem<int32_t> *__restrict__ irr_col, T *spart) {
+#pragma clang fp contract(off)
     // one segment's sums, descriptor d = {first node, end node, row}
     auto seg_sum = [&](const gi4 d, int sg) {
         int q = d.x;
@@ -335,7 +368,7 @@ __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem
             for (int mm = 0; mm < MB; ++mm) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    acc[mm] += cv[u] * S[idx[u]];
+                    acc[mm] = mad_(cv[u], S[idx[u]], acc[mm]);
                     idx[u] = (idx[u] + col[u]) & mask2M;
                 }
             }
@@ -346,7 +379,7 @@ __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem
             int idx = (col * (k0 + 1)) & mask2M;
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) {
-                acc[mm] += cv * S[idx];
+                acc[mm] = mad_(cv, S[idx], acc[mm]);
                 idx = (idx + col) & mask2M;
             }
         }
@@ -361,64 +394,163 @@ __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem
     for (int sg = threadIdx.x + kPf * NT; sg < n_seg; sg += NT) seg_sum(seg_desc[sg], sg);
 }
 
-// Phase B of the tridiagonal solves for one lane of a LANES-lane mode group:
-// v holds h^2 rho of the lane's C rows t0 .. t0+C-1 on entry and U^ on exit,
-// e their Thomas coefficients (rows past n: v = e = 0).  The forward sweep
+// Cross-lane moves for the scans of phase B, per element type: DPP moves
+// within the wavefront (lanes whose source lies outside the pattern keep
+// `old`) and reads of one lane's value by every lane.
+__device__ __forceinline__ unsigned long long u64_of(double v) { return __builtin_bit_cast(unsigned long long, v); }
+__device__ __forceinline__ double f64_of(unsigned long long u) { return __builtin_bit_cast(double, u); }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const unsigned long long o = u64_of(old), x = u64_of(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)x, CTRL, 0xf, 0xf, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(x >> 32), CTRL, 0xf, 0xf, false);
+    return f64_of(((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const unsigned long long x = u64_of(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return f64_of(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_f32(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+template <class T> struct Xl;
+template <> struct Xl<double> {
+    template <int CTRL> __device__ static double dpp(double old, double v) { return dpp_f64<CTRL>(old, v); }
+    __device__ static double at(double v, int l) { return lane_f64(v, l); }
+};
+template <> struct Xl<float> {
+    template <int CTRL> __device__ static float dpp(float old, float v) { return dpp_f32<CTRL>(old, v); }
+    __device__ static float at(float v, int l) { return lane_f32(v, l); }
+};
+template <> struct Xl<cd> {
+    template <int CTRL> __device__ static cd dpp(cd old, cd v) {
+        return make_cd(dpp_f64<CTRL>(old.x, v.x), dpp_f64<CTRL>(old.y, v.y));
+    }
+    __device__ static cd at(cd v, int l) { return make_cd(lane_f64(v.x, l), lane_f64(v.y, l)); }
+};
+template <> struct Xl<cf> {
+    template <int CTRL> __device__ static cf dpp(cf old, cf v) {
+        return make_cf(dpp_f32<CTRL>(old.x, v.x), dpp_f32<CTRL>(old.y, v.y));
+    }
+    __device__ static cf at(cf v, int l) { return make_cf(lane_f32(v.x, l), lane_f32(v.y, l)); }
+};
+
+// DPP controls (GFX9 encoding): row_shl:k 0x100+k, row_shr:k 0x110+k,
+// wave_shl:1 0x130, wave_shr:1 0x138
+constexpr int kDppRowShl = 0x100, kDppRowShr = 0x110, kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+
+// (A, B) <- (A, B) o (Ap, Bp) with (Ap, Bp) the map of lanes `CTRL` away
+// (identity where there is none): y = A (Ap x + Bp) + B
+template <class T, int CTRL>
+__device__ __forceinline__ void compose_dpp(T &A, T &B) {
+    const T Ap = Xl<T>::template dpp<CTRL>(one<T>(), A);
+    const T Bp = Xl<T>::template dpp<CTRL>(zero<T>(), B);
+    B = mad_(A, Bp, B);
+    A = mul_(A, Ap);
+}
+
+// Phase B of the tridiagonal solves for one lane of a LANES-lane mode group
+// (LANES = 64: the wavefront; 32: each half of it): v holds h^2 rho of the
+// lane's C rows t0 .. t0+C-1 on entry and U^ on exit, e their Thomas
+// coefficients (rows past n: v = e = 0).  The forward sweep
 // x_t = e_t (x_{t-1} - rho_t) and the backward sweep U_t = e_t U_{t+1} + x_t
-// are affine maps composed per lane and then across the group by shuffle
-// scans (Hillis-Steele), each lane finishing its rows from the carried-in
-// value.
+// are affine maps: each lane composes its rows' maps, the lanes' maps are
+// composed in order (within rows of 16 lanes by DPP shifts, then across rows
+// from the rows' totals read from their last / first lane), and each lane
+// finishes its rows from the value carried in.
 template <class T, int LANES, int C>
 __device__ __forceinline__ void thomas_rows(T (&v)[C], const T (&e)[C], int lane, int t0, int n) {
+#pragma clang fp contract(off)
+    static_assert(LANES == 64 || LANES == 32, "mode groups of 32 or 64 lanes");
+    const int row = (threadIdx.x & 63) >> 4;
     T A = one<T>(), B = zero<T>();
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         if (t0 + c < n) {
-            B = e[c] * (B - v[c]);
-            A = e[c] * A;
+            B = mul_(e[c], B - v[c]);
+            A = mul_(e[c], A);
         }
     }
-#pragma unroll
-    for (int off = 1; off < LANES; off <<= 1) {
-        T Ap = Shfl<T>::up(A, off, LANES), Bp = Shfl<T>::up(B, off, LANES);
-        if (lane >= off) {
-            B = A * Bp + B;
-            A = A * Ap;
+    // forward: prefix over the lanes of each row of 16, then the rows before
+    compose_dpp<T, kDppRowShr + 1>(A, B);
+    compose_dpp<T, kDppRowShr + 2>(A, B);
+    compose_dpp<T, kDppRowShr + 4>(A, B);
+    compose_dpp<T, kDppRowShr + 8>(A, B);
+    {
+        const T A0 = Xl<T>::at(A, 15), B0 = Xl<T>::at(B, 15);
+        const T A2 = Xl<T>::at(A, 47), B2 = Xl<T>::at(B, 47);
+        T Ae = one<T>(), Be = zero<T>();
+        if (LANES == 64) {
+            const T A1 = Xl<T>::at(A, 31), B1 = Xl<T>::at(B, 31);
+            const T B01 = mad_(A1, B0, B1), A01 = mul_(A1, A0);
+            const T B012 = mad_(A2, B01, B2), A012 = mul_(A2, A01);
+            if (row == 1) { Ae = A0; Be = B0; }
+            if (row == 2) { Ae = A01; Be = B01; }
+            if (row == 3) { Ae = A012; Be = B012; }
+        } else {
+            if (row == 1) { Ae = A0; Be = B0; }
+            if (row == 3) { Ae = A2; Be = B2; }
         }
+        B = mad_(A, Be, B);
     }
-    T x = Shfl<T>::up(B, 1, LANES);
+    T x = Xl<T>::template dpp<kDppWaveShr1>(zero<T>(), B);
     if (lane == 0) x = zero<T>();
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        x = e[c] * (x - v[c]);
+        x = mul_(e[c], x - v[c]);
         v[c] = x;
     }
     A = one<T>();
     B = zero<T>();
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
-        B = e[c] * B + v[c];
-        A = e[c] * A;
+        B = mad_(e[c], B, v[c]);
+        A = mul_(e[c], A);
     }
-#pragma unroll
-    for (int off = 1; off < LANES; off <<= 1) {
-        T Ap = Shfl<T>::down(A, off, LANES), Bp = Shfl<T>::down(B, off, LANES);
-        if (lane + off < LANES) {
-            B = A * Bp + B;
-            A = A * Ap;
+    // backward: suffix over the lanes of each row, then the rows after
+    compose_dpp<T, kDppRowShl + 1>(A, B);
+    compose_dpp<T, kDppRowShl + 2>(A, B);
+    compose_dpp<T, kDppRowShl + 4>(A, B);
+    compose_dpp<T, kDppRowShl + 8>(A, B);
+    {
+        const T A1 = Xl<T>::at(A, 16), B1 = Xl<T>::at(B, 16);
+        const T A3 = Xl<T>::at(A, 48), B3 = Xl<T>::at(B, 48);
+        T Ae = one<T>(), Be = zero<T>();
+        if (LANES == 64) {
+            const T A2 = Xl<T>::at(A, 32), B2 = Xl<T>::at(B, 32);
+            const T B23 = mad_(A2, B3, B2), A23 = mul_(A2, A3);
+            const T B123 = mad_(A1, B23, B1);
+            if (row == 2) { Ae = A3; Be = B3; }
+            if (row == 1) { Ae = A23; Be = B23; }
+            if (row == 0) { Be = B123; Ae = mul_(A1, A23); }
+        } else {
+            if (row == 0) { Ae = A1; Be = B1; }
+            if (row == 2) { Ae = A3; Be = B3; }
         }
+        B = mad_(A, Be, B);
     }
-    T y = Shfl<T>::down(B, 1, LANES);
+    T y = Xl<T>::template dpp<kDppWaveShl1>(zero<T>(), B);
     if (lane == LANES - 1) y = zero<T>();
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
-        y = e[c] * y + v[c];
+        y = mad_(e[c], y, v[c]);
         v[c] = y;
     }
 }
 
 template <class T, class TC, int MB, int LANES, int C, bool STAGE>
 __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
+#pragma clang fp contract(off)
     typedef typename Real<T>::type R;
     const int M = A.M;
     const double h2 = A.h2;
@@ -599,6 +731,7 @@ typedef int gi2 __attribute__((ext_vector_type(2)));
 
 template <class T, class TC, int MB, int C, bool STAGE>
 __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
+#pragma clang fp contract(off)
     typedef typename Real<T>::type R;
     constexpr int LANES = 64, NT = MB * LANES;
     constexpr int CH = RowsOut<C>::CH;
@@ -691,13 +824,17 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
     // phase B: the lane's rows from the partial sums (0 + the row's segments
     // in order, as the tile kernel's zeroed tile plus its row merge), then
     // the scans
-    T v[C];
+    // every row's first partial sum read at once (clamped: a row without
+    // nodes reads a valid entry and ignores it), later segments after
+    T v[C], first[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) first[c] = spart[min(rsp[c].x, n_seg - 1) * MB + m];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         T acc = zero<T>();
         const int s0 = rsp[c].x, s1 = rsp[c].y;
         if (s0 < s1) {
-            T a = spart[s0 * MB + m];
+            T a = first[c];
             for (int sg = s0 + 1; sg < s1; ++sg) a += spart[sg * MB + m];
             acc += a;
         }
