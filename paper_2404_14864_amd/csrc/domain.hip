@@ -365,7 +365,8 @@ __global__ void k_colloc(CurveParams c, double L, double h, int M, int Nb, const
 
 __global__ void k_tables(int M, double *sine, double *twiddle, double *scu) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < 2 * M) sine[m] = sinpi((double)m / (double)M);
+    // a period and its first quarter again (2M + M/2 entries)
+    if (m < 2 * M + M / 2) sine[m] = sinpi((double)(m & (2 * M - 1)) / (double)M);
     if (m < max(1, M / 32)) {  // the same values as the table at 64 m and 64 m + M/2
         const int q = (64 * m) & (2 * M - 1), qc = (64 * m + M / 2) & (2 * M - 1);
         scu[2 * m] = sinpi((double)q / (double)M);
@@ -549,10 +550,10 @@ int build_domain(kfbi_domain *d) {
     k_colloc<<<(Nb + 127) / 128, 128, 0, s>>>(c, L, h, M, Nb, d->flags, d->col, d->st, err + 1);
     KFBI_CHECK_LAUNCH();
 
-    KFBI_TRY(dalloc(d, (void **)&d->sine, 2 * (size_t)M * sizeof(double)));
+    KFBI_TRY(dalloc(d, (void **)&d->sine, (2 * (size_t)M + M / 2) * sizeof(double)));
     KFBI_TRY(dalloc(d, (void **)&d->scu, 2 * (size_t)std::max(1, M / 32) * sizeof(double)));
     KFBI_TRY(dalloc(d, (void **)&d->twiddle, 2 * (size_t)M * sizeof(double)));
-    k_tables<<<(2 * M + 255) / 256, 256, 0, s>>>(M, d->sine, d->twiddle, d->scu);
+    k_tables<<<(2 * M + M / 2 + 255) / 256, 256, 0, s>>>(M, d->sine, d->twiddle, d->scu);
     KFBI_CHECK_LAUNCH();
 
     // inside-node count (host, from the flags; setup only)

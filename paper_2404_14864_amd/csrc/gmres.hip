@@ -78,54 +78,6 @@ constexpr size_t kGmIterLds = 131072;
 constexpr size_t kGmSlotLds = 147456;
 
 
-// Cross-lane exchanges of the wavefront reductions on the VALU (gfx950),
-// not through the LDS unit: the partner of lane l differs from l in bit B,
-// and for the row mirrors also in lower bits, which the later levels of a
-// reduction cover anyway.
-//   B = 5, 4: permlane32 / permlane16 swaps (l ^ 32, l ^ 16);
-//   B = 3, 2: row mirror (i -> 15 - i in each row of 16), half-row mirror
-//             (i -> 7 - i in each half row);
-//   B = 1, 0: quad permutations (l ^ 2, l ^ 1).
-template <int B>
-__device__ __forceinline__ unsigned xl32(unsigned u) {
-    const int lane = threadIdx.x & 63;
-    if constexpr (B == 5) {
-        const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-        return lane < 32 ? r[1] : r[0];
-    } else if constexpr (B == 4) {
-        const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-        return (lane & 16) ? r[0] : r[1];
-    } else if constexpr (B == 3) {
-        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x140, 0xf, 0xf, false);
-    } else if constexpr (B == 2) {
-        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x141, 0xf, 0xf, false);
-    } else if constexpr (B == 1) {
-        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x4E, 0xf, 0xf, false);
-    } else {
-        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xf, 0xf, false);
-    }
-}
-template <int B>
-__device__ __forceinline__ double xl(double v) {
-    return __hiloint2double((int)xl32<B>((unsigned)__double2hiint(v)), (int)xl32<B>((unsigned)__double2loint(v)));
-}
-template <int B>
-__device__ __forceinline__ cd xl(cd v) {
-    return make_cd(xl<B>(v.x), xl<B>(v.y));
-}
-
-// sum over the wavefront, in every lane (all 64 lanes active)
-template <class T>
-__device__ inline T wave_sum(T v) {
-    v += xl<5>(v);
-    v += xl<4>(v);
-    v += xl<3>(v);
-    v += xl<2>(v);
-    v += xl<1>(v);
-    v += xl<0>(v);
-    return v;
-}
-
 // sixteen wavefront sums at once by a butterfly that halves the values per
 // lane at each exchange (8 + 4 + 2 + 1 + 2 exchanges instead of 16 x 6):
 // lane l returns the total of v[(l >> 2) & 15]
@@ -918,10 +870,11 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     // flight before the first use.
     const bool staged = j + 1 <= nst;
     for (int pass = 0; pass < 2; ++pass) {
-        // the second pass also forms ||w'||^2 (slot j + 1 of its reduction),
-        // from which the norm of the result follows without a reduction of
-        // its own
-        const int jn = pass == 1 ? j + 1 : j;
+        // each pass also forms the squared norm of its input (slot j + 1 of
+        // its reduction): the first decides whether a second pass is needed,
+        // the last gives the norm of the result without a reduction of its
+        // own
+        const int jn = j + 1;
         // the products in chunks of 4, 8 or 16 (the fewest that cover the
         // jn + 1 terms, so that few lanes of the reduction carry zeros)
         auto chunk = [&](auto kk, int i0) {
@@ -1021,12 +974,22 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
                 }
             }
         }
+        // the second pass (Daniel, Gragg, Kaufman and Stewart's criterion)
+        // only when the first removed more than half of ||w||^2, i.e. when
+        // ||w'|| = sqrt(||w||^2 - sum |h_i|^2) <= ||w|| / sqrt(2): otherwise
+        // w' is orthogonal to the basis to working precision already.  The
+        // values are in LDS, so every thread takes the same branch.
+        if (pass == 0) {
+            double r2 = snrm;
+            for (int i = 0; i <= j; ++i) r2 -= abs2(hs[i]);
+            if (r2 > 0.5 * snrm) break;
+        }
     }
-    // ||w''||^2 = ||w'||^2 - sum |h2_i|^2 (w'' = w' - sum h2_i v_i, the v_i
-    // orthonormal).  The second pass removes only a rounding-size part of w'
-    // unless w' lay almost in the span; then (half of ||w'||^2 or more
-    // removed) the norm is summed directly.  Every thread forms the same
-    // value from LDS, so the branch is uniform.
+    // The result's norm from the last pass: ||out||^2 = ||in||^2 - sum |h_i|^2
+    // (out = in - sum h_i v_i, the v_i orthonormal), unless that pass
+    // removed half of ||in||^2 or more (only possible after a second pass
+    // when w' lay almost in the span); then it is summed directly.  Every
+    // thread forms the same value from LDS, so the branch is uniform.
     double hn2 = snrm;
     for (int i = 0; i <= j; ++i) hn2 -= abs2(hs[i]);
     double hn;

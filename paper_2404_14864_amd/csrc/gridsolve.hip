@@ -937,8 +937,7 @@ __device__ void eval_nodes_body(const EvalArgs<T, TO> &A, int blk) {
     int i = node % (M + 1), j = node / (M + 1);
     const T *row = uhat + (size_t)(j - 1) * n;
     T acc = mode_sum<0, T>(gview(sine), cview(A.scu), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+    acc = wave_sum(acc);
     if (lane == 0) out[p] = to_high(acc * (R)(2.0 / M));
 }
 
@@ -981,7 +980,9 @@ __global__ __launch_bounds__(64) void k_corr_phi(CorrPhiArgs<TC> A) {
 // U+(z_k) = sum_p w6[k][p] U_p + sum_o bop[k][o] phi[k-2+o] in FP64 (the
 // compact form of the six-point rule with the jump terms of the outside
 // nodes, eq. 3.36).
-template <class T, class TO>
+// KR > 0: M = 64 KR, the row's modes loaded into registers at once (the
+// same sums as KR = 0, which loops over the modes)
+template <class T, class TO, int KR>
 __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     typedef typename Real<T>::type R;
     const int M = A.M, Nb = A.Nb, node_stride = A.node_stride;
@@ -1000,9 +1001,21 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     const int node = __builtin_amdgcn_readfirstlane(nodes[(size_t)k * node_stride + p]);
     const int i = node % (M + 1);
     const T *row = uhat + (size_t)(node / (M + 1) - 1) * n;
-    T acc = mode_sum<0, T>(gview(sine), cview(A.scu), M, n, i, lane, [&](int q) { return gld(gview(row) + lane + 64 * q); });
+    T acc;
+    if constexpr (KR > 0) {
+        T v[KR];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+        for (int j = 0; j < KR; ++j) {
+            const int q = lane + 64 * j;
+            const T x = gld(gview(row) + min(q, n - 1));
+            v[j] = q < n ? x : zero<T>();
+        }
+        acc = mode_sum<KR, T>(gview(sine), cview(A.scu), M, n, i, lane, [&](int jj) { return v[jj]; });
+    } else {
+        acc = mode_sum<0, T>(gview(sine), cview(A.scu), M, n, i, lane,
+                             [&](int q) { return gld(gview(row) + lane + 64 * q); });
+    }
+    acc = wave_sum(acc);
     if (lane == 0) su[p] = to_high(acc * (R)(2.0 / M));
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1019,10 +1032,34 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     }
 }
 
-template <class T, class TO>
+template <class T, class TO, int KR>
 __global__ __launch_bounds__(384) void k_eval_extract(EvxArgs<T, TO> A) {
-    eval_extract_body(A, blockIdx.x);
+    eval_extract_body<T, TO, KR>(A, blockIdx.x);
 }
+
+// the register-row form of the evaluation for M = 64 .. 1024, the loop above
+template <class F>
+void evx_dispatch(int M, const F &f) {
+    switch (M) {
+        case 64: f.template go<1>(); break;
+        case 128: f.template go<2>(); break;
+        case 256: f.template go<4>(); break;
+        case 512: f.template go<8>(); break;
+        case 1024: f.template go<16>(); break;
+        default: f.template go<0>(); break;
+    }
+}
+
+template <class T, class TO>
+struct EvxLaunch {
+    EvxArgs<T, TO> A;
+    int blocks;
+    hipStream_t s;
+    template <int KR>
+    void go() const {
+        k_eval_extract<T, TO, KR><<<blocks, 384, 0, s>>>(A);
+    }
+};
 
 // Grid values at the stencil nodes by rows: U = (2/M) sum_k U^[t][k]
 // sin(pi i k / M) at each distinct stencil node (t, i), in the same sum and
@@ -1098,8 +1135,7 @@ __device__ void eval_rows_body(const ErowArgs<T, TO> &A, int blk) {
             // uniform over the wavefront: scalar index arithmetic
             const int i = __builtin_amdgcn_readfirstlane(scol[c - P0]);
             T acc = mode_sum<KR, T>(S, scu, M, n, i, lane, [&](int jj) { return v[jj]; });
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc += Shfl<T>::xr(acc, off);
+            acc = wave_sum(acc);
             // every lane holds the sum: all write the same value
             gst(ust + c, to_high(acc * scale));
         }
@@ -1593,7 +1629,8 @@ int ensure_coefficients(kfbi_domain *d, double kre, double kim) {
 namespace {
 __global__ void k_sine32(int M, float *s, float *scu) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < 2 * M) s[m] = (float)sinpi((double)m / (double)M);
+    // a period and its first quarter again (2M + M/2 entries)
+    if (m < 2 * M + M / 2) s[m] = (float)sinpi((double)(m & (2 * M - 1)) / (double)M);
     if (m < max(1, M / 32)) {
         const int q = (64 * m) & (2 * M - 1), qc = (64 * m + M / 2) & (2 * M - 1);
         scu[2 * m] = (float)sinpi((double)q / (double)M);
@@ -1605,7 +1642,7 @@ __global__ void k_sine32(int M, float *s, float *scu) {
 size_t low_tables_bytes_pending(const kfbi_domain *d) {
     if (d->uhat32) return 0;
     const size_t M = (size_t)d->M, n = M - 1, ls = d->cplx ? sizeof(cf) : sizeof(float);
-    return 2 * n * n * ls + n * ls + n * sizeof(int32_t) + 2 * M * sizeof(float) +
+    return 2 * n * n * ls + n * ls + n * sizeof(int32_t) + (2 * M + M / 2) * sizeof(float) +
            2 * (size_t)std::max(1, d->M / 32) * sizeof(float);
 }
 
@@ -1620,9 +1657,9 @@ int ensure_coefficients_low(kfbi_domain *d, double kre, double kim) {
         KFBI_TRY(dalloc(d, &d->etab32, (size_t)n * n * ls));
         KFBI_TRY(dalloc(d, &d->elim32, (size_t)n * ls));
         KFBI_TRY(dalloc(d, (void **)&d->tconv32, (size_t)n * sizeof(int32_t)));
-        KFBI_TRY(dalloc(d, (void **)&d->sine32, (size_t)2 * M * sizeof(float)));
+        KFBI_TRY(dalloc(d, (void **)&d->sine32, (size_t)(2 * M + M / 2) * sizeof(float)));
         KFBI_TRY(dalloc(d, (void **)&d->scu32, (size_t)2 * std::max(1, M / 32) * sizeof(float)));
-        k_sine32<<<(2 * M + 255) / 256, 256, 0, d->stream>>>(M, d->sine32, d->scu32);
+        k_sine32<<<(2 * M + M / 2 + 255) / 256, 256, 0, d->stream>>>(M, d->sine32, d->scu32);
         KFBI_CHECK_LAUNCH();
     }
     const double h2 = d->h * d->h;
@@ -1710,15 +1747,15 @@ int eval_extract_ctl(kfbi_domain *d, const void *uhat, const void *phi, void *kv
     const int Nb = d->Nb;
     const int ps = prof_begin(d);
     if (d->cplx) {
-        if (low) k_eval_extract<cf, cd><<<Nb, 384, 0, d->stream>>>(evx_args<cf, cd>(d, uhat, phi, kv_out, done));
-        else k_eval_extract<cd, cd><<<Nb, 384, 0, d->stream>>>(evx_args<cd, cd>(d, uhat, phi, kv_out, done));
+        if (low) evx_dispatch(d->M, EvxLaunch<cf, cd>{evx_args<cf, cd>(d, uhat, phi, kv_out, done), Nb, d->stream});
+        else evx_dispatch(d->M, EvxLaunch<cd, cd>{evx_args<cd, cd>(d, uhat, phi, kv_out, done), Nb, d->stream});
     } else {
         if (low)
-            k_eval_extract<float, double><<<Nb, 384, 0, d->stream>>>(
-                evx_args<float, double>(d, uhat, phi, kv_out, done));
+            evx_dispatch(d->M, EvxLaunch<float, double>{evx_args<float, double>(d, uhat, phi, kv_out, done), Nb,
+                                                        d->stream});
         else
-            k_eval_extract<double, double><<<Nb, 384, 0, d->stream>>>(
-                evx_args<double, double>(d, uhat, phi, kv_out, done));
+            evx_dispatch(d->M, EvxLaunch<double, double>{evx_args<double, double>(d, uhat, phi, kv_out, done), Nb,
+                                                         d->stream});
     }
     KFBI_CHECK_LAUNCH();
     const double es = low ? elem_size(d) / 2.0 : elem_size(d), eo = elem_size(d);
@@ -1776,7 +1813,7 @@ template <class T, class TO>
 __global__ __launch_bounds__(384) void kb_eval_extract(const EvxArgs<T, TO> *__restrict__ A,
                                                        const BlkMap *__restrict__ map) {
     const BlkMap e = map[blockIdx.x];
-    eval_extract_body(A[e.inst], e.local);
+    eval_extract_body<T, TO, 0>(A[e.inst], e.local);  // members of any M
 }
 template <class TC>
 __global__ __launch_bounds__(64) void kb_corr_phi(const CorrPhiArgs<TC> *__restrict__ A,

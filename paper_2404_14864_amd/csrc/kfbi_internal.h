@@ -56,6 +56,64 @@ __host__ __device__ inline cf operator*(cf a, double s) { return make_cf((float)
 __host__ __device__ inline cf &operator+=(cf &a, cf b) { a.x += b.x; a.y += b.y; return a; }
 __host__ __device__ inline cf &operator-=(cf &a, cf b) { a.x -= b.x; a.y -= b.y; return a; }
 
+// Cross-lane exchanges of the wavefront reductions on the VALU (gfx950),
+// not through the LDS unit: the partner of lane l differs from l in bit B,
+// and for the row mirrors also in lower bits, which the later levels of a
+// reduction cover anyway.
+//   B = 5, 4: permlane32 / permlane16 swaps (l ^ 32, l ^ 16);
+//   B = 3, 2: row mirror (i -> 15 - i in each row of 16), half-row mirror
+//             (i -> 7 - i in each half row);
+//   B = 1, 0: quad permutations (l ^ 2, l ^ 1).
+template <int B>
+__device__ __forceinline__ unsigned xl32(unsigned u) {
+    const int lane = threadIdx.x & 63;
+    if constexpr (B == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return lane < 32 ? r[1] : r[0];
+    } else if constexpr (B == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else if constexpr (B == 3) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x140, 0xf, 0xf, false);
+    } else if constexpr (B == 2) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x141, 0xf, 0xf, false);
+    } else if constexpr (B == 1) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0x4E, 0xf, 0xf, false);
+    } else {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, 0xB1, 0xf, 0xf, false);
+    }
+}
+template <int B>
+__device__ __forceinline__ double xl(double v) {
+    return __hiloint2double((int)xl32<B>((unsigned)__double2hiint(v)), (int)xl32<B>((unsigned)__double2loint(v)));
+}
+template <int B>
+__device__ __forceinline__ float xl(float v) {
+    return __uint_as_float(xl32<B>(__float_as_uint(v)));
+}
+template <int B>
+__device__ __forceinline__ cd xl(cd v) {
+    return make_cd(xl<B>(v.x), xl<B>(v.y));
+}
+template <int B>
+__device__ __forceinline__ cf xl(cf v) {
+    return make_cf(xl<B>(v.x), xl<B>(v.y));
+}
+
+// sum over the wavefront, in every lane, the same bits in every lane (each
+// exchange pairs two lanes that add the same two values; all 64 lanes
+// active)
+template <class T>
+__device__ inline T wave_sum(T v) {
+    v += xl<5>(v);
+    v += xl<4>(v);
+    v += xl<3>(v);
+    v += xl<2>(v);
+    v += xl<1>(v);
+    v += xl<0>(v);
+    return v;
+}
+
 // element type conversions between the FP64 path and the FP32 grid solve
 __host__ __device__ inline float to_low(double a) { return (float)a; }
 __host__ __device__ inline cf to_low(cd a) { return make_cf((float)a.x, (float)a.y); }
@@ -220,7 +278,7 @@ struct kfbi_domain {
     int erow_blk_max = 0;  // most nodes in kErowRows consecutive rows
     kfbi::Colloc *col = nullptr;        // Nb
     kfbi::Stencil *st = nullptr;        // Nb
-    double *sine = nullptr;             // 2M: sin(pi m / M)
+    double *sine = nullptr;             // 2M + M/2: sin(pi m / M), m mod 2M
     // the sine table at the angles 64 m (sin, cos pairs): a mode sum's
     // uniform step angles, m < max(1, M / 32)
     double *scu = nullptr;
