@@ -370,18 +370,19 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
  * five-point system, section 3.4) per class of members with equal M.  The
  * first kfbi_batch_helmholtz of each precision (unless KFBI_BATCH_NO_TUNE)
  * times, on the members' own tables, every shape that computes the same
- * values (1, 2 or 4 sine modes per 256-, 128- or 64-lane workgroup; the
- * sparse input staged in LDS or read from HBM; for sparse input, the right-
- * hand side and solution held in an LDS tile or in registers) and keeps the
- * fastest.  Writes min(cap, rows) rows of 6 int32 {M, kind (0: sparse FP64,
+ * values (1, 2 or 4 sine modes per 64-, 128- or 256-lane workgroup, and 8
+ * per 512 lanes in the register-row kernel; the sparse input staged in LDS
+ * or read from HBM; for sparse input, the right-hand side and solution held
+ * in an LDS tile or in registers) and keeps the fastest.  Writes min(cap, rows) rows of 6 int32 {M, kind (0: sparse FP64,
  * 1: with dense input FP64, 2: sparse FP32), modes per workgroup, staged,
  * tuned, register rows} to rows (may be NULL when cap is 0), the time of the
  * kept shape in microseconds per launch of the class (or -1 when untuned) to
  * us (may be NULL), and the row count to n_rows.  Errors: KFBI_EINVAL.
  * The environment variable KFBI_TRIDIAG_KERNEL = "tile" or "rows", when set,
  * limits this timing and that of single domains (at a domain's first solve)
- * to the LDS-tile or the register-row kernel (for tests and diagnosis; the
- * values are the same). */
+ * to the LDS-tile or the register-row kernel, and "tile:<mb>" / "rows:<mb>"
+ * also to mb modes per workgroup (for tests and diagnosis; the values are
+ * the same). */
 int kfbi_batch_tuning(const kfbi_batch *b, int32_t cap, int32_t *rows, double *us, int32_t *n_rows);
 
 /* Per-kernel device timing (instrumentation for benchmarks).  When enabled,

@@ -2085,7 +2085,9 @@ int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) 
             const int pref = tri_kernel_pref();
             for (int rows = 0; rows < (kind == 1 ? 1 : 2); ++rows) {
                 if (kind != 1 && pref >= 0 && rows != pref) continue;
-                for (int mb : {1, 2, 4}) {
+                for (int mb : {1, 2, 4, 8}) {
+                    if (mb == 8 && !rows) continue;  // 32-lane groups: other values
+                    if (tri_mb_pref() > 0 && mb != tri_mb_pref()) continue;
                     for (int stage : {0, 1}) {
                         BatchTriShape S;
                         if (batch_tri_shape(cd.data(), (int)cd.size(), true, low, &S, mb, stage, rows != 0) != KFBI_OK)

@@ -1335,7 +1335,7 @@ TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0, bool row
     int mb = mb_force > 0 ? mb_force : d->tri_mb;
     if (mb <= 0) mb = tri_default_mb<T>(n);
     S.mb = mb;
-    S.lanes = mb == 8 ? 32 : 64;
+    S.lanes = (mb == 8 && !rows) ? 32 : 64;
     S.c = 1;
     while (S.lanes * S.c < n) S.c <<= 1;
     S.blocks = (n + mb - 1) / mb;
@@ -1356,7 +1356,7 @@ TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0, bool row
 }
 
 // whether the register-row kernel has an instantiation for this shape
-inline bool tri_rows_ok(const TriShape &S) { return S.mb <= 4 && S.lanes == 64 && S.c >= 4 && S.c <= 32; }
+inline bool tri_rows_ok(const TriShape &S) { return S.mb <= 8 && S.lanes == 64 && S.c >= 4 && S.c <= 32; }
 
 }  // namespace
 
@@ -1367,9 +1367,17 @@ inline bool tri_rows_ok(const TriShape &S) { return S.mb <= 4 && S.lanes == 64 &
 int tri_kernel_pref() {
     const char *v = std::getenv("KFBI_TRIDIAG_KERNEL");
     if (!v) return -1;
-    if (std::strcmp(v, "tile") == 0) return 0;
-    if (std::strcmp(v, "rows") == 0) return 1;
+    if (std::strncmp(v, "tile", 4) == 0) return 0;
+    if (std::strncmp(v, "rows", 4) == 0) return 1;
     return -1;
+}
+
+// "tile:<mb>" / "rows:<mb>" also fix the modes per workgroup; 0 when not
+int tri_mb_pref() {
+    const char *v = std::getenv("KFBI_TRIDIAG_KERNEL");
+    if (!v || std::strlen(v) < 6 || v[4] != ':') return 0;
+    const int mb = std::atoi(v + 5);
+    return (mb == 1 || mb == 2 || mb == 4 || mb == 8) ? mb : 0;
 }
 
 namespace {
@@ -1480,7 +1488,7 @@ void tri_dispatch(int mb, int c, bool stage, const F &f) {
 #undef KFBI_TRI
 }
 
-// the register-row kernel: mb in {1, 2, 4}, c in {4, ..., 32} (tri_rows_ok)
+// the register-row kernel: mb in {1, 2, 4, 8}, c in {4, ..., 32} (tri_rows_ok)
 template <class F>
 void tri_rows_dispatch(int mb, int c, bool stage, const F &f) {
 #define KFBI_TRR(MBv, CC)                                   \
@@ -1496,6 +1504,7 @@ void tri_rows_dispatch(int mb, int c, bool stage, const F &f) {
         default: KFBI_TRR(MBv, 32); break;    \
     }
     switch (mb) {
+        case 8: KFBI_TRR_C(8); break;
         case 4: KFBI_TRR_C(4); break;
         case 2: KFBI_TRR_C(2); break;
         default: KFBI_TRR_C(1); break;
@@ -1515,9 +1524,14 @@ template <class T>
 int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uhat, const int *done) {
     typedef typename High<T>::type TC;
     const int n = d->M - 1;
-    // sparse input: the row kernel when timing chose it
-    TriShape S = tri_shape<T>(d, corr != nullptr, 0, corr && !rhat && d->tri_rows);
-    if (S.rows && !tri_rows_ok(S)) S = tri_shape<T>(d, corr != nullptr);
+    // sparse input: the row kernel when timing chose it.  Dense input runs
+    // the tile kernel, at the timed modes per workgroup unless those are 8
+    // (a row-kernel choice: the tile kernel's 8-mode shape has 32-lane groups
+    // and other values), then at its default
+    const bool rows = corr && !rhat && d->tri_rows;
+    const int mb_tile = (d->tri_rows && d->tri_mb == 8) ? tri_default_mb<T>(n) : 0;
+    TriShape S = tri_shape<T>(d, corr != nullptr, rows ? 0 : mb_tile, rows);
+    if (S.rows && !tri_rows_ok(S)) S = tri_shape<T>(d, corr != nullptr, mb_tile);
     if (S.c > 32 || S.lds > kTriLdsMax) {
         set_error("grid too large for the tridiagonal kernel");
         return KFBI_ENOTSUP;
@@ -1565,7 +1579,9 @@ int tune_tridiag_t(kfbi_domain *d) {
     const int pref = tri_kernel_pref();
     for (int rows : {0, 1}) {
         if (pref >= 0 && rows != pref) continue;
-        for (int mb : {1, 2, 4}) {
+        for (int mb : {1, 2, 4, 8}) {
+            if (mb == 8 && !rows) continue;  // the tile kernel's 8-mode shape has 32-lane groups
+            if (tri_mb_pref() > 0 && mb != tri_mb_pref()) continue;
             const TriShape S = tri_shape<T>(d, true, mb, rows != 0);
             if (S.c > 32 || S.lds > kTriLdsMax || (rows && !tri_rows_ok(S))) continue;
             for (int stage : {0, 1}) {

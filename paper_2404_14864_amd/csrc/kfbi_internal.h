@@ -678,6 +678,8 @@ int batch_blocks(const kfbi_domain *d, int kind);
 // the sparse input when it fits, 0 never, 1 always (error if it does not fit)
 // KFBI_TRIDIAG_KERNEL from the environment: 0 "tile", 1 "rows", -1 either
 int tri_kernel_pref();
+// KFBI_TRIDIAG_KERNEL "tile:<mb>" / "rows:<mb>": the modes per workgroup, 0 when not fixed
+int tri_mb_pref();
 // rows: the register-row kernel (sparse input, 64-lane groups of at least 4
 // rows per lane; refused with KFBI_ENOTSUP otherwise)
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb = 0,

@@ -101,6 +101,20 @@ def test_single_solve_same_bits_with_either_kernel(name, desc, cplx, kappa, prec
     assert np.array_equal(pt, pr)
 
 
+def test_eight_mode_row_choice_leaves_dense_launches_valid():
+    """The register-row kernel timed at 8 modes per workgroup (512 lanes) on
+    a 2048 grid: the dense-input launches of the b-solve and the final solve
+    run the tile kernel at its own default shape, and the solve gives the
+    tile kernel's bits."""
+    desc = W.domain_c2_wave(2048)
+    opts = {"fixed_iters": 6}
+    ut, pt, _ = _solve(desc, False, 40.0, "tile", 5, **opts)
+    ur, pr, _ = _solve(desc, False, 40.0, "rows:8", 5, **opts)
+    assert np.all(np.isfinite(ut))
+    assert np.array_equal(ut, ur)
+    assert np.array_equal(pt, pr)
+
+
 def test_batch_same_bits_with_either_kernel():
     descs = [W.domain_c4_instance(q, grids=(256, 512, 1024))[0] for q in range(6)]
     runs = {}
