@@ -43,10 +43,18 @@ HBM_PEAK_GBS = 8000.0
 # by the same counters on a device copy of known size; the commands and
 # counts are in profiles/*_hbm_traffic.md.  Kernels not listed (or changed
 # since they were counted) report null.
-TRAFFIC = {}
+TRAFFIC = {
+    # Schroedinger 1024, complex128: 18.41 MB per sparse launch, 36.08 MB per
+    # dense launch, weighted 80 / 20 like the algorithmic bytes of the profiled
+    # steps (profiles/tridiag_schrodinger1024_c128_hbm_traffic.md)
+    "k_tridiag / k_tridiag_rows": 21945868.0,
+}
 # the kernel each profile label belongs to: the two tridiagonal labels are
-# one kernel launched from one site (sparse or dense right-hand side)
-KERNEL_OF = {"tridiag_sparse": "k_tridiag", "tridiag_dense": "k_tridiag", "dst": "k_dst_rows",
+# the y-direction solves launched from one site (sparse or dense right-hand
+# side); a sparse launch runs the LDS-tile or the register-row kernel, as the
+# domain's launch-shape timing chose, a dense one the tile kernel
+KTRI = "k_tridiag / k_tridiag_rows"
+KERNEL_OF = {"tridiag_sparse": KTRI, "tridiag_dense": KTRI, "dst": "k_dst_rows",
              "idst": "k_dst_rows", "eval_nodes": "k_eval_extract / k_eval_nodes",
              "corrections": "k_corr_phi / k_corrections", "extract": "k_extract", "arnoldi": "k_gm_slot"}
 REPLAYABLE = ("tridiag_sparse", "tridiag_dense", "eval_nodes", "corrections", "arnoldi")
