@@ -385,12 +385,12 @@ __device__ inline T extract_k(int k, int Nb, const T *__restrict__ ust, const do
                               const T *__restrict__ bop, const T *__restrict__ phi) {
     T acc = zero<T>();
 #pragma unroll
-    for (int p = 0; p < 6; ++p) acc += ust[6 * k + p] * w6[6 * k + p];
+    for (int p = 0; p < 6; ++p) acc = mad_(ust[6 * k + p], w6[6 * k + p], acc);
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
         int idx = k - 2 + o;
         idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
-        acc += bop[5 * k + o] * phi[idx];
+        acc = mad_(bop[5 * k + o], phi[idx], acc);
     }
     return acc;
 }

@@ -304,38 +304,6 @@ constexpr int kCorrWin = 16;
 constexpr int kPf = 2;
 typedef int gi4 __attribute__((ext_vector_type(4)));
 
-// a * b + c and a * b with every fused step written out (nothing left for
-// the compiler to contract), so that each kernel inlining the sweeps below
-// rounds alike whatever surrounds it.  The complex forms take the real part
-// as fma(ar, br, fma(-ai, bi, cr)) and the imaginary part as
-// fma(ar, bi, fma(ai, br, ci)).
-__device__ __forceinline__ double mad_(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float mad_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ cd mad_(cd a, cd b, cd c) {
-    return make_cd(__builtin_fma(a.x, b.x, __builtin_fma(-a.y, b.y, c.x)),
-                   __builtin_fma(a.x, b.y, __builtin_fma(a.y, b.x, c.y)));
-}
-__device__ __forceinline__ cf mad_(cf a, cf b, cf c) {
-    return make_cf(__builtin_fmaf(a.x, b.x, __builtin_fmaf(-a.y, b.y, c.x)),
-                   __builtin_fmaf(a.x, b.y, __builtin_fmaf(a.y, b.x, c.y)));
-}
-__device__ __forceinline__ cd mad_(cd a, double b, cd c) {
-    return make_cd(__builtin_fma(a.x, b, c.x), __builtin_fma(a.y, b, c.y));
-}
-__device__ __forceinline__ cf mad_(cf a, float b, cf c) {
-    return make_cf(__builtin_fmaf(a.x, b, c.x), __builtin_fmaf(a.y, b, c.y));
-}
-__device__ __forceinline__ double mul_(double a, double b) { return a * b; }
-__device__ __forceinline__ float mul_(float a, float b) { return a * b; }
-__device__ __forceinline__ cd mul_(cd a, cd b) {
-    const double p = a.y * b.y, q = a.y * b.x;
-    return make_cd(__builtin_fma(a.x, b.x, -p), __builtin_fma(a.x, b.y, q));
-}
-__device__ __forceinline__ cf mul_(cf a, cf b) {
-    const float p = a.y * b.y, q = a.y * b.x;
-    return make_cf(__builtin_fmaf(a.x, b.x, -p), __builtin_fmaf(a.x, b.y, q));
-}
-
 // Phase A of the sparse solves: the sums over every segment (at most kSegLen
 // irregular nodes of one row) of corr[q] sin(pi i_q k / M) for the MB modes
 // k = k0+1 .. k0+MB, into spart[segment * MB + mode].  Thread i of NT takes
@@ -998,6 +966,21 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
     const int k = blk;
     const int n = M - 1;
+    // the extraction's weights and density window, loaded by thread 0 now so
+    // that they arrive during the row sums
+    double wq[6];
+    TO bq[5], fq[5];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wq[q] = w6[6 * k + q];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            int idx = k - 2 + o;
+            idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
+            bq[o] = bop[5 * k + o];
+            fq[o] = phi[idx];
+        }
+    }
     const int node = __builtin_amdgcn_readfirstlane(nodes[(size_t)k * node_stride + p]);
     const int i = node % (M + 1);
     const T *row = uhat + (size_t)(node / (M + 1) - 1) * n;
@@ -1021,13 +1004,9 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
     if (threadIdx.x == 0) {
         TO r = zero<TO>();
 #pragma unroll
-        for (int q = 0; q < 6; ++q) r += su[q] * w6[6 * k + q];
+        for (int q = 0; q < 6; ++q) r = mad_(su[q], wq[q], r);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) {
-            int idx = k - 2 + o;
-            idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
-            r += bop[5 * k + o] * phi[idx];
-        }
+        for (int o = 0; o < 5; ++o) r = mad_(bq[o], fq[o], r);
         kv[k] = r;
     }
 }
@@ -1160,12 +1139,12 @@ __device__ void extract_merged_body(const ExmArgs<T> &A, int blk) {
     const gmem<T> *__restrict__ phi = gview(A.phi);
     T r = zero<T>();
 #pragma unroll
-    for (int q = 0; q < 6; ++q) r += gld(ust + nid[6 * k + q]) * w6[6 * k + q];
+    for (int q = 0; q < 6; ++q) r = mad_(gld(ust + nid[6 * k + q]), (double)w6[6 * k + q], r);
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
         int idx = k - 2 + o;
         idx = idx < 0 ? idx + Nb : (idx >= Nb ? idx - Nb : idx);
-        r += gld(bop + 5 * k + o) * gld(phi + idx);
+        r = mad_(gld(bop + 5 * k + o), gld(phi + idx), r);
     }
     gst(gview(A.kv) + k, r);
 }

@@ -56,6 +56,38 @@ __host__ __device__ inline cf operator*(cf a, double s) { return make_cf((float)
 __host__ __device__ inline cf &operator+=(cf &a, cf b) { a.x += b.x; a.y += b.y; return a; }
 __host__ __device__ inline cf &operator-=(cf &a, cf b) { a.x -= b.x; a.y -= b.y; return a; }
 
+// a * b + c and a * b with every fused step written out (nothing left for
+// the compiler to contract), so that each kernel inlining them rounds alike
+// whatever surrounds it (the tridiagonal sweeps, the extraction sums).  The complex forms take the real part
+// as fma(ar, br, fma(-ai, bi, cr)) and the imaginary part as
+// fma(ar, bi, fma(ai, br, ci)).
+__device__ __forceinline__ double mad_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float mad_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ cd mad_(cd a, cd b, cd c) {
+    return make_cd(__builtin_fma(a.x, b.x, __builtin_fma(-a.y, b.y, c.x)),
+                   __builtin_fma(a.x, b.y, __builtin_fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ cf mad_(cf a, cf b, cf c) {
+    return make_cf(__builtin_fmaf(a.x, b.x, __builtin_fmaf(-a.y, b.y, c.x)),
+                   __builtin_fmaf(a.x, b.y, __builtin_fmaf(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ cd mad_(cd a, double b, cd c) {
+    return make_cd(__builtin_fma(a.x, b, c.x), __builtin_fma(a.y, b, c.y));
+}
+__device__ __forceinline__ cf mad_(cf a, float b, cf c) {
+    return make_cf(__builtin_fmaf(a.x, b, c.x), __builtin_fmaf(a.y, b, c.y));
+}
+__device__ __forceinline__ double mul_(double a, double b) { return a * b; }
+__device__ __forceinline__ float mul_(float a, float b) { return a * b; }
+__device__ __forceinline__ cd mul_(cd a, cd b) {
+    const double p = a.y * b.y, q = a.y * b.x;
+    return make_cd(__builtin_fma(a.x, b.x, -p), __builtin_fma(a.x, b.y, q));
+}
+__device__ __forceinline__ cf mul_(cf a, cf b) {
+    const float p = a.y * b.y, q = a.y * b.x;
+    return make_cf(__builtin_fmaf(a.x, b.x, -p), __builtin_fmaf(a.x, b.y, q));
+}
+
 // Cross-lane exchanges of the wavefront reductions on the VALU (gfx950),
 // not through the LDS unit: the partner of lane l differs from l in bit B,
 // and for the row mirrors also in lower bits, which the later levels of a
