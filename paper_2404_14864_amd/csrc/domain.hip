@@ -366,11 +366,10 @@ __global__ void k_colloc(CurveParams c, double L, double h, int M, int Nb, const
 __global__ void k_tables(int M, double *sine, double *twiddle, double *scu) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     // a period and its first quarter again (2M + M/2 entries)
-    if (m < 2 * M + M / 2) sine[m] = sinpi((double)(m & (2 * M - 1)) / (double)M);
+    if (m < 2 * M + M / 2) sine[m] = sinpi_sym(m, M);
     if (m < max(1, M / 32)) {  // the same values as the table at 64 m and 64 m + M/2
-        const int q = (64 * m) & (2 * M - 1), qc = (64 * m + M / 2) & (2 * M - 1);
-        scu[2 * m] = sinpi((double)q / (double)M);
-        scu[2 * m + 1] = sinpi((double)qc / (double)M);
+        scu[2 * m] = sinpi_sym(64 * m, M);
+        scu[2 * m + 1] = sinpi_sym(64 * m + M / 2, M);
     }
     if (m < M) {  // exp(-2 pi i m / 2M)
         twiddle[2 * m] = cospi((double)m / (double)M);

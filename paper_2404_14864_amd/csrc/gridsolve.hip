@@ -276,6 +276,12 @@ __global__ void k_coef(int M, double kh2_re, double kh2_im, S *etab, S *elim, in
 // LDS per workgroup on gfx950: 160 KB
 constexpr size_t kTriLdsMax = 163840;
 
+// LDS slots (8 bytes each) of the tridiagonal kernels' sine table: the
+// whole period sin(pi r / M), r = 0 .. 2M-1, in the tile kernel; the half
+// period r = 0 .. M-1 in the register-row kernel, which reads it through
+// sin_folded (the same values, one select more per read, half the LDS)
+__host__ __device__ inline int tri_sine_slots(int M, bool folded) { return folded ? M : 2 * M; }
+
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
 // b mod 8).  xcd_tile maps workgroup b to a tile index so that each XCD
 // owns one contiguous run of tiles (a bijection on [0, G) for any G): the
@@ -309,13 +315,16 @@ typedef int gi4 __attribute__((ext_vector_type(4)));
 // k = k0+1 .. k0+MB, into spart[segment * MB + mode].  Thread i of NT takes
 // segments i, i + NT, ... (the first kPf from the descriptors it loaded
 // ahead); four nodes per step keep several LDS round trips in flight, and
-// each mode's terms are added in node order.
-template <class T, class TC, int MB, int NT, bool STAGE>
+// each mode's terms are added in node order.  S is the sine table of
+// tri_sine_slots: the whole period, or (FOLD) the half period read through
+// sin_folded.
+template <class T, class TC, int MB, int NT, bool STAGE, bool FOLD>
 __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem<gi4> *__restrict__ seg_desc,
-                                             int n_seg, int k0, int mask2M, const typename Real<T>::type *S,
+                                             int n_seg, int k0, int M, const typename Real<T>::type *S,
                                              const T *sval, const int32_t *scol, const gmem<TC> *__restrict__ corr,
                                              const gmem<int32_t> *__restrict__ irr_col, T *spart) {
 #pragma clang fp contract(off)
+    const int mask2M = 2 * M - 1;
     // one segment's sums, descriptor d = {first node, end node, row}
     auto seg_sum = [&](const gi4 d, int sg) {
         int q = d.x;
@@ -336,7 +345,7 @@ __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem
             for (int mm = 0; mm < MB; ++mm) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    acc[mm] = mad_(cv[u], S[idx[u]], acc[mm]);
+                    acc[mm] = mad_(cv[u], FOLD ? sin_folded(S, idx[u], M) : S[idx[u]], acc[mm]);
                     idx[u] = (idx[u] + col[u]) & mask2M;
                 }
             }
@@ -347,7 +356,7 @@ __device__ __forceinline__ void segment_sums(const gi4 (&sdesc)[kPf], const gmem
             int idx = (col * (k0 + 1)) & mask2M;
 #pragma unroll
             for (int mm = 0; mm < MB; ++mm) {
-                acc[mm] = mad_(cv, S[idx], acc[mm]);
+                acc[mm] = mad_(cv, FOLD ? sin_folded(S, idx, M) : S[idx], acc[mm]);
                 idx = (idx + col) & mask2M;
             }
         }
@@ -537,11 +546,10 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     extern __shared__ double lds[];
     constexpr int NT = MB * LANES;
     const int n = M - 1;
-    const int mask2M = 2 * M - 1;
     if (done && *done) return;
     const int nnz = sp.nnz, n_act = sp.n_act, n_seg = sp.n_seg;
-    R *S = reinterpret_cast<R *>(lds);                   // 2M sine values
-    T *tile = reinterpret_cast<T *>(lds + 2 * M);       // n*MB + n/C + 1
+    R *S = reinterpret_cast<R *>(lds);                   // the sine table, a whole period
+    T *tile = reinterpret_cast<T *>(lds + tri_sine_slots(M, false));  // n*MB + n/C + 1
     const int tile_len = n * MB + n / C + 1;
     T *spart = tile + tile_len;                          // n_seg*MB partial sums
     // staged sparse right-hand side: values and columns
@@ -572,14 +580,15 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
         lim = gld(elim + k);
     }
     // sine table and staging: loads batched so that several are in flight
-    for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * NT) {
+    const int nsq = tri_sine_slots(M, false);
+    for (int q0 = threadIdx.x; q0 < nsq; q0 += 4 * NT) {
         R v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (q0 + u * NT < 2 * M) v[u] = sine[q0 + u * NT];
+            if (q0 + u * NT < nsq) v[u] = sine[q0 + u * NT];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (q0 + u * NT < 2 * M) S[q0 + u * NT] = v[u];
+            if (q0 + u * NT < nsq) S[q0 + u * NT] = v[u];
     }
     if (STAGE && corr) {
         for (int q0 = threadIdx.x; q0 < nnz; q0 += 4 * NT) {
@@ -622,7 +631,7 @@ __device__ void tridiag_body(const TriArgs<T, TC> &A, int tile_idx) {
     // segments' partial sums in order, so the result does not depend on
     // the schedule.
     if (sparse) {
-        segment_sums<T, TC, MB, NT, STAGE>(sdesc, seg_desc, n_seg, k0, mask2M, S, sval, scol, corr, irr_col, spart);
+        segment_sums<T, TC, MB, NT, STAGE, false>(sdesc, seg_desc, n_seg, k0, M, S, sval, scol, corr, irr_col, spart);
         __syncthreads();
         // one row's segments added in order, descriptor d = {row, first
         // segment, end segment}
@@ -719,11 +728,10 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
     const gmem<int> *__restrict__ done = gview(A.done);
     extern __shared__ double lds[];
     const int n = M - 1;
-    const int mask2M = 2 * M - 1;
     if (done && *done) return;
     const int nnz = sp.nnz, n_seg = sp.n_seg;
-    R *S = reinterpret_cast<R *>(lds);                   // 2M sine values
-    T *spart = reinterpret_cast<T *>(lds + 2 * M);      // n_seg*MB partial sums
+    R *S = reinterpret_cast<R *>(lds);                   // the sine table, half a period
+    T *spart = reinterpret_cast<T *>(lds + tri_sine_slots(M, true));  // n_seg*MB partial sums
     T *obuf = spart;                                     // later: the output chunks
     T *sval = spart + n_seg * MB;
     int32_t *scol = reinterpret_cast<int32_t *>(sval + (STAGE ? nnz : 0));
@@ -748,14 +756,15 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
         tc = tconv[k];
         lim = gld(elim + k);
     }
-    for (int q0 = threadIdx.x; q0 < 2 * M; q0 += 4 * NT) {
+    const int nsq = tri_sine_slots(M, true);
+    for (int q0 = threadIdx.x; q0 < nsq; q0 += 4 * NT) {
         R v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (q0 + u * NT < 2 * M) v[u] = sine[q0 + u * NT];
+            if (q0 + u * NT < nsq) v[u] = sine[q0 + u * NT];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (q0 + u * NT < 2 * M) S[q0 + u * NT] = v[u];
+            if (q0 + u * NT < nsq) S[q0 + u * NT] = v[u];
     }
     if (STAGE) {
         for (int q0 = threadIdx.x; q0 < nnz; q0 += 4 * NT) {
@@ -787,7 +796,7 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
         e[c] = (t < tc && t < n) ? gld(etab + (size_t)t * n + k) : lim;
     }
     // phase A
-    segment_sums<T, TC, MB, NT, STAGE>(sdesc, seg_desc, n_seg, k0, mask2M, S, sval, scol, corr, irr_col, spart);
+    segment_sums<T, TC, MB, NT, STAGE, true>(sdesc, seg_desc, n_seg, k0, M, S, sval, scol, corr, irr_col, spart);
     __syncthreads();
     // phase B: the lane's rows from the partial sums (0 + the row's segments
     // in order, as the tile kernel's zeroed tile plus its row merge), then
@@ -1319,7 +1328,7 @@ TriShape tri_shape(const kfbi_domain *d, bool sparse, int mb_force = 0, bool row
     while (S.lanes * S.c < n) S.c <<= 1;
     S.blocks = (n + mb - 1) / mb;
     S.rows = rows;
-    const size_t sine = (size_t)2 * d->M * sizeof(double);
+    const size_t sine = (size_t)tri_sine_slots(d->M, rows) * sizeof(double);
     const size_t spart = sparse ? (size_t)d->n_seg * mb * sizeof(T) : 0;
     const size_t stage = sparse ? (size_t)d->n_irr * (sizeof(T) + sizeof(int32_t)) : 0;
     if (rows) {
@@ -1625,11 +1634,10 @@ namespace {
 __global__ void k_sine32(int M, float *s, float *scu) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     // a period and its first quarter again (2M + M/2 entries)
-    if (m < 2 * M + M / 2) s[m] = (float)sinpi((double)(m & (2 * M - 1)) / (double)M);
+    if (m < 2 * M + M / 2) s[m] = (float)sinpi_sym(m, M);
     if (m < max(1, M / 32)) {
-        const int q = (64 * m) & (2 * M - 1), qc = (64 * m + M / 2) & (2 * M - 1);
-        scu[2 * m] = (float)sinpi((double)q / (double)M);
-        scu[2 * m + 1] = (float)sinpi((double)qc / (double)M);
+        scu[2 * m] = (float)sinpi_sym(64 * m, M);
+        scu[2 * m + 1] = (float)sinpi_sym(64 * m + M / 2, M);
     }
 }
 }  // namespace

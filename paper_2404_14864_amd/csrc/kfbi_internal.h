@@ -88,6 +88,27 @@ __device__ __forceinline__ cf mul_(cf a, cf b) {
     return make_cf(__builtin_fmaf(a.x, b.x, -p), __builtin_fmaf(a.x, b.y, q));
 }
 
+// sin(pi q / M) for any integer q (M a power of two), formed from the first
+// quarter period so that the tables built from it are exactly odd about M
+// and even about M/2: then a kernel may keep only part of the period and
+// fold its lookups without changing a value.
+__device__ inline double sinpi_sym(int q, int M) {
+    q &= 2 * M - 1;
+    const bool neg = q >= M;
+    int r = q & (M - 1);
+    if (r > (M >> 1)) r = M - r;
+    const double v = sinpi((double)r / (double)M);
+    return neg ? -v : v;
+}
+
+// a lookup of sin(pi idx / M), 0 <= idx < 2M, in a half-period table
+// S[r] = sin(pi r / M), 0 <= r < M (built by sinpi_sym)
+template <class R>
+__device__ __forceinline__ R sin_folded(const R *S, int idx, int M) {
+    const R v = S[idx & (M - 1)];
+    return idx >= M ? -v : v;
+}
+
 // Cross-lane exchanges of the wavefront reductions on the VALU (gfx950),
 // not through the LDS unit: the partner of lane l differs from l in bit B,
 // and for the row mirrors also in lower bits, which the later levels of a
