@@ -753,6 +753,9 @@ template <class T>
 struct SlotArgs {
     const int *off;  // nonzero: member not solved in this call (batched solves)
     int replay;      // nonzero: timing replay, the control block is not advanced
+    int quiet;       // nonzero: publish to the host mirror only when the solve
+                     // finishes (the host reads the mirror once a batch of
+                     // slots has run; the batch's last slot is not quiet)
     GmCtl *ctl;
     GmMirror *mir;
     T *V, *H, *g;
@@ -829,7 +832,7 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
             ctl->thresh = t1 > t0 ? t1 : t0;
             ctl->slot = c.slot + 1;
             gm_set_state(ctl, stop ? kStDone : kStIter);
-            gm_publish(ctl, mir);
+            if (stop || !A.quiet) gm_publish(ctl, mir);
         }
         return;
     }
@@ -1061,7 +1064,7 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
         if (tid == 0 && !A.replay) {
             ctl->slot = c.slot + 1;
             gm_set_state(ctl, kStIter);
-            gm_publish(ctl, mir);
+            if (!A.quiet) gm_publish(ctl, mir);
         }
         return;
     }
@@ -1096,7 +1099,7 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
         const bool finished = sconv || sit >= limit;
         ctl->slot = c.slot + 1;
         gm_set_state(ctl, finished ? kStDone : kStStart);
-        gm_publish(ctl, mir);
+        if (finished || !A.quiet) gm_publish(ctl, mir);
     }
 }
 
@@ -1418,6 +1421,7 @@ SlotArgs<T> slot_args(GmPtrs &P, GmMirror *mir, int Nb, int m, int nvl) {
     SlotArgs<T> A;
     A.off = nullptr;
     A.replay = 0;
+    A.quiet = 0;
     A.ctl = P.ctl;
     A.mir = mir;
     A.V = (T *)P.V;
@@ -1443,7 +1447,7 @@ static bool slots_supported(kfbi_domain *d, int m) {
 
 template <class T>
 static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index, hipStream_t s,
-                       bool replay = false) {
+                       bool replay = false, bool quiet = false) {
     int nvl;
     const size_t lds = slot_lds<T>(Nb, m, &nvl);
     const int ept = (Nb + kGmThreads - 1) / kGmThreads;
@@ -1451,6 +1455,7 @@ static int launch_slot(kfbi_domain *d, GmPtrs &P, int Nb, int m, int slot_index,
     const int ps = prof_begin(d);
     SlotArgs<T> A = slot_args<T>(P, mir, Nb, m, nvl);
     A.replay = replay ? 1 : 0;
+    A.quiet = quiet ? 1 : 0;
 #define KFBI_SLOT(E) k_gm_slot<T, E><<<1, kGmThreads, lds, s>>>(A)
     if (ept <= 1) KFBI_SLOT(1);
     else if (ept <= 2) KFBI_SLOT(2);
@@ -1514,7 +1519,8 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
                 KFBI_CHECK_LAUNCH();
                 prof_end(d, ps, KFBI_K_ARNOLDI, 6.0 * Nb * sizeof(T));
             } else {
-                KFBI_TRY(launch_slot<T>(d, P, Nb, m, n_enq + c, s));
+                // only the batch's last slot publishes unconditionally
+                KFBI_TRY(launch_slot<T>(d, P, Nb, m, n_enq + c, s, false, c + 1 < want));
             }
         }
         n_enq += want;
