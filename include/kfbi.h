@@ -372,8 +372,8 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
  * times, on the members' own tables, every shape that computes the same
  * values (1, 2 or 4 sine modes per 64-, 128- or 256-lane workgroup, and 8
  * per 512 lanes in the register-row kernel; the sparse input staged in LDS
- * or read from HBM; for sparse input, the right-hand side and solution held
- * in an LDS tile or in registers) and keeps the fastest.  Writes min(cap, rows) rows of 6 int32 {M, kind (0: sparse FP64,
+ * or read from HBM; the right-hand side and solution held in an LDS tile or
+ * in registers) and keeps the fastest.  Writes min(cap, rows) rows of 6 int32 {M, kind (0: sparse FP64,
  * 1: with dense input FP64, 2: sparse FP32), modes per workgroup, staged,
  * tuned, register rows} to rows (may be NULL when cap is 0), the time of the
  * kept shape in microseconds per launch of the class (or -1 when untuned) to

@@ -1967,6 +1967,7 @@ int batch_create(kfbi_domain *const *doms, int n, kfbi_batch **out) {
         for (int kind = 0; kind < 3; ++kind) {
             const int st = batch_tri_shape(cd.data(), (int)cd.size(), true, kind == 2, &C.shape[kind]);
             if (st != KFBI_OK) { batch_destroy(b); return st; }
+            C.shape[kind].dense = kind == 1;
             C.tuned[kind] = false;
             C.us[kind] = -1.0;
         }
@@ -2089,8 +2090,8 @@ int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) 
             BatchTriShape best = C.shape[kind];
             double best_us = 1e300;
             const int pref = tri_kernel_pref();
-            for (int rows = 0; rows < (kind == 1 ? 1 : 2); ++rows) {
-                if (kind != 1 && pref >= 0 && rows != pref) continue;
+            for (int rows = 0; rows < 2; ++rows) {
+                if (pref >= 0 && rows != pref) continue;
                 for (int mb : {1, 2, 4, 8}) {
                     if (mb == 8 && !rows) continue;  // 32-lane groups: other values
                     if (tri_mb_pref() > 0 && mb != tri_mb_pref()) continue;
@@ -2098,6 +2099,7 @@ int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) 
                         BatchTriShape S;
                         if (batch_tri_shape(cd.data(), (int)cd.size(), true, low, &S, mb, stage, rows != 0) != KFBI_OK)
                             continue;
+                        S.dense = rows != 0 && kind == 1;
                         double us = 0.0;
                         KFBI_TRY(tune_time(b, low ? kBaTri32 : kBaTri64, args, C, S, &us));
                         if (us < best_us) {

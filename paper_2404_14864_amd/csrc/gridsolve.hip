@@ -706,7 +706,9 @@ constexpr size_t rows_obuf_bytes() {
 
 typedef int gi2 __attribute__((ext_vector_type(2)));
 
-template <class T, class TC, int MB, int C, bool STAGE>
+// DENSE: the right-hand side also has the dense part rhat (b-solve, final
+// solve), each lane reading its own rows of it (batched launches only)
+template <class T, class TC, int MB, int C, bool STAGE, bool DENSE>
 __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
 #pragma clang fp contract(off)
     typedef typename Real<T>::type R;
@@ -750,6 +752,19 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
     gi2 rsp[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) rsp[c] = row_span[t0 + c];
+    // the dense part of the lane's rows: every load issued at a clamped,
+    // in-bounds index and masked afterwards
+    T rh[DENSE ? C : 1];
+    if constexpr (DENSE) {
+        const gmem<T> *__restrict__ rhat = gview(A.rhat);
+        const int kc = k < n ? k : n - 1;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int t = t0 + c;
+            const T x = gld(rhat + (size_t)(t < n ? t : n - 1) * n + kc);
+            rh[c] = (t < n && k < n) ? x : zero<T>();
+        }
+    }
     int tc = 0;
     T lim = zero<T>();
     if (k < n) {
@@ -798,9 +813,9 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
     // phase A
     segment_sums<T, TC, MB, NT, STAGE, true>(sdesc, seg_desc, n_seg, k0, M, S, sval, scol, corr, irr_col, spart);
     __syncthreads();
-    // phase B: the lane's rows from the partial sums (0 + the row's segments
-    // in order, as the tile kernel's zeroed tile plus its row merge), then
-    // the scans
+    // phase B: the lane's rows from the partial sums (0, or the dense part,
+    // plus the row's segments in order, as the tile kernel's tile plus its
+    // row merge), then the scans
     // every row's first partial sum read at once (clamped: a row without
     // nodes reads a valid entry and ignores it), later segments after
     T v[C], first[C];
@@ -809,6 +824,7 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         T acc = zero<T>();
+        if constexpr (DENSE) acc = rh[c];
         const int s0 = rsp[c].x, s1 = rsp[c].y;
         if (s0 < s1) {
             T a = first[c];
@@ -840,7 +856,7 @@ __device__ void tridiag_rows_body(const TriArgs<T, TC> &A, int tile_idx) {
 
 template <class T, class TC, int MB, int C, bool STAGE>
 __global__ __launch_bounds__(MB * 64) void k_tridiag_rows(TriArgs<T, TC> A) {
-    tridiag_rows_body<T, TC, MB, C, STAGE>(A, xcd_tile(blockIdx.x, gridDim.x));
+    tridiag_rows_body<T, TC, MB, C, STAGE, false>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1413,8 +1429,9 @@ struct TriLaunchOne {
     void go() const {
         k_tridiag<T, TC, MB, L, C, ST><<<blocks, MB * L, lds, s>>>(A);
     }
-    template <int MB, int C, bool ST>
+    template <int MB, int C, bool ST, bool DENSE>
     void go_rows() const {
+        static_assert(!DENSE, "single-domain dense launches run the tile kernel");
         k_tridiag_rows<T, TC, MB, C, ST><<<blocks, MB * 64, lds, s>>>(A);
     }
 };
@@ -1426,11 +1443,11 @@ __global__ __launch_bounds__(MB *LANES) void kb_tridiag(const TriArgs<T, TC> *__
     tridiag_body<T, TC, MB, LANES, C, STAGE>(A[e.inst], e.local);
 }
 
-template <class T, class TC, int MB, int C, bool STAGE>
+template <class T, class TC, int MB, int C, bool STAGE, bool DENSE>
 __global__ __launch_bounds__(MB * 64) void kb_tridiag_rows(const TriArgs<T, TC> *__restrict__ A,
                                                          const BlkMap *__restrict__ map) {
     const BlkMap e = map[xcd_tile(blockIdx.x, gridDim.x)];
-    tridiag_rows_body<T, TC, MB, C, STAGE>(A[e.inst], e.local);
+    tridiag_rows_body<T, TC, MB, C, STAGE, DENSE>(A[e.inst], e.local);
 }
 
 template <class T, class TC>
@@ -1444,9 +1461,9 @@ struct TriLaunchBatch {
     void go() const {
         kb_tridiag<T, TC, MB, L, C, ST><<<blocks, MB * L, lds, s>>>(A, map);
     }
-    template <int MB, int C, bool ST>
+    template <int MB, int C, bool ST, bool DENSE>
     void go_rows() const {
-        kb_tridiag_rows<T, TC, MB, C, ST><<<blocks, MB * 64, lds, s>>>(A, map);
+        kb_tridiag_rows<T, TC, MB, C, ST, DENSE><<<blocks, MB * 64, lds, s>>>(A, map);
     }
 };
 
@@ -1476,13 +1493,21 @@ void tri_dispatch(int mb, int c, bool stage, const F &f) {
 #undef KFBI_TRI
 }
 
-// the register-row kernel: mb in {1, 2, 4, 8}, c in {4, ..., 32} (tri_rows_ok)
-template <class F>
-void tri_rows_dispatch(int mb, int c, bool stage, const F &f) {
-#define KFBI_TRR(MBv, CC)                                   \
-    do {                                                    \
-        if (stage) f.template go_rows<MBv, CC, true>();     \
-        else f.template go_rows<MBv, CC, false>();          \
+// the register-row kernel: mb in {1, 2, 4, 8}, c in {4, ..., 32} (tri_rows_ok);
+// WITH_DENSE: also the dense-input form (batched launches)
+template <bool WITH_DENSE, class F>
+void tri_rows_dispatch(int mb, int c, bool stage, bool dense, const F &f) {
+#define KFBI_TRR(MBv, CC)                                                 \
+    do {                                                                  \
+        if constexpr (WITH_DENSE) {                                       \
+            if (dense) {                                                  \
+                if (stage) f.template go_rows<MBv, CC, true, true>();     \
+                else f.template go_rows<MBv, CC, false, true>();          \
+                break;                                                    \
+            }                                                             \
+        }                                                                 \
+        if (stage) f.template go_rows<MBv, CC, true, false>();            \
+        else f.template go_rows<MBv, CC, false, false>();                 \
     } while (0)
 #define KFBI_TRR_C(MBv)                       \
     switch (c) {                              \
@@ -1504,7 +1529,7 @@ void tri_rows_dispatch(int mb, int c, bool stage, const F &f) {
 // a tile- or row-kernel launch of shape S
 template <class F>
 void tri_launch(const TriShape &S, bool stage, const F &f) {
-    if (S.rows) tri_rows_dispatch(S.mb, S.c, stage, f);
+    if (S.rows) tri_rows_dispatch<false>(S.mb, S.c, stage, false, f);
     else tri_dispatch(S.mb, S.c, stage, f);
 }
 
@@ -1961,10 +1986,7 @@ int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, Batc
         mb = cplx ? (low ? tri_default_mb<cf>(n0) : tri_default_mb<cd>(n0))
                   : (low ? tri_default_mb<float>(n0) : tri_default_mb<double>(n0));
     }
-    if (rows && !sparse) {
-        set_error("the register-row tridiagonal kernel takes sparse input only");
-        return KFBI_ENOTSUP;
-    }
+
     for (int q = 0; q < n; ++q) {
         kfbi_domain *d = doms[q];
         const TriShape S = cplx ? (low ? tri_shape<cf>(d, sparse, mb, rows) : tri_shape<cd>(d, sparse, mb, rows))
@@ -1977,6 +1999,7 @@ int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, Batc
             out->mb = S.mb;
             out->c = S.c;
             out->rows = rows;
+            out->dense = false;
             out->lds = S.lds_base;
             out->stage_lds = S.lds_stage;
         } else {
@@ -2021,13 +2044,13 @@ int batch_launch_t(int kind, const void *args, const BlkMap *map, int blocks, in
             break;
         case kBaTri64: {
             TriLaunchBatch<T, T> L{(const TriArgs<T, T> *)args, map, blocks, shape->lds, s};
-            if (shape->rows) tri_rows_dispatch(shape->mb, shape->c, shape->stage, L);
+            if (shape->rows) tri_rows_dispatch<true>(shape->mb, shape->c, shape->stage, shape->dense, L);
             else tri_dispatch(shape->mb, shape->c, shape->stage, L);
             break;
         }
         case kBaTri32: {
             TriLaunchBatch<TL, T> L{(const TriArgs<TL, T> *)args, map, blocks, shape->lds, s};
-            if (shape->rows) tri_rows_dispatch(shape->mb, shape->c, shape->stage, L);
+            if (shape->rows) tri_rows_dispatch<false>(shape->mb, shape->c, shape->stage, false, L);
             else tri_dispatch(shape->mb, shape->c, shape->stage, L);
             break;
         }

@@ -720,7 +720,8 @@ enum {
 struct BatchTriShape {
     int mb, c;
     bool stage;
-    bool rows;  // the register-row kernel (sparse input only)
+    bool rows;   // the register-row kernel
+    bool dense;  // its dense-input form (the class's dense launches)
     size_t lds, stage_lds;
     int blocks_per;
 };
@@ -733,8 +734,8 @@ int batch_blocks(const kfbi_domain *d, int kind);
 int tri_kernel_pref();
 // KFBI_TRIDIAG_KERNEL "tile:<mb>" / "rows:<mb>": the modes per workgroup, 0 when not fixed
 int tri_mb_pref();
-// rows: the register-row kernel (sparse input, 64-lane groups of at least 4
-// rows per lane; refused with KFBI_ENOTSUP otherwise)
+// rows: the register-row kernel (64-lane groups of at least 4 rows per lane;
+// refused with KFBI_ENOTSUP otherwise); the caller sets dense
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb = 0,
                     int stage_pref = -1, bool rows = false);
 int batch_tri_blocks(const kfbi_domain *d, int mb);

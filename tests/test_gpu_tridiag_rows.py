@@ -7,9 +7,9 @@ timing to one kernel; each case solves the same problem on two domains, one
 timed with each.
 
 Bar: bit-for-bit equality of U and phi (FP64, complex128, and the mixed
-solves' FP32 / complex64 inner kernels), single domains and batches, and
-the register-row kernel kept by the batch timing when it is the only one
-allowed.  Inputs: the heat, wave, Schroedinger and batched workloads'
+solves' FP32 / complex64 inner kernels), single domains and batches (whose
+dense-input launches also have a register-row form), and the register-row
+kernel kept by the batch timing when it is the only one allowed.  Inputs: the heat, wave, Schroedinger and batched workloads'
 domains (ellipse and star), seeded smooth random f and g.
 """
 
@@ -143,6 +143,9 @@ def test_batch_same_bits_with_either_kernel():
                     kfbi.kfbi_domain_destroy(h)
     for a, c in zip(runs["tile"][0], runs["rows"][0]):
         assert np.array_equal(a, c)
-    sparse_rows = [r["register_rows"] for r in runs["rows"][1] if r["tuned"] and r["kind"] == "sparse64"]
-    assert sparse_rows and all(sparse_rows)
+    # the register-row kernel served the sparse launches and, in its dense-input
+    # form, the b-solve's and final solve's launches of every class it fits
+    for kind in ("sparse64", "dense64"):
+        rows = [r["register_rows"] for r in runs["rows"][1] if r["tuned"] and r["kind"] == kind]
+        assert rows and all(rows), kind
     assert not any(r["register_rows"] for r in runs["tile"][1])
