@@ -129,54 +129,84 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
     }
     __syncthreads();
     // in-place radix-2 decimation-in-time, twiddle exp(-2 pi i m / N2).
-    // Consecutive stages are taken in pairs: each thread carries a group of
-    // four points through both stages in registers (the same butterflies in
-    // the same order), so there is one barrier per pair of stages.  An odd
-    // number of stages starts with a single one.
+    // Stages are taken three at a time: each thread carries a group of eight
+    // points through three stages in registers, so there is one LDS round
+    // trip and one barrier per three stages.  The logN2 mod 3 stages left
+    // over go first, as a single stage or a pair.
+    auto tw = [&](int m, double &wr, double &wi) {
+        wr = twiddle[2 * m];
+        wi = twiddle[2 * m + 1];
+    };
+    // butterfly (x, y) <- (x + w y, x - w y)
+    auto bfly = [](double2 &x, double2 &y, double wr, double wi) {
+        const double vr = y.x * wr - y.y * wi, vi = y.x * wi + y.y * wr;
+        y = make_double2(x.x - vr, x.y - vi);
+        x = make_double2(x.x + vr, x.y + vi);
+    };
     int len = 2, tstep = M;
-    if (logN2 & 1) {
+    const int lead = logN2 % 3;
+    if (lead == 1) {
         for (int b = threadIdx.x; b < M; b += blockDim.x) {
             const int i0 = 2 * b, i1 = i0 + 1;
-            const double wr = twiddle[0], wi = twiddle[1];
+            double wr, wi;
+            tw(0, wr, wi);
             double2 u = a[i0], v = a[i1];
-            double vr = v.x * wr - v.y * wi, vi = v.x * wi + v.y * wr;
-            a[i0] = make_double2(u.x + vr, u.y + vi);
-            a[i1] = make_double2(u.x - vr, u.y - vi);
+            bfly(u, v, wr, wi);
+            a[i0] = u;
+            a[i1] = v;
         }
         __syncthreads();
         len = 4;
         tstep = M >> 1;
-    }
-    for (; len <= M; len <<= 2, tstep >>= 2) {
-        const int half = len >> 1, tstep2 = tstep >> 1;
+    } else if (lead == 2) {
+        // stages of lengths 2 and 4: groups of four points
         for (int b = threadIdx.x; b < (M >> 1); b += blockDim.x) {
+            const int i0 = 4 * b;
+            double2 x0 = a[i0], x1 = a[i0 + 1], x2 = a[i0 + 2], x3 = a[i0 + 3];
+            double wr, wi;
+            tw(0, wr, wi);
+            bfly(x0, x1, wr, wi);
+            bfly(x2, x3, wr, wi);
+            bfly(x0, x2, wr, wi);
+            tw(M >> 1, wr, wi);
+            bfly(x1, x3, wr, wi);
+            a[i0] = x0;
+            a[i0 + 1] = x1;
+            a[i0 + 2] = x2;
+            a[i0 + 3] = x3;
+        }
+        __syncthreads();
+        len = 8;
+        tstep = M >> 2;
+    }
+    for (; len <= M; len <<= 3, tstep >>= 3) {
+        // stages of lengths len, 2 len, 4 len on the points
+        // i0 + q half, q < 8 (i0 = grp 8 half + pos, pos < half)
+        const int half = len >> 1, t2 = tstep >> 1, t3 = tstep >> 2;
+        for (int b = threadIdx.x; b < (M >> 2); b += blockDim.x) {
             const int grp = b / half, pos = b - grp * half;
-            const int i0 = grp * 2 * len + pos, i1 = i0 + half, i2 = i0 + len, i3 = i2 + half;
-            double2 x0 = a[i0], x1 = a[i1], x2 = a[i2], x3 = a[i3];
-            // stage of length len: (i0, i1) and (i2, i3), twiddle of pos
-            {
-                const double wr = twiddle[2 * pos * tstep], wi = twiddle[2 * pos * tstep + 1];
-                double vr = x1.x * wr - x1.y * wi, vi = x1.x * wi + x1.y * wr;
-                x1 = make_double2(x0.x - vr, x0.y - vi);
-                x0 = make_double2(x0.x + vr, x0.y + vi);
-                vr = x3.x * wr - x3.y * wi;
-                vi = x3.x * wi + x3.y * wr;
-                x3 = make_double2(x2.x - vr, x2.y - vi);
-                x2 = make_double2(x2.x + vr, x2.y + vi);
+            const int i0 = grp * 8 * half + pos;
+            double2 x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = a[i0 + q * half];
+            double wr, wi;
+            tw(pos * tstep, wr, wi);
+#pragma unroll
+            for (int q = 0; q < 8; q += 2) bfly(x[q], x[q + 1], wr, wi);
+            double wr2, wi2;
+            tw(pos * t2, wr, wi);
+            tw((pos + half) * t2, wr2, wi2);
+            bfly(x[0], x[2], wr, wi);
+            bfly(x[1], x[3], wr2, wi2);
+            bfly(x[4], x[6], wr, wi);
+            bfly(x[5], x[7], wr2, wi2);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                tw((pos + q * half) * t3, wr, wi);
+                bfly(x[q], x[q + 4], wr, wi);
             }
-            // stage of length 2 len: (i0, i2) at pos and (i1, i3) at pos + half
-            {
-                double wr = twiddle[2 * pos * tstep2], wi = twiddle[2 * pos * tstep2 + 1];
-                double vr = x2.x * wr - x2.y * wi, vi = x2.x * wi + x2.y * wr;
-                a[i0] = make_double2(x0.x + vr, x0.y + vi);
-                a[i2] = make_double2(x0.x - vr, x0.y - vi);
-                wr = twiddle[2 * (pos + half) * tstep2];
-                wi = twiddle[2 * (pos + half) * tstep2 + 1];
-                vr = x3.x * wr - x3.y * wi;
-                vi = x3.x * wi + x3.y * wr;
-                a[i1] = make_double2(x1.x + vr, x1.y + vi);
-                a[i3] = make_double2(x1.x - vr, x1.y - vi);
-            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[i0 + q * half] = x[q];
         }
         __syncthreads();
     }
