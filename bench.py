@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # counts are in profiles/*_hbm_traffic.md.  Kernels not listed (or changed
 # since they were counted) report null.
 TRAFFIC = {
-    # Schroedinger 1024, complex128: 18.41 MB per sparse launch, 36.08 MB per
+    # Schroedinger 1024, complex128: 18.37 MB per sparse launch, 36.08 MB per
     # dense launch, weighted 80 / 20 like the algorithmic bytes of the profiled
     # steps (profiles/tridiag_schrodinger1024_c128_hbm_traffic.md)
-    "k_tridiag / k_tridiag_rows": 21945868.0,
+    "k_tridiag / k_tridiag_rows": 21908926.0,
 }
 # the kernel each profile label belongs to: the two tridiagonal labels are
 # the y-direction solves launched from one site (sparse or dense right-hand
