@@ -380,9 +380,10 @@ int kfbi_batch_step(kfbi_batch *b, kfbi_stepper *const *st, const uint8_t *activ
  * us (may be NULL), and the row count to n_rows.  Errors: KFBI_EINVAL.
  * The environment variable KFBI_TRIDIAG_KERNEL = "tile" or "rows", when set,
  * limits this timing and that of single domains (at a domain's first solve)
- * to the LDS-tile or the register-row kernel, and "tile:<mb>" / "rows:<mb>"
- * also to mb modes per workgroup (for tests and diagnosis; the values are
- * the same). */
+ * to the LDS-tile or the register-row kernel, "tile:<mb>" / "rows:<mb>" also
+ * to mb modes per workgroup, and "<kernel>:<mb>:<s>" also to the sparse input
+ * staged in LDS (s = 1) or not (s = 0) (for tests and diagnosis; the values
+ * are the same). */
 int kfbi_batch_tuning(const kfbi_batch *b, int32_t cap, int32_t *rows, double *us, int32_t *n_rows);
 
 /* Per-kernel device timing (instrumentation for benchmarks).  When enabled,

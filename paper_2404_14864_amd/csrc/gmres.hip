@@ -2096,6 +2096,7 @@ int batch_tune_run(kfbi_batch *b, bool low, char *d_buf, const uint8_t *active) 
                     if (mb == 8 && !rows) continue;  // 32-lane groups: other values
                     if (tri_mb_pref() > 0 && mb != tri_mb_pref()) continue;
                     for (int stage : {0, 1}) {
+                        if (tri_stage_pref() >= 0 && stage != tri_stage_pref()) continue;
                         BatchTriShape S;
                         if (batch_tri_shape(cd.data(), (int)cd.size(), true, low, &S, mb, stage, rows != 0) != KFBI_OK)
                             continue;

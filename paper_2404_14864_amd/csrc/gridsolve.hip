@@ -1414,6 +1414,18 @@ int tri_mb_pref() {
     return (mb == 1 || mb == 2 || mb == 4 || mb == 8) ? mb : 0;
 }
 
+// "<kernel>:<mb>:<s>" also fixes the staging of the sparse input (s = 0 or
+// 1); -1 when not
+int tri_stage_pref() {
+    const char *v = std::getenv("KFBI_TRIDIAG_KERNEL");
+    if (!v) return -1;
+    const char *c = std::strchr(v, ':');
+    if (!c) return -1;
+    c = std::strchr(c + 1, ':');
+    if (!c || (c[1] != '0' && c[1] != '1')) return -1;
+    return c[1] - '0';
+}
+
 namespace {
 
 template <class T>
@@ -1629,6 +1641,7 @@ int tune_tridiag_t(kfbi_domain *d) {
             if (S.c > 32 || S.lds > kTriLdsMax || (rows && !tri_rows_ok(S))) continue;
             for (int stage : {0, 1}) {
                 if (stage && S.lds_stage > kTriLdsMax) continue;
+                if (tri_stage_pref() >= 0 && stage != tri_stage_pref()) continue;
                 const size_t lds = stage ? S.lds_stage : S.lds;
                 TriLaunchOne<T, TC> L{tri_args<T>(d, nullptr, d->corr, d->uhat, nullptr), S.blocks, lds, s};
                 tri_launch(S, stage != 0, L);

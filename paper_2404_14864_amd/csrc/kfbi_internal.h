@@ -734,6 +734,8 @@ int batch_blocks(const kfbi_domain *d, int kind);
 int tri_kernel_pref();
 // KFBI_TRIDIAG_KERNEL "tile:<mb>" / "rows:<mb>": the modes per workgroup, 0 when not fixed
 int tri_mb_pref();
+// KFBI_TRIDIAG_KERNEL "<kernel>:<mb>:<s>": staging of the sparse input, -1 when not fixed
+int tri_stage_pref();
 // rows: the register-row kernel (64-lane groups of at least 4 rows per lane;
 // refused with KFBI_ENOTSUP otherwise); the caller sets dense
 int batch_tri_shape(kfbi_domain *const *doms, int n, bool sparse, bool low, BatchTriShape *out, int mb = 0,
