@@ -1615,22 +1615,21 @@ int launch_tridiag(kfbi_domain *d, const void *rhat, const void *corr, void *uha
 // modes per workgroup (64-lane mode groups: the same operations in the same
 // order for every mode), with and without LDS staging, in the tile and the
 // register-row kernels, on the domain's own tables, and keeps the fastest.
-// Writes only the scratch transforms.
+// Each shape is timed in three rounds over all shapes (20 launches each,
+// after one untimed) and scored by its best round, so that a clock ramp or
+// a transient on the device does not decide the choice.  Writes only the
+// scratch transforms.
 template <class T>
 int tune_tridiag_t(kfbi_domain *d) {
     typedef typename High<T>::type TC;
     hipStream_t s = d->stream;
-    const int n = d->M - 1;
     KFBI_HIP(hipMemsetAsync(d->corr, 0, (size_t)d->n_irr * sizeof(TC), s));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    KFBI_HIP(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        set_error("hipEventCreate failed");
-        return KFBI_EDEVICE;
-    }
-    int best_mb = tri_default_mb<T>(n), best_stage = -1, best_rows = 0, st = KFBI_OK;
-    float best = 1e30f;
+    struct Cand {
+        int rows, mb, stage;
+        TriShape S;
+        float best;
+    };
+    std::vector<Cand> cands;
     const int pref = tri_kernel_pref();
     for (int rows : {0, 1}) {
         if (pref >= 0 && rows != pref) continue;
@@ -1642,25 +1641,32 @@ int tune_tridiag_t(kfbi_domain *d) {
             for (int stage : {0, 1}) {
                 if (stage && S.lds_stage > kTriLdsMax) continue;
                 if (tri_stage_pref() >= 0 && stage != tri_stage_pref()) continue;
-                const size_t lds = stage ? S.lds_stage : S.lds;
-                TriLaunchOne<T, TC> L{tri_args<T>(d, nullptr, d->corr, d->uhat, nullptr), S.blocks, lds, s};
-                tri_launch(S, stage != 0, L);
-                if (hipEventRecord(e0, s) != hipSuccess) st = KFBI_EDEVICE;
-                for (int r = 0; r < 20; ++r) tri_launch(S, stage != 0, L);
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = KFBI_EDEVICE;
-                float ms = 0.f;
-                if (st == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = KFBI_EDEVICE;
-                if (st != KFBI_OK) break;
-                if (ms < best) {
-                    best = ms;
-                    best_mb = mb;
-                    best_stage = stage ? -1 : 0;
-                    best_rows = rows;
-                }
+                cands.push_back(Cand{rows, mb, stage, S, 1e30f});
             }
-            if (st != KFBI_OK) break;
         }
-        if (st != KFBI_OK) break;
+    }
+    if (cands.empty()) return KFBI_OK;  // the default shape stays
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KFBI_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        set_error("hipEventCreate failed");
+        return KFBI_EDEVICE;
+    }
+    int st = KFBI_OK;
+    for (int round = 0; round < 3 && st == KFBI_OK; ++round) {
+        for (Cand &c : cands) {
+            const size_t lds = c.stage ? c.S.lds_stage : c.S.lds;
+            TriLaunchOne<T, TC> L{tri_args<T>(d, nullptr, d->corr, d->uhat, nullptr), c.S.blocks, lds, s};
+            tri_launch(c.S, c.stage != 0, L);
+            if (hipEventRecord(e0, s) != hipSuccess) st = KFBI_EDEVICE;
+            for (int r = 0; r < 20; ++r) tri_launch(c.S, c.stage != 0, L);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) st = KFBI_EDEVICE;
+            float ms = 0.f;
+            if (st == KFBI_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = KFBI_EDEVICE;
+            if (st != KFBI_OK) break;
+            c.best = std::min(c.best, ms);
+        }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -1668,9 +1674,12 @@ int tune_tridiag_t(kfbi_domain *d) {
         set_error("timing the tridiagonal launch shapes failed");
         return st;
     }
-    d->tri_mb = best_mb;
-    d->tri_stage = best_stage;
-    d->tri_rows = best_rows;
+    const Cand *win = &cands[0];
+    for (const Cand &c : cands)
+        if (c.best < win->best) win = &c;
+    d->tri_mb = win->mb;
+    d->tri_stage = win->stage ? -1 : 0;
+    d->tri_rows = win->rows;
     return KFBI_OK;
 }
 
