@@ -966,7 +966,10 @@ __device__ void eval_nodes_body(const EvalArgs<T, TO> &A, int blk) {
 
 template <class T, class TO>
 __global__ __launch_bounds__(256) void k_eval_nodes(EvalArgs<T, TO> A) {
-    eval_nodes_body(A, blockIdx.x);
+    // each XCD takes one run of consecutive nodes, which lie on one arc of
+    // the boundary: the rows of U^ that arc needs are then fetched into one
+    // XCD's L2, not into all eight
+    eval_nodes_body(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // corrections of a density with the merged operator, one thread per node
@@ -1068,7 +1071,9 @@ __device__ void eval_extract_body(const EvxArgs<T, TO> &A, int blk) {
 
 template <class T, class TO, int KR>
 __global__ __launch_bounds__(384) void k_eval_extract(EvxArgs<T, TO> A) {
-    eval_extract_body<T, TO, KR>(A, blockIdx.x);
+    // one run of consecutive collocation points (one arc) per XCD, as in
+    // k_eval_nodes
+    eval_extract_body<T, TO, KR>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // the register-row form of the evaluation for M = 64 .. 1024, the loop above
