@@ -846,28 +846,29 @@ __device__ void gm_slot_body(const SlotArgs<T> &A, int) {
     }
     if (tid <= j) sgv[tid] = g[tid];
     const int nst = j + 1 < nvl ? j + 1 : nvl;
-    // stage the basis: eight loads in flight per thread (clamped, in
-    // bounds), then the LDS writes, so the copy costs about one memory
-    // round trip rather than one per element
-    for (int k = tid; k < Nb; k += kGmThreads) sw[k] = kv[k];
-    {
-        const int total = nst * Nb;
-        for (int q0 = tid; q0 < total; q0 += 8 * kGmThreads) {
-            T v8[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v8[u] = V[min(q0 + u * kGmThreads, total - 1)];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (q0 + u * kGmThreads < total) sV[q0 + u * kGmThreads] = v8[u];
-        }
-    }
-    __syncthreads();
+    // the thread's elements of w = K v_j straight into registers, and the
+    // basis staged in LDS with sixteen loads in flight per thread (clamped,
+    // in bounds) before the LDS writes: every load is issued before the
+    // first wait, so the set-up costs about one memory round trip
     T wl[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int k = tid + e * kGmThreads;
-        wl[e] = k < Nb ? sw[k] : zero<T>();
+        const T x = kv[min(k, Nb - 1)];
+        wl[e] = k < Nb ? x : zero<T>();
     }
+    {
+        const int total = nst * Nb;
+        for (int q0 = tid; q0 < total; q0 += 16 * kGmThreads) {
+            T v16[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v16[u] = V[min(q0 + u * kGmThreads, total - 1)];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (q0 + u * kGmThreads < total) sV[q0 + u * kGmThreads] = v16[u];
+        }
+    }
+    __syncthreads();
     // CGS2 against v_0..v_j.  All of v_0..v_j staged: branch-free dot
     // products (clamped LDS reads, masked terms) so that every read is in
     // flight before the first use.
