@@ -1498,8 +1498,13 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
     k_gm_init<T><<<1, kGmThreads, 0, s>>>(gm_init_args<T>(P, Nb, o, mixed, x0));
     KFBI_CHECK_LAUNCH();
     const int *skip64 = &P.ctl->skip64, *skip32 = &P.ctl->skip32, *skip_tail = &P.ctl->skip_tail;
-    // first batch: the previous solve's slot count on this domain plus one
-    int want = d->last_slots > 0 ? d->last_slots + 1 : (fixed > 0 ? fixed + 2 : 12);
+    // first batch: the most slots any of the last four solves on this domain
+    // took.  A steady count then leaves no surplus slot (each costs a gated
+    // launch per kernel) and a count that varies by one is rarely short (a
+    // short batch costs a wait for the host to enqueue more)
+    int want = 0;
+    for (int q = 0; q < 4; ++q) want = std::max(want, d->slot_hist[q]);
+    if (want == 0) want = fixed > 0 ? fixed + 2 : 12;
     int n_enq = 0, last_batch = 0, seq_last = 0;
     for (int batch = 0;; ++batch) {
         last_batch = batch;
@@ -1555,6 +1560,7 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
         seq_last = seq;
         if (st == kStDone) {
             d->last_slots = seq;
+            d->slot_hist[d->slot_pos++ & 3] = seq;
             break;
         }
         want = 4;
@@ -1880,6 +1886,8 @@ struct kfbi_batch {
     char *h_args = nullptr, *d_args = nullptr;
     size_t use_off[kfbi::kUses] = {}, use_size[kfbi::kUses] = {}, args_bytes = 0;
     int last_slots = 0;
+    int slot_hist[4] = {0, 0, 0, 0};  // slots of the last four batched solves
+    int slot_pos = 0;
     int nb_max = 0, m_lds = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int *d_one = nullptr;  // a device word holding 1: the gate of members not solved in a call
@@ -2327,7 +2335,11 @@ int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im
     KFBI_CHECK_LAUNCH();
     // slots until every member has finished
     const int ept = (b->nb_max + kGmThreads - 1) / kGmThreads;
-    int want = b->last_slots > 0 ? b->last_slots + 1 : (o.fixed_iters > 0 ? o.fixed_iters + 2 : 16);
+    // first batch: the most slots any of the last four batched solves took
+    // (as for single domains)
+    int want = 0;
+    for (int q = 0; q < 4; ++q) want = std::max(want, b->slot_hist[q]);
+    if (want == 0) want = o.fixed_iters > 0 ? o.fixed_iters + 2 : 16;
     int n_enq = 0;
     for (;;) {
         for (int c = 0; c < want; ++c) {
@@ -2426,6 +2438,7 @@ int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im
         if (!mh->converged && o.fixed_iters <= 0) st = KFBI_ENOCONV;
     }
     b->last_slots = max_seq;
+    b->slot_hist[b->slot_pos++ & 3] = max_seq;
     KFBI_HIP(hipEventRecord(b->ev1, s));
     if (!(o.flags & KFBI_SOLVE_ASYNC)) {
         KFBI_HIP(hipEventSynchronize(b->ev1));

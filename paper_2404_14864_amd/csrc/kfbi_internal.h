@@ -396,6 +396,8 @@ struct kfbi_domain {
     size_t gm_bytes = 0;
     int last_iters = 0;                 // iterations of the previous solve (chunk sizing)
     int last_slots = 0;                 // grid solves of the previous device-driven solve
+    int slot_hist[4] = {0, 0, 0, 0};    //   and of the last four (ring, next at slot_pos & 3)
+    int slot_pos = 0;
     void *mirror_host = nullptr;        // pinned host copy of the GMRES control block
     void *mirror_dev = nullptr;         //   and its device address
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // solve timing
