@@ -1734,12 +1734,15 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     // U = IS(f, phi).U on the grid (gate: null, or the finish flag of the
     // device-driven schedule)
     auto final_solve = [&](const int *gate) -> int {
+        bool copied = false;  // phi_inout written by the corrections' launch
         if (bc) KFBI_TRY(compute_corrections_psi_ctl(d, kre, kim, f_gamma, P.x, d->corr, gate));
-        else if (d->op_merged && (f_grid != nullptr) == (f_gamma != nullptr))
+        else if (d->op_merged && (f_grid != nullptr) == (f_gamma != nullptr)) {
             // corrections of f (from the b-solve) plus the density's, by the
-            // merged operator
-            KFBI_TRY(corrections_of_density(d, P.x, d->corr, gate, f_grid ? d->corr_f : nullptr));
-        else KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
+            // merged operator; the same launch copies the density out
+            copied = gate && phi_inout;
+            KFBI_TRY(corrections_of_density(d, P.x, d->corr, gate, f_grid ? d->corr_f : nullptr,
+                                            copied ? phi_inout : nullptr));
+        } else KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
         KFBI_TRY(tridiag_solve_ctl(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat, gate));
         if (u_grid_out) KFBI_TRY(idst_rows_dense_ctl(d, d->uhat, u_grid_out, gate));
         if (bc && trace_out) {
@@ -1748,7 +1751,7 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
             KFBI_TRY(extract_boundary_psi_ctl(d, kre, kim, d->ust, f_gamma, P.x, false, nullptr, 1.0, trace_out,
                                               gate));
         }
-        if (phi_inout) {
+        if (phi_inout && !copied) {
             if (gate) {
                 const int n = (int)(vb / sizeof(double));
                 k_copy_gated<double><<<(n + 255) / 256, 256, 0, s>>>(n, (double *)phi_inout, (const double *)P.x,

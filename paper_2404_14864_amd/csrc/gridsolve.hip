@@ -258,6 +258,15 @@ __global__ __launch_bounds__(256) void k_zero_edge_rows(ZeroArgs<T> A) {
     zero_edge_body(A, blockIdx.x);
 }
 
+// the DST of rows into a grid array with, from the workgroups past the
+// transform's nd, the zeros of the grid's first and last rows (one launch
+// instead of two; the two write disjoint rows)
+template <class T>
+__global__ __launch_bounds__(256) void k_dst_rows_grid(DstArgs<T> A, ZeroArgs<T> Z, int nd) {
+    if ((int)blockIdx.x < nd) dst_rows_body(A, blockIdx.x);
+    else zero_edge_body(Z, (int)blockIdx.x - nd);
+}
+
 // ---------------------------------------------------------------------------
 // Thomas coefficients.  With e_1 = 1/d, e_t = 1/(d - e_{t-1}) the forward
 // sweep is x_t = e_t (x_{t-1} - rho_t) and the backward sweep
@@ -994,9 +1003,18 @@ __device__ void corr_phi_body(const CorrPhiArgs<TC> &A, int blk) {
     corr[q] = acc;
 }
 
+// With copy_out, the workgroups past those of the corrections copy the
+// density there (one launch instead of two)
 template <class TC>
 __global__ __launch_bounds__(64) void k_corr_phi(CorrPhiArgs<TC> A) {
-    corr_phi_body(A, blockIdx.x);
+    const int nbc = (A.nnz + 63) / 64;
+    if ((int)blockIdx.x < nbc) {
+        corr_phi_body(A, blockIdx.x);
+        return;
+    }
+    if (A.done && *A.done) return;
+    const int k = ((int)blockIdx.x - nbc) * 64 + (int)threadIdx.x;
+    if (k < A.Nb) A.copy_out[k] = A.phi[k];
 }
 
 // K phi at the collocation points, one workgroup of six wavefronts per
@@ -1244,25 +1262,26 @@ int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask
     const int M = d->M, n = M - 1;
     const DstArgs<T> A = dst_args<T>(d, in, in_grid, mask, out, out_grid, scale, done);
     const int ps = prof_begin(d);
-    k_dst_rows<T><<<dst_blocks<T>(M), 256, dst_lds(M), d->stream>>>(A);
+    const int nd = dst_blocks<T>(M);
+    if (out_grid)
+        k_dst_rows_grid<T><<<nd + (M + 1 + 255) / 256, 256, dst_lds(M), d->stream>>>(
+            A, ZeroArgs<T>{M, (T *)out, done}, nd);
+    else
+        k_dst_rows<T><<<nd, 256, dst_lds(M), d->stream>>>(A);
     KFBI_CHECK_LAUNCH();
     {
         const double es = sizeof(T), nn = (double)n * n, grid = (double)(M + 1) * (M + 1);
         const double bytes = in_grid ? es * (nn + nn) + (mask ? nn : 0.0) : es * (nn + grid);
         prof_end(d, ps, in_grid ? KFBI_K_DST : KFBI_K_IDST, bytes);
     }
-    if (out_grid) {
-        k_zero_edge_rows<T><<<(M + 1 + 255) / 256, 256, 0, d->stream>>>(ZeroArgs<T>{M, (T *)out, done});
-        KFBI_CHECK_LAUNCH();
-    }
     return KFBI_OK;
 }
 
 template <class TC>
 CorrPhiArgs<TC> corr_phi_args(kfbi_domain *d, const void *phi, void *corr, const int *done,
-                              const void *base = nullptr) {
+                              const void *base = nullptr, void *copy_out = nullptr) {
     return CorrPhiArgs<TC>{(const TC *)phi, d->Nb,  d->n_irr, (const TC *)d->mcoef, d->mbase, (TC *)corr, done,
-                           (const TC *)base};
+                           (const TC *)base, (TC *)copy_out};
 }
 
 template <class T, class TO>
@@ -1814,14 +1833,16 @@ int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out) {
 
 
 
-int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done, const void *base) {
+int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done, const void *base,
+                           void *copy_out) {
     const int nnz = d->n_irr;
+    const int blocks = (nnz + 63) / 64 + (copy_out ? (d->Nb + 63) / 64 : 0);
     const int ps = prof_begin(d);
     if (d->cplx)
-        k_corr_phi<cd><<<(nnz + 63) / 64, 64, 0, d->stream>>>(corr_phi_args<cd>(d, phi, corr_out, done, base));
+        k_corr_phi<cd><<<blocks, 64, 0, d->stream>>>(corr_phi_args<cd>(d, phi, corr_out, done, base, copy_out));
     else
-        k_corr_phi<double><<<(nnz + 63) / 64, 64, 0, d->stream>>>(
-            corr_phi_args<double>(d, phi, corr_out, done, base));
+        k_corr_phi<double><<<blocks, 64, 0, d->stream>>>(
+            corr_phi_args<double>(d, phi, corr_out, done, base, copy_out));
     KFBI_CHECK_LAUNCH();
     const double es = elem_size(d);
     prof_end(d, ps, KFBI_K_CORRECTIONS, (double)nnz * (kCorrWin * es + 4.0 + es) + (double)d->Nb * es);

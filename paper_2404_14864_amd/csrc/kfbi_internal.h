@@ -456,7 +456,7 @@ const void *gmres_last_density(kfbi_domain *d);
 // corrections of a density with the merged operator (many workgroups),
 // plus base (nullable) node by node
 int corrections_of_density(kfbi_domain *d, const void *phi, void *corr_out, const int *done,
-                           const void *base = nullptr);
+                           const void *base = nullptr, void *copy_out = nullptr);
 
 // interface pieces (interface.hip)
 int compute_corrections(kfbi_domain *d, double kre, double kim, const void *phi,
@@ -606,6 +606,8 @@ struct CorrPhiArgs {
     TC *corr;
     const int *done;
     const TC *base;       // nullable: corrections added to the density's
+    TC *copy_out;         // nullable: the launch also copies the density here
+                          // (workgroups past the corrections' own)
 };
 
 template <class T, class TO>
