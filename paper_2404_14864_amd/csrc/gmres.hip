@@ -1559,7 +1559,6 @@ static int gmres_run_slots(kfbi_domain *d, GmPtrs &P, const void *x0, const kfbi
         }
         seq_last = seq;
         if (st == kStDone) {
-            d->last_slots = seq;
             d->slot_hist[d->slot_pos++ & 3] = seq;
             break;
         }
@@ -1721,10 +1720,14 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
         // the density to them (the interface problem is affine in phi)
         KFBI_TRY(compute_corrections(d, kre, kim, nullptr, f_gamma, d->corr_f));
         KFBI_TRY(tridiag_solve(d, d->rhat, d->corr_f, d->uhat));
-        KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
-        if (bc) KFBI_TRY(extract_boundary_psi_ctl(d, kre, kim, d->ust, f_gamma, nullptr, true, g_gamma, -1.0, P.b,
-                                                  nullptr));
-        else KFBI_TRY(extract_boundary(d, kre, kim, d->ust, nullptr, f_gamma, g_gamma, -1.0, P.b));
+        if (bc) {
+            KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));
+            KFBI_TRY(extract_boundary_psi_ctl(d, kre, kim, d->ust, f_gamma, nullptr, true, g_gamma, -1.0, P.b,
+                                              nullptr));
+        } else {
+            // stencil values and extraction in one launch
+            KFBI_TRY(eval_extract_boundary(d, kre, kim, d->uhat, f_gamma, g_gamma, -1.0, P.b));
+        }
     } else {
         KFBI_HIP(hipMemcpyAsync(P.b, g_gamma, vb, hipMemcpyDeviceToDevice, s));
     }
@@ -1888,7 +1891,6 @@ struct kfbi_batch {
     // argument staging
     char *h_args = nullptr, *d_args = nullptr;
     size_t use_off[kfbi::kUses] = {}, use_size[kfbi::kUses] = {}, args_bytes = 0;
-    int last_slots = 0;
     int slot_hist[4] = {0, 0, 0, 0};  // slots of the last four batched solves
     int slot_pos = 0;
     int nb_max = 0, m_lds = 0;
@@ -2440,7 +2442,6 @@ int batch_helmholtz_t(kfbi_batch *b, const double *kappa, const double *kappa_im
         }
         if (!mh->converged && o.fixed_iters <= 0) st = KFBI_ENOCONV;
     }
-    b->last_slots = max_seq;
     b->slot_hist[b->slot_pos++ & 3] = max_seq;
     KFBI_HIP(hipEventRecord(b->ev1, s));
     if (!(o.flags & KFBI_SOLVE_ASYNC)) {

@@ -37,6 +37,7 @@
 #include <cstring>
 
 #include "kfbi_internal.h"
+#include "jumps.h"
 
 namespace kfbi {
 
@@ -251,11 +252,6 @@ __device__ void zero_edge_body(const ZeroArgs<T> &A, int blk) {
     if (i > M) return;
     A.grid[i] = zero<T>();
     A.grid[(size_t)M * (M + 1) + i] = zero<T>();
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_zero_edge_rows(ZeroArgs<T> A) {
-    zero_edge_body(A, blockIdx.x);
 }
 
 // the DST of rows into a grid array with, from the workgroups past the
@@ -1118,6 +1114,59 @@ struct EvxLaunch {
     }
 };
 
+// The b-solve's stencil values and general extraction in one launch: one
+// workgroup of six wavefronts per collocation point; wavefront p evaluates
+// stencil node p (the sums of k_eval_nodes, as in k_eval_extract), thread 0
+// forms U+ with the jumps of f and the boundary data (as k_extract) from the
+// six values in LDS.
+template <class T, int KR>
+__device__ void eval_extract_gen_body(const EvalArgs<T, T> &E, const ExtArgs<T> &X, int blk) {
+    typedef typename Real<T>::type R;
+    __shared__ T su[6];
+    const int M = E.M, n = M - 1;
+    const int lane = threadIdx.x & 63, p = threadIdx.x >> 6;
+    const int k = blk;
+    const int node = __builtin_amdgcn_readfirstlane(E.nodes[(size_t)k * E.node_stride + p]);
+    const int i = node % (M + 1);
+    const T *row = E.uhat + (size_t)(node / (M + 1) - 1) * n;
+    T acc;
+    if constexpr (KR > 0) {
+        T v[KR];
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+            const int q = lane + 64 * j;
+            const T x = gld(gview(row) + min(q, n - 1));
+            v[j] = q < n ? x : zero<T>();
+        }
+        acc = mode_sum<KR, T>(gview(E.sine), cview(E.scu), M, n, i, lane, [&](int jj) { return v[jj]; });
+    } else {
+        acc = mode_sum<0, T>(gview(E.sine), cview(E.scu), M, n, i, lane,
+                             [&](int q) { return gld(gview(row) + lane + 64 * q); });
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) su[p] = acc * (R)(2.0 / M);
+    __syncthreads();
+    if (threadIdx.x == 0) extract_point(X, k, [&](int q) { return su[q]; });
+}
+
+template <class T, int KR>
+__global__ __launch_bounds__(384) void k_eval_extract_gen(EvalArgs<T, T> E, ExtArgs<T> X) {
+    eval_extract_gen_body<T, KR>(E, X, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <class T>
+struct EvxGenLaunch {
+    EvalArgs<T, T> E;
+    ExtArgs<T> X;
+    int blocks;
+    hipStream_t s;
+    template <int KR>
+    void go() const {
+        k_eval_extract_gen<T, KR><<<blocks, 384, 0, s>>>(E, X);
+    }
+};
+
+
 // Grid values at the stencil nodes by rows: U = (2/M) sum_k U^[t][k]
 // sin(pi i k / M) at each distinct stencil node (t, i), in the same sum and
 // reduction order as k_eval_nodes.  Each wavefront takes kErowRows/4 rows
@@ -1888,6 +1937,31 @@ int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, cons
     KFBI_CHECK_LAUNCH();
     const double es = low ? elem_size(d) / 2.0 : elem_size(d);
     prof_end(d, ps, KFBI_K_EVAL_NODES, (double)nn * ((d->M - 1) * es + 4.0 + elem_size(d)));
+    return KFBI_OK;
+}
+
+// The b-solve's stencil values and extraction, out = g + scale U+ with the
+// jumps of f alone (no density), in one launch (k_eval_extract_gen)
+int eval_extract_boundary(kfbi_domain *d, double kre, double kim, const void *uhat, const void *f_gamma,
+                          const void *g, double scale, void *out) {
+    alignas(16) unsigned char buf[sizeof(ExtArgs<cd>)];
+    batch_fill_ext(d, kre, kim, nullptr, nullptr, f_gamma, g, scale, out, nullptr, buf);
+    const int Nb = d->Nb;
+    const int ps = prof_begin(d);
+    if (d->cplx) {
+        ExtArgs<cd> X = *(const ExtArgs<cd> *)buf;
+        X.nid = nullptr;
+        evx_dispatch(d->M, EvxGenLaunch<cd>{eval_args<cd, cd>(d, uhat, nullptr, nullptr), X, Nb, d->stream});
+    } else {
+        ExtArgs<double> X = *(const ExtArgs<double> *)buf;
+        X.nid = nullptr;
+        evx_dispatch(d->M, EvxGenLaunch<double>{eval_args<double, double>(d, uhat, nullptr, nullptr), X, Nb,
+                                                d->stream});
+    }
+    KFBI_CHECK_LAUNCH();
+    const double es = elem_size(d);
+    prof_end(d, ps, KFBI_K_EXTRACT,
+             (double)Nb * (6.0 * ((d->M - 1) * es + 4.0) + sizeof(Colloc) + sizeof(Stencil) + 3.0 * es));
     return KFBI_OK;
 }
 

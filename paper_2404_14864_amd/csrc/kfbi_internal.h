@@ -395,8 +395,8 @@ struct kfbi_domain {
     void *gm = nullptr;                 // device GmresState (+ basis)
     size_t gm_bytes = 0;
     int last_iters = 0;                 // iterations of the previous solve (chunk sizing)
-    int last_slots = 0;                 // grid solves of the previous device-driven solve
-    int slot_hist[4] = {0, 0, 0, 0};    //   and of the last four (ring, next at slot_pos & 3)
+    int slot_hist[4] = {0, 0, 0, 0};    // grid solves of the last four device-driven solves
+                                        // (ring, next entry at slot_pos & 3)
     int slot_pos = 0;
     void *mirror_host = nullptr;        // pinned host copy of the GMRES control block
     void *mirror_dev = nullptr;         //   and its device address
@@ -441,6 +441,8 @@ int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out);
 int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done);
 // U at the 6 Nb stencil nodes
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out);
+int eval_extract_boundary(kfbi_domain *d, double kre, double kim, const void *uhat, const void *f_gamma,
+                          const void *g, double scale, void *out);
 int eval_stencil_nodes_ctl(kfbi_domain *d, const void *uhat, void *ust_out, const int *done, bool low = false);
 // K phi at the collocation points from the mode-space solution of phi's
 // corrections (merged operator form: stencil weights w6, jump terms bop)
