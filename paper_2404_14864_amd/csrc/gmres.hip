@@ -1715,10 +1715,10 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
     if (mixed) KFBI_TRY(ensure_coefficients_low(d, kre, kim));
     // b = g - IS(f, 0).U+ (Dirichlet), b = g - IS(f, 0, 0).dU+/dn (Neumann)
     if (f_grid) {
-        KFBI_TRY(dst_rows_dense(d, f_grid, true, d->rhat));
-        // the corrections of f alone are kept: the final solve adds those of
-        // the density to them (the interface problem is affine in phi)
-        KFBI_TRY(compute_corrections(d, kre, kim, nullptr, f_gamma, d->corr_f));
+        // the DST of f and the corrections of f alone in one launch; the
+        // corrections are kept: the final solve adds those of the density to
+        // them (the interface problem is affine in phi)
+        KFBI_TRY(dst_rows_dense_corr(d, f_grid, d->rhat, kre, kim, f_gamma, d->corr_f));
         KFBI_TRY(tridiag_solve(d, d->rhat, d->corr_f, d->uhat));
         if (bc) {
             KFBI_TRY(eval_stencil_nodes(d, d->uhat, d->ust));

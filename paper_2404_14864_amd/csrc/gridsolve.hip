@@ -254,6 +254,15 @@ __device__ void zero_edge_body(const ZeroArgs<T> &A, int blk) {
     A.grid[(size_t)M * (M + 1) + i] = zero<T>();
 }
 
+// the b-solve's DST of f with, from the workgroups past the transform's nd,
+// the corrections of f at the irregular nodes (independent work; one launch
+// instead of two)
+template <class T>
+__global__ __launch_bounds__(256) void k_dst_rows_corr(DstArgs<T> A, CorrArgs<T> C, int nd) {
+    if ((int)blockIdx.x < nd) dst_rows_body(A, blockIdx.x);
+    else corrections_body(C, (int)blockIdx.x - nd);
+}
+
 // the DST of rows into a grid array with, from the workgroups past the
 // transform's nd, the zeros of the grid's first and last rows (one launch
 // instead of two; the two write disjoint rows)
@@ -1855,6 +1864,30 @@ int dst_rows_dense(kfbi_domain *d, const void *grid, bool mask_inside, void *rha
     const uint8_t *mask = mask_inside ? d->flags : nullptr;
     if (d->cplx) return launch_dst<cd>(d, grid, true, mask, rhat_out, false, 1.0);
     return launch_dst<double>(d, grid, true, mask, rhat_out, false, 1.0);
+}
+
+// the b-solve's forward DST of f (masked to the inside) and the
+// corrections of f alone (no density), in one launch
+int dst_rows_dense_corr(kfbi_domain *d, const void *grid, void *rhat_out, double kre, double kim,
+                        const void *f_gamma, void *corr_out) {
+    alignas(16) unsigned char buf[sizeof(CorrArgs<cd>)];
+    batch_fill_corr(d, kre, kim, nullptr, f_gamma, corr_out, nullptr, buf);
+    const int M = d->M, n = M - 1;
+    const int ps = prof_begin(d);
+    if (d->cplx) {
+        const int nd = dst_blocks<cd>(M);
+        k_dst_rows_corr<cd><<<nd + (d->n_irr + 255) / 256, 256, dst_lds(M), d->stream>>>(
+            dst_args<cd>(d, grid, true, d->flags, rhat_out, false, 1.0, nullptr), *(const CorrArgs<cd> *)buf, nd);
+    } else {
+        const int nd = dst_blocks<double>(M);
+        k_dst_rows_corr<double><<<nd + (d->n_irr + 255) / 256, 256, dst_lds(M), d->stream>>>(
+            dst_args<double>(d, grid, true, d->flags, rhat_out, false, 1.0, nullptr),
+            *(const CorrArgs<double> *)buf, nd);
+    }
+    KFBI_CHECK_LAUNCH();
+    const double es = elem_size(d), nn = (double)n * n;
+    prof_end(d, ps, KFBI_K_DST, es * (nn + nn) + nn + (double)d->n_irr * (sizeof(IrrNode) + es));
+    return KFBI_OK;
 }
 
 int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out) {

@@ -28,59 +28,6 @@ namespace kfbi {
 namespace {
 
 template <class T>
-__device__ void corrections_body(const CorrArgs<T> &A, int blk) {
-    const int n_irr = A.n_irr, Nb = A.Nb;
-    const IrrNode *__restrict__ irr = A.irr;
-    const Edge *__restrict__ edges = A.edges;
-    const double dth = A.dth, h = A.h;
-    const T kappa = A.kappa;
-    const T *phi_base = A.phi_base;
-    const int *jptr = A.jptr;
-    const T *__restrict__ fg = A.fg;
-    const T *__restrict__ psi = A.psi;
-    T *__restrict__ corr = A.corr;
-    if (A.done && *A.done) return;
-    int q = blk * blockDim.x + threadIdx.x;
-    if (q >= n_irr) return;
-    const T *phi = at_slot(phi_base, jptr, 0, (size_t)Nb);
-    const double i12d = 1.0 / (12.0 * dth), i12d2 = 1.0 / (12.0 * dth * dth);
-    const IrrNode R = irr[q];
-    T acc = zero<T>();
-    for (int s = 0; s < R.nedge; ++s) {
-        const Edge &E = edges[R.edge[s]];
-        T p = zero<T>(), pt = zero<T>(), ptt = zero<T>(), fv = zero<T>();
-        for (int o = 0; o < 4; ++o) {
-            int kk = wrapk(E.k0 - 1 + o, Nb);
-            double w = E.w[o];
-            if (phi) {
-                T a, b, c;
-                bdata(phi, Nb, kk, i12d, i12d2, a, b, c);
-                p += a * w;
-                pt += b * w;
-                ptt += c * w;
-            }
-            if (fg) fv += fg[kk] * w;
-        }
-        Jumps<T> J = jumps_dirichlet(E.fr, p, pt, ptt, fv, kappa);
-        if (psi) {
-            T s = zero<T>(), st = zero<T>();
-            for (int o = 0; o < 4; ++o) {
-                T a, b, c;
-                bdata(psi, Nb, wrapk(E.k0 - 1 + o, Nb), i12d, i12d2, a, b, c);
-                s += a * E.w[o];
-                st += b * E.w[o];
-            }
-            add_jumps(J, jumps_psi(E.fr, s, st));
-        }
-        const T ua = E.axis == 0 ? J.ux : J.uy;
-        const T uaa = E.axis == 0 ? J.uxx : J.uyy;
-        const double dd = R.d[s];
-        acc += J.u + ua * dd + uaa * (0.5 * dd * dd);
-    }
-    corr[q] = acc * (-R.sgn / (h * h));
-}
-
-template <class T>
 __global__ __launch_bounds__(128) void k_corrections(CorrArgs<T> A) {
     corrections_body(A, blockIdx.x);
 }

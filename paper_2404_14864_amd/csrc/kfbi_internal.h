@@ -433,6 +433,8 @@ int noalloc_scratch(hipStream_t s, void **out);
 int ensure_coefficients(kfbi_domain *d, double kre, double kim);
 // R = dense rhs (grid array, nullable) masked to inside nodes when mask_inside
 int dst_rows_dense(kfbi_domain *d, const void *grid, bool mask_inside, void *rhat_out);
+int dst_rows_dense_corr(kfbi_domain *d, const void *grid, void *rhat_out, double kre, double kim,
+                        const void *f_gamma, void *corr_out);
 // Uhat = T^{-1} h^2 (rhat (nullable) + synth(corr))
 int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out);
 int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out, const int *done);
