@@ -786,11 +786,11 @@ int kfbi_stepper_init(kfbi_stepper *s, const void *u0, const void *lap0, const v
 // the recurrence carries there: g itself for the Dirichlet problem, the
 // extracted U+ for the Neumann problem (g is then du/dn).
 static int step_solve(kfbi_stepper *s, const void *g_next, void *u_out, const kfbi_solve_opts *opts,
-                      kfbi_solve_stats *stats, const void **trace) {
+                      kfbi_solve_stats *stats, const void **trace, const GridUpdate *up = nullptr) {
     const bool neu = s->p.bc == KFBI_BC_NEUMANN;
     *trace = neu ? s->tr : g_next;
     return helmholtz_solve(s->dom, s->kre, s->kim, s->f, s->fg, g_next, u_out, s->phi, opts, stats, neu ? 1 : 0,
-                           neu ? s->tr : nullptr);
+                           neu ? s->tr : nullptr, up);
 }
 
 int kfbi_step_heat(kfbi_stepper *s, const void *g_next, const void *src, const void *srcg, void *u_out,
@@ -834,9 +834,14 @@ int kfbi_step_schrodinger(kfbi_stepper *s, const void *g_next, void *u_out, cons
     if (s->eq != KFBI_SCHRODINGER || !s->initialized) { set_error("not an initialised Schroedinger stepper"); return KFBI_EINVAL; }
     KFBI_TRY(schr_b_step(s));
     const void *tr = nullptr;
-    int st = step_solve(s, g_next, u_out, opts, stats, &tr);
+    // Strang splitting with Dirichlet data: the next u* = 2 u^{n+1} - u**
+    // (grid and Gamma) is formed by the final solve's inverse transform as it
+    // writes u^{n+1}, with the same sums as schr_state_update
+    const bool fused = s->p.split != KFBI_SPLIT_GODUNOV && s->p.bc != KFBI_BC_NEUMANN;
+    const GridUpdate up{s->A, s->Ag, g_next, 2.0, 0.0, -1.0, 0.0};
+    int st = step_solve(s, g_next, u_out, opts, stats, &tr, fused ? &up : nullptr);
     if (st != KFBI_OK && st != KFBI_ENOCONV) return st;
-    KFBI_TRY(schr_state_update(s, u_out, tr));
+    if (!fused) KFBI_TRY(schr_state_update(s, u_out, tr));
     return st;
 }
 

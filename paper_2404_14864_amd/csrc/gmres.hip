@@ -1650,7 +1650,7 @@ int replay_slot(kfbi_domain *d, int reps, double *avg_ms, double *bytes) {
 
 int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, const void *f_gamma,
                     const void *g_gamma, void *u_grid_out, void *phi_inout, const kfbi_solve_opts *opts,
-                    kfbi_solve_stats *stats, int bc, void *trace_out) {
+                    kfbi_solve_stats *stats, int bc, void *trace_out, const GridUpdate *up) {
     kfbi_solve_opts o;
     o.tol = 1e-10;
     o.max_iter = 500;
@@ -1747,7 +1747,8 @@ int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid, 
                                             copied ? phi_inout : nullptr));
         } else KFBI_TRY(compute_corrections_ctl(d, kre, kim, P.x, nullptr, f_gamma, d->corr, gate));
         KFBI_TRY(tridiag_solve_ctl(d, f_grid ? d->rhat : nullptr, d->corr, d->uhat, gate));
-        if (u_grid_out) KFBI_TRY(idst_rows_dense_ctl(d, d->uhat, u_grid_out, gate));
+        // the inverse transform also makes the caller's state update, if any
+        if (u_grid_out) KFBI_TRY(idst_rows_dense_ctl(d, d->uhat, u_grid_out, gate, up));
         if (bc && trace_out) {
             // U+ of the solution at the collocation points (the trace of u)
             KFBI_TRY(eval_stencil_nodes_ctl(d, d->uhat, d->ust, gate));

@@ -79,6 +79,16 @@ template <> __device__ inline cf one<cf>() { return make_cf(1.0f, 0.0f); }
 
 __device__ inline unsigned bitrev(unsigned m, int bits) { return __brev(m) >> (32 - bits); }
 
+// c0 x0 + c1 x1 summed from zero in this order (the stepper's update kernel)
+template <class T>
+__device__ __forceinline__ T lin2(T c0, T x0, T c1, T x1) {
+    T acc = zero<T>();
+    acc += c0 * x0;
+    acc += c1 * x1;
+    return acc;
+}
+
+
 // ---------------------------------------------------------------------------
 // dense DST-I of rows.
 //   in(t, i)  for i = 1..M-1 at in[in_off(t) + i - 1]
@@ -211,20 +221,24 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
         }
         __syncthreads();
     }
-    // unpack
+    // unpack (and, with upd, the state update at each written node)
+    T *upd = A.upd;
     for (int k = 1 + threadIdx.x; k <= n; k += blockDim.x) {
         double2 Z = a[k];
         for (int r = 0; r < rows_per; ++r) {
             int t = t_first + r;
             if (t >= n) continue;
             size_t idx = out_grid ? (size_t)(t + 1) * (M + 1) + k : (size_t)t * n + (k - 1);
+            T val;
             if constexpr (CPLX) {
                 // S_k = i Y_k / 2
-                gst(out + idx, make_cd(-0.5 * scale * Z.y, 0.5 * scale * Z.x));
+                val = make_cd(-0.5 * scale * Z.y, 0.5 * scale * Z.x);
             } else {
                 double v = (r == 0) ? -0.5 * Z.y : 0.5 * Z.x;
-                gst(out + idx, scale * v);
+                val = scale * v;
             }
+            gst(out + idx, val);
+            if (upd) upd[idx] = lin2(A.upd_c0, val, A.upd_c1, upd[idx]);
         }
     }
     if (out_grid) {  // boundary columns of the interior rows
@@ -234,6 +248,10 @@ __device__ void dst_rows_body(const DstArgs<T> &A, int blk) {
             size_t base = (size_t)(t + 1) * (M + 1);
             gst(out + base, zero<T>());
             gst(out + base + M, zero<T>());
+            if (upd) {
+                upd[base] = lin2(A.upd_c0, zero<T>(), A.upd_c1, upd[base]);
+                upd[base + M] = lin2(A.upd_c0, zero<T>(), A.upd_c1, upd[base + M]);
+            }
         }
     }
 }
@@ -250,8 +268,22 @@ __device__ void zero_edge_body(const ZeroArgs<T> &A, int blk) {
     const int M = A.M;
     int i = blk * blockDim.x + threadIdx.x;
     if (i > M) return;
+    const size_t last = (size_t)M * (M + 1) + i;
     A.grid[i] = zero<T>();
-    A.grid[(size_t)M * (M + 1) + i] = zero<T>();
+    A.grid[last] = zero<T>();
+    if (A.upd) {
+        A.upd[i] = lin2(A.upd_c0, zero<T>(), A.upd_c1, A.upd[i]);
+        A.upd[last] = lin2(A.upd_c0, zero<T>(), A.upd_c1, A.upd[last]);
+    }
+}
+
+// the Gamma part of the state update (ZeroArgs::upd_ag)
+template <class T>
+__device__ void gamma_update_body(const ZeroArgs<T> &A, int blk) {
+    if (A.done && *A.done) return;
+    const int i = blk * blockDim.x + threadIdx.x;
+    if (i >= A.nb) return;
+    A.upd_ag[i] = lin2(A.upd_c0, A.upd_g[i], A.upd_c1, A.upd_ag[i]);
 }
 
 // the b-solve's DST of f with, from the workgroups past the transform's nd,
@@ -267,9 +299,11 @@ __global__ __launch_bounds__(256) void k_dst_rows_corr(DstArgs<T> A, CorrArgs<T>
 // transform's nd, the zeros of the grid's first and last rows (one launch
 // instead of two; the two write disjoint rows)
 template <class T>
-__global__ __launch_bounds__(256) void k_dst_rows_grid(DstArgs<T> A, ZeroArgs<T> Z, int nd) {
-    if ((int)blockIdx.x < nd) dst_rows_body(A, blockIdx.x);
-    else zero_edge_body(Z, (int)blockIdx.x - nd);
+__global__ __launch_bounds__(256) void k_dst_rows_grid(DstArgs<T> A, ZeroArgs<T> Z, int nd, int nz) {
+    const int b = blockIdx.x;
+    if (b < nd) dst_rows_body(A, b);
+    else if (b < nd + nz) zero_edge_body(Z, b - nd);
+    else gamma_update_body(Z, b - nd - nz);  // with a state update only
 }
 
 // ---------------------------------------------------------------------------
@@ -1291,6 +1325,10 @@ __global__ __launch_bounds__(256) void k_extract_merged(ExmArgs<T> A) {
 }
 
 // argument blocks and launch shapes shared by the single and batched paths
+template <class T> T coef_of(double re, double im);
+template <> double coef_of<double>(double re, double) { return re; }
+template <> cd coef_of<cd>(double re, double im) { return make_cd(re, im); }
+
 template <class T>
 DstArgs<T> dst_args(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out, bool out_grid,
                     double scale, const int *done) {
@@ -1306,6 +1344,9 @@ DstArgs<T> dst_args(kfbi_domain *d, const void *in, bool in_grid, const uint8_t 
     A.scale = scale;
     A.twiddle = d->twiddle;
     A.done = done;
+    A.upd = nullptr;
+    A.upd_c0 = zero<T>();
+    A.upd_c1 = zero<T>();
     return A;
 }
 template <class T>
@@ -1316,15 +1357,25 @@ inline size_t dst_lds(int M) { return (size_t)2 * M * sizeof(double2); }
 
 template <class T>
 int launch_dst(kfbi_domain *d, const void *in, bool in_grid, const uint8_t *mask, void *out,
-               bool out_grid, double scale, const int *done = nullptr) {
+               bool out_grid, double scale, const int *done = nullptr, const GridUpdate *up = nullptr) {
     const int M = d->M, n = M - 1;
-    const DstArgs<T> A = dst_args<T>(d, in, in_grid, mask, out, out_grid, scale, done);
+    DstArgs<T> A = dst_args<T>(d, in, in_grid, mask, out, out_grid, scale, done);
     const int ps = prof_begin(d);
-    const int nd = dst_blocks<T>(M);
-    if (out_grid)
-        k_dst_rows_grid<T><<<nd + (M + 1 + 255) / 256, 256, dst_lds(M), d->stream>>>(
-            A, ZeroArgs<T>{M, (T *)out, done}, nd);
-    else
+    const int nd = dst_blocks<T>(M), nz = (M + 1 + 255) / 256;
+    if (out_grid) {
+        ZeroArgs<T> Z{M, (T *)out, done};
+        int ng = 0;  // workgroups of the Gamma part of a state update
+        if (up) {
+            A.upd = Z.upd = (T *)up->a;
+            A.upd_c0 = Z.upd_c0 = coef_of<T>(up->c0r, up->c0i);
+            A.upd_c1 = Z.upd_c1 = coef_of<T>(up->c1r, up->c1i);
+            Z.upd_g = (const T *)up->g;
+            Z.upd_ag = (T *)up->ag;
+            Z.nb = d->Nb;
+            ng = (d->Nb + 255) / 256;
+        }
+        k_dst_rows_grid<T><<<nd + nz + ng, 256, dst_lds(M), d->stream>>>(A, Z, nd, nz);
+    } else
         k_dst_rows<T><<<nd, 256, dst_lds(M), d->stream>>>(A);
     KFBI_CHECK_LAUNCH();
     {
@@ -1894,10 +1945,10 @@ int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out) {
     return idst_rows_dense_ctl(d, uhat, grid_out, nullptr);
 }
 
-int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done) {
+int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done, const GridUpdate *up) {
     double scale = 2.0 / d->M;
-    if (d->cplx) return launch_dst<cd>(d, uhat, false, nullptr, grid_out, true, scale, done);
-    return launch_dst<double>(d, uhat, false, nullptr, grid_out, true, scale, done);
+    if (d->cplx) return launch_dst<cd>(d, uhat, false, nullptr, grid_out, true, scale, done, up);
+    return launch_dst<double>(d, uhat, false, nullptr, grid_out, true, scale, done, up);
 }
 
 int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out) {

@@ -440,7 +440,9 @@ int tridiag_solve(kfbi_domain *d, const void *rhat, const void *corr, void *uhat
 int tridiag_solve_ctl(kfbi_domain *d, const void *rhat, const void *corr, void *uhat_out, const int *done);
 // U on the full grid from Uhat
 int idst_rows_dense(kfbi_domain *d, const void *uhat, void *grid_out);
-int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done);
+struct GridUpdate;  // below
+int idst_rows_dense_ctl(kfbi_domain *d, const void *uhat, void *grid_out, const int *done,
+                        const GridUpdate *up = nullptr);
 // U at the 6 Nb stencil nodes
 int eval_stencil_nodes(kfbi_domain *d, const void *uhat, void *ust_out);
 int eval_extract_boundary(kfbi_domain *d, double kre, double kim, const void *uhat, const void *f_gamma,
@@ -502,7 +504,7 @@ int interface_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
 int helmholtz_solve(kfbi_domain *d, double kre, double kim, const void *f_grid,
                     const void *f_gamma, const void *g_gamma, void *u_grid_out,
                     void *phi_inout, const kfbi_solve_opts *opts, kfbi_solve_stats *stats,
-                    int bc = 0, void *trace_out = nullptr);
+                    int bc = 0, void *trace_out = nullptr, const GridUpdate *up = nullptr);
 
 inline size_t elem_size(const kfbi_domain *d) { return d->cplx ? sizeof(cd) : sizeof(double); }
 
@@ -561,6 +563,8 @@ struct DstArgs {
     double scale;
     const double *twiddle;
     const int *done;
+    T *upd;         // nullable (grid output only): upd = c0 out + c1 upd, node by node
+    T upd_c0, upd_c1;
 };
 
 template <class T>
@@ -568,6 +572,21 @@ struct ZeroArgs {
     int M;
     T *grid;
     const int *done;
+    T *upd;         // nullable: as DstArgs::upd, on the zeroed rows
+    T upd_c0, upd_c1;
+    const T *upd_g;  // with upd: upd_ag = c0 upd_g + c1 upd_ag on Gamma (nb values)
+    T *upd_ag;
+    int nb;
+};
+
+// An update of a time step's carried state that the final solve's inverse
+// transform makes as it writes the grid solution u: a = c0 u + c1 a on the
+// grid and ag = c0 g + c1 ag on Gamma (the same sums as the stepper's own
+// update kernel; real domains use the real parts)
+struct GridUpdate {
+    void *a, *ag;
+    const void *g;
+    double c0r, c0i, c1r, c1i;
 };
 
 struct TriSparse {
